@@ -1,0 +1,133 @@
+"""Pins of the oracle's combination technique and its convergence.
+
+References: Example 1 of the paper (explicit coefficients), the first line of
+eq. (TD-combi-tec) (sum over k in {0,1}^d) against the binomial second line,
+enumeration counts, sum c_i = 1, and the measured/provable rates of
+Tables 1-2 for the paper's own regular quarter-annulus problem.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+
+def _fld(kind, *prm):
+    return {"kind": kind, "params": list(prm) + [0.0] * (4 - len(prm)), "data": None}
+
+
+def _components(dim, w, lmin=0):
+    wl = W.config("cfg1" if dim == 2 else "cfg3", w=w, lmin=lmin)
+    return O.Problem(wl).components()
+
+
+def test_example_1():
+    # d = 2, J = 1: f_[1,0] + f_[0,1] - f_[0,0]
+    lv, cc = _components(2, 1)
+    got = {tuple(l): c for l, c in zip(lv.tolist(), cc.tolist())}
+    assert got == {(0, 0): -1.0, (0, 1): 1.0, (1, 0): 1.0}
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("lmin", [0, 1])
+def test_binomial_form_equals_first_line(dim, lmin):
+    for w in range(dim * lmin, dim * lmin + 9):
+        lv, cc = _components(dim, w, lmin)
+        got = {tuple(l): c for l, c in zip(lv.tolist(), cc.tolist())}
+        J = w - dim * lmin
+        # every level in the simplex |b| <= J: first-line coefficient
+        for b in np.ndindex(*([J + 1] * dim)):
+            if sum(b) > J:
+                continue
+            lev = np.array(b, dtype=np.int32) + lmin
+            c1 = O.lib().orc_comb_coef_sum(dim, w, lmin, lev.ctypes.data_as(O._ip))
+            assert c1 == got.get(tuple(lev.tolist()), 0.0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coefficients_sum_to_one_and_counts(dim):
+    for lmin in (0, 1):
+        for w in range(dim * lmin, dim * lmin + 13):
+            lv, cc = _components(dim, w, lmin)
+            J = w - dim * lmin
+            assert abs(cc.sum() - 1.0) < 1e-15
+            if dim == 2:
+                assert len(lv) == (2 * J + 1 if J >= 1 else 1)
+            else:
+                assert len(lv) == sum(math.comb(J - j + 2, 2) for j in range(3) if J - j >= 0)
+            assert np.all(lv >= lmin)
+            assert np.all(lv.sum(axis=1) >= w - dim + 1) and np.all(lv.sum(axis=1) <= w)
+            # lexicographic order with level 1 slowest
+            assert [tuple(x) for x in lv.tolist()] == sorted(tuple(x) for x in lv.tolist())
+
+
+@pytest.mark.parametrize("name,count,ndof", [("cfg1", 13, 640), ("cfg2", 21, 22545),
+                                             ("cfg3", 46, 15188), ("cfg5", 85, 18413)])
+def test_config_sizes(name, count, ndof):
+    P = O.Problem(W.config(name))
+    lv, cc = P.components()
+    assert len(lv) == count
+    tot = 0
+    for l in lv:
+        nb = P.nbasis(l)
+        tot += int(np.prod([n - 2 for n in nb]))
+    assert tot == ndof
+
+
+def test_cfg4_sizes():
+    P = O.Problem(W.config("cfg4"))
+    lv, _ = P.components()
+    assert len(lv) == 23
+    assert P.ndof([3, 2]) == 3 * 8 * 4 + 8 + 4 - 0  # three 8x4-element patches, merged edges
+
+
+def test_combination_reproduces_constant_shift():
+    """Sum c_i = 1: a field that every component reproduces exactly is
+    reproduced by the combination (here u = 1 + x + 2y on the L-shape)."""
+    wl = W.config("cfg4", w=4, f=_fld("const", 0.0), g=_fld("affine", 1.0, 1.0, 2.0))
+    P = O.Problem(wl)
+    coefs = P.solve_all()
+    pts, pid = W.eval_points(2, 40, seed=3, npatch=3)
+    off = np.array([[-1, 0], [0, 0], [-1, -1]], float)
+    x = pts + off[pid]
+    # graded knots (gamma = 3) make the smallest elements tiny: allow rounding growth
+    assert np.abs(P.sg_eval(coefs, pts, pid) - (1 + x[:, 0] + 2 * x[:, 1])).max() < 1e-11
+
+
+def _annulus_paper(J, r=2):
+    # the paper's regular annulus problem: a = 1, f = -Laplace(u), Sec. 4.2
+    return W.config("cfg2", w=J, r=r, f=_fld("annulus_rhs", 0.0), a=_fld("const", 1.0),
+                    exact=_fld("annulus_u"))
+
+
+@pytest.mark.slow
+def test_sparse_grid_rates_regular_annulus():
+    """SG-IGA on the paper's regular quarter-annulus problem, d = 2, p = 3,
+    C^2: Table 2 reports L2 / H1 rates 4.15 / 3.06, Table 1 proves 4 / 3.
+    Rates are least-squares slopes of log2(error) against the level over the
+    last levels; they must lie within 0.3 of the provable rates.  The paper
+    does not state which levels its fit uses; over levels 5-8 the oracle's
+    L2 rate is about 3.85, so the measured-value check allows 0.4."""
+    res = []
+    for J in range(5, 9):
+        P = O.Problem(_annulus_paper(J))
+        e = P.sg_errors(P.solve_all(), 128)
+        res.append((J, e[0] / e[2], e[1] / e[3]))
+    r = np.array(res)
+    l2 = -np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0]
+    h1 = -np.polyfit(r[:, 0], np.log2(r[:, 2]), 1)[0]
+    assert abs(l2 - 4.0) < 0.3 and abs(h1 - 3.0) < 0.3
+    assert abs(l2 - 4.15) < 0.4 and abs(h1 - 3.06) < 0.4
+
+
+def test_full_tensor_beats_sparse_grid_error_at_same_level():
+    """u_[J,J] uses the full tensor space, which contains every component
+    space of the combination: its error is no larger (Sec. 3 and Table 2)."""
+    J = 4
+    P = O.Problem(_annulus_paper(J))
+    e_sg = P.sg_errors(P.solve_all(), 64)
+    c, _ = P.solve([J, J])
+    e_full = P.full_errors([J, J], c, 64)
+    assert e_full[0] < e_sg[0] and e_full[1] < e_sg[1]
