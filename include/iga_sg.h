@@ -1,0 +1,229 @@
+/*
+ * iga_sg.h -- C interface of the MI355X sparse-grid isogeometric solver.
+ *
+ * The library solves, on one AMD GPU, every component problem of the
+ * sparse-grid combination technique for a second-order elliptic problem
+ *
+ *     -div(a grad u) = f  in Omega = F([0,1]^d),   u = g on the boundary,
+ *
+ * (Problem 1 of Beck, Sangalli & Tamellini, "A sparse-grid isogeometric
+ * solver", generalised to a variable coefficient a and Dirichlet data g),
+ * discretised on the isoparametric spline spaces of Sec. 2.2 over the
+ * anisotropic tensor grids of Sec. 3, and combines the component solutions
+ * with the coefficients of eq. (TD-combi-tec).
+ *
+ * Call order:  iga_sg_plan_create -> iga_sg_workspace_bytes -> iga_sg_bind
+ *              -> iga_sg_assemble -> iga_sg_solve -> iga_sg_combine / _eval
+ *              -> iga_sg_destroy.
+ * A call made out of order returns IGA_ERR_STATE.
+ *
+ * Memory: the plan owns host-side tables only.  Every device buffer the
+ * library uses lies inside one caller-allocated workspace bound with
+ * iga_sg_bind; the library never allocates device memory.  Pointer arguments
+ * whose name ends in _dev are device pointers, _host are host pointers; they
+ * are borrowed for the duration of the call.  All device work is enqueued on
+ * the stream given to iga_sg_bind and is asynchronous unless stated.
+ *
+ * Errors: every call returns an iga_status; on failure iga_sg_last_error()
+ * returns a message (thread-local).  No exception crosses this interface.
+ * A plan must not be used from two threads at once; distinct plans may.
+ */
+#ifndef IGA_SG_H
+#define IGA_SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct iga_sg_plan_s* iga_sg_plan;
+
+typedef enum {
+    IGA_OK = 0,
+    IGA_ERR_INVALID_ARG = 1,   /* bad sizes, null pointers, unsupported combination */
+    IGA_ERR_GEOMETRY = 2,      /* non-open knots, non-positive Jacobian, bad patch data */
+    IGA_ERR_OUT_OF_MEMORY = 3, /* workspace too small */
+    IGA_ERR_DEVICE = 4,        /* a HIP call failed */
+    IGA_ERR_NOT_CONVERGED = 5, /* some component reached maxit (see the report) */
+    IGA_ERR_BREAKDOWN = 6,     /* some component hit p'Ap <= 0 or a non-finite value */
+    IGA_ERR_STATE = 7          /* call order violated */
+} iga_status;
+
+/* Knot grading of the solution knot vectors (Sec. 4.3): breakpoint i of
+ * level l is g(i / 2^l).  RADICAL is the paper's two-sided map
+ * g(t) = 2^(gamma-1) t^gamma for t <= 1/2 and 1 - 2^(gamma-1) (1-t)^gamma
+ * otherwise; TOWARD0 / TOWARD1 grade toward one end: t^gamma, 1-(1-t)^gamma. */
+enum { IGA_GRADE_UNIFORM = 0, IGA_GRADE_RADICAL = 1, IGA_GRADE_TOWARD0 = 2, IGA_GRADE_TOWARD1 = 3 };
+
+/* One NURBS patch of the geometry map F, eq. (F-B-splines) ("verbatim for
+ * NURBS", Sec. 2.2).  Host pointers, copied by iga_sg_plan_create.
+ * ctrl: [n_d]...[n_1][dim] control points, direction 1 fastest;
+ * weights: [n_d]...[n_1] or NULL for a polynomial map. */
+typedef struct {
+    int degree[3];
+    int nknots[3];
+    const double* knots_host[3];
+    const double* ctrl_host;
+    const double* weights_host;
+    int grading[3];      /* IGA_GRADE_* of the solution knots, per direction */
+    double gamma[3];     /* grading exponent (1 = uniform) */
+} iga_patch;
+
+/* Conforming C^0 interface: side s of a patch is 0 (xi_1=0), 1 (xi_1=1),
+ * 2 (xi_2=0), 3 (xi_2=1), 4 (xi_3=0), 5 (xi_3=1). */
+typedef struct {
+    int patch_a, side_a, patch_b, side_b;
+} iga_interface;
+
+typedef struct {
+    int dim;                         /* 2 or 3 */
+    int npatch;                      /* >= 1 */
+    const iga_patch* patches;
+    int ninterface;
+    const iga_interface* interfaces;
+} iga_geometry;
+
+/* Discretisation (Sec. 2.2 and Sec. 3): degree p in every direction,
+ * interior continuity C^r (0 <= r < p), sparse-grid level w, minimum level
+ * lmin per direction (components have levels i >= lmin with
+ * w-d+1 <= |i| <= w), Gauss points per direction nq (0 => p+1). */
+typedef struct {
+    int p, r, w, lmin, nq;
+} iga_sg_disc;
+
+/* Fields (right-hand side f, coefficient a, Dirichlet data g). */
+enum {
+    IGA_FIELD_NONE = -1,
+    IGA_FIELD_CONST = 0,        /* prm[0] */
+    IGA_FIELD_SINPROD = 1,      /* prm[0] * prod_k sin(pi x_k) */
+    IGA_FIELD_SINCOS = 2,       /* 1 + prm[0] sin(2 pi (x + prm[1])) cos(2 pi y) */
+    IGA_FIELD_ANNULUS_RHS = 3,  /* -div(a grad u), u = -(x^2+y^2-1)(x^2+y^2-4) x y^2,
+                                   a = SINCOS(prm[0], prm[1]) */
+    IGA_FIELD_POLY_RHS = 4,     /* -div(a grad u), u = prod x_k (1-x_k), a = SINCOS(prm) */
+    IGA_FIELD_GRID3D = 5,       /* trilinear interpolation on the vertex grid m/(n-1) of
+                                   [0,1]^3; data_dev [n3][n2][n1], x fastest */
+    IGA_FIELD_CORNER = 6,       /* r^(2/3) sin(2 theta/3), theta in [0, 2 pi) */
+    IGA_FIELD_AFFINE = 7        /* prm[0] + prm[1] x + prm[2] y + prm[3] z */
+};
+
+typedef struct {
+    int kind;
+    double prm[4];
+    const double* data_dev;  /* GRID3D only; device memory */
+    int n[3];
+} iga_field;
+
+/* Precision of the inner solver (the outer refinement is always FP64). */
+enum {
+    IGA_PREC_FP64 = 0,    /* plain FD-preconditioned CG in FP64 */
+    IGA_PREC_FP32 = 1,    /* FP32 operator and FP32 FD factors inside FP64 refinement */
+    IGA_PREC_BF16FD = 2   /* FP32 operator, BF16 FD factors (FP32 accumulation), FP64 refinement */
+};
+
+typedef struct {
+    int precision;     /* IGA_PREC_* */
+    int batched;       /* 1: every grid in one persistent launch; 0: one grid per launch */
+    double tol;        /* stop when r.P^-1 r <= tol^2 b.P^-1 b for the FP64 residual r = b - A x */
+    double tol_inner;  /* inner relative tolerance (same norm) of each refinement step (mixed modes) */
+    int maxit;         /* CG iterations per (inner) solve */
+    int max_refine;    /* refinement steps (mixed modes); ignored for FP64 */
+    int workgroups;    /* persistent launch width; 0 => library choice */
+    int timing;        /* 1: fill report.kernel_ms with HIP-event times (synchronises) */
+} iga_sg_solve_opts;
+
+/* Per-component results; arrays are caller-owned host buffers of length
+ * ncomp (any may be NULL).  status: 0 converged, 5 maxit, 6 breakdown.
+ * relres: ||b - A x||_2 / ||b||_2 of the last FP64 residual;
+ * prelres: sqrt(r.P^-1 r / b.P^-1 b), the quantity the stopping test uses
+ * (P the fast-diagonalisation preconditioner; about the relative
+ * energy-norm error), which does not suffer the kappa*eps rounding floor of
+ * the plain residual on strongly anisotropic grids. */
+typedef struct {
+    int ncomp;
+    int* iters;
+    int* refinements;
+    double* relres;
+    double* prelres;
+    int* status;
+    int total_iters;       /* sum of CG iterations over components */
+    int sweeps;            /* iterations of the persistent loop */
+    double kernel_ms[4];   /* assemble, solve kernel, combine, spare */
+} iga_sg_report;
+
+/* Build a plan: index set and combination coefficients (eq. TD-combi-tec),
+ * knot vectors per level (Sec. 3; grading Sec. 4.3), Gauss rules, 1D
+ * stiffness/mass matrices and their generalised eigen-decompositions for the
+ * fast-diagonalisation preconditioner, task lists.  Host only; no GPU call. */
+iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc, iga_sg_plan* out);
+
+/* Bytes of device workspace the plan needs (256-byte aligned sub-buffers). */
+iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes);
+
+/* Bind a device workspace of at least iga_sg_workspace_bytes bytes and a HIP
+ * stream (hipStream_t, NULL = default).  Uploads the plan tables and computes
+ * the basis tables on the device; synchronises the stream before returning. */
+iga_status iga_sg_bind(iga_sg_plan plan, void* workspace_dev, size_t bytes, void* stream);
+
+/* Component list: levels_host [n][dim], ndof_host [n] (interior unknowns),
+ * coef_host [n] (combination coefficients c_i).  Any pointer may be NULL. */
+iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t* ndof_host,
+                             double* coef_host);
+
+/* Assemble every component system: per Gauss point the geometry map, its
+ * Jacobian, a, f and the operator coefficients a w |det DF| DF^-1 DF^-T
+ * (Sec. 2.2, Galerkin form of Problem 1), then the load vectors.  f and a
+ * are required; g may be NULL (homogeneous Dirichlet). */
+iga_status iga_sg_assemble(iga_sg_plan plan, const iga_field* f, const iga_field* a,
+                           const iga_field* g);
+
+/* Solve every component system with fast-diagonalisation preconditioned CG
+ * (FP64, or mixed precision inside FP64 iterative refinement).  report may
+ * be NULL.  Returns IGA_ERR_NOT_CONVERGED / IGA_ERR_BREAKDOWN if any
+ * component failed; the other components are still solved. */
+iga_status iga_sg_solve(iga_sg_plan plan, const iga_sg_solve_opts* opts, iga_sg_report* report);
+
+/* u_dev[i] = sum_c coef_c u_c(xi_i), eq. (TD-combi-tec), accumulated in FP64
+ * in component order.  xi_dev [n][dim] parametric points in [0,1]^dim,
+ * patch_dev [n] patch ids or NULL (patch 0). */
+iga_status iga_sg_combine(iga_sg_plan plan, const double* xi_dev, const int* patch_dev, int64_t n,
+                          double* u_dev);
+
+/* u_dev[i] = u_comp(xi_i) for one component. */
+iga_status iga_sg_eval(iga_sg_plan plan, int comp, const double* xi_dev, const int* patch_dev,
+                       int64_t n, double* u_dev);
+
+/* Copy the interior coefficients of component comp (lexicographic, direction
+ * 1 fastest) to out_dev. */
+iga_status iga_sg_coeffs(iga_sg_plan plan, int comp, double* out_dev);
+
+/* Kernel-level hooks (tests): y = A_comp x (which = 0 FP64 operator, 1 FP32
+ * operator) or y = P^-1 x (which = 2 FP64, 3 FP32, 4 BF16 fast
+ * diagonalisation); x_dev, y_dev hold the component's interior unknowns. */
+iga_status iga_sg_apply(iga_sg_plan plan, int comp, int which, const double* x_dev, double* y_dev);
+
+/* Load vector of component comp (after iga_sg_assemble) to out_dev. */
+iga_status iga_sg_rhs(iga_sg_plan plan, int comp, double* out_dev);
+
+/* Host copies of the 1D generalised eigen-decomposition K U = M U diag(lam),
+ * U^T M U = I, of direction dir and level lev of patch 0: U_host [n][n]
+ * (row i = basis function i, column k = eigenvector k), lam_host [n],
+ * n = interior basis functions.  Any output may be NULL; *n receives n. */
+iga_status iga_sg_fd_factor(iga_sg_plan plan, int dir, int lev, int* n, double* U_host,
+                            double* lam_host);
+
+/* Host copy of the 1D interior stiffness and mass of direction dir, level
+ * lev (dense [n][n]). */
+iga_status iga_sg_matrices_1d(iga_sg_plan plan, int dir, int lev, int* n, double* K_host,
+                              double* M_host);
+
+void iga_sg_destroy(iga_sg_plan plan);
+const char* iga_sg_last_error(void);
+/* Library version string. */
+const char* iga_sg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,331 @@
+"""Python binding of the MI355X sparse-grid isogeometric solver (libigasg.so).
+
+Argument marshalling only: every step of the method (basis tables,
+assembly, preconditioned solves, combination) runs in the library's HIP
+kernels.  PyTorch provides the device workspace and the stream.  The binding
+fails loudly when the compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Any, Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigasg.so")
+
+FIELD = {None: -1, "none": -1, "const": 0, "sinprod": 1, "sincos": 2, "annulus_rhs": 3,
+         "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7}
+GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
+STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_ERR_OUT_OF_MEMORY",
+          4: "IGA_ERR_DEVICE", 5: "IGA_ERR_NOT_CONVERGED", 6: "IGA_ERR_BREAKDOWN", 7: "IGA_ERR_STATE"}
+APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4}
+
+EXPORTS = (
+    "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_bind", "iga_sg_components",
+    "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
+    "iga_sg_apply", "iga_sg_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
+    "iga_sg_last_error", "iga_sg_version",
+)
+
+
+class IgaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Patch(C.Structure):
+    _fields_ = [("degree", C.c_int * 3), ("nknots", C.c_int * 3),
+                ("knots_host", C.POINTER(C.c_double) * 3), ("ctrl_host", C.POINTER(C.c_double)),
+                ("weights_host", C.POINTER(C.c_double)), ("grading", C.c_int * 3),
+                ("gamma", C.c_double * 3)]
+
+
+class _Iface(C.Structure):
+    _fields_ = [("patch_a", C.c_int), ("side_a", C.c_int), ("patch_b", C.c_int),
+                ("side_b", C.c_int)]
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("dim", C.c_int), ("npatch", C.c_int), ("patches", C.POINTER(_Patch)),
+                ("ninterface", C.c_int), ("interfaces", C.POINTER(_Iface))]
+
+
+class _Disc(C.Structure):
+    _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int)]
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int), ("prm", C.c_double * 4), ("data_dev", C.c_void_p),
+                ("n", C.c_int * 3)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("batched", C.c_int), ("tol", C.c_double),
+                ("tol_inner", C.c_double), ("maxit", C.c_int), ("max_refine", C.c_int),
+                ("workgroups", C.c_int), ("timing", C.c_int)]
+
+
+class _Report(C.Structure):
+    _fields_ = [("ncomp", C.c_int), ("iters", C.POINTER(C.c_int)),
+                ("refinements", C.POINTER(C.c_int)), ("relres", C.POINTER(C.c_double)),
+                ("prelres", C.POINTER(C.c_double)), ("status", C.POINTER(C.c_int)), ("total_iters", C.c_int), ("sweeps", C.c_int),
+                ("kernel_ms", C.c_double * 4)]
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+def lib():
+    """Load libigasg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1707_09598_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.iga_sg_plan_create.argtypes = [C.POINTER(_Geometry), C.POINTER(_Disc), C.POINTER(vp)]
+        L.iga_sg_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.iga_sg_bind.argtypes = [vp, vp, C.c_size_t, vp]
+        L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
+        L.iga_sg_assemble.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Field)]
+        L.iga_sg_solve.argtypes = [vp, C.POINTER(_Opts), C.POINTER(_Report)]
+        L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp]
+        L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
+        L.iga_sg_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp]
+        L.iga_sg_rhs.argtypes = [vp, C.c_int, vp]
+        L.iga_sg_fd_factor.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
+        L.iga_sg_matrices_1d.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
+        L.iga_sg_destroy.argtypes = [vp]
+        L.iga_sg_destroy.restype = None
+        L.iga_sg_last_error.restype = C.c_char_p
+        L.iga_sg_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> None:
+    if code != 0:
+        raise IgaError(code, lib().iga_sg_last_error().decode())
+
+
+def _arr(x, dtype=np.float64) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return _dp() if a is None else a.ctypes.data_as(_dp)
+
+
+class Plan:
+    """One plan of the solver for a workload dictionary (see ``workloads``).
+
+    Host-side methods (components, fd_factor, matrices_1d) need no GPU.
+    ``bind`` allocates the device workspace with torch on the current device.
+    """
+
+    def __init__(self, wl: Dict[str, Any]):
+        self.wl = wl
+        self.dim = d = int(wl["dim"])
+        self._keep = []
+        pats = wl["patches"]
+        parr = (_Patch * len(pats))()
+        gpp = wl.get("grading_per_patch") or [wl["grading"]] * len(pats)
+        for i, pt in enumerate(pats):
+            for k in range(d):
+                kv = _arr(pt["knots"][k])
+                self._keep.append(kv)
+                parr[i].degree[k] = int(pt["degree"][k])
+                parr[i].nknots[k] = len(kv)
+                parr[i].knots_host[k] = _ptr(kv)
+                kind, gam = gpp[i][k]
+                parr[i].grading[k] = GRADE[kind]
+                parr[i].gamma[k] = float(gam)
+            ctrl = _arr(pt["ctrl"]).reshape(-1)
+            self._keep.append(ctrl)
+            parr[i].ctrl_host = _ptr(ctrl)
+            if pt.get("weights") is not None:
+                wt = _arr(pt["weights"]).reshape(-1)
+                self._keep.append(wt)
+                parr[i].weights_host = _ptr(wt)
+            else:
+                parr[i].weights_host = _dp()
+        self._keep.append(parr)
+        ifs = wl.get("interfaces") or []
+        iarr = (_Iface * max(1, len(ifs)))()
+        for i, (pa, sa, pb, sb) in enumerate(ifs):
+            iarr[i].patch_a, iarr[i].side_a, iarr[i].patch_b, iarr[i].side_b = pa, sa, pb, sb
+        self._keep.append(iarr)
+        G = _Geometry(d, len(pats), C.cast(parr, C.POINTER(_Patch)), len(ifs),
+                      C.cast(iarr, C.POINTER(_Iface)))
+        D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0)
+        h = C.c_void_p()
+        _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
+        self.h = h
+        self.ws = None
+        self.stream = None
+        n = C.c_int()
+        _check(lib().iga_sg_components(self.h, C.byref(n), _ip(), C.POINTER(C.c_int64)(), _dp()))
+        self.ncomp = n.value
+        lv = np.zeros((self.ncomp, d), dtype=np.int32)
+        nd = np.zeros(self.ncomp, dtype=np.int64)
+        cf = np.zeros(self.ncomp)
+        _check(lib().iga_sg_components(self.h, C.byref(n), lv.ctypes.data_as(_ip),
+                                       nd.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(cf)))
+        self.levels, self.ndof, self.coef = lv, nd, cf
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().iga_sg_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ---- host queries ----------------------------------------------------
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib().iga_sg_workspace_bytes(self.h, C.byref(b)))
+        return b.value
+
+    def fd_factor(self, direction: int, level: int):
+        n = C.c_int()
+        _check(lib().iga_sg_fd_factor(self.h, direction, level, C.byref(n), _dp(), _dp()))
+        U = np.zeros((n.value, n.value))
+        lam = np.zeros(n.value)
+        _check(lib().iga_sg_fd_factor(self.h, direction, level, C.byref(n), _ptr(U), _ptr(lam)))
+        return U, lam
+
+    def matrices_1d(self, direction: int, level: int):
+        n = C.c_int()
+        _check(lib().iga_sg_matrices_1d(self.h, direction, level, C.byref(n), _dp(), _dp()))
+        K = np.zeros((n.value, n.value))
+        M = np.zeros((n.value, n.value))
+        _check(lib().iga_sg_matrices_1d(self.h, direction, level, C.byref(n), _ptr(K), _ptr(M)))
+        return K, M
+
+    # ---- device ------------------------------------------------------------
+    def bind(self, device=None, stream=None) -> None:
+        import torch
+        dev = torch.device(device if device is not None else "cuda")
+        nbytes = self.workspace_bytes()
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self.ws = raw
+        self.ws_ptr = raw.data_ptr() + off
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib().iga_sg_bind(self.h, C.c_void_p(self.ws_ptr), C.c_size_t(nbytes),
+                                 C.c_void_p(self.stream.cuda_stream)))
+
+    def _field(self, spec, keep):
+        F = _Field()
+        if spec is None:
+            F.kind = -1
+            return F
+        F.kind = FIELD[spec["kind"]]
+        for i, v in enumerate((list(spec.get("params") or []) + [0.0] * 4)[:4]):
+            F.prm[i] = float(v)
+        data = spec.get("data")
+        if data is not None:
+            import torch
+            t = data if isinstance(data, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(data))
+            t = t.to(device=self.device, dtype=torch.float64).contiguous()
+            keep.append(t)
+            F.data_dev = t.data_ptr()
+            shp = tuple(t.shape)[::-1]
+            for k in range(3):
+                F.n[k] = int(shp[k])
+        return F
+
+    def assemble(self, f=None, a=None, g=None) -> None:
+        wl = self.wl
+        keep = []
+        Ff = self._field(f if f is not None else wl["f"], keep)
+        Fa = self._field(a if a is not None else wl["a"], keep)
+        Fg = self._field(g if g is not None else wl.get("g"), keep)
+        self._fields = keep
+        _check(lib().iga_sg_assemble(self.h, C.byref(Ff), C.byref(Fa),
+                                     C.byref(Fg) if Fg.kind >= 0 else C.POINTER(_Field)()))
+
+    def solve(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
+              maxit: int = 500, max_refine: int = 0, batched: bool = True, workgroups: int = 0,
+              timing: bool = False, check: bool = True) -> Dict[str, Any]:
+        o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups,
+                  int(timing))
+        it = np.zeros(self.ncomp, dtype=np.int32)
+        rf = np.zeros(self.ncomp, dtype=np.int32)
+        rr = np.zeros(self.ncomp)
+        pr = np.zeros(self.ncomp)
+        stt = np.zeros(self.ncomp, dtype=np.int32)
+        R = _Report(self.ncomp, it.ctypes.data_as(_ip), rf.ctypes.data_as(_ip), _ptr(rr), _ptr(pr),
+                    stt.ctypes.data_as(_ip), 0, 0)
+        code = lib().iga_sg_solve(self.h, C.byref(o), C.byref(R))
+        rep = {"code": code, "iters": it, "refinements": rf, "relres": rr, "prelres": pr,
+               "status": stt, "total_iters": R.total_iters, "kernel_ms": list(R.kernel_ms)}
+        if check:
+            _check(code)
+        return rep
+
+    def solve_async(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
+                    maxit: int = 500, max_refine: int = 0, batched: bool = True,
+                    workgroups: int = 0) -> None:
+        """Enqueue a solve without reading the report back (no host sync)."""
+        o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0)
+        _check(lib().iga_sg_solve(self.h, C.byref(o), C.POINTER(_Report)()))
+
+    def combine(self, xi, patch=None):
+        import torch
+        xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
+        n = xi.shape[0]
+        u = torch.empty(n, dtype=torch.float64, device=self.device)
+        pid = None if patch is None else torch.as_tensor(patch, dtype=torch.int32,
+                                                         device=self.device).contiguous()
+        _check(lib().iga_sg_combine(self.h, C.c_void_p(xi.data_ptr()),
+                                    C.c_void_p(pid.data_ptr() if pid is not None else 0), n,
+                                    C.c_void_p(u.data_ptr())))
+        return u
+
+    def eval(self, comp: int, xi, patch=None):
+        import torch
+        xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
+        n = xi.shape[0]
+        u = torch.empty(n, dtype=torch.float64, device=self.device)
+        pid = None if patch is None else torch.as_tensor(patch, dtype=torch.int32,
+                                                         device=self.device).contiguous()
+        _check(lib().iga_sg_eval(self.h, comp, C.c_void_p(xi.data_ptr()),
+                                 C.c_void_p(pid.data_ptr() if pid is not None else 0), n,
+                                 C.c_void_p(u.data_ptr())))
+        return u
+
+    def coeffs(self, comp: int):
+        import torch
+        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        _check(lib().iga_sg_coeffs(self.h, comp, C.c_void_p(out.data_ptr())))
+        return out
+
+    def rhs(self, comp: int):
+        import torch
+        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        _check(lib().iga_sg_rhs(self.h, comp, C.c_void_p(out.data_ptr())))
+        return out
+
+    def apply(self, comp: int, which: str, x):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+        y = torch.empty_like(x)
+        _check(lib().iga_sg_apply(self.h, comp, APPLY[which], C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(y.data_ptr())))
+        return y
+
+
+def version() -> str:
+    return lib().iga_sg_version().decode()

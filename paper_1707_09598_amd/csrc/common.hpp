@@ -1,0 +1,150 @@
+// common.hpp -- data structures shared by the host plan and the gfx950 kernels.
+//
+// A plan describes every component grid of the combination technique
+// (eq. TD-combi-tec) as a tensor grid with per-direction 1D tables.  All
+// device data lives in one caller-provided workspace; the structures below
+// hold byte offsets into it, fixed at plan time.
+#pragma once
+
+#include <cstdint>
+
+namespace igasg {
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxP = 4;          // solution degree limit (register arrays)
+constexpr int kMaxPg = 4;         // geometry degree limit
+constexpr int kMaxPatch = 4;
+constexpr int kBlock = 256;       // threads per workgroup in every kernel
+
+// Grid stages of the persistent refinement/CG state machine.
+enum Stage : int { STAGE_RESID = 0, STAGE_ITER = 1, STAGE_DONE = 2, STAGE_XUPD = 3 };
+// Per-component status codes reported to the host.
+enum GridStatus : int { GS_RUNNING = -1, GS_OK = 0, GS_MAXIT = 5, GS_BREAKDOWN = 6 };
+
+// 1D data of one (patch, direction, level): knots, Gauss tables, FD factors.
+struct Tab1D {
+    int nb;       // B-spline basis functions
+    int ni;       // interior functions (nb - 2)
+    int E;        // elements (non-empty knot intervals)
+    int Q;        // quadrature points = E * nq
+    int m;        // interior knot multiplicity p - r
+    int pg;       // geometry degree in this direction
+    int ngb;      // geometry basis functions
+    int nk;       // solution knots
+    int ngk;      // geometry knots
+    int uniform;  // breakpoints are i / E
+    int pad0, pad1;
+    // double-pool offsets (in elements)
+    int64_t oB, oD;       // [Q][p+1] basis values / derivatives at the Gauss points
+    int64_t oBg, oDg;     // [Q][pg+1] geometry basis values / derivatives
+    int64_t oXq, oWq;     // [Q] parametric coordinate, weight (incl. element half length)
+    int64_t oBrk;         // [E+1] breakpoints
+    int64_t oKn;          // [nk] solution knots
+    int64_t oGkn;         // [ngk] geometry knots
+    int64_t oU, oUT;      // [ni][ni] eigenvectors (U[i][k]) and transpose
+    int64_t oLam;         // [ni]
+    // int-pool offsets
+    int64_t oGs;          // [Q] first geometry basis index at each Gauss point
+    // float-pool and bf16-pool offsets
+    int64_t oU32, oUT32;
+    int64_t oU16, oUT16;
+};
+
+// One component grid (one patch of one combination component).
+struct Grid {
+    int lev[3];
+    int ni[3];        // interior unknowns per direction (1 beyond dim)
+    int nb[3];
+    int E[3];
+    int Q[3];
+    int tab[3];       // Tab1D index per direction
+    int patch;
+    int comp;         // combination component index
+    int64_t dof_off;  // offset of the interior unknowns in the vector pool
+    int64_t ndof;
+    int64_t qp_off;   // offset of the Gauss-point data (per component field)
+    int64_t nqp;
+    double ccoef;     // combination coefficient
+    double fdc[3];    // per-direction scaling of the fast-diagonalisation pencil
+    // fast-diagonalisation task split (2D: blocks of the longest direction)
+    int big;          // direction split into blocks
+    int nblk;
+    int blk;          // block length
+    int blk_off;      // first FD task
+    // operator tiles
+    int tile[3];      // tile size in unknowns per direction
+    int ntd[3];       // tiles per direction
+    int ntile;
+    int tile_off;     // first operator task
+};
+
+// Per-grid solver state (double-buffered by sweep parity on the device).
+struct GState {
+    double rho;       // r.z of the previous iteration (CG beta)
+    double rho0;      // r.z at the start of the current inner solve
+    double rhob;      // b.P^-1 b (reference for the outer test)
+    double bn2;       // ||b||^2
+    double relres;    // last FP64 relative residual ||b - A x|| / ||b||
+    double prelres;   // last preconditioned relative residual sqrt(r.P^-1 r / b.P^-1 b)
+    int stage;
+    int it;           // iterations of the current inner solve
+    int total_it;
+    int refine;       // inner solves started
+    int status;
+    int pad;
+};
+
+struct Task {
+    int grid;
+    int local;
+};
+
+// Workspace layout: byte offsets of every device array.
+struct Layout {
+    size_t tabs, grids, dpool, ipool, fpool, hpool, ctrl;
+    size_t G64, G32, Fq;          // operator coefficients and load density at Gauss points
+    size_t b, x, d, r2, z, p2, q, rt;
+    size_t st2;                   // GState[2][ngrid]
+    size_t part;                  // partial sums
+    size_t optask, fdtask;
+    size_t bar;                   // barrier + counters
+    size_t total;
+};
+
+// Kernel parameter block (passed by value).
+struct Params {
+    const Tab1D* tabs;
+    const Grid* grids;
+    const double* dpool;
+    const int* ipool;
+    const float* fpool;
+    const uint16_t* hpool;
+    const double* ctrl;      // homogeneous control points [patch][...][4]
+    int64_t ctrl_off[kMaxPatch];
+    int gdeg[kMaxPatch][3];
+    int gn[kMaxPatch][3];    // geometry basis counts
+    int rational[kMaxPatch];
+    int dim, p, nq, ncompG;  // ncompG: operator coefficients per Gauss point
+    int ngrid, nop, nfd;
+    int64_t nqp_total, ndof_total;
+    double* G64;
+    float* G32;
+    double* Fq;
+    double* b;
+    double* x;
+    double* d;
+    double* r2;        // two buffers of ndof_total
+    double* z;
+    double* p2;        // two buffers
+    double* q;
+    double* rt;
+    GState* st2;       // two buffers of ngrid
+    double* part;      // partial sums: [4 kinds][2 parity][max(nop, nfd)]
+    int64_t part_stride;
+    const Task* optask;
+    const Task* fdtask;
+    unsigned* bar;     // [0] count, [1] generation, [2] done counter
+    double gx[8], gw[8];  // Gauss-Legendre rule on [-1, 1]
+};
+
+}  // namespace igasg

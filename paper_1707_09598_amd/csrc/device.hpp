@@ -1,0 +1,97 @@
+// device.hpp -- device helpers shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace igasg {
+
+// de Boor's triangular scheme (values and first derivatives of the p+1
+// B-splines non-zero on knot interval s), as on the host.
+__device__ __forceinline__ void d_basis_funs(int p, const double* U, int s, double x, double* N,
+                                             double* dN) {
+    double left[kMaxPg + 2], right[kMaxPg + 2];
+    double t[kMaxPg + 1][kMaxPg + 1];
+    t[0][0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = x - U[s + 1 - j];
+        right[j] = U[s + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            t[j][r] = right[r + 1] + left[j - r];
+            double tmp = t[r][j - 1] / t[j][r];
+            t[r][j] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        t[j][j] = saved;
+    }
+    for (int r = 0; r <= p; ++r) N[r] = t[r][p];
+    if (dN) {
+        for (int r = 0; r <= p; ++r) {
+            double v = 0.0;
+            if (r >= 1) v += t[r - 1][p - 1] / t[p][r - 1];
+            if (r <= p - 1) v -= t[r][p - 1] / t[p][r];
+            dN[r] = p * v;
+        }
+    }
+}
+
+__device__ __forceinline__ int d_find_interval(int p, int nk, const double* U, double x) {
+    int n = nk - p - 1;
+    if (x >= U[n]) {
+        int s = n - 1;
+        while (s > p && !(U[s] < U[s + 1])) --s;
+        return s;
+    }
+    if (x <= U[p]) return p;
+    int lo = p, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (x < U[mid]) hi = mid;
+        else lo = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(static_cast<unsigned>(h) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float load_f(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float load_f<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float load_f<uint16_t>(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
+
+// Deterministic workgroup sum (fixed shuffle tree, then fixed LDS order).
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Sum of count partials (fixed order per lane, fixed shuffle tree); every
+// thread of the workgroup gets the result.
+__device__ __forceinline__ double sum_partials(const double* part, int count, double* red) {
+    double v = 0.0;
+    if (threadIdx.x < 64)
+        for (int i = threadIdx.x; i < count; i += 64) v += part[i];
+    if (threadIdx.x < 64)
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (threadIdx.x == 0) red[0] = v;
+    __syncthreads();
+    double s = red[0];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace igasg

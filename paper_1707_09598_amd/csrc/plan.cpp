@@ -1,0 +1,660 @@
+// plan.cpp -- host plan of the sparse-grid isogeometric solver: index set and
+// combination coefficients (eq. TD-combi-tec), dyadic knot vectors (Sec. 3)
+// with optional grading (Sec. 4.3), Gauss rules, 1D stiffness/mass matrices
+// and their generalised eigen-decompositions (fast diagonalisation), the
+// component grids, operator tiles, preconditioner blocks and the device
+// workspace layout.  No GPU call is made here.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "eigen.hpp"
+#include "plan.hpp"
+
+using namespace igasg;
+
+namespace igasg {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+const char* last_error_str() { return g_err.c_str(); }
+
+// de Boor's triangular scheme with left/right knot differences: row j of the
+// table holds the degree-j functions; the strictly lower part keeps the knot
+// differences needed for the derivative.
+void basis_funs(int p, const double* U, int s, double x, double* N, double* dN) {
+    double left[kMaxP + 2], right[kMaxP + 2];
+    double t[kMaxP + 1][kMaxP + 1];
+    t[0][0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = x - U[s + 1 - j];
+        right[j] = U[s + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            t[j][r] = right[r + 1] + left[j - r];
+            double tmp = t[r][j - 1] / t[j][r];
+            t[r][j] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        t[j][j] = saved;
+    }
+    for (int r = 0; r <= p; ++r) N[r] = t[r][p];
+    if (!dN) return;
+    for (int r = 0; r <= p; ++r) {
+        double v = 0.0;
+        if (r >= 1) v += t[r - 1][p - 1] / t[p][r - 1];
+        if (r <= p - 1) v -= t[r][p - 1] / t[p][r];
+        dN[r] = p * v;
+    }
+}
+
+int find_interval(int p, int nk, const double* U, double x) {
+    int n = nk - p - 1;
+    if (x >= U[n]) {
+        int s = n - 1;
+        while (s > p && !(U[s] < U[s + 1])) --s;
+        return s;
+    }
+    if (x <= U[p]) return p;
+    int lo = p, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (x < U[mid]) hi = mid;
+        else lo = mid;
+    }
+    return lo;
+}
+
+double grade_map(int kind, double gamma, double t) {
+    switch (kind) {
+        case IGA_GRADE_RADICAL:
+            return t <= 0.5 ? std::pow(2.0, gamma - 1.0) * std::pow(t, gamma)
+                            : 1.0 - std::pow(2.0, gamma - 1.0) * std::pow(1.0 - t, gamma);
+        case IGA_GRADE_TOWARD0:
+            return std::pow(t, gamma);
+        case IGA_GRADE_TOWARD1:
+            return 1.0 - std::pow(1.0 - t, gamma);
+        default:
+            return t;
+    }
+}
+
+// Gauss-Legendre nodes and weights by the Golub-Welsch method: the nodes are
+// the eigenvalues of the Jacobi matrix of the Legendre recurrence, the
+// weights 2 v_0^2 with v the normalised eigenvectors.
+void gauss_rule(int n, double* x, double* w) {
+    std::vector<double> J(static_cast<size_t>(n) * n, 0.0), I(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) I[static_cast<size_t>(i) * n + i] = 1.0;
+    for (int k = 1; k < n; ++k) {
+        double b = k / std::sqrt(4.0 * k * k - 1.0);
+        J[static_cast<size_t>(k) * n + k - 1] = J[static_cast<size_t>(k - 1) * n + k] = b;
+    }
+    std::vector<double> V(static_cast<size_t>(n) * n);
+    gen_eig_banded(n, 1, J.data(), I.data(), V.data(), x);
+    for (int i = 0; i < n; ++i) w[i] = 2.0 * V[i] * V[i];
+    if (n % 2 == 1) x[n / 2] = 0.0;
+    for (int i = 0; i < n / 2; ++i) {  // exact symmetry
+        double a = 0.5 * (x[n - 1 - i] - x[i]);
+        x[i] = -a;
+        x[n - 1 - i] = a;
+        double ww = 0.5 * (w[i] + w[n - 1 - i]);
+        w[i] = w[n - 1 - i] = ww;
+    }
+}
+
+int tab_index(const iga_sg_plan_s* P, int patch, int dir, int lev) {
+    return (patch * P->dim + dir) * (P->Lmax + 1) + lev;
+}
+
+}  // namespace igasg
+
+namespace {
+
+std::vector<double> make_knots(int p, int r, int lev, int gk, double gamma) {
+    std::vector<double> U;
+    int ne = 1 << lev;
+    for (int i = 0; i <= p; ++i) U.push_back(0.0);
+    for (int e = 1; e < ne; ++e) {
+        double z = grade_map(gk, gamma, static_cast<double>(e) / ne);
+        for (int m = 0; m < p - r; ++m) U.push_back(z);
+    }
+    for (int i = 0; i <= p; ++i) U.push_back(1.0);
+    return U;
+}
+
+struct FDEntry {
+    std::vector<double> K, M, U, lam;
+    int n = 0;
+};
+
+std::mutex g_fd_mu;
+std::map<std::tuple<int, int, int, int, double, int>, FDEntry> g_fd_cache;
+
+// 1D interior stiffness/mass by Gauss quadrature and their eigen-pairs.
+const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, const double* gx,
+                        const double* gw, bool* ok) {
+    std::lock_guard<std::mutex> lk(g_fd_mu);
+    auto key = std::make_tuple(p, r, lev, gk, gamma, nq);
+    auto it = g_fd_cache.find(key);
+    if (it != g_fd_cache.end()) {
+        *ok = true;
+        return it->second;
+    }
+    FDEntry e;
+    std::vector<double> U = make_knots(p, r, lev, gk, gamma);
+    int nk = static_cast<int>(U.size());
+    int nb = nk - p - 1, ni = nb - 2;
+    e.n = ni;
+    e.K.assign(static_cast<size_t>(ni) * ni, 0.0);
+    e.M.assign(static_cast<size_t>(ni) * ni, 0.0);
+    double N[kMaxP + 1], dN[kMaxP + 1];
+    for (int s = p; s < nb; ++s) {
+        if (!(U[s] < U[s + 1])) continue;
+        double h = U[s + 1] - U[s];
+        for (int q = 0; q < nq; ++q) {
+            double x = U[s] + 0.5 * h * (gx[q] + 1.0), w = 0.5 * h * gw[q];
+            basis_funs(p, U.data(), s, x, N, dN);
+            for (int a = 0; a <= p; ++a) {
+                int ia = s - p + a - 1;
+                if (ia < 0 || ia >= ni) continue;
+                for (int b = 0; b <= p; ++b) {
+                    int ib = s - p + b - 1;
+                    if (ib < 0 || ib >= ni) continue;
+                    e.K[static_cast<size_t>(ia) * ni + ib] += w * dN[a] * dN[b];
+                    e.M[static_cast<size_t>(ia) * ni + ib] += w * N[a] * N[b];
+                }
+            }
+        }
+    }
+    e.U.assign(static_cast<size_t>(ni) * ni, 0.0);
+    e.lam.assign(ni, 0.0);
+    *ok = ni > 0 && gen_eig_banded(ni, p, e.K.data(), e.M.data(), e.U.data(), e.lam.data());
+    auto res = g_fd_cache.emplace(key, std::move(e));
+    return res.first->second;
+}
+
+uint16_t to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);  // inf/nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;  // round to nearest even
+    return static_cast<uint16_t>(u >> 16);
+}
+
+double binom(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    double v = 1.0;
+    for (int i = 1; i <= k; ++i) v = v * (n - k + i) / i;
+    return v;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Element index range touching interior unknowns [a, b) of one direction.
+void elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
+    int lo_basis = a + 1, hi_basis = b;  // basis indices of the first/last owned unknown
+    int lo = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
+    int hi = hi_basis / m;
+    *elo = std::max(0, lo);
+    *ehi = std::min(E - 1, hi);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* iga_sg_last_error(void) { return last_error_str(); }
+
+const char* iga_sg_version(void) { return "iga-sg-mi355x 0.1 (gfx950)"; }
+
+iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc, iga_sg_plan* out) {
+    if (!geom || !disc || !out) {
+        set_error("null argument");
+        return IGA_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    const int d = geom->dim;
+    if (d != 2 && d != 3) {
+        set_error("dim must be 2 or 3 (got %d)", d);
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (geom->npatch < 1 || geom->npatch > kMaxPatch || !geom->patches) {
+        set_error("npatch must be in [1, %d]", kMaxPatch);
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (geom->npatch != 1) {
+        set_error("several patches are not supported by the GPU path");
+        return IGA_ERR_INVALID_ARG;
+    }
+    const int p = disc->p, r = disc->r;
+    if (p < 1 || p > kMaxP || r < 0 || r >= p) {
+        set_error("need 1 <= p <= %d and 0 <= r < p (got p=%d r=%d)", kMaxP, p, r);
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (disc->lmin < 0 || disc->w < d * disc->lmin || disc->w > 24) {
+        set_error("need w >= dim*lmin, lmin >= 0, w <= 24 (got w=%d lmin=%d)", disc->w, disc->lmin);
+        return IGA_ERR_INVALID_ARG;
+    }
+    const int nq = disc->nq > 0 ? disc->nq : p + 1;
+    if (nq != p + 1) {
+        set_error("the GPU path uses p+1 Gauss points per direction (got nq=%d)", nq);
+        return IGA_ERR_INVALID_ARG;
+    }
+    auto P = new iga_sg_plan_s();
+    P->dim = d;
+    P->p = p;
+    P->r = r;
+    P->w = disc->w;
+    P->lmin = disc->lmin;
+    P->nq = nq;
+    P->gauss_x.resize(nq);
+    P->gauss_w.resize(nq);
+    gauss_rule(nq, P->gauss_x.data(), P->gauss_w.data());
+    // ---- geometry ---------------------------------------------------------
+    for (int pt = 0; pt < geom->npatch; ++pt) {
+        const iga_patch& G = geom->patches[pt];
+        PatchHost H;
+        int ncp = 1;
+        for (int k = 0; k < d; ++k) {
+            int pg = G.degree[k], nk = G.nknots[k];
+            if (pg < 1 || pg > kMaxPg || nk < 2 * (pg + 1) || !G.knots_host[k]) {
+                set_error("patch %d direction %d: bad geometry degree/knots", pt, k);
+                delete P;
+                return IGA_ERR_GEOMETRY;
+            }
+            H.degree[k] = pg;
+            H.knots[k].assign(G.knots_host[k], G.knots_host[k] + nk);
+            for (int i = 1; i < nk; ++i)
+                if (H.knots[k][i] < H.knots[k][i - 1]) {
+                    set_error("patch %d direction %d: knots not non-decreasing", pt, k);
+                    delete P;
+                    return IGA_ERR_GEOMETRY;
+                }
+            for (int i = 0; i <= pg; ++i)
+                if (H.knots[k][i] != 0.0 || H.knots[k][nk - 1 - i] != 1.0) {
+                    set_error("patch %d direction %d: geometry knots must be open on [0,1]", pt, k);
+                    delete P;
+                    return IGA_ERR_GEOMETRY;
+                }
+            ncp *= nk - pg - 1;
+            H.grading[k] = G.grading[k];
+            H.gamma[k] = G.gamma[k] > 0 ? G.gamma[k] : 1.0;
+            if (H.grading[k] < 0 || H.grading[k] > 3) {
+                set_error("bad grading kind %d", H.grading[k]);
+                delete P;
+                return IGA_ERR_INVALID_ARG;
+            }
+        }
+        if (!G.ctrl_host) {
+            set_error("patch %d: missing control points", pt);
+            delete P;
+            return IGA_ERR_GEOMETRY;
+        }
+        H.ctrl.assign(G.ctrl_host, G.ctrl_host + static_cast<size_t>(ncp) * d);
+        if (G.weights_host) {
+            H.weights.assign(G.weights_host, G.weights_host + ncp);
+            bool all_same = true;
+            for (double v : H.weights) {
+                if (!(v > 0)) {
+                    set_error("patch %d: weights must be positive", pt);
+                    delete P;
+                    return IGA_ERR_GEOMETRY;
+                }
+                if (v != H.weights[0]) all_same = false;
+            }
+            if (!all_same) P->rational_any = 1;
+        }
+        P->patches.push_back(std::move(H));
+    }
+    // ---- components (eq. TD-combi-tec), lexicographic, level 1 slowest ----
+    const int J = P->w - d * P->lmin;
+    {
+        int b[3] = {0, 0, 0};
+        int lim1 = d > 1 ? J : 0, lim2 = d > 2 ? J : 0;
+        for (b[0] = 0; b[0] <= J; ++b[0])
+            for (b[1] = 0; b[1] <= lim1; ++b[1])
+                for (b[2] = 0; b[2] <= lim2; ++b[2]) {
+                    int s = b[0] + b[1] + b[2];
+                    if (s > J || s < J - d + 1) continue;
+                    for (int k = 0; k < d; ++k) P->comp_levels.push_back(b[k] + P->lmin);
+                    int j = J - s;
+                    P->comp_coef.push_back(((j & 1) ? -1.0 : 1.0) * binom(d - 1, j));
+                }
+    }
+    P->ncomp = static_cast<int>(P->comp_coef.size());
+    P->Lmax = P->lmin + J;
+    // ---- 1D tables per (patch, dir, level) ---------------------------------
+    const int ntab = geom->npatch * d * (P->Lmax + 1);
+    P->tabs.resize(ntab);
+    P->K1d.resize(ntab);
+    P->M1d.resize(ntab);
+    std::map<std::tuple<int, double, int>, std::array<int64_t, 7>> fd_off;
+    for (int pt = 0; pt < geom->npatch; ++pt)
+        for (int k = 0; k < d; ++k)
+            for (int lev = 0; lev <= P->Lmax; ++lev) {
+                Tab1D& T = P->tabs[tab_index(P, pt, k, lev)];
+                std::memset(&T, 0, sizeof(T));
+                const PatchHost& H = P->patches[pt];
+                std::vector<double> U = make_knots(p, r, lev, H.grading[k], H.gamma[k]);
+                T.nk = static_cast<int>(U.size());
+                T.nb = T.nk - p - 1;
+                T.ni = T.nb - 2;
+                T.E = 1 << lev;
+                T.Q = T.E * nq;
+                T.m = p - r;
+                T.pg = H.degree[k];
+                T.ngk = static_cast<int>(H.knots[k].size());
+                T.ngb = T.ngk - T.pg - 1;
+                T.uniform = H.grading[k] == IGA_GRADE_UNIFORM || H.gamma[k] == 1.0;
+                auto& dp = P->dpool;
+                T.oKn = static_cast<int64_t>(dp.size());
+                dp.insert(dp.end(), U.begin(), U.end());
+                T.oBrk = static_cast<int64_t>(dp.size());
+                for (int e = 0; e <= T.E; ++e) dp.push_back(U[p + e * T.m]);
+                T.oGkn = static_cast<int64_t>(dp.size());
+                dp.insert(dp.end(), H.knots[k].begin(), H.knots[k].end());
+                // Gauss tables are computed on the device at bind time
+                T.oB = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + static_cast<size_t>(T.Q) * (p + 1));
+                T.oD = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + static_cast<size_t>(T.Q) * (p + 1));
+                T.oBg = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + static_cast<size_t>(T.Q) * (T.pg + 1));
+                T.oDg = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + static_cast<size_t>(T.Q) * (T.pg + 1));
+                T.oXq = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + T.Q);
+                T.oWq = static_cast<int64_t>(dp.size());
+                dp.resize(dp.size() + T.Q);
+                T.oGs = static_cast<int64_t>(P->ipool.size());
+                P->ipool.resize(P->ipool.size() + T.Q);
+                // fast-diagonalisation factors (shared by equal knot families)
+                bool ok = true;
+                const FDEntry& F = fd_entry(p, r, lev, H.grading[k], H.gamma[k], nq, P->gauss_x.data(),
+                                            P->gauss_w.data(), &ok);
+                if (!ok) {
+                    set_error("eigen-decomposition failed (level %d)", lev);
+                    delete P;
+                    return IGA_ERR_GEOMETRY;
+                }
+                P->K1d[tab_index(P, pt, k, lev)] = F.K;
+                P->M1d[tab_index(P, pt, k, lev)] = F.M;
+                auto fkey = std::make_tuple(H.grading[k], H.gamma[k], lev);
+                auto fit = fd_off.find(fkey);
+                if (fit == fd_off.end()) {
+                    std::array<int64_t, 7> o;
+                    int n = F.n;
+                    o[0] = static_cast<int64_t>(dp.size());
+                    dp.insert(dp.end(), F.U.begin(), F.U.end());
+                    o[1] = static_cast<int64_t>(dp.size());
+                    for (int i = 0; i < n; ++i)
+                        for (int j = 0; j < n; ++j) dp.push_back(F.U[static_cast<size_t>(j) * n + i]);
+                    o[2] = static_cast<int64_t>(dp.size());
+                    dp.insert(dp.end(), F.lam.begin(), F.lam.end());
+                    o[3] = static_cast<int64_t>(P->fpool.size());
+                    for (double v : F.U) P->fpool.push_back(static_cast<float>(v));
+                    o[4] = static_cast<int64_t>(P->fpool.size());
+                    for (int i = 0; i < n; ++i)
+                        for (int j = 0; j < n; ++j)
+                            P->fpool.push_back(static_cast<float>(F.U[static_cast<size_t>(j) * n + i]));
+                    o[5] = static_cast<int64_t>(P->hpool.size());
+                    for (double v : F.U) P->hpool.push_back(to_bf16(static_cast<float>(v)));
+                    o[6] = static_cast<int64_t>(P->hpool.size());
+                    for (int i = 0; i < n; ++i)
+                        for (int j = 0; j < n; ++j)
+                            P->hpool.push_back(to_bf16(static_cast<float>(F.U[static_cast<size_t>(j) * n + i])));
+                    fit = fd_off.emplace(fkey, o).first;
+                }
+                T.oU = fit->second[0];
+                T.oUT = fit->second[1];
+                T.oLam = fit->second[2];
+                T.oU32 = fit->second[3];
+                T.oUT32 = fit->second[4];
+                T.oU16 = fit->second[5];
+                T.oUT16 = fit->second[6];
+            }
+    // homogeneous control points (w P, w) per patch
+    for (int pt = 0; pt < geom->npatch; ++pt) {
+        const PatchHost& H = P->patches[pt];
+        P->ctrl_off[pt] = static_cast<int64_t>(P->ctrl.size());
+        size_t ncp = H.ctrl.size() / d;
+        for (size_t i = 0; i < ncp; ++i) {
+            double wt = H.weights.empty() ? 1.0 : H.weights[i];
+            for (int c = 0; c < 3; ++c) P->ctrl.push_back(c < d ? wt * H.ctrl[i * d + c] : 0.0);
+            P->ctrl.push_back(wt);
+        }
+    }
+    P->ncompG = P->rational_any ? (d == 2 ? 6 : 10) : (d == 2 ? 3 : 6);
+    // ---- grids, tiles, preconditioner blocks --------------------------------
+    size_t lds_max = 0;
+    for (int c = 0; c < P->ncomp; ++c)
+        for (int pt = 0; pt < geom->npatch; ++pt) {
+            Grid g;
+            std::memset(&g, 0, sizeof(g));
+            g.comp = c;
+            g.patch = pt;
+            g.ccoef = P->comp_coef[c];
+            g.ndof = 1;
+            g.nqp = 1;
+            for (int k = 0; k < 3; ++k) {
+                if (k < d) {
+                    int lev = P->comp_levels[c * d + k];
+                    const Tab1D& T = P->tabs[tab_index(P, pt, k, lev)];
+                    g.lev[k] = lev;
+                    g.ni[k] = T.ni;
+                    g.nb[k] = T.nb;
+                    g.E[k] = T.E;
+                    g.Q[k] = T.Q;
+                    g.tab[k] = tab_index(P, pt, k, lev);
+                } else {
+                    g.ni[k] = g.nb[k] = g.E[k] = g.Q[k] = 1;
+                    g.tab[k] = -1;
+                }
+                g.ndof *= g.ni[k];
+                g.nqp *= g.Q[k];
+                g.fdc[k] = 1.0;
+            }
+            g.dof_off = P->ndof_total;
+            P->ndof_total += g.ndof;
+            g.qp_off = P->nqp_total;
+            P->nqp_total += g.nqp;
+            // operator tiles: minimise the elements processed (halo recompute)
+            const int m = p - r;
+            if (d == 2) {
+                const int TT = 256;
+                long best = -1;
+                for (int t2 = 1; t2 <= std::min(g.ni[1], TT); ++t2) {
+                    int t1 = std::min(g.ni[0], std::max(1, TT / t2));
+                    int n1 = (g.ni[0] + t1 - 1) / t1, n2 = (g.ni[1] + t2 - 1) / t2;
+                    int lo, hi, e1, e2;
+                    elem_range(0, t1, p, m, g.E[0], &lo, &hi);
+                    e1 = hi - lo + 1 + (t1 < g.ni[0] ? 1 : 0);
+                    elem_range(0, t2, p, m, g.E[1], &lo, &hi);
+                    e2 = hi - lo + 1 + (t2 < g.ni[1] ? 1 : 0);
+                    long work = static_cast<long>(n1) * n2 * e1 * e2 + 64L * n1 * n2;
+                    if (best < 0 || work < best) {
+                        best = work;
+                        g.tile[0] = t1;
+                        g.tile[1] = t2;
+                    }
+                }
+                g.tile[2] = 1;
+            } else {
+                g.tile[0] = g.ni[0];
+                g.tile[1] = g.ni[1];
+                g.tile[2] = g.ni[2];
+            }
+            g.ntile = 1;
+            for (int k = 0; k < 3; ++k) {
+                g.ntd[k] = (g.ni[k] + g.tile[k] - 1) / g.tile[k];
+                g.ntile *= g.ntd[k];
+            }
+            // LDS of one operator tile: halo unknowns + element outputs
+            if (d == 2) {
+                size_t halo = 1, nel = 1;
+                for (int k = 0; k < d; ++k) {
+                    int lo, hi, best = 0;
+                    for (int t = 0; t < g.ntd[k]; ++t) {
+                        int a = t * g.tile[k], b = std::min(g.ni[k], a + g.tile[k]);
+                        elem_range(a, b, p, m, g.E[k], &lo, &hi);
+                        best = std::max(best, hi - lo + 1);
+                    }
+                    nel *= best;
+                    halo *= static_cast<size_t>(best) * m + p + 1;
+                }
+                size_t pl = 1;
+                for (int k = 0; k < d; ++k) pl *= (p + 1);
+                size_t lds = (halo + nel * pl + kBlock) * sizeof(double);
+                lds_max = std::max(lds_max, lds);
+            }
+            // fast-diagonalisation blocks (2D: split the longest direction)
+            if (d == 2) {
+                g.big = g.ni[1] > g.ni[0] ? 1 : 0;
+                int nbig = g.ni[g.big], nsm = g.ni[1 - g.big];
+                int bs = nbig;
+                if (nbig > 64) bs = std::max(8, std::min(64, (2048 + nsm - 1) / nsm));
+                g.blk = bs;
+                g.nblk = (nbig + bs - 1) / bs;
+                size_t lds = (2 * static_cast<size_t>(g.ndof) + static_cast<size_t>(nsm) * bs + kBlock) *
+                             sizeof(double);
+                lds_max = std::max(lds_max, lds);
+            } else {
+                g.big = 0;
+                g.blk = g.ni[0];
+                g.nblk = 1;
+                size_t lds = (3 * static_cast<size_t>(g.ndof) + kBlock) * sizeof(double);
+                lds_max = std::max(lds_max, lds);
+            }
+            P->grids.push_back(g);
+        }
+    if (lds_max > 64 * 1024) {
+        set_error("a component grid needs %zu bytes of LDS (limit 64 KiB)", lds_max);
+        delete P;
+        return IGA_ERR_INVALID_ARG;
+    }
+    P->lds_bytes = lds_max;
+    // task lists in decreasing grid size (longest-processing-time order)
+    std::vector<int> ord(P->grids.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = static_cast<int>(i);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return P->grids[a].ndof > P->grids[b].ndof; });
+    for (int gi : ord) {
+        Grid& g = P->grids[gi];
+        g.tile_off = static_cast<int>(P->optask.size());
+        for (int t = 0; t < g.ntile; ++t) P->optask.push_back({gi, t});
+        g.blk_off = static_cast<int>(P->fdtask.size());
+        for (int t = 0; t < g.nblk; ++t) P->fdtask.push_back({gi, t});
+    }
+    // ---- workspace layout ----------------------------------------------------
+    Layout& L = P->lay;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t ng = P->grids.size(), nd = static_cast<size_t>(P->ndof_total),
+                 nqp = static_cast<size_t>(P->nqp_total);
+    L.tabs = take(sizeof(Tab1D) * P->tabs.size());
+    L.grids = take(sizeof(Grid) * ng);
+    L.dpool = take(sizeof(double) * P->dpool.size());
+    L.ipool = take(sizeof(int) * P->ipool.size());
+    L.fpool = take(sizeof(float) * P->fpool.size());
+    L.hpool = take(sizeof(uint16_t) * P->hpool.size());
+    L.ctrl = take(sizeof(double) * P->ctrl.size());
+    L.G64 = take(sizeof(double) * nqp * P->ncompG);
+    L.G32 = take(sizeof(float) * nqp * P->ncompG);
+    L.Fq = take(sizeof(double) * nqp);
+    L.b = take(sizeof(double) * nd);
+    L.x = take(sizeof(double) * nd);
+    L.d = take(sizeof(double) * nd);
+    L.r2 = take(sizeof(double) * nd * 2);
+    L.z = take(sizeof(double) * nd);
+    L.p2 = take(sizeof(double) * nd * 2);
+    L.q = take(sizeof(double) * nd);
+    L.rt = take(sizeof(double) * nd);
+    L.st2 = take(sizeof(GState) * ng * 2);
+    size_t pst = std::max(P->optask.size(), P->fdtask.size());
+    L.part = take(sizeof(double) * pst * 8);
+    L.optask = take(sizeof(Task) * P->optask.size());
+    L.fdtask = take(sizeof(Task) * P->fdtask.size());
+    L.bar = take(256);
+    L.total = off;
+    *out = P;
+    return IGA_OK;
+}
+
+iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes) {
+    if (!plan || !bytes) {
+        set_error("null argument");
+        return IGA_ERR_INVALID_ARG;
+    }
+    *bytes = plan->lay.total;
+    return IGA_OK;
+}
+
+iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t* ndof_host,
+                             double* coef_host) {
+    if (!plan) {
+        set_error("null plan");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (n) *n = plan->ncomp;
+    for (int c = 0; c < plan->ncomp; ++c) {
+        if (levels_host)
+            for (int k = 0; k < plan->dim; ++k) levels_host[c * plan->dim + k] = plan->comp_levels[c * plan->dim + k];
+        if (coef_host) coef_host[c] = plan->comp_coef[c];
+        if (ndof_host) {
+            int64_t s = 0;
+            for (const Grid& g : plan->grids)
+                if (g.comp == c) s += g.ndof;
+            ndof_host[c] = s;
+        }
+    }
+    return IGA_OK;
+}
+
+iga_status iga_sg_fd_factor(iga_sg_plan plan, int dir, int lev, int* n, double* U_host, double* lam_host) {
+    if (!plan || dir < 0 || dir >= plan->dim || lev < 0 || lev > plan->Lmax) {
+        set_error("bad plan/direction/level");
+        return IGA_ERR_INVALID_ARG;
+    }
+    const Tab1D& T = plan->tabs[tab_index(plan, 0, dir, lev)];
+    if (n) *n = T.ni;
+    size_t nn = static_cast<size_t>(T.ni) * T.ni;
+    if (U_host) std::memcpy(U_host, &plan->dpool[T.oU], nn * sizeof(double));
+    if (lam_host) std::memcpy(lam_host, &plan->dpool[T.oLam], T.ni * sizeof(double));
+    return IGA_OK;
+}
+
+iga_status iga_sg_matrices_1d(iga_sg_plan plan, int dir, int lev, int* n, double* K_host, double* M_host) {
+    if (!plan || dir < 0 || dir >= plan->dim || lev < 0 || lev > plan->Lmax) {
+        set_error("bad plan/direction/level");
+        return IGA_ERR_INVALID_ARG;
+    }
+    int ti = tab_index(plan, 0, dir, lev);
+    const Tab1D& T = plan->tabs[ti];
+    if (n) *n = T.ni;
+    size_t nn = static_cast<size_t>(T.ni) * T.ni;
+    if (K_host) std::memcpy(K_host, plan->K1d[ti].data(), nn * sizeof(double));
+    if (M_host) std::memcpy(M_host, plan->M1d[ti].data(), nn * sizeof(double));
+    return IGA_OK;
+}
+
+}  // extern "C"

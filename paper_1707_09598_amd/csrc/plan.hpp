@@ -1,0 +1,76 @@
+// plan.hpp -- host-side plan of the sparse-grid solver.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/iga_sg.h"
+#include "common.hpp"
+
+struct iga_sg_plan_s;
+
+namespace igasg {
+
+void set_error(const char* fmt, ...);
+
+struct PatchHost {
+    int degree[3];
+    std::vector<double> knots[3];
+    std::vector<double> ctrl;      // [..][dim]
+    std::vector<double> weights;   // empty => polynomial
+    int grading[3];
+    double gamma[3];
+};
+
+// Host Cox-de Boor: values and first derivatives of the p+1 functions that
+// are non-zero on knot interval s (knots[s] <= x < knots[s+1]).
+void basis_funs(int p, const double* U, int s, double x, double* N, double* dN);
+int find_interval(int p, int nk, const double* U, double x);
+double grade_map(int kind, double gamma, double t);
+void gauss_rule(int n, double* x, double* w);
+
+}  // namespace igasg
+
+struct iga_sg_plan_s {
+    int dim = 0, p = 0, r = 0, w = 0, lmin = 0, nq = 0;
+    std::vector<igasg::PatchHost> patches;
+    std::vector<iga_interface> ifaces;
+    // components of the combination technique
+    int ncomp = 0;
+    std::vector<int> comp_levels;  // [ncomp][dim]
+    std::vector<double> comp_coef;
+    // tables and pools
+    int Lmax = 0;
+    std::vector<igasg::Tab1D> tabs;
+    std::vector<double> dpool;
+    std::vector<int> ipool;
+    std::vector<float> fpool;
+    std::vector<uint16_t> hpool;
+    std::vector<double> gauss_x, gauss_w;
+    // per (patch, dir, level) 1D interior matrices (dense, host only)
+    std::vector<std::vector<double>> K1d, M1d;
+    std::vector<igasg::Grid> grids;
+    std::vector<igasg::Task> optask, fdtask;
+    std::vector<double> ctrl;  // homogeneous control points, concatenated per patch
+    int64_t ctrl_off[igasg::kMaxPatch] = {0, 0, 0, 0};
+    int ncompG = 0;
+    int rational_any = 0;
+    int64_t nqp_total = 0, ndof_total = 0;
+    size_t lds_bytes = 0;
+    igasg::Layout lay{};
+    // binding
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* stream = nullptr;
+    bool bound = false, assembled = false, solved = false;
+    int num_cu = 0;
+    int max_wg = 0;
+    void* ev[8] = {nullptr};  // timing events
+};
+
+namespace igasg {
+int tab_index(const iga_sg_plan_s* P, int patch, int dir, int lev);
+Params make_params(iga_sg_plan_s* P);
+}  // namespace igasg
