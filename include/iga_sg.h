@@ -130,7 +130,8 @@ typedef struct {
     int maxit;         /* CG iterations per (inner) solve */
     int max_refine;    /* refinement steps (mixed modes); ignored for FP64 */
     int workgroups;    /* persistent launch width; 0 => library choice */
-    int timing;        /* 1: fill report.kernel_ms with HIP-event times (synchronises) */
+    int timing;        /* 1: fill report.kernel_ms with HIP-event times (synchronises);
+                          2: also trace the phases of the persistent solve (report.phase_us) */
 } iga_sg_solve_opts;
 
 /* Per-component results; arrays are caller-owned host buffers of length
@@ -148,8 +149,11 @@ typedef struct {
     double* prelres;
     int* status;
     int total_iters;       /* sum of CG iterations over components */
-    int sweeps;            /* iterations of the persistent loop */
-    double kernel_ms[4];   /* assemble, solve kernel, combine, spare */
+    int sweeps;            /* iterations of the persistent loop (timing = 2) */
+    double kernel_ms[4];   /* [1]: solve launch(es) in ms (timing >= 1) */
+    double phase_us[6];    /* timing = 2: mean wall time of the operator, update/forward and
+                              backward phases per sweep (barrier included), then the mean
+                              longest busy time of any workgroup in each phase */
 } iga_sg_report;
 
 /* Build a plan: index set and combination coefficients (eq. TD-combi-tec),

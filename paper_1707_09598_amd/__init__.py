@@ -73,8 +73,9 @@ class _Opts(C.Structure):
 class _Report(C.Structure):
     _fields_ = [("ncomp", C.c_int), ("iters", C.POINTER(C.c_int)),
                 ("refinements", C.POINTER(C.c_int)), ("relres", C.POINTER(C.c_double)),
-                ("prelres", C.POINTER(C.c_double)), ("status", C.POINTER(C.c_int)), ("total_iters", C.c_int), ("sweeps", C.c_int),
-                ("kernel_ms", C.c_double * 4)]
+                ("prelres", C.POINTER(C.c_double)), ("status", C.POINTER(C.c_int)),
+                ("total_iters", C.c_int), ("sweeps", C.c_int), ("kernel_ms", C.c_double * 4),
+                ("phase_us", C.c_double * 6)]
 
 
 _lib = None
@@ -83,9 +84,19 @@ _ip = C.POINTER(C.c_int)
 
 
 def lib():
-    """Load libigasg.so (raises if it has not been built)."""
+    """Load libigasg.so (raises if it has not been built).
+
+    torch is imported first: it ships its own HIP runtime under the same
+    soname (libamdhip64.so.7), so loading torch first makes the dynamic
+    loader bind this library to torch's runtime; loading this library
+    first would leave two HIP runtimes in the process.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401  (see docstring)
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_1707_09598_amd/build.py "
                               "(or __graft_entry__.build()) first")
@@ -270,7 +281,8 @@ class Plan:
                     stt.ctypes.data_as(_ip), 0, 0)
         code = lib().iga_sg_solve(self.h, C.byref(o), C.byref(R))
         rep = {"code": code, "iters": it, "refinements": rf, "relres": rr, "prelres": pr,
-               "status": stt, "total_iters": R.total_iters, "kernel_ms": list(R.kernel_ms)}
+               "status": stt, "total_iters": R.total_iters, "kernel_ms": list(R.kernel_ms),
+               "sweeps": R.sweeps, "phase_us": list(R.phase_us)}
         if check:
             _check(code)
         return rep

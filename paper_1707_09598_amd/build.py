@@ -9,6 +9,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -17,12 +18,13 @@ BUILD = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIP_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
-CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v2", "-Wall", "-pthread"]
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v2", "-Wall", "-pthread", f"-I{INCLUDE}"]
 
 
 def _run(cmd):
@@ -35,17 +37,19 @@ def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(OUT):
         return OUT
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
         if src.endswith(".cpp"):
-            _run(["g++", *CXX_FLAGS, "-c", path, "-o", obj])
+            jobs.append((["g++", *CXX_FLAGS, "-c", path, "-o", obj], obj))
         elif src.endswith(".hip"):
-            _run([HIPCC, *HIP_FLAGS, "-c", path, "-o", obj])
-        else:
-            continue
-        objs.append(obj)
+            jobs.append(([HIPCC, *HIP_FLAGS, "-c", path, "-o", obj], obj))
+    # translation units are independent: compile them concurrently
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "8")), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = OUT + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, OUT)

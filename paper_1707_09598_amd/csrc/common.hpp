@@ -15,6 +15,7 @@ constexpr int kMaxP = 4;          // solution degree limit (register arrays)
 constexpr int kMaxPg = 4;         // geometry degree limit
 constexpr int kMaxPatch = 4;
 constexpr int kBlock = 256;       // threads per workgroup in every kernel
+constexpr int kBigRed = 1024;     // doubles of LDS for cross-wavefront partial sums of FD tasks
 
 // Grid stages of the persistent refinement/CG state machine.
 enum Stage : int { STAGE_RESID = 0, STAGE_ITER = 1, STAGE_DONE = 2, STAGE_XUPD = 3 };
@@ -33,7 +34,8 @@ struct Tab1D {
     int nk;       // solution knots
     int ngk;      // geometry knots
     int uniform;  // breakpoints are i / E
-    int pad0, pad1;
+    int ldu;      // row stride of the U tables (multiple of 8 elements)
+    int pad1;
     // double-pool offsets (in elements)
     int64_t oB, oD;       // [Q][p+1] basis values / derivatives at the Gauss points
     int64_t oBg, oDg;     // [Q][pg+1] geometry basis values / derivatives
@@ -71,11 +73,13 @@ struct Grid {
     int nblk;
     int blk;          // block length
     int blk_off;      // first FD task
+    int fdstage;      // single-block grids: the long direction's factor is staged in LDS
     // operator tiles
     int tile[3];      // tile size in unknowns per direction
     int ntd[3];       // tiles per direction
     int ntile;
     int tile_off;     // first operator task
+    int pad_;
 };
 
 // Per-grid solver state (double-buffered by sweep parity on the device).
@@ -108,6 +112,7 @@ struct Layout {
     size_t part;                  // partial sums
     size_t optask, fdtask;
     size_t bar;                   // barrier + counters
+    size_t trace;                 // phase timestamps
     size_t total;
 };
 

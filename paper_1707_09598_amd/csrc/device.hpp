@@ -94,4 +94,13 @@ __device__ __forceinline__ double sum_partials(const double* part, int count, do
     return s;
 }
 
+// Element range touching interior unknowns [a, b) of one direction.
+__device__ __forceinline__ void d_elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
+    int lo_basis = a + 1, hi_basis = b;
+    int lo = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
+    int hi = hi_basis / m;
+    *elo = lo < 0 ? 0 : lo;
+    *ehi = hi > E - 1 ? E - 1 : hi;
+}
+
 }  // namespace igasg

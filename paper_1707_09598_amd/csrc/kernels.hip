@@ -20,6 +20,7 @@
 
 #include "device.hpp"
 #include "plan.hpp"
+#include "solve.hpp"
 
 using namespace igasg;
 
@@ -33,6 +34,8 @@ using namespace igasg;
     } while (0)
 
 namespace igasg {
+
+constexpr int kTraceSweeps = 4096;
 
 // ===========================================================================
 // fields
@@ -312,14 +315,6 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
     }
 }
 
-// Element range touching interior unknowns [a, b) of one direction.
-__device__ __forceinline__ void d_elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
-    int lo_basis = a + 1, hi_basis = b;
-    int lo = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
-    int hi = hi_basis / m;
-    *elo = lo < 0 ? 0 : lo;
-    *ehi = hi > E - 1 ? E - 1 : hi;
-}
 
 // Load vector: b_i = sum over Gauss points of the supporting elements of
 // B_i(q) Fq(q) (Fq = f w |det DF| / W), one thread per unknown.
@@ -378,648 +373,6 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     }
 }
 
-// ===========================================================================
-// operator application (2D): one workgroup per tile of unknowns; the
-// elements touching the tile are recomputed (halo), element outputs are staged
-// in LDS and summed per owned unknown in a fixed order (no atomics).
-// ===========================================================================
-struct OpIO {
-    const double* in_a;   // input (or z)
-    const double* in_b;   // added as beta * in_b (or nullptr)
-    double beta;
-    double* out_in;       // owned part of in_a + beta in_b is written here (or nullptr)
-    double* out;          // A x (or b - A x when rhs != nullptr)
-    const double* rhs;
-    double* part;         // per-tile partial: in.(A in) or ||b - A x||^2 (or nullptr)
-    int lowp;             // 1: FP32 coefficients and arithmetic
-};
-
-template <int PP, bool RAT, typename T>
-__device__ __forceinline__ void elem_apply_2d(const double* X, int nh1, int x1, int x2, const double* B1,
-                                              const double* D1, const double* B2, const double* D2,
-                                              const T* G, int64_t nqp, int64_t qrow0, int Q1, double* Y) {
-    constexpr int NQ = PP + 1;
-    T c[PP + 1][PP + 1], y[PP + 1][PP + 1];
-#pragma unroll
-    for (int a2 = 0; a2 <= PP; ++a2)
-#pragma unroll
-        for (int a1 = 0; a1 <= PP; ++a1) {
-            c[a1][a2] = static_cast<T>(X[(x2 + a2) * nh1 + x1 + a1]);
-            y[a1][a2] = T(0);
-        }
-#pragma unroll
-    for (int j2 = 0; j2 < NQ; ++j2) {
-        T b2[PP + 1], d2[PP + 1];
-#pragma unroll
-        for (int a = 0; a <= PP; ++a) {
-            b2[a] = static_cast<T>(B2[j2 * (PP + 1) + a]);
-            d2[a] = static_cast<T>(D2[j2 * (PP + 1) + a]);
-        }
-        T tb[PP + 1], td[PP + 1], sb[PP + 1], sd[PP + 1];
-#pragma unroll
-        for (int a1 = 0; a1 <= PP; ++a1) {
-            T u = T(0), v = T(0);
-#pragma unroll
-            for (int a2 = 0; a2 <= PP; ++a2) {
-                u += b2[a2] * c[a1][a2];
-                v += d2[a2] * c[a1][a2];
-            }
-            tb[a1] = u;
-            td[a1] = v;
-            sb[a1] = T(0);
-            sd[a1] = T(0);
-        }
-        const T* Gr = G + qrow0 + static_cast<int64_t>(j2) * Q1;
-#pragma unroll
-        for (int j1 = 0; j1 < NQ; ++j1) {
-            T b1[PP + 1], d1[PP + 1];
-#pragma unroll
-            for (int a = 0; a <= PP; ++a) {
-                b1[a] = static_cast<T>(B1[j1 * (PP + 1) + a]);
-                d1[a] = static_cast<T>(D1[j1 * (PP + 1) + a]);
-            }
-            T v0 = T(0), v1 = T(0), v2 = T(0);
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) {
-                if (RAT) v0 += b1[a1] * tb[a1];
-                v1 += d1[a1] * tb[a1];
-                v2 += b1[a1] * td[a1];
-            }
-            T F0 = T(0), F1, F2;
-            if (RAT) {
-                T g00 = Gr[j1], g01 = Gr[nqp + j1], g02 = Gr[2 * nqp + j1];
-                T g11 = Gr[3 * nqp + j1], g12 = Gr[4 * nqp + j1], g22 = Gr[5 * nqp + j1];
-                F0 = g00 * v0 + g01 * v1 + g02 * v2;
-                F1 = g01 * v0 + g11 * v1 + g12 * v2;
-                F2 = g02 * v0 + g12 * v1 + g22 * v2;
-            } else {
-                T g11 = Gr[j1], g12 = Gr[nqp + j1], g22 = Gr[2 * nqp + j1];
-                F1 = g11 * v1 + g12 * v2;
-                F2 = g12 * v1 + g22 * v2;
-            }
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) {
-                sb[a1] += (RAT ? b1[a1] * F0 : T(0)) + d1[a1] * F1;
-                sd[a1] += b1[a1] * F2;
-            }
-        }
-#pragma unroll
-        for (int a2 = 0; a2 <= PP; ++a2)
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) y[a1][a2] += b2[a2] * sb[a1] + d2[a2] * sd[a1];
-    }
-#pragma unroll
-    for (int a2 = 0; a2 <= PP; ++a2)
-#pragma unroll
-        for (int a1 = 0; a1 <= PP; ++a1) Y[a1 + (PP + 1) * a2] = static_cast<double>(y[a1][a2]);
-}
-
-template <int PP>
-__device__ void op_tile_2d(const Params& P, const Grid& g, int tile, const OpIO& io, double* lds) {
-    const int p = PP;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
-    const int m1 = T1.m, m2 = T2.m;
-    const int t1 = tile % g.ntd[0], t2 = tile / g.ntd[0];
-    const int a1 = t1 * g.tile[0], b1 = min(g.ni[0], a1 + g.tile[0]);
-    const int a2 = t2 * g.tile[1], b2 = min(g.ni[1], a2 + g.tile[1]);
-    int el1, eh1, el2, eh2;
-    d_elem_range(a1, b1, p, m1, g.E[0], &el1, &eh1);
-    d_elem_range(a2, b2, p, m2, g.E[1], &el2, &eh2);
-    const int ne1 = eh1 - el1 + 1, ne2 = eh2 - el2 + 1;
-    const int hl1 = el1 * m1 - 1, hl2 = el2 * m2 - 1;           // interior index of halo start
-    const int nh1 = eh1 * m1 + p - 1 - hl1 + 1, nh2 = eh2 * m2 + p - 1 - hl2 + 1;
-    double* X = lds;
-    double* Y = lds + nh1 * nh2;
-    double* red = Y + ne1 * ne2 * (p + 1) * (p + 1);
-    const int64_t off = g.dof_off;
-    const int n1 = g.ni[0], n2 = g.ni[1];
-    for (int idx = threadIdx.x; idx < nh1 * nh2; idx += kBlock) {
-        int i1 = hl1 + idx % nh1, i2 = hl2 + idx / nh1;
-        double v = 0.0;
-        if (i1 >= 0 && i1 < n1 && i2 >= 0 && i2 < n2) {
-            int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-            v = io.in_a[gi];
-            if (io.in_b) v += io.beta * io.in_b[gi];
-            if (io.out_in && i1 >= a1 && i1 < b1 && i2 >= a2 && i2 < b2) io.out_in[gi] = v;
-        }
-        X[idx] = v;
-    }
-    __syncthreads();
-    const int nqp1 = P.nq * (p + 1);
-    const int64_t nqp = g.nqp;
-    for (int el = threadIdx.x; el < ne1 * ne2; el += kBlock) {
-        int e1 = el1 + el % ne1, e2 = el2 + el / ne1;
-        const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
-        const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
-        const double* B2 = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1;
-        const double* D2 = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1;
-        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2;
-        const int64_t qrow0 = static_cast<int64_t>(e2) * P.nq * g.Q[0] + static_cast<int64_t>(e1) * P.nq;
-        double* Ye = Y + el * (p + 1) * (p + 1);
-        const bool rat = P.rational[g.patch] != 0;
-        if (io.lowp) {
-            const float* G = P.G32 + g.qp_off * P.ncompG;
-            if (rat) elem_apply_2d<PP, true, float>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-            else elem_apply_2d<PP, false, float>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-        } else {
-            const double* G = P.G64 + g.qp_off * P.ncompG;
-            if (rat) elem_apply_2d<PP, true, double>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-            else elem_apply_2d<PP, false, double>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-        }
-    }
-    __syncthreads();
-    const int w1 = b1 - a1, nown = w1 * (b2 - a2);
-    double dot = 0.0;
-    for (int o = threadIdx.x; o < nown; o += kBlock) {
-        const int i1 = a1 + o % w1, i2 = a2 + o / w1;
-        const int I1 = i1 + 1, I2 = i2 + 1;
-        int lo1, hi1, lo2, hi2;
-        d_elem_range(i1, i1 + 1, p, m1, g.E[0], &lo1, &hi1);
-        d_elem_range(i2, i2 + 1, p, m2, g.E[1], &lo2, &hi2);
-        double s = 0.0;
-        for (int e2 = lo2; e2 <= hi2; ++e2)
-            for (int e1 = lo1; e1 <= hi1; ++e1) {
-                int el = (e2 - el2) * ne1 + (e1 - el1);
-                s += Y[el * (p + 1) * (p + 1) + (I1 - e1 * m1) + (p + 1) * (I2 - e2 * m2)];
-            }
-        const int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-        if (io.rhs) {
-            s = io.rhs[gi] - s;
-            dot += s * s;
-        } else {
-            dot += X[(i2 - hl2) * nh1 + (i1 - hl1)] * s;
-        }
-        io.out[gi] = s;
-    }
-    if (io.part) {
-        double t = wg_sum(dot, red);
-        if (threadIdx.x == 0) *io.part = t;
-    }
-    __syncthreads();
-}
-
-// ===========================================================================
-// fast diagonalisation: z = (U1 (x) U2) diag(1/(c1 l1 + c2 l2)) (U1 (x) U2)^T r
-// as mode products (workgroup GEMMs with split K)
-// ===========================================================================
-// C(b, m, n) = sum_k A(b, m, k) B(b, k, n); operands in LDS or global memory.
-template <typename TA, typename TB, typename TC>
-__device__ void wg_gemm(int nbat, int M, int N, int K, const TA* A, int64_t sAb, int64_t sAm, int64_t sAk,
-                        const TB* B, int64_t sBb, int64_t sBk, int64_t sBn, double* C, int64_t sCb,
-                        int64_t sCm, int64_t sCn, double* red) {
-    const int O = nbat * M * N;
-    auto ld = [](auto* p, int64_t i) -> TC {
-        using V = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
-        if constexpr (std::is_same<V, uint16_t>::value) return static_cast<TC>(bf16_to_f32(p[i]));
-        else return static_cast<TC>(p[i]);
-    };
-    if (O * 2 >= kBlock || K <= 8) {
-        for (int o = threadIdx.x; o < O; o += kBlock) {
-            const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-            const TA* a = A + b * sAb + m * sAm;
-            const TB* bb = B + b * sBb + n * sBn;
-            TC s = TC(0);
-            for (int k = 0; k < K; ++k) s += ld(a, k * sAk) * ld(bb, k * sBk);
-            C[b * sCb + m * sCm + n * sCn] = static_cast<double>(s);
-        }
-        __syncthreads();
-        return;
-    }
-    int S = kBlock / O;
-    if (S > (K + 3) / 4) S = (K + 3) / 4;
-    const int kc = (K + S - 1) / S;
-    const int o = threadIdx.x % O, sl = threadIdx.x / O;
-    if (sl < S) {
-        const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-        const TA* a = A + b * sAb + m * sAm;
-        const TB* bb = B + b * sBb + n * sBn;
-        TC s = TC(0);
-        const int k1 = min(K, (sl + 1) * kc);
-        for (int k = sl * kc; k < k1; ++k) s += ld(a, k * sAk) * ld(bb, k * sBk);
-        red[sl * O + o] = static_cast<double>(s);
-    }
-    __syncthreads();
-    if (threadIdx.x < O) {
-        const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-        double s = 0.0;
-        for (int t = 0; t < S; ++t) s += red[t * O + o];
-        C[b * sCb + m * sCm + n * sCn] = s;
-    }
-    __syncthreads();
-}
-
-// U tables for one precision: element-type pointers to U and U^T of a Tab1D.
-template <typename TU>
-__device__ __forceinline__ const TU* u_ptr(const Params& P, const Tab1D& T, bool trans);
-template <>
-__device__ __forceinline__ const double* u_ptr<double>(const Params& P, const Tab1D& T, bool trans) {
-    return P.dpool + (trans ? T.oUT : T.oU);
-}
-template <>
-__device__ __forceinline__ const float* u_ptr<float>(const Params& P, const Tab1D& T, bool trans) {
-    return P.fpool + (trans ? T.oUT32 : T.oU32);
-}
-template <>
-__device__ __forceinline__ const uint16_t* u_ptr<uint16_t>(const Params& P, const Tab1D& T, bool trans) {
-    return P.hpool + (trans ? T.oUT16 : T.oU16);
-}
-
-struct FdIO {
-    const double* r_old;  // full grid input
-    const double* q;      // r = r_old - alpha q when q != nullptr
-    double alpha;
-    double* r_out;        // owned part of r written here (or nullptr)
-    double* dvec;         // dvec += alpha * pvec on owned part (or nullptr)
-    const double* pvec;
-    double* part;         // ||r_owned||^2 (forward) or r_owned . z_owned (backward)
-    double* rt;           // transformed vector (grid-sized)
-    double* z;            // backward output
-    const double* rdot;   // backward: dot partner (or nullptr)
-    int prec;             // 0 FP64, 1 FP32, 2 BF16 factors
-};
-
-// Owned index set of a block: unknowns whose index along g.big lies in the block.
-__device__ __forceinline__ bool owned_2d(const Grid& g, int blk, int i1, int i2) {
-    const int ib = g.big == 0 ? i1 : i2;
-    return ib >= blk * g.blk && ib < min(g.ni[g.big], (blk + 1) * g.blk);
-}
-
-template <typename TU, typename TC>
-__device__ void fd_fwd_2d(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    const int n1 = g.ni[0], n2 = g.ni[1], n = n1 * n2;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
-    double* R = lds;
-    double* S = lds + n;
-    double* red = S + n;      // kBlock doubles of split-K / reduction scratch
-    const int64_t off = g.dof_off;
-    double nrm = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-        double v = io.r_old[off + i];
-        if (io.q) v -= io.alpha * io.q[off + i];
-        R[i] = v;
-        const int i1 = i % n1, i2 = i / n1;
-        if (owned_2d(g, blk, i1, i2)) {
-            if (io.r_out) io.r_out[off + i] = v;
-            if (io.dvec) io.dvec[off + i] += io.alpha * io.pvec[off + i];
-            nrm += v * v;
-        }
-    }
-    if (io.part) {
-        double t = wg_sum(nrm, red);
-        if (threadIdx.x == 0) *io.part = t;
-    }
-    __syncthreads();
-    const int k0 = blk * g.blk;
-    const int bs = min(g.blk, g.ni[g.big] - k0);
-    double* Out = red + kBlock;  // block of the transformed vector
-    const double* lam1 = P.dpool + T1.oLam;
-    const double* lam2 = P.dpool + T2.oLam;
-    if (g.big == 0) {
-        // S[k2][i1] = sum_i2 UT2[k2][i2] R[i2][i1]
-        wg_gemm<TU, double, TC>(1, n2, n1, n2, u_ptr<TU>(P, T2, true), 0, n2, 1, R, 0, n1, 1, S, 0, n1, 1, red);
-        // Rt[k2][k1] = sum_i1 S[k2][i1] U1[i1][k1], k1 in block
-        wg_gemm<double, TU, TC>(1, n2, bs, n1, S, 0, n1, 1, u_ptr<TU>(P, T1, false) + k0, 0, n1, 1, Out, 0, bs,
-                                1, red);
-        for (int o = threadIdx.x; o < n2 * bs; o += kBlock) {
-            const int k2 = o / bs, kk = o % bs, k1 = k0 + kk;
-            io.rt[off + static_cast<int64_t>(k2) * n1 + k1] = Out[o] / (g.fdc[0] * lam1[k1] + g.fdc[1] * lam2[k2]);
-        }
-    } else {
-        // S[i2][k1] = sum_i1 R[i2][i1] U1[i1][k1]
-        wg_gemm<double, TU, TC>(1, n2, n1, n1, R, 0, n1, 1, u_ptr<TU>(P, T1, false), 0, n1, 1, S, 0, n1, 1, red);
-        // Rt[k2][k1] = sum_i2 UT2[k2][i2] S[i2][k1], k2 in block
-        wg_gemm<TU, double, TC>(1, bs, n1, n2, u_ptr<TU>(P, T2, true) + static_cast<int64_t>(k0) * n2, 0, n2, 1, S,
-                                0, n1, 1, Out, 0, n1, 1, red);
-        for (int o = threadIdx.x; o < bs * n1; o += kBlock) {
-            const int kk = o / n1, k1 = o % n1, k2 = k0 + kk;
-            io.rt[off + static_cast<int64_t>(k2) * n1 + k1] = Out[o] / (g.fdc[0] * lam1[k1] + g.fdc[1] * lam2[k2]);
-        }
-    }
-    __syncthreads();
-}
-
-template <typename TU, typename TC>
-__device__ void fd_bwd_2d(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    const int n1 = g.ni[0], n2 = g.ni[1], n = n1 * n2;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
-    double* Rt = lds;
-    double* Tm = lds + n;
-    double* red = Tm + n;     // kBlock doubles of split-K / reduction scratch
-    const int64_t off = g.dof_off;
-    for (int i = threadIdx.x; i < n; i += kBlock) Rt[i] = io.rt[off + i];
-    __syncthreads();
-    const int k0 = blk * g.blk;
-    const int bs = min(g.blk, g.ni[g.big] - k0);
-    double* Out = red + kBlock;
-    double dot = 0.0;
-    if (g.big == 0) {
-        // T[i2][k1] = sum_k2 U2[i2][k2] Rt[k2][k1]
-        wg_gemm<TU, double, TC>(1, n2, n1, n2, u_ptr<TU>(P, T2, false), 0, n2, 1, Rt, 0, n1, 1, Tm, 0, n1, 1, red);
-        // Z[i2][i1] = sum_k1 T[i2][k1] UT1[k1][i1], i1 in block
-        wg_gemm<double, TU, TC>(1, n2, bs, n1, Tm, 0, n1, 1, u_ptr<TU>(P, T1, true) + k0, 0, n1, 1, Out, 0, bs, 1,
-                                red);
-        for (int o = threadIdx.x; o < n2 * bs; o += kBlock) {
-            const int i2 = o / bs, i1 = k0 + o % bs;
-            const int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-            io.z[gi] = Out[o];
-            if (io.rdot) dot += io.rdot[gi] * Out[o];
-        }
-    } else {
-        // T[k2][i1] = sum_k1 Rt[k2][k1] UT1[k1][i1]
-        wg_gemm<double, TU, TC>(1, n2, n1, n1, Rt, 0, n1, 1, u_ptr<TU>(P, T1, true), 0, n1, 1, Tm, 0, n1, 1, red);
-        // Z[i2][i1] = sum_k2 U2[i2][k2] T[k2][i1], i2 in block
-        wg_gemm<TU, double, TC>(1, bs, n1, n2, u_ptr<TU>(P, T2, false) + static_cast<int64_t>(k0) * n2, 0, n2, 1,
-                                Tm, 0, n1, 1, Out, 0, n1, 1, red);
-        for (int o = threadIdx.x; o < bs * n1; o += kBlock) {
-            const int i2 = k0 + o / n1, i1 = o % n1;
-            const int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-            io.z[gi] = Out[o];
-            if (io.rdot) dot += io.rdot[gi] * Out[o];
-        }
-    }
-    if (io.part) {
-        double t = wg_sum(dot, red);
-        if (threadIdx.x == 0) *io.part = t;
-    }
-    __syncthreads();
-}
-
-__device__ void fd_fwd(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    if (io.prec == 0) fd_fwd_2d<double, double>(P, g, blk, io, lds);
-    else if (io.prec == 1) fd_fwd_2d<float, float>(P, g, blk, io, lds);
-    else fd_fwd_2d<uint16_t, float>(P, g, blk, io, lds);
-}
-
-__device__ void fd_bwd(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    if (io.prec == 0) fd_bwd_2d<double, double>(P, g, blk, io, lds);
-    else if (io.prec == 1) fd_bwd_2d<float, float>(P, g, blk, io, lds);
-    else fd_bwd_2d<uint16_t, float>(P, g, blk, io, lds);
-}
-
-// ===========================================================================
-// grid-wide barrier (all workgroups co-resident: cooperative launch)
-// ===========================================================================
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nwg) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
-                __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-}
-
-// ===========================================================================
-// persistent refinement + PCG over all component grids
-//
-// One sweep = three phases separated by grid-wide barriers:
-//   1 operator   ITER: p = z + beta p, q = A p (inner precision), p.q
-//                RESID: r = b - A x (FP64), ||r||^2
-//   2 update     ITER: alpha, d += alpha p, r -= alpha q, FD forward of r
-//                XUPD: x += d, d = 0;  RESID: FD forward of r
-//   3 commit     FD backward -> z, r.z; next state written by block 0
-// Convergence tests use the preconditioned residual r.P^-1 r (relative to
-// b.P^-1 b for the FP64 outer test, to its value at the start of an inner
-// solve for the inner test); they are evaluated identically by every task of
-// a grid from the same partial sums, so all tasks take the same decision.
-// ===========================================================================
-struct SolveArgs {
-    int op_b, op_e, fd_b, fd_e;   // task ranges
-    int ndone_target;             // grids in this launch
-    int prec;                     // inner precision (IGA_PREC_*)
-    int maxit, max_refine, max_sweeps;
-    double tol2, tol_in2;
-};
-
-__device__ __forceinline__ double* part_ptr(const Params& P, int kind, int parity) {
-    return P.part + static_cast<int64_t>(kind * 2 + parity) * P.part_stride;
-}
-enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3 };
-enum { ACT_SKIP = 0, ACT_RESID, ACT_ITER, ACT_XUPD, ACT_DONE };
-
-struct Decision {
-    int act, status;
-    double rho, rhob, rho0;
-};
-
-__device__ Decision decide(const Params& P, const SolveArgs& A, const Grid& g, const GState& st, int nxt,
-                           double* red) {
-    Decision D;
-    D.status = GS_OK;
-    D.rho = 0.0;
-    D.rhob = st.rhob;
-    D.rho0 = st.rho0;
-    if (st.stage == STAGE_DONE) {
-        D.act = ACT_SKIP;
-        return D;
-    }
-    if (st.stage == STAGE_RESID) {
-        D.act = ACT_RESID;
-        return D;
-    }
-    if (st.stage == STAGE_XUPD) {
-        D.act = ACT_XUPD;
-        return D;
-    }
-    const double rho = sum_partials(part_ptr(P, PK_RZ, nxt) + g.blk_off, g.nblk, red);
-    D.rho = rho;
-    if (!isfinite(rho) || rho < 0.0) {
-        D.act = ACT_DONE;
-        D.status = GS_BREAKDOWN;
-    } else if (st.it == 0) {
-        const double rhob = st.refine == 1 ? rho : st.rhob;
-        D.rhob = rhob;
-        if (rho <= A.tol2 * rhob) {
-            D.act = ACT_DONE;
-            D.status = GS_OK;
-        } else if (st.refine > A.max_refine) {
-            D.act = ACT_DONE;
-            D.status = GS_MAXIT;
-        } else {
-            D.act = ACT_ITER;
-            D.rho0 = rho;
-        }
-    } else if (rho <= A.tol_in2 * st.rho0 || st.it >= A.maxit) {
-        D.act = ACT_XUPD;
-    } else {
-        D.act = ACT_ITER;
-    }
-    return D;
-}
-
-template <int PP>
-__global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
-    extern __shared__ double lds[];
-    double* red = lds;
-    const unsigned nwg = gridDim.x;
-    const int64_t N = P.ndof_total;
-    const int lowp = A.prec != IGA_PREC_FP64;
-    const int fdprec = A.prec == IGA_PREC_FP64 ? 0 : (A.prec == IGA_PREC_FP32 ? 1 : 2);
-    for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
-        const int cur = sweep & 1, nxt = cur ^ 1;
-        GState* S0 = P.st2 + cur * P.ngrid;
-        GState* S1 = P.st2 + nxt * P.ngrid;
-        double* r_new = P.r2 + cur * N;
-        double* r_old = P.r2 + nxt * N;
-        double* p_new = P.p2 + cur * N;
-        double* p_old = P.p2 + nxt * N;
-        // ---------------- phase 1: operator -------------------------------------
-        for (int t = A.op_b + blockIdx.x; t < A.op_e; t += nwg) {
-            const Task tk = P.optask[t];
-            const Grid& g = P.grids[tk.grid];
-            const GState st = S0[tk.grid];
-            if (st.stage == STAGE_DONE) {
-                if (tk.local == 0 && threadIdx.x == 0) S1[tk.grid] = st;  // carry forward
-                continue;
-            }
-            const Decision D = decide(P, A, g, st, nxt, red);
-            OpIO io;
-            if (D.act == ACT_ITER) {
-                io.in_a = P.z;
-                io.in_b = p_old;
-                io.beta = st.it == 0 ? 0.0 : D.rho / st.rho;
-                io.out_in = p_new;
-                io.out = P.q;
-                io.rhs = nullptr;
-                io.part = part_ptr(P, PK_PQ, cur) + g.tile_off + tk.local;
-                io.lowp = lowp;
-            } else if (D.act == ACT_RESID) {
-                io.in_a = P.x;
-                io.in_b = nullptr;
-                io.beta = 0.0;
-                io.out_in = nullptr;
-                io.out = r_new;
-                io.rhs = P.b;
-                io.part = part_ptr(P, PK_RES, cur) + g.tile_off + tk.local;
-                io.lowp = 0;
-            } else {
-                continue;
-            }
-            op_tile_2d<PP>(P, g, tk.local, io, lds);
-        }
-        grid_barrier(P.bar, nwg);
-        // ---------------- phase 2: update + FD forward ---------------------------
-        for (int t = A.fd_b + blockIdx.x; t < A.fd_e; t += nwg) {
-            const Task tk = P.fdtask[t];
-            const Grid& g = P.grids[tk.grid];
-            const GState st = S0[tk.grid];
-            if (st.stage == STAGE_DONE) continue;
-            const Decision D = decide(P, A, g, st, nxt, red);
-            const int n1 = g.ni[0];
-            if (D.act == ACT_XUPD) {
-                for (int i = threadIdx.x; i < g.ndof; i += kBlock) {
-                    if (!owned_2d(g, tk.local, i % n1, i / n1)) continue;
-                    const int64_t k = g.dof_off + i;
-                    P.x[k] += P.d[k];
-                    P.d[k] = 0.0;
-                }
-                continue;
-            }
-            FdIO io;
-            io.rt = P.rt;
-            io.prec = fdprec;
-            io.z = nullptr;
-            io.rdot = nullptr;
-            io.part = part_ptr(P, PK_RR, cur) + g.blk_off + tk.local;
-            if (D.act == ACT_ITER) {
-                const double pq = sum_partials(part_ptr(P, PK_PQ, cur) + g.tile_off, g.ntile, red);
-                if (!(pq > 0.0) || !isfinite(D.rho / pq)) continue;  // breakdown: committed in phase 3
-                io.alpha = D.rho / pq;
-                io.r_old = r_old;
-                io.q = P.q;
-                io.r_out = r_new;
-                io.dvec = P.d;
-                io.pvec = p_new;
-            } else if (D.act == ACT_RESID) {
-                io.alpha = 0.0;
-                io.r_old = r_new;
-                io.q = nullptr;
-                io.r_out = nullptr;
-                io.dvec = nullptr;
-                io.pvec = nullptr;
-            } else {
-                continue;
-            }
-            fd_fwd(P, g, tk.local, io, lds);
-        }
-        grid_barrier(P.bar, nwg);
-        // ---------------- phase 3: FD backward and commit ---------------------------
-        for (int t = A.fd_b + blockIdx.x; t < A.fd_e; t += nwg) {
-            const Task tk = P.fdtask[t];
-            const int gi = tk.grid;
-            const Grid& g = P.grids[gi];
-            const GState st = S0[gi];
-            if (st.stage == STAGE_DONE) continue;
-            const Decision D = decide(P, A, g, st, nxt, red);
-            GState ns = st;
-            bool run_bwd = false, finish = false;
-            if (D.act == ACT_ITER) {
-                const double pq = sum_partials(part_ptr(P, PK_PQ, cur) + g.tile_off, g.ntile, red);
-                ns.rhob = D.rhob;
-                ns.rho0 = D.rho0;
-                if (!(pq > 0.0) || !isfinite(D.rho / pq)) {
-                    ns.stage = STAGE_DONE;
-                    ns.status = GS_BREAKDOWN;
-                    ns.total_it += st.it;
-                    finish = true;
-                } else {
-                    ns.stage = STAGE_ITER;
-                    ns.it = st.it + 1;
-                    ns.rho = D.rho;
-                    run_bwd = true;
-                }
-            } else if (D.act == ACT_XUPD) {
-                ns.stage = STAGE_RESID;
-                ns.total_it += st.it;
-                ns.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
-            } else if (D.act == ACT_RESID) {
-                const double rn2 = sum_partials(part_ptr(P, PK_RES, cur) + g.tile_off, g.ntile, red);
-                const double bn2 = st.refine == 0 ? rn2 : st.bn2;
-                ns.bn2 = bn2;
-                ns.relres = bn2 > 0.0 ? sqrt(rn2 / bn2) : 0.0;
-                ns.stage = STAGE_ITER;
-                ns.it = 0;
-                ns.refine = st.refine + 1;
-                run_bwd = true;
-            } else if (D.act == ACT_DONE) {
-                ns.stage = STAGE_DONE;
-                ns.status = D.status;
-                ns.rhob = D.rhob;
-                ns.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
-                finish = true;
-            }
-            if (run_bwd) {
-                FdIO io;
-                io.rt = P.rt;
-                io.z = P.z;
-                io.rdot = r_new;
-                io.prec = fdprec;
-                io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + tk.local;
-                fd_bwd(P, g, tk.local, io, lds);
-            }
-            if (tk.local == 0 && threadIdx.x == 0) {
-                S1[gi] = ns;
-                if (finish) atomicAdd(&P.bar[2], 1u);
-            }
-            __syncthreads();
-        }
-        grid_barrier(P.bar, nwg);
-        const unsigned done = __hip_atomic_load(&P.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (static_cast<int>(done) >= A.ndone_target) break;
-    }
-}
-
 // Reset solver state and vectors of a grid range before a solve.
 __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1, int64_t i0, int64_t i1) {
     const int64_t N = P.ndof_total;
@@ -1068,12 +421,20 @@ __global__ void __launch_bounds__(kBlock) k_apply_op(Params P, int gi, OpIO io) 
 __global__ void __launch_bounds__(kBlock) k_apply_fd_fwd(Params P, int gi, FdIO io) {
     extern __shared__ double lds[];
     const Grid& g = P.grids[gi];
-    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) fd_fwd(P, g, t, io, lds);
+    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) {
+        if (io.prec == 0) fd_fwd_p<0>(P, g, t, io, lds);
+        else if (io.prec == 1) fd_fwd_p<1>(P, g, t, io, lds);
+        else fd_fwd_p<2>(P, g, t, io, lds);
+    }
 }
 __global__ void __launch_bounds__(kBlock) k_apply_fd_bwd(Params P, int gi, FdIO io) {
     extern __shared__ double lds[];
     const Grid& g = P.grids[gi];
-    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) fd_bwd(P, g, t, io, lds);
+    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) {
+        if (io.prec == 0) fd_bwd_p<0>(P, g, t, io, lds);
+        else if (io.prec == 1) fd_bwd_p<1>(P, g, t, io, lds);
+        else fd_bwd_p<2>(P, g, t, io, lds);
+    }
 }
 
 // ===========================================================================
@@ -1220,12 +581,18 @@ Params make_params(iga_sg_plan_s* P) {
     return K;
 }
 
-const void* solve_kernel(int p) {
+// k_solve<PP, *> lives in one translation unit per degree (solve_p*.hip)
+const void* solve_kernel_p1(int prec);
+const void* solve_kernel_p2(int prec);
+const void* solve_kernel_p3(int prec);
+const void* solve_kernel_p4(int prec);
+
+const void* solve_kernel(int p, int prec) {
     switch (p) {
-        case 1: return reinterpret_cast<const void*>(k_solve<1>);
-        case 2: return reinterpret_cast<const void*>(k_solve<2>);
-        case 3: return reinterpret_cast<const void*>(k_solve<3>);
-        default: return reinterpret_cast<const void*>(k_solve<4>);
+        case 1: return solve_kernel_p1(prec);
+        case 2: return solve_kernel_p2(prec);
+        case 3: return solve_kernel_p3(prec);
+        default: return solve_kernel_p4(prec);
     }
 }
 
@@ -1308,7 +675,12 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     HIP_OK(hipGetDeviceProperties(&prop, dev));
     P->num_cu = prop.multiProcessorCount;
     int occ = 0;
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_kernel(P->p), kBlock, P->lds_bytes));
+    occ = 1 << 20;
+    for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD}) {
+        int o = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec), kBlock, P->lds_bytes));
+        occ = std::min(occ, o);
+    }
     P->max_wg = std::max(1, occ) * P->num_cu;
     for (int i = 0; i < 8; ++i)
         if (!P->ev[i]) HIP_OK(hipEventCreate(reinterpret_cast<hipEvent_t*>(&P->ev[i])));
@@ -1380,6 +752,10 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     double ti = o->precision == IGA_PREC_FP64 ? o->tol : (o->tol_inner > 0 ? o->tol_inner : 1e-4);
     A.tol_in2 = ti * ti;
     A.max_sweeps = (A.maxit + 2) * (A.max_refine + 1) + 4;
+    char* trbase = reinterpret_cast<char*>(P->ws) + P->lay.trace;
+    A.trace = o->timing >= 2 ? reinterpret_cast<unsigned long long*>(trbase) : nullptr;
+    A.trace_sweeps = kTraceSweeps;
+    if (A.trace) HIP_OK(hipMemsetAsync(trbase, 0, sizeof(unsigned long long) * (1 + 6 * kTraceSweeps), st));
     const size_t lds = P->lds_bytes;
     hipEvent_t e0 = static_cast<hipEvent_t>(P->ev[0]), e1 = static_cast<hipEvent_t>(P->ev[1]);
     if (o->timing) HIP_OK(hipEventRecord(e0, st));
@@ -1397,7 +773,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         if (o->workgroups > 0) want = o->workgroups;
         int nwg = std::max(1, std::min(want, P->max_wg));
         void* args[] = {&K, &A};
-        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p), dim3(nwg), dim3(kBlock), args,
+        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision), dim3(nwg), dim3(kBlock), args,
                                           static_cast<unsigned>(lds), st));
         return IGA_OK;
     };
@@ -1456,6 +832,24 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             float ms = 0.0f;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
             rep->kernel_ms[1] = ms;
+        }
+        if (A.trace && o->batched) {
+            std::vector<unsigned long long> tr(1 + 6 * kTraceSweeps);
+            unsigned sweeps = 0;
+            HIP_OK(hipMemcpy(tr.data(), A.trace, sizeof(unsigned long long) * tr.size(), hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(&sweeps, reinterpret_cast<char*>(P->ws) + P->lay.bar + 12, sizeof(unsigned),
+                             hipMemcpyDeviceToHost));
+            const int ns = std::min<int>(static_cast<int>(sweeps), kTraceSweeps);
+            rep->sweeps = static_cast<int>(sweeps);
+            double acc[6] = {0, 0, 0, 0, 0, 0};
+            for (int s = 0; s < ns; ++s) {
+                for (int ph = 0; ph < 3; ++ph) {
+                    unsigned long long prev = (ph == 0) ? (s == 0 ? tr[0] : tr[1 + 6 * (s - 1) + 2]) : tr[1 + 6 * s + ph - 1];
+                    acc[ph] += static_cast<double>(tr[1 + 6 * s + ph] - prev);
+                    acc[3 + ph] += static_cast<double>(tr[1 + 6 * s + 3 + ph]);
+                }
+            }
+            for (int i = 0; i < 6; ++i) rep->phase_us[i] = ns > 0 ? acc[i] / ns * 0.01 : 0.0;  // 100 MHz
         }
     }
     if (ret == IGA_ERR_NOT_CONVERGED) set_error("some component did not reach the tolerance");

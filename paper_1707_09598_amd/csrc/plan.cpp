@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <array>
 #include <map>
@@ -206,6 +207,14 @@ double binom(int n, int k) {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+// Tuning knobs (tile sizes) read from the environment, with defaults.
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    int x = std::atoi(v);
+    return x > 0 ? x : dflt;
+}
+
 // Element index range touching interior unknowns [a, b) of one direction.
 void elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
     int lo_basis = a + 1, hi_basis = b;  // basis indices of the first/last owned unknown
@@ -398,29 +407,39 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 auto fkey = std::make_tuple(H.grading[k], H.gamma[k], lev);
                 auto fit = fd_off.find(fkey);
                 if (fit == fd_off.end()) {
+                    // U and U^T stored row-major with a padded row stride (a multiple of 8
+                    // elements, zero-filled) so that rows start 16-byte aligned in every
+                    // precision; the pools are padded to 8 elements before each table
                     std::array<int64_t, 7> o;
-                    int n = F.n;
-                    o[0] = static_cast<int64_t>(dp.size());
-                    dp.insert(dp.end(), F.U.begin(), F.U.end());
-                    o[1] = static_cast<int64_t>(dp.size());
-                    for (int i = 0; i < n; ++i)
-                        for (int j = 0; j < n; ++j) dp.push_back(F.U[static_cast<size_t>(j) * n + i]);
+                    const int n = F.n, ld = (n + 7) & ~7;
+                    auto Uat = [&](int i, int j, bool tr) {
+                        return tr ? F.U[static_cast<size_t>(j) * n + i] : F.U[static_cast<size_t>(i) * n + j];
+                    };
+                    for (int t = 0; t < 2; ++t) {
+                        dp.resize((dp.size() + 7) & ~static_cast<size_t>(7), 0.0);
+                        o[t] = static_cast<int64_t>(dp.size());
+                        for (int i = 0; i < n; ++i)
+                            for (int j = 0; j < ld; ++j) dp.push_back(j < n ? Uat(i, j, t == 1) : 0.0);
+                    }
                     o[2] = static_cast<int64_t>(dp.size());
                     dp.insert(dp.end(), F.lam.begin(), F.lam.end());
-                    o[3] = static_cast<int64_t>(P->fpool.size());
-                    for (double v : F.U) P->fpool.push_back(static_cast<float>(v));
-                    o[4] = static_cast<int64_t>(P->fpool.size());
-                    for (int i = 0; i < n; ++i)
-                        for (int j = 0; j < n; ++j)
-                            P->fpool.push_back(static_cast<float>(F.U[static_cast<size_t>(j) * n + i]));
-                    o[5] = static_cast<int64_t>(P->hpool.size());
-                    for (double v : F.U) P->hpool.push_back(to_bf16(static_cast<float>(v)));
-                    o[6] = static_cast<int64_t>(P->hpool.size());
-                    for (int i = 0; i < n; ++i)
-                        for (int j = 0; j < n; ++j)
-                            P->hpool.push_back(to_bf16(static_cast<float>(F.U[static_cast<size_t>(j) * n + i])));
+                    for (int t = 0; t < 2; ++t) {
+                        P->fpool.resize((P->fpool.size() + 7) & ~static_cast<size_t>(7), 0.0f);
+                        o[3 + t] = static_cast<int64_t>(P->fpool.size());
+                        for (int i = 0; i < n; ++i)
+                            for (int j = 0; j < ld; ++j)
+                                P->fpool.push_back(j < n ? static_cast<float>(Uat(i, j, t == 1)) : 0.0f);
+                    }
+                    for (int t = 0; t < 2; ++t) {
+                        P->hpool.resize((P->hpool.size() + 7) & ~static_cast<size_t>(7), 0);
+                        o[5 + t] = static_cast<int64_t>(P->hpool.size());
+                        for (int i = 0; i < n; ++i)
+                            for (int j = 0; j < ld; ++j)
+                                P->hpool.push_back(j < n ? to_bf16(static_cast<float>(Uat(i, j, t == 1))) : 0);
+                    }
                     fit = fd_off.emplace(fkey, o).first;
                 }
+                T.ldu = (F.n + 7) & ~7;
                 T.oU = fit->second[0];
                 T.oUT = fit->second[1];
                 T.oLam = fit->second[2];
@@ -477,7 +496,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             // operator tiles: minimise the elements processed (halo recompute)
             const int m = p - r;
             if (d == 2) {
-                const int TT = 256;
+                const int TT = env_int("IGA_OP_TILE", 128);
                 long best = -1;
                 for (int t2 = 1; t2 <= std::min(g.ni[1], TT); ++t2) {
                     int t1 = std::min(g.ni[0], std::max(1, TT / t2));
@@ -526,14 +545,28 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             // fast-diagonalisation blocks (2D: split the longest direction)
             if (d == 2) {
                 g.big = g.ni[1] > g.ni[0] ? 1 : 0;
-                int nbig = g.ni[g.big], nsm = g.ni[1 - g.big];
+                const int nbig = g.ni[g.big], nsm = g.ni[1 - g.big];
+                const size_t n = static_cast<size_t>(g.ndof);
+                // long directions: blocks of 8, 16 or 32 columns, about 64 KB of the
+                // FP64 factor per block, streamed by the whole workgroup
                 int bs = nbig;
-                if (nbig > 64) bs = std::max(8, std::min(64, (2048 + nsm - 1) / nsm));
+                const int wide_min = env_int("IGA_FD_WIDE", 16);
+                if (nbig >= wide_min) {
+                    int b = 8;
+                    while (b < 32 && static_cast<size_t>(2 * b) * nbig * sizeof(double) <= 65536) b *= 2;
+                    if (b < nbig) bs = b;
+                }
                 g.blk = bs;
                 g.nblk = (nbig + bs - 1) / bs;
-                size_t lds = (2 * static_cast<size_t>(g.ndof) + static_cast<size_t>(nsm) * bs + kBlock) *
-                             sizeof(double);
-                lds_max = std::max(lds_max, lds);
+                const bool wide = g.nblk > 1;
+                size_t lds = 2 * n + kBigRed + (wide ? static_cast<size_t>(nsm) * bs : n) +
+                             static_cast<size_t>(nsm) * nsm;
+                g.fdstage = 0;
+                if (!wide && (lds + static_cast<size_t>(nbig) * nbig) * sizeof(double) <= 60 * 1024) {
+                    g.fdstage = 1;
+                    lds += static_cast<size_t>(nbig) * nbig;
+                }
+                lds_max = std::max(lds_max, lds * sizeof(double));
             } else {
                 g.big = 0;
                 g.blk = g.ni[0];
@@ -548,7 +581,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         delete P;
         return IGA_ERR_INVALID_ARG;
     }
-    P->lds_bytes = lds_max;
+    P->lds_bytes = lds_max + 32 * sizeof(double);  // + per-task context slots
     // task lists in decreasing grid size (longest-processing-time order)
     std::vector<int> ord(P->grids.size());
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = static_cast<int>(i);
@@ -595,6 +628,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.bar = take(256);
+    L.trace = take(sizeof(unsigned long long) * (1 + 6 * 4096));
     L.total = off;
     *out = P;
     return IGA_OK;
@@ -637,8 +671,10 @@ iga_status iga_sg_fd_factor(iga_sg_plan plan, int dir, int lev, int* n, double* 
     }
     const Tab1D& T = plan->tabs[tab_index(plan, 0, dir, lev)];
     if (n) *n = T.ni;
-    size_t nn = static_cast<size_t>(T.ni) * T.ni;
-    if (U_host) std::memcpy(U_host, &plan->dpool[T.oU], nn * sizeof(double));
+    if (U_host)
+        for (int i = 0; i < T.ni; ++i)
+            std::memcpy(U_host + static_cast<size_t>(i) * T.ni, &plan->dpool[T.oU + static_cast<int64_t>(i) * T.ldu],
+                        T.ni * sizeof(double));
     if (lam_host) std::memcpy(lam_host, &plan->dpool[T.oLam], T.ni * sizeof(double));
     return IGA_OK;
 }

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/iga_sg.h"
+#include "iga_sg.h"
 #include "common.hpp"
 
 struct iga_sg_plan_s;

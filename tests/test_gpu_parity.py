@@ -56,13 +56,16 @@ def _bound(S, wl):
     return P
 
 
-@pytest.mark.parametrize("name,w", [("cfg1", 4), ("cfg2", 5), ("cfg2", 7)])
-def test_rhs_and_operator_parity(S, name, w):
+@pytest.mark.parametrize("name,w,comps", [("cfg1", 4, None), ("cfg2", 5, None), ("cfg2", 7, None),
+                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20])])
+def test_rhs_and_operator_parity(S, name, w, comps):
     wl = W.config(name, w=w)
     log(f"case rhs/operator {name} w={w}")
     P = _bound(S, wl)
     Po = O.Problem(wl)
     for c, lv in enumerate(P.levels):
+        if comps is not None and c not in comps:
+            continue
         A, b = Po.assemble_dense(lv)
         perm = oracle_perm(Po.nbasis(lv))
         Ag = A[np.ix_(perm, perm)]
@@ -75,18 +78,31 @@ def test_rhs_and_operator_parity(S, name, w):
         assert rel(y32, Ag @ x) < 1e-5, (c, lv)
 
 
-@pytest.mark.parametrize("name,w", [("cfg1", 5), ("cfg2", 7)])
-def test_fast_diagonalisation_parity(S, name, w):
+@pytest.mark.parametrize("name,w,comps", [("cfg1", 5, None), ("cfg2", 7, None),
+                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20])])
+def test_fast_diagonalisation_parity(S, name, w, comps):
     wl = W.config(name, w=w)
     log(f"case fd {name} w={w}")
     P = _bound(S, wl)
     for c, lv in enumerate(P.levels):
+        if comps is not None and c not in comps:
+            continue
         K1, M1 = P.matrices_1d(0, int(lv[0]))
         K2, M2 = P.matrices_1d(1, int(lv[1]))
         Pk = np.kron(M2, K1) + np.kron(K2, M1)  # direction 1 fastest
         x = W.random_vector(len(Pk), seed=7 + c)
+        # dense reference with one refinement step (residual in extended
+        # precision) so that its own error stays well below the FP64 bar
         ref = np.linalg.solve(Pk, x)
-        for which, tol in (("fd64", 1e-12), ("fd32", 1e-5), ("fd16", 2e-2)):
+        res = (x.astype(np.longdouble) - Pk.astype(np.longdouble) @ ref.astype(np.longdouble)).astype(np.float64)
+        ref = ref + np.linalg.solve(Pk, res)
+        # the transform is backward stable: its forward error is about
+        # kappa(P) eps, with kappa(P) from the 1D eigenvalues
+        l1 = P.fd_factor(0, int(lv[0]))[1]
+        l2 = P.fd_factor(1, int(lv[1]))[1]
+        kappa = (l1.max() + l2.max()) / (l1.min() + l2.min())
+        tol64 = max(1e-12, 100 * 2.2e-16 * kappa)
+        for which, tol in (("fd64", tol64), ("fd32", 1e-5), ("fd16", 2e-2)):
             z = P.apply(c, which, x).cpu().numpy()
             assert rel(z, ref) < tol, (c, lv, which, rel(z, ref))
 
@@ -94,10 +110,12 @@ def test_fast_diagonalisation_parity(S, name, w):
 def _solve_and_compare(S, wl, precision, batched, tol_coef, tol_sg, npts=4096):
     P = _bound(S, wl)
     rep = P.solve(precision=precision, tol=1e-11, tol_inner=1e-5, maxit=400, max_refine=6,
-                  batched=batched)
+                  batched=batched, check=False)
+    log(f"  code {rep['code']} status {rep['status'].tolist()}")
     log(f"  iters {rep['iters'].tolist()} refine {rep['refinements'].tolist()}")
-    log(f"  relres max {rep['relres'].max():.3e} prelres max {rep['prelres'].max():.3e}")
-    assert np.all(rep["status"] == 0)
+    log(f"  relres {np.array2string(rep['relres'], precision=2)}")
+    log(f"  prelres {np.array2string(rep['prelres'], precision=2)}")
+    assert rep["code"] == 0 and np.all(rep["status"] == 0)
     Po = O.Problem(wl)
     coefs = Po.solve_all()
     worst = 0.0
