@@ -132,6 +132,9 @@ typedef struct {
     int workgroups;    /* persistent launch width; 0 => library choice */
     int timing;        /* 1: fill report.kernel_ms with HIP-event times (synchronises);
                           2: also trace the phases of the persistent solve (report.phase_us) */
+    int continue_cg;   /* refinement steps of the mixed modes: 0 restarts CG from the new FP64
+                          residual (classic iterative refinement); 1 replaces the recursive
+                          residual by the FP64 one and continues CG with its search direction */
 } iga_sg_solve_opts;
 
 /* Per-component results; arrays are caller-owned host buffers of length

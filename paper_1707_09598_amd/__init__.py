@@ -67,7 +67,7 @@ class _Field(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("batched", C.c_int), ("tol", C.c_double),
                 ("tol_inner", C.c_double), ("maxit", C.c_int), ("max_refine", C.c_int),
-                ("workgroups", C.c_int), ("timing", C.c_int)]
+                ("workgroups", C.c_int), ("timing", C.c_int), ("continue_cg", C.c_int)]
 
 
 class _Report(C.Structure):
@@ -269,9 +269,9 @@ class Plan:
 
     def solve(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
               maxit: int = 500, max_refine: int = 0, batched: bool = True, workgroups: int = 0,
-              timing: bool = False, check: bool = True) -> Dict[str, Any]:
+              timing: bool = False, check: bool = True, continue_cg: bool = False) -> Dict[str, Any]:
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups,
-                  int(timing))
+                  int(timing), int(continue_cg))
         it = np.zeros(self.ncomp, dtype=np.int32)
         rf = np.zeros(self.ncomp, dtype=np.int32)
         rr = np.zeros(self.ncomp)
@@ -289,9 +289,10 @@ class Plan:
 
     def solve_async(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
                     maxit: int = 500, max_refine: int = 0, batched: bool = True,
-                    workgroups: int = 0) -> None:
+                    workgroups: int = 0, continue_cg: bool = False) -> None:
         """Enqueue a solve without reading the report back (no host sync)."""
-        o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0)
+        o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0,
+                  int(continue_cg))
         _check(lib().iga_sg_solve(self.h, C.byref(o), C.POINTER(_Report)()))
 
     def combine(self, xi, patch=None):

@@ -8,6 +8,12 @@
 
 #include <cstdint>
 
+#if defined(__HIPCC__)
+#define IGA_HD __host__ __device__
+#else
+#define IGA_HD
+#endif
+
 namespace igasg {
 
 constexpr int kMaxDim = 3;
@@ -18,7 +24,7 @@ constexpr int kBlock = 256;       // threads per workgroup in every kernel
 constexpr int kBigRed = 1024;     // doubles of LDS for cross-wavefront partial sums of FD tasks
 
 // Grid stages of the persistent refinement/CG state machine.
-enum Stage : int { STAGE_RESID = 0, STAGE_ITER = 1, STAGE_DONE = 2, STAGE_XUPD = 3 };
+enum Stage : int { STAGE_RESID = 0, STAGE_ITER = 1, STAGE_DONE = 2 };
 // Per-component status codes reported to the host.
 enum GridStatus : int { GS_RUNNING = -1, GS_OK = 0, GS_MAXIT = 5, GS_BREAKDOWN = 6 };
 
@@ -68,6 +74,7 @@ struct Grid {
     int64_t nqp;
     double ccoef;     // combination coefficient
     double fdc[3];    // per-direction scaling of the fast-diagonalisation pencil
+    int64_t oDinv;    // double pool: 1 / (sum of the pencil eigenvalues), ndof values
     // fast-diagonalisation task split (2D: blocks of the longest direction)
     int big;          // direction split into blocks
     int nblk;
@@ -102,6 +109,68 @@ struct Task {
     int grid;
     int local;
 };
+
+// A task's grid and 1D tables, copied into LDS once per solve launch so that
+// the tasks of a sweep read their description without a memory round trip.
+struct TaskMeta {
+    Grid g;
+    Tab1D t[2];
+    int grid, local;
+};
+static_assert(sizeof(Grid) % 8 == 0 && sizeof(Tab1D) % 8 == 0 && sizeof(TaskMeta) % 8 == 0, "8-byte words");
+constexpr int kMetaOp = 2;     // cached operator tasks per workgroup
+constexpr int kMetaFd = 5;     // cached fast-diagonalisation tasks per workgroup
+constexpr int kMetaSlots = kMetaOp + kMetaFd + 1;  // + one slot for tasks beyond the cache
+constexpr int kCtxBytes = 256;  // LDS for the per-task context
+constexpr int kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+
+// LDS layout (byte offsets) of a 2D fast-diagonalisation task:
+//   R, S      two grid-sized FP64 work vectors
+//   red       cross-wavefront partial sums
+//   Out       block output
+//   Own       three FP64 values per owned unknown (fetched operands)
+//   Us, Ub    staged factor rows (short direction; long direction of a
+//             single-block grid) in the factor precision, row stride ldu
+//   Slab      long-direction factor rows of a blocked grid: rows x 256
+//             threads x 16 bytes, in the order the threads consume them
+struct FdLayout {
+    int R, S, red, Out, Own, Us, Ub, Slab, rows, total;
+};
+// rows of the slab per thread for block width bs (16-byte chunks of 16/usize values)
+inline IGA_HD int fd_slab_rows(int nbig, int bs, int usize) {
+    const int rpt = 256 * (16 / usize) / bs;  // rows per workgroup pass
+    return (nbig + rpt - 1) / rpt;
+}
+inline IGA_HD FdLayout fd_layout(const Grid& g, int ldu_s, int ldu_b, int usize) {
+    const int n = g.ni[0] * g.ni[1], nsm = g.ni[1 - g.big], nbig = g.ni[g.big];
+    const bool wide = g.nblk > 1;
+    const int bs = g.blk < nbig ? g.blk : nbig;
+    FdLayout L;
+    int o = 0;
+    L.R = o;
+    o += 8 * n;
+    L.S = o;
+    o += 8 * n;
+    L.red = o;
+    o += 8 * kBigRed;
+    L.Out = o;
+    o += 8 * (wide ? nsm * bs : n);
+    L.Own = o;
+    o += 8 * 3 * nsm * bs;
+    o = (o + 15) & ~15;
+    L.Us = o;
+    o += nsm * ldu_s * usize;
+    o = (o + 15) & ~15;
+    L.Ub = o;
+    if (!wide && g.fdstage) o += nbig * ldu_b * usize;
+    o = (o + 15) & ~15;
+    L.Slab = o;
+    L.rows = wide ? fd_slab_rows(nbig, bs, usize) : 0;
+    o += L.rows * 256 * 16;
+    L.total = o;
+    return L;
+}
+constexpr size_t kSolveLdsHead = kCtxBytes + kMetaSlots * sizeof(TaskMeta);
 
 // Workspace layout: byte offsets of every device array.
 struct Layout {

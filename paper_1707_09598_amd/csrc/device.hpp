@@ -94,11 +94,37 @@ __device__ __forceinline__ double sum_partials(const double* part, int count, do
     return s;
 }
 
+// Exact quotient and remainder of i / d for 0 <= i < 2^21 and d >= 1 from a
+// float reciprocal and one correction step: division by a run-time integer
+// is a long dependent instruction sequence on the GPU.  The float product has
+// relative error below 2^-23, so the truncated quotient is off by at most one.
+struct FDiv {
+    int d;
+    float rcp;
+    __device__ explicit FDiv(int d_) : d(d_), rcp(1.0f / static_cast<float>(d_)) {}
+    __device__ __forceinline__ int div(int i, int* rem) const {
+        int q = static_cast<int>(static_cast<float>(i) * rcp);
+        int r = i - q * d;
+        if (r < 0) {
+            --q;
+            r += d;
+        } else if (r >= d) {
+            ++q;
+            r -= d;
+        }
+        *rem = r;
+        return q;
+    }
+};
+
+// x / m for the knot multiplicity m (1 for maximal regularity).
+__device__ __forceinline__ int div_mult(int x, int m) { return m == 1 ? x : x / m; }
+
 // Element range touching interior unknowns [a, b) of one direction.
 __device__ __forceinline__ void d_elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
     int lo_basis = a + 1, hi_basis = b;
-    int lo = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
-    int hi = hi_basis / m;
+    int lo = (lo_basis - p <= 0) ? 0 : div_mult(lo_basis - p + m - 1, m);
+    int hi = div_mult(hi_basis, m);
     *elo = lo < 0 ? 0 : lo;
     *ehi = hi > E - 1 ? E - 1 : hi;
 }

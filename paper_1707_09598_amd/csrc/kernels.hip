@@ -409,31 +409,27 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
     }
 }
 
-// Standalone operator / preconditioner launches (test hooks).
+// Standalone operator / preconditioner launches (test hooks).  Same LDS
+// layout as the solve kernel: context, task descriptions, work arrays.
 template <int PP>
 __global__ void __launch_bounds__(kBlock) k_apply_op(Params P, int gi, OpIO io) {
-    extern __shared__ double lds[];
-    const Grid& g = P.grids[gi];
+    extern __shared__ double lds_all[];
+    TaskMeta* M = reinterpret_cast<TaskMeta*>(reinterpret_cast<char*>(lds_all) + kCtxBytes);
+    double* lds = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + kSolveLdsHead);
+    meta_fill(P, Task{gi, 0}, M);
     OpIO a = io;
     a.part = nullptr;
-    for (int t = blockIdx.x; t < g.ntile; t += gridDim.x) op_tile_2d<PP>(P, g, t, a, lds);
+    for (int t = blockIdx.x; t < M->g.ntile; t += gridDim.x) op_tile_2d<PP>(P, M->g, M->t[0], M->t[1], t, a, lds);
 }
-__global__ void __launch_bounds__(kBlock) k_apply_fd_fwd(Params P, int gi, FdIO io) {
-    extern __shared__ double lds[];
-    const Grid& g = P.grids[gi];
-    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) {
-        if (io.prec == 0) fd_fwd_p<0>(P, g, t, io, lds);
-        else if (io.prec == 1) fd_fwd_p<1>(P, g, t, io, lds);
-        else fd_fwd_p<2>(P, g, t, io, lds);
-    }
-}
-__global__ void __launch_bounds__(kBlock) k_apply_fd_bwd(Params P, int gi, FdIO io) {
-    extern __shared__ double lds[];
-    const Grid& g = P.grids[gi];
-    for (int t = blockIdx.x; t < g.nblk; t += gridDim.x) {
-        if (io.prec == 0) fd_bwd_p<0>(P, g, t, io, lds);
-        else if (io.prec == 1) fd_bwd_p<1>(P, g, t, io, lds);
-        else fd_bwd_p<2>(P, g, t, io, lds);
+__global__ void __launch_bounds__(kBlock) k_apply_fd(Params P, int gi, FdIO io, int fwd) {
+    extern __shared__ double lds_all[];
+    TaskMeta* M = reinterpret_cast<TaskMeta*>(reinterpret_cast<char*>(lds_all) + kCtxBytes);
+    double* lds = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + kSolveLdsHead);
+    meta_fill(P, Task{gi, 0}, M);
+    for (int t = blockIdx.x; t < M->g.nblk; t += gridDim.x) {
+        if (io.prec == 0) fd_apply_block<0>(P, *M, t, io, lds, fwd != 0);
+        else if (io.prec == 1) fd_apply_block<1>(P, *M, t, io, lds, fwd != 0);
+        else fd_apply_block<2>(P, *M, t, io, lds, fwd != 0);
     }
 }
 
@@ -674,8 +670,23 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     hipDeviceProp_t prop;
     HIP_OK(hipGetDeviceProperties(&prop, dev));
     P->num_cu = prop.multiProcessorCount;
-    int occ = 0;
-    occ = 1 << 20;
+    if (P->lds_bytes > prop.sharedMemPerBlock) {
+        set_error("plan needs %zu bytes of LDS per workgroup, the device offers %zu", P->lds_bytes,
+                  static_cast<size_t>(prop.sharedMemPerBlock));
+        return IGA_ERR_DEVICE;
+    }
+    // kernels that take the plan's LDS size: allow dynamic LDS beyond 64 KiB
+    {
+        const void* ks[] = {reinterpret_cast<const void*>(k_apply_op<1>), reinterpret_cast<const void*>(k_apply_op<2>),
+                            reinterpret_cast<const void*>(k_apply_op<3>), reinterpret_cast<const void*>(k_apply_op<4>),
+                            reinterpret_cast<const void*>(k_apply_fd)};
+        for (const void* k : ks)
+            HIP_OK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
+        for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD})
+            HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(P->lds_bytes)));
+    }
+    int occ = 1 << 20;
     for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD}) {
         int o = 0;
         HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec), kBlock, P->lds_bytes));
@@ -752,6 +763,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     double ti = o->precision == IGA_PREC_FP64 ? o->tol : (o->tol_inner > 0 ? o->tol_inner : 1e-4);
     A.tol_in2 = ti * ti;
     A.max_sweeps = (A.maxit + 2) * (A.max_refine + 1) + 4;
+    A.continue_cg = o->continue_cg != 0 && o->precision != IGA_PREC_FP64;
     char* trbase = reinterpret_cast<char*>(P->ws) + P->lay.trace;
     A.trace = o->timing >= 2 ? reinterpret_cast<unsigned long long*>(trbase) : nullptr;
     A.trace_sweeps = kTraceSweeps;
@@ -978,9 +990,9 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
         io.rt = K.rt;
         io.z = ys;
         io.prec = which - 2;
-        hipLaunchKernelGGL(k_apply_fd_fwd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io);
+        hipLaunchKernelGGL(k_apply_fd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io, 1);
         HIP_OK(hipGetLastError());
-        hipLaunchKernelGGL(k_apply_fd_bwd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io);
+        hipLaunchKernelGGL(k_apply_fd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io, 0);
         HIP_OK(hipGetLastError());
     }
     return IGA_OK;

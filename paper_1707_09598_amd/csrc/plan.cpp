@@ -491,6 +491,24 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             }
             g.dof_off = P->ndof_total;
             P->ndof_total += g.ndof;
+            // inverse eigenvalue sums of the fast-diagonalisation pencil, direction 1 fastest
+            {
+                auto& dp = P->dpool;
+                g.oDinv = static_cast<int64_t>(dp.size());
+                const double* lam[3] = {nullptr, nullptr, nullptr};
+                for (int k = 0; k < d; ++k) lam[k] = &dp[P->tabs[g.tab[k]].oLam];
+                std::vector<double> dv(static_cast<size_t>(g.ndof));
+                for (int64_t i = 0; i < g.ndof; ++i) {
+                    int64_t rem = i;
+                    double s = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        s += g.fdc[k] * lam[k][rem % g.ni[k]];
+                        rem /= g.ni[k];
+                    }
+                    dv[static_cast<size_t>(i)] = 1.0 / s;
+                }
+                dp.insert(dp.end(), dv.begin(), dv.end());
+            }
             g.qp_off = P->nqp_total;
             P->nqp_total += g.nqp;
             // operator tiles: minimise the elements processed (halo recompute)
@@ -559,14 +577,11 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.blk = bs;
                 g.nblk = (nbig + bs - 1) / bs;
                 const bool wide = g.nblk > 1;
-                size_t lds = 2 * n + kBigRed + (wide ? static_cast<size_t>(nsm) * bs : n) +
-                             static_cast<size_t>(nsm) * nsm;
-                g.fdstage = 0;
-                if (!wide && (lds + static_cast<size_t>(nbig) * nbig) * sizeof(double) <= 60 * 1024) {
-                    g.fdstage = 1;
-                    lds += static_cast<size_t>(nbig) * nbig;
-                }
-                lds_max = std::max(lds_max, lds * sizeof(double));
+                const int ls = P->tabs[g.tab[1 - g.big]].ldu, lb = P->tabs[g.tab[g.big]].ldu;
+                // single-block grids stage the long factor as well when it fits
+                g.fdstage = wide ? 0 : 1;
+                if (!wide && fd_layout(g, ls, lb, 8).total + kSolveLdsHead > kLdsLimit) g.fdstage = 0;
+                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(g, ls, lb, 8).total));
             } else {
                 g.big = 0;
                 g.blk = g.ni[0];
@@ -576,12 +591,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             }
             P->grids.push_back(g);
         }
-    if (lds_max > 64 * 1024) {
-        set_error("a component grid needs %zu bytes of LDS (limit 64 KiB)", lds_max);
+    if (lds_max + kSolveLdsHead > kLdsLimit) {
+        set_error("a component grid needs %zu bytes of LDS (limit %d)", lds_max + kSolveLdsHead, kLdsLimit);
         delete P;
         return IGA_ERR_INVALID_ARG;
     }
-    P->lds_bytes = lds_max + 32 * sizeof(double);  // + per-task context slots
+    P->lds_bytes = lds_max + kSolveLdsHead;  // + task context and cached task descriptions
     // task lists in decreasing grid size (longest-processing-time order)
     std::vector<int> ord(P->grids.size());
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = static_cast<int>(i);

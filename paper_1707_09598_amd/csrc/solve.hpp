@@ -113,10 +113,9 @@ __device__ __forceinline__ void elem_apply_2d(const double* X, int nh1, int x1, 
 }
 
 template <int PP>
-__device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, int tile, const OpIO& io, double* lds) {
+__device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const Tab1D& T1, const Tab1D& T2,
+                                           int tile, const OpIO& io, double* lds) {
     const int p = PP;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
     const int m1 = T1.m, m2 = T2.m;
     const int t1 = tile % g.ntd[0], t2 = tile / g.ntd[0];
     const int a1 = t1 * g.tile[0], b1 = min(g.ni[0], a1 + g.tile[0]);
@@ -132,8 +131,11 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, int t
     double* red = Y + ne1 * ne2 * (p + 1) * (p + 1);
     const int64_t off = g.dof_off;
     const int n1 = g.ni[0], n2 = g.ni[1];
+    const FDiv dh(nh1);
     for (int idx = threadIdx.x; idx < nh1 * nh2; idx += kBlock) {
-        int i1 = hl1 + idx % nh1, i2 = hl2 + idx / nh1;
+        int r1;
+        const int q1 = dh.div(idx, &r1);
+        int i1 = hl1 + r1, i2 = hl2 + q1;
         double v = 0.0;
         if (i1 >= 0 && i1 < n1 && i2 >= 0 && i2 < n2) {
             int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
@@ -146,8 +148,11 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, int t
     __syncthreads();
     const int nqp1 = P.nq * (p + 1);
     const int64_t nqp = g.nqp;
+    const FDiv de(ne1);
     for (int el = threadIdx.x; el < ne1 * ne2; el += kBlock) {
-        int e1 = el1 + el % ne1, e2 = el2 + el / ne1;
+        int r1;
+        const int q1 = de.div(el, &r1);
+        int e1 = el1 + r1, e2 = el2 + q1;
         const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
         const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
         const double* B2 = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1;
@@ -169,8 +174,11 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, int t
     __syncthreads();
     const int w1 = b1 - a1, nown = w1 * (b2 - a2);
     double dot = 0.0;
+    const FDiv dw(w1);
     for (int o = threadIdx.x; o < nown; o += kBlock) {
-        const int i1 = a1 + o % w1, i2 = a2 + o / w1;
+        int r1;
+        const int q1 = dw.div(o, &r1);
+        const int i1 = a1 + r1, i2 = a2 + q1;
         const int I1 = i1 + 1, I2 = i2 + 1;
         int lo1, hi1, lo2, hi2;
         d_elem_range(i1, i1 + 1, p, m1, g.E[0], &lo1, &hi1);
@@ -199,54 +207,54 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, int t
 
 // ===========================================================================
 // fast diagonalisation: z = (U1 (x) U2) diag(1/(c1 l1 + c2 l2)) (U1 (x) U2)^T r
-// as mode products (workgroup GEMMs with split K)
+// as mode products
 // ===========================================================================
-// C(b, m, n) = sum_k A(b, m, k) B(b, k, n); operands in LDS or global memory.
+// Small dense product in LDS or global memory, C = A B (M x N, inner K):
+// threads take the longer output index and a chunk of 8 of the other one, so
+// every operand value read is used up to 8 times and nothing is split over K.
 template <typename TA, typename TB, typename TC>
-__device__ void wg_gemm(int nbat, int M, int N, int K, const TA* A, int64_t sAb, int64_t sAm, int64_t sAk,
-                        const TB* B, int64_t sBb, int64_t sBk, int64_t sBn, double* C, int64_t sCb,
-                        int64_t sCm, int64_t sCn, double* red) {
-    const int O = nbat * M * N;
-    auto ld = [](auto* p, int64_t i) -> TC {
+__device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
+                                           int sBn, double* C, int sCm, int sCn) {
+    auto ld = [](auto* p, int i) -> TC {
         using V = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
         if constexpr (std::is_same<V, uint16_t>::value) return static_cast<TC>(bf16_to_f32(p[i]));
         else return static_cast<TC>(p[i]);
     };
-    // split K when there are fewer outputs than threads: short sequential
-    // dot products keep the latency of a phase low
-    int S = O >= kBlock ? 1 : kBlock / O;
-    if (S > (K + 15) / 16) S = (K + 15) / 16;
-    if (S <= 1) {
-        for (int o = threadIdx.x; o < O; o += kBlock) {
-            const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-            const TA* a = A + b * sAb + m * sAm;
-            const TB* bb = B + b * sBb + n * sBn;
-            TC s = TC(0);
-#pragma unroll 8
-            for (int k = 0; k < K; ++k) s += ld(a, k * sAk) * ld(bb, k * sBk);
-            C[b * sCb + m * sCm + n * sCn] = static_cast<double>(s);
+    const bool cols = N >= M;
+    const int L = cols ? N : M, S = cols ? M : N;
+    const int nch = (S + 7) >> 3;
+    const FDiv dl(L);
+    for (int it = threadIdx.x; it < L * nch; it += kBlock) {
+        int l;
+        const int s0 = dl.div(it, &l) * 8;
+        int sq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sq[q] = min(s0 + q, S - 1);  // clamped: loads stay in range
+        TC acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = TC(0);
+        if (cols) {
+#pragma unroll 4
+            for (int k = 0; k < K; ++k) {
+                const TC b = ld(B, k * sBk + l * sBn);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += ld(A, sq[q] * sAm + k * sAk) * b;
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < K; ++k) {
+                const TC a = ld(A, l * sAm + k * sAk);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += a * ld(B, k * sBk + sq[q] * sBn);
+            }
         }
-        __syncthreads();
-        return;
-    }
-    const int kc = (K + S - 1) / S;
-    const int o = threadIdx.x % O, sl = threadIdx.x / O;
-    if (sl < S) {
-        const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-        const TA* a = A + b * sAb + m * sAm;
-        const TB* bb = B + b * sBb + n * sBn;
-        TC s = TC(0);
-        const int k1 = min(K, (sl + 1) * kc);
-#pragma unroll 8
-        for (int k = sl * kc; k < k1; ++k) s += ld(a, k * sAk) * ld(bb, k * sBk);
-        red[sl * O + o] = static_cast<double>(s);
-    }
-    __syncthreads();
-    if (threadIdx.x < O) {
-        const int n = o % N, mb = o / N, m = mb % M, b = mb / M;
-        double s = 0.0;
-        for (int t = 0; t < S; ++t) s += red[t * O + o];
-        C[b * sCb + m * sCm + n * sCn] = s;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (s0 + q < S) {
+                if (cols) C[(s0 + q) * sCm + l * sCn] = static_cast<double>(acc[q]);
+                else C[l * sCm + (s0 + q) * sCn] = static_cast<double>(acc[q]);
+            }
+        }
     }
     __syncthreads();
 }
@@ -285,11 +293,6 @@ struct FdIO {
     int prec;             // 0 FP64, 1 FP32, 2 BF16 factors
 };
 
-// Owned index set of a block: unknowns whose index along g.big lies in the block.
-__device__ __forceinline__ bool owned_2d(const Grid& g, int blk, int i1, int i2) {
-    const int ib = g.big == 0 ? i1 : i2;
-    return ib >= blk * g.blk && ib < min(g.ni[g.big], (blk + 1) * g.blk);
-}
 
 // Big-direction mode product of one FD block:
 //   C[m][j] = sum_k V(m, k) U(k, c0 + j),  m < msm, j < bsa <= BS, k < K,
@@ -303,16 +306,18 @@ __device__ __forceinline__ bool owned_2d(const Grid& g, int blk, int i1, int i2)
 template <typename TU> struct VecU;
 template <> struct VecU<double> {
     static constexpr int CPL = 2;
-    template <typename TC> __device__ static void load(const double* p, TC* u) {
-        const double2 v = *reinterpret_cast<const double2*>(p);
+    using Raw = double2;
+    __device__ static Raw zero() { return make_double2(0.0, 0.0); }
+    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
         u[0] = static_cast<TC>(v.x);
         u[1] = static_cast<TC>(v.y);
     }
 };
 template <> struct VecU<float> {
     static constexpr int CPL = 4;
-    template <typename TC> __device__ static void load(const float* p, TC* u) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
+    using Raw = float4;
+    __device__ static Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
         u[0] = v.x;
         u[1] = v.y;
         u[2] = v.z;
@@ -321,8 +326,9 @@ template <> struct VecU<float> {
 };
 template <> struct VecU<uint16_t> {
     static constexpr int CPL = 8;
-    template <typename TC> __device__ static void load(const uint16_t* p, TC* u) {
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
+    using Raw = uint4;
+    __device__ static Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
+    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -331,13 +337,196 @@ template <> struct VecU<uint16_t> {
         }
     }
 };
+template <typename TU>
+__device__ __forceinline__ typename VecU<TU>::Raw load_raw(const TU* p) {
+    return *reinterpret_cast<const typename VecU<TU>::Raw*>(p);
+}
 
+// Direct global -> LDS copies (gfx950 global_load_lds): each active lane of
+// a wavefront moves SIZE bytes from its own global address to
+// lds_wave_base + lane * SIZE (SIZE 4 or 16 bytes); lds_wave_base is uniform
+// over the wavefront.
+// The copies bypass registers, so a task issues all of them back to back.
+__device__ __forceinline__ void g2l4(const void* src, void* lds_wave_base) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_wave_base, 4, 0, 0);
+}
+__device__ __forceinline__ void g2l16(const void* src, void* lds_wave_base) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+// Wait for this wavefront's outstanding copies, then for the workgroup.
+__device__ __forceinline__ void g2l_wait_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+// dst[i] = src[i], i < n (FP64 values moved as dwords: 8-byte copies do not exist)
+__device__ __forceinline__ void g2l_vec(const double* src, int n, double* dst) {
+    const int wave = threadIdx.x >> 6, nd = 2 * n;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int base = 0; base < nd; base += kBlock)
+        if (base + static_cast<int>(threadIdx.x) < nd) g2l4(s + base + threadIdx.x, d + base + wave * 64);
+}
+// bytes (a multiple of 16) copied as 16-byte chunks
+__device__ __forceinline__ void g2l_bytes(const void* src, int bytes, void* dst) {
+    const int wave = threadIdx.x >> 6, nc = bytes >> 4;
+    const char* s = static_cast<const char*>(src);
+    char* d = static_cast<char*>(dst);
+    for (int base = 0; base < nc; base += kBlock)
+        if (base + static_cast<int>(threadIdx.x) < nc)
+            g2l16(s + 16 * (base + threadIdx.x), d + 16 * (base + wave * 64));
+}
+
+// Block geometry of FD task blk of a 2D grid.  Owned unknowns (index along
+// the long direction inside the block) are enumerated o < nown in the order
+// of the block outputs: long direction fastest for big == 0, short direction
+// fastest (contiguous) for big == 1.
+struct FdBlock {
+    int n1, n2, n, big, nbig, nsm, k0, bs, nown;
+    bool wide, sbig;
+    FDiv dbs;
+    __device__ explicit FdBlock(const Grid& g, int blk)
+        : n1(g.ni[0]), n2(g.ni[1]), n(g.ni[0] * g.ni[1]), big(g.big), nbig(g.ni[g.big]), nsm(g.ni[1 - g.big]),
+          k0(blk * g.blk), bs(min(g.blk, g.ni[g.big] - blk * g.blk)), nown(0), wide(g.nblk > 1),
+          sbig(g.nblk <= 1 && g.fdstage != 0), dbs(min(g.blk, g.ni[g.big] - blk * g.blk)) {
+        nown = nsm * bs;
+    }
+    __device__ __forceinline__ int gi(int o) const {
+        if (big == 0) {
+            int kk;
+            const int i2 = dbs.div(o, &kk);
+            return i2 * n1 + k0 + kk;
+        }
+        return k0 * n1 + o;
+    }
+};
+// owned gather: dst[o] = src[gi(o)], o < nown (as dwords)
+__device__ __forceinline__ void g2l_owned(const double* src, const FdBlock& B, double* dst) {
+    const int wave = threadIdx.x >> 6, nd = 2 * B.nown;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int base = 0; base < nd; base += kBlock) {
+        const int w = base + threadIdx.x;
+        if (w < nd) g2l4(s + 2 * B.gi(w >> 1) + (w & 1), d + base + wave * 64);
+    }
+}
+
+// LDS pointers of an FD task for factor element type TU.
+template <typename TU>
+struct FdLds {
+    double *R, *S, *red, *Out, *Own;
+    TU *Us, *Ub;
+    typename VecU<TU>::Raw* Slab;
+    int rows, ldu_s, ldu_b;
+};
+template <typename TU>
+__device__ __forceinline__ FdLds<TU> fd_lds(const TaskMeta& M, double* lds) {
+    const Grid& g = M.g;
+    const int ls = M.t[1 - g.big].ldu, lb = M.t[g.big].ldu;
+    const FdLayout Y = fd_layout(g, ls, lb, sizeof(TU));
+    char* base = reinterpret_cast<char*>(lds);
+    FdLds<TU> L;
+    L.R = reinterpret_cast<double*>(base + Y.R);
+    L.S = reinterpret_cast<double*>(base + Y.S);
+    L.red = reinterpret_cast<double*>(base + Y.red);
+    L.Out = reinterpret_cast<double*>(base + Y.Out);
+    L.Own = reinterpret_cast<double*>(base + Y.Own);
+    L.Us = reinterpret_cast<TU*>(base + Y.Us);
+    L.Ub = reinterpret_cast<TU*>(base + Y.Ub);
+    L.Slab = reinterpret_cast<typename VecU<TU>::Raw*>(base + Y.Slab);
+    L.rows = Y.rows;
+    L.ldu_s = ls;
+    L.ldu_b = lb;
+    return L;
+}
+
+template <typename TU>
+__device__ __forceinline__ void fd_factor_ptrs(const Params& P, const TaskMeta& M, bool fwd, const TU** Us,
+                                               const TU** Ub, const TU** Ubig) {
+    // forward: short factor transposed (big == 0: UT2; big == 1: U1), long factor U (block columns);
+    // backward: short factor (big == 0: U2; big == 1: UT1), long factor U^T (block columns);
+    // single-block long factor as consumed by the second product
+    const Tab1D& T1 = M.t[0];
+    const Tab1D& T2 = M.t[1];
+    if (M.g.big == 0) {
+        *Us = u_ptr<TU>(P, T2, fwd);
+        *Ub = u_ptr<TU>(P, T1, !fwd);
+        *Ubig = u_ptr<TU>(P, T1, !fwd);
+    } else {
+        *Us = u_ptr<TU>(P, T1, !fwd);
+        *Ub = u_ptr<TU>(P, T2, fwd);
+        *Ubig = u_ptr<TU>(P, T2, !fwd);
+    }
+}
+
+// Issue the copies of the factors an FD task reads: the short-direction
+// factor, the long one of a single-block grid, the slab of a blocked grid.
+template <typename TU>
+__device__ __forceinline__ void fd_issue_factors(const Params& P, const TaskMeta& M, const FdBlock& B, bool fwd,
+                                                 const FdLds<TU>& L) {
+    const TU *Us, *Ub, *Ubig;
+    fd_factor_ptrs<TU>(P, M, fwd, &Us, &Ub, &Ubig);
+    g2l_bytes(Us, B.nsm * L.ldu_s * static_cast<int>(sizeof(TU)), L.Us);
+    if (B.sbig) g2l_bytes(Ub, B.nbig * L.ldu_b * static_cast<int>(sizeof(TU)), L.Ub);
+    if (B.wide) {
+        constexpr int CPL = VecU<TU>::CPL;
+        const int lpr = M.g.blk / CPL;  // lanes per row segment (power of two)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int rpw = 64 / lpr, rpt = 4 * rpw;
+        const int jc = (lane & (lpr - 1)) * CPL;
+        const int r0 = wave * rpw + lane / lpr;
+        if (jc < B.bs) {
+            const TU* ub = Ubig + B.k0 + jc;
+            for (int s = 0; s < L.rows; ++s) {
+                const int k = r0 + s * rpt;
+                if (k < B.nbig) g2l16(ub + static_cast<int64_t>(k) * L.ldu_b, L.Slab + s * kBlock + wave * 64);
+            }
+        }
+    }
+}
+
+// Issue the copies of a forward task: r (and q) over the grid, owned p, d and
+// 1 / lambda, the factors.
+template <typename TU>
+__device__ __forceinline__ void fd_issue_fwd(const Params& P, const TaskMeta& M, int blk, const double* r_src,
+                                             const double* q_src, const double* p_src, const double* d_src,
+                                             double* lds) {
+    const Grid& g = M.g;
+    const FdBlock B(g, blk);
+    const FdLds<TU> L = fd_lds<TU>(M, lds);
+    const int64_t off = g.dof_off;
+    g2l_vec(r_src + off, B.n, L.R);
+    if (q_src) g2l_vec(q_src + off, B.n, L.S);
+    if (p_src) g2l_owned(p_src + off, B, L.Own);
+    if (d_src) g2l_owned(d_src + off, B, L.Own + B.nown);
+    g2l_owned(P.dpool + g.oDinv, B, L.Own + 2 * B.nown);
+    fd_issue_factors<TU>(P, M, B, true, L);
+}
+
+template <typename TU>
+__device__ __forceinline__ void fd_issue_bwd(const Params& P, const TaskMeta& M, int blk, const double* rt_src,
+                                             const double* rdot, double* lds) {
+    const Grid& g = M.g;
+    const FdBlock B(g, blk);
+    const FdLds<TU> L = fd_lds<TU>(M, lds);
+    const int64_t off = g.dof_off;
+    g2l_vec(rt_src + off, B.n, L.R);
+    if (rdot) g2l_owned(rdot + off, B, L.Own);
+    fd_issue_factors<TU>(P, M, B, false, L);
+}
+
+// Long-direction product of a blocked grid from the LDS slab:
+//   C[m][j] = sum_k V(m, k) U(k, k0 + j), m < msm, j < bsa, k < K,
+// V(m,k) = V[m*sVm + k*sVk].  Thread (lane, wave) holds column group
+// jc = (lane % LPR) * CPL of rows r0 + s * RPT; partial sums over a chunk of MMC
+// rows of V are reduced by a fixed butterfly over the lanes of a column group
+// and a fixed-order sum over the four wavefronts (deterministic).
 template <int BS, typename TU, typename TC>
-__device__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int sVk, const TU* U, int64_t ldu,
-                         int c0, double* red, double* C, int sCm, int sCj) {
+__device__ __forceinline__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int sVk,
+                                         const typename VecU<TU>::Raw* slab, double* red, double* C, int sCm,
+                                         int sCj) {
     constexpr int CPL = VecU<TU>::CPL;
     constexpr int LPR = BS / CPL;  // lanes per row segment
-    constexpr int RPW = 64 / LPR;  // rows per wavefront load
+    constexpr int RPW = 64 / LPR;  // rows per wavefront copy
     constexpr int RPT = 4 * RPW;   // rows per workgroup pass
     constexpr int ACC = (sizeof(TC) == 8 ? 32 : 64) / CPL;
     constexpr int MMC = ACC < kBigRed / (4 * BS) ? ACC : kBigRed / (4 * BS);
@@ -346,7 +535,7 @@ __device__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int 
     const int jc = (lane % LPR) * CPL;
     const int r0 = wave * RPW + lane / LPR;
     const bool live = jc < bsa;
-    const TU* ub = U + c0 + jc;
+    const int rows = (K + RPT - 1) / RPT;
     for (int m0 = 0; m0 < msm; m0 += MMC) {
         const int mc = min(MMC, msm - m0);
         TC acc[MMC][CPL];
@@ -355,29 +544,34 @@ __device__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int 
 #pragma unroll
             for (int j = 0; j < CPL; ++j) acc[m][j] = TC(0);
         if (live) {
-#pragma unroll 4
-            for (int k = r0; k < K; k += RPT) {
-                TC u[CPL];
-                VecU<TU>::load(ub + static_cast<int64_t>(k) * ldu, u);
-                const double* vk = V + static_cast<int64_t>(m0) * sVm + static_cast<int64_t>(k) * sVk;
+#pragma unroll 2
+            for (int s = 0; s < rows; ++s) {
+                const int k = r0 + s * RPT;
+                if (k < K) {
+                    TC u[CPL];
+                    VecU<TU>::unpack(slab[s * kBlock + threadIdx.x], u);
+                    const double* vk = V + static_cast<int64_t>(m0) * sVm + static_cast<int64_t>(k) * sVk;
 #pragma unroll
-                for (int m = 0; m < MMC; ++m) {
-                    if (m < mc) {
-                        const TC v = static_cast<TC>(vk[m * sVm]);
+                    for (int m = 0; m < MMC; ++m) {
+                        if (m < mc) {
+                            const TC v = static_cast<TC>(vk[m * sVm]);
 #pragma unroll
-                        for (int j = 0; j < CPL; ++j) acc[m][j] += v * u[j];
+                            for (int j = 0; j < CPL; ++j) acc[m][j] += v * u[j];
+                        }
                     }
                 }
             }
         }
 #pragma unroll
         for (int m = 0; m < MMC; ++m) {
+            if (m < mc) {  // uniform: only the rows of V in use are reduced
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-                double v = static_cast<double>(acc[m][j]);
+                for (int j = 0; j < CPL; ++j) {
+                    TC v = acc[m][j];
 #pragma unroll
-                for (int sft = LPR; sft < 64; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                if (lane < LPR && m < mc) red[(wave * MMC + m) * BS + jc + j] = v;
+                    for (int sft = LPR; sft < 64; sft <<= 1) v += __shfl_xor(v, sft, 64);
+                    if (lane < LPR) red[(wave * MMC + m) * BS + jc + j] = static_cast<double>(v);
+                }
             }
         }
         __syncthreads();
@@ -396,191 +590,147 @@ __device__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int 
 // Dispatch on the block width BS of the grid (8, 16 or 32 columns).
 template <typename TU, typename TC>
 __device__ __forceinline__ void fd_big(int BS, int K, int msm, int bsa, const double* V, int sVm, int sVk,
-                                       const TU* U, int64_t ldu, int c0, double* red, double* C, int sCm, int sCj) {
-    if (BS <= 8) fd_big_t<8, TU, TC>(K, msm, bsa, V, sVm, sVk, U, ldu, c0, red, C, sCm, sCj);
-    else if (BS <= 16) fd_big_t<16, TU, TC>(K, msm, bsa, V, sVm, sVk, U, ldu, c0, red, C, sCm, sCj);
-    else fd_big_t<32, TU, TC>(K, msm, bsa, V, sVm, sVk, U, ldu, c0, red, C, sCm, sCj);
+                                       const typename VecU<TU>::Raw* slab, double* red, double* C, int sCm,
+                                       int sCj) {
+    if (BS <= 8) fd_big_t<8, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
+    else if (BS <= 16) fd_big_t<16, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
+    else fd_big_t<32, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
 }
 
-// Cooperative copy of an n x n U factor (row stride ldu) into LDS as dense FP64.
-template <typename TU>
-__device__ __forceinline__ void stage_factor(double* dst, const TU* src, int n, int ldu) {
-    for (int i = threadIdx.x; i < n * n; i += kBlock) dst[i] = static_cast<double>(load_val(src, (i / n) * ldu + i % n));
-}
-
-// LDS layout of an FD task: R (n) | S (n) | red (kBigRed) | Out | Us | Ub
-struct FdLds {
-    double *R, *S, *red, *Out, *Us, *Ub;
-};
-__device__ __forceinline__ FdLds fd_lds(const Grid& g, double* lds) {
-    const int n = g.ni[0] * g.ni[1];
-    const int nsm = g.ni[1 - g.big];
-    FdLds L;
-    L.R = lds;
-    L.S = lds + n;
-    L.red = L.S + n;
-    L.Out = L.red + kBigRed;
-    L.Us = L.Out + (g.nblk > 1 ? nsm * g.blk : n);
-    L.Ub = L.Us + nsm * nsm;
-    return L;
-}
-
-// Forward transform of one FD block: Rt = (U1 (x) U2)^T r scaled by the
-// inverse eigenvalue sums, for the block of the long direction.  The short
-// direction's factor (and, for single-block grids, the long one when it fits)
-// is staged in LDS first; blocked long directions stream their factor rows.
+// Forward transform of one FD block, after fd_issue_fwd and g2l_wait_sync:
+//   r = r_old - alpha q (grid, LDS), owned: r_out = r, d += alpha p,
+//   part = ||r_owned||^2, Rt = (U1 (x) U2)^T r on the block times 1 / lambda.
 template <typename TU, typename TC>
-__device__ __forceinline__ void fd_fwd_2d(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    const int n1 = g.ni[0], n2 = g.ni[1], n = n1 * n2;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
-    const int ld1 = T1.ldu, ld2 = T2.ldu;
-    const FdLds L = fd_lds(g, lds);
-    const bool wide = g.nblk > 1, sbig = !wide && g.fdstage;
+__device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, int blk, const FdIO& io,
+                                           double* lds) {
+    const Grid& g = M.g;
+    const FdBlock B(g, blk);
+    const FdLds<TU> L = fd_lds<TU>(M, lds);
     const int64_t off = g.dof_off;
+    const int n1 = B.n1, n2 = B.n2;
+    const TU *Us, *Ub, *Ubig;
+    fd_factor_ptrs<TU>(P, M, true, &Us, &Ub, &Ubig);
+    if (io.q)
+        for (int i = threadIdx.x; i < B.n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
+    __syncthreads();
+    const double* Pw = L.Own;
+    const double* Dw = L.Own + B.nown;
+    const double* Iw = L.Own + 2 * B.nown;
     double nrm = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-        double v = io.r_old[off + i];
-        if (io.q) v -= io.alpha * io.q[off + i];
-        L.R[i] = v;
-        const int i1 = i % n1, i2 = i / n1;
-        if (owned_2d(g, blk, i1, i2)) {
-            if (io.r_out) io.r_out[off + i] = v;
-            if (io.dvec) io.dvec[off + i] += io.alpha * io.pvec[off + i];
-            nrm += v * v;
-        }
-    }
-    if (g.big == 0) {
-        stage_factor(L.Us, u_ptr<TU>(P, T2, true), n2, ld2);
-        if (sbig) stage_factor(L.Ub, u_ptr<TU>(P, T1, false), n1, ld1);
-    } else {
-        stage_factor(L.Us, u_ptr<TU>(P, T1, false), n1, ld1);
-        if (sbig) stage_factor(L.Ub, u_ptr<TU>(P, T2, true), n2, ld2);
+    for (int o = threadIdx.x; o < B.nown; o += kBlock) {
+        const int gi = B.gi(o);
+        const double v = L.R[gi];
+        if (io.r_out) io.r_out[off + gi] = v;
+        if (io.dvec) io.dvec[off + gi] = Dw[o] + io.alpha * Pw[o];
+        nrm += v * v;
     }
     if (io.part) {
-        double t = wg_sum(nrm, L.red);
+        const double t = wg_sum(nrm, L.red);
         if (threadIdx.x == 0) *io.part = t;
     }
     __syncthreads();
-    const int k0 = blk * g.blk;
-    const int bs = min(g.blk, g.ni[g.big] - k0);
-    const double* lam1 = P.dpool + T1.oLam;
-    const double* lam2 = P.dpool + T2.oLam;
-    if (g.big == 0) {
+    const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
+    if (B.big == 0) {
         // S[k2][i1] = sum_i2 UT2[k2][i2] R[i2][i1]
-        wg_gemm<double, double, TC>(1, n2, n1, n2, L.Us, 0, n2, 1, L.R, 0, n1, 1, L.S, 0, n1, 1, L.red);
+        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1);
         // Rt[k2][k1] = sum_i1 S[k2][i1] U1[i1][k1], k1 in block
-        if (wide)
-            fd_big<TU, TC>(g.blk, n1, n2, bs, L.S, n1, 1, u_ptr<TU>(P, T1, false), ld1, k0, L.red, L.Out, bs, 1);
-        else if (sbig)
-            wg_gemm<double, double, TC>(1, n2, bs, n1, L.S, 0, n1, 1, L.Ub + k0, 0, n1, 1, L.Out, 0, bs, 1, L.red);
+        if (B.wide)
+            fd_big<TU, TC>(g.blk, n1, n2, bs, L.S, n1, 1, L.Slab, L.red, L.Out, bs, 1);
+        else if (B.sbig)
+            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
         else
-            wg_gemm<double, TU, TC>(1, n2, bs, n1, L.S, 0, n1, 1, u_ptr<TU>(P, T1, false) + k0, 0, ld1, 1, L.Out,
-                                    0, bs, 1, L.red);
-        for (int o = threadIdx.x; o < n2 * bs; o += kBlock) {
-            const int k2 = o / bs, kk = o % bs, k1 = k0 + kk;
-            io.rt[off + static_cast<int64_t>(k2) * n1 + k1] = L.Out[o] / (g.fdc[0] * lam1[k1] + g.fdc[1] * lam2[k2]);
-        }
+            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
     } else {
         // S[i2][k1] = sum_i1 R[i2][i1] U1[i1][k1]
-        wg_gemm<double, double, TC>(1, n2, n1, n1, L.R, 0, n1, 1, L.Us, 0, n1, 1, L.S, 0, n1, 1, L.red);
+        small_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1);
         // Rt[k2][k1] = sum_i2 U2[i2][k2] S[i2][k1], k2 in block
-        if (wide)
-            fd_big<TU, TC>(g.blk, n2, n1, bs, L.S, 1, n1, u_ptr<TU>(P, T2, false), ld2, k0, L.red, L.Out, 1, n1);
-        else if (sbig)
-            wg_gemm<double, double, TC>(1, bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * n2, 0, n2, 1, L.S, 0, n1,
-                                        1, L.Out, 0, n1, 1, L.red);
+        if (B.wide)
+            fd_big<TU, TC>(g.blk, n2, n1, bs, L.S, 1, n1, L.Slab, L.red, L.Out, 1, n1);
+        else if (B.sbig)
+            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
         else
-            wg_gemm<TU, double, TC>(1, bs, n1, n2, u_ptr<TU>(P, T2, true) + static_cast<int64_t>(k0) * ld2, 0, ld2,
-                                    1, L.S, 0, n1, 1, L.Out, 0, n1, 1, L.red);
-        for (int o = threadIdx.x; o < bs * n1; o += kBlock) {
-            const int kk = o / n1, k1 = o % n1, k2 = k0 + kk;
-            io.rt[off + static_cast<int64_t>(k2) * n1 + k1] = L.Out[o] / (g.fdc[0] * lam1[k1] + g.fdc[1] * lam2[k2]);
-        }
+            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
     }
+    for (int o = threadIdx.x; o < B.nown; o += kBlock) io.rt[off + B.gi(o)] = L.Out[o] * Iw[o];
     __syncthreads();
 }
 
-// Backward transform of one FD block: z = (U1 (x) U2) Rt on the block.
+// Backward transform of one FD block, after fd_issue_bwd and g2l_wait_sync:
+// z = (U1 (x) U2) Rt on the block; part = rdot . z over the block.
 template <typename TU, typename TC>
-__device__ __forceinline__ void fd_bwd_2d(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    const int n1 = g.ni[0], n2 = g.ni[1], n = n1 * n2;
-    const Tab1D& T1 = P.tabs[g.tab[0]];
-    const Tab1D& T2 = P.tabs[g.tab[1]];
-    const int ld1 = T1.ldu, ld2 = T2.ldu;
-    const FdLds L = fd_lds(g, lds);
-    const bool wide = g.nblk > 1, sbig = !wide && g.fdstage;
+__device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, int blk, const FdIO& io,
+                                           double* lds) {
+    const Grid& g = M.g;
+    const FdBlock B(g, blk);
+    const FdLds<TU> L = fd_lds<TU>(M, lds);
+    const int64_t off = g.dof_off;
+    const int n1 = B.n1, n2 = B.n2;
+    const TU *Us, *Ub, *Ubig;
+    fd_factor_ptrs<TU>(P, M, false, &Us, &Ub, &Ubig);
     double* Rt = L.R;
     double* Tm = L.S;
-    const int64_t off = g.dof_off;
-    for (int i = threadIdx.x; i < n; i += kBlock) Rt[i] = io.rt[off + i];
-    if (g.big == 0) {
-        stage_factor(L.Us, u_ptr<TU>(P, T2, false), n2, ld2);
-        if (sbig) stage_factor(L.Ub, u_ptr<TU>(P, T1, true), n1, ld1);
-    } else {
-        stage_factor(L.Us, u_ptr<TU>(P, T1, true), n1, ld1);
-        if (sbig) stage_factor(L.Ub, u_ptr<TU>(P, T2, false), n2, ld2);
-    }
-    __syncthreads();
-    const int k0 = blk * g.blk;
-    const int bs = min(g.blk, g.ni[g.big] - k0);
-    double dot = 0.0;
-    if (g.big == 0) {
+    const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
+    if (B.big == 0) {
         // T[i2][k1] = sum_k2 U2[i2][k2] Rt[k2][k1]
-        wg_gemm<double, double, TC>(1, n2, n1, n2, L.Us, 0, n2, 1, Rt, 0, n1, 1, Tm, 0, n1, 1, L.red);
+        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1);
         // Z[i2][i1] = sum_k1 T[i2][k1] UT1[k1][i1], i1 in block
-        if (wide)
-            fd_big<TU, TC>(g.blk, n1, n2, bs, Tm, n1, 1, u_ptr<TU>(P, T1, true), ld1, k0, L.red, L.Out, bs, 1);
-        else if (sbig)
-            wg_gemm<double, double, TC>(1, n2, bs, n1, Tm, 0, n1, 1, L.Ub + k0, 0, n1, 1, L.Out, 0, bs, 1, L.red);
+        if (B.wide)
+            fd_big<TU, TC>(g.blk, n1, n2, bs, Tm, n1, 1, L.Slab, L.red, L.Out, bs, 1);
+        else if (B.sbig)
+            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
         else
-            wg_gemm<double, TU, TC>(1, n2, bs, n1, Tm, 0, n1, 1, u_ptr<TU>(P, T1, true) + k0, 0, ld1, 1, L.Out, 0,
-                                    bs, 1, L.red);
-        for (int o = threadIdx.x; o < n2 * bs; o += kBlock) {
-            const int i2 = o / bs, i1 = k0 + o % bs;
-            const int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-            io.z[gi] = L.Out[o];
-            if (io.rdot) dot += io.rdot[gi] * L.Out[o];
-        }
+            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
     } else {
         // T[k2][i1] = sum_k1 Rt[k2][k1] UT1[k1][i1]
-        wg_gemm<double, double, TC>(1, n2, n1, n1, Rt, 0, n1, 1, L.Us, 0, n1, 1, Tm, 0, n1, 1, L.red);
+        small_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1);
         // Z[i2][i1] = sum_k2 UT2[k2][i2] T[k2][i1], i2 in block
-        if (wide)
-            fd_big<TU, TC>(g.blk, n2, n1, bs, Tm, 1, n1, u_ptr<TU>(P, T2, true), ld2, k0, L.red, L.Out, 1, n1);
-        else if (sbig)
-            wg_gemm<double, double, TC>(1, bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * n2, 0, n2, 1, Tm, 0, n1, 1,
-                                        L.Out, 0, n1, 1, L.red);
+        if (B.wide)
+            fd_big<TU, TC>(g.blk, n2, n1, bs, Tm, 1, n1, L.Slab, L.red, L.Out, 1, n1);
+        else if (B.sbig)
+            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
         else
-            wg_gemm<TU, double, TC>(1, bs, n1, n2, u_ptr<TU>(P, T2, false) + static_cast<int64_t>(k0) * ld2, 0, ld2,
-                                    1, Tm, 0, n1, 1, L.Out, 0, n1, 1, L.red);
-        for (int o = threadIdx.x; o < bs * n1; o += kBlock) {
-            const int i2 = k0 + o / n1, i1 = o % n1;
-            const int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
-            io.z[gi] = L.Out[o];
-            if (io.rdot) dot += io.rdot[gi] * L.Out[o];
-        }
+            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
+    }
+    double dot = 0.0;
+    const double* Rd = L.Own;
+    for (int o = threadIdx.x; o < B.nown; o += kBlock) {
+        const int64_t gi = off + B.gi(o);
+        io.z[gi] = L.Out[o];
+        if (io.rdot) dot += Rd[o] * L.Out[o];
     }
     if (io.part) {
-        double t = wg_sum(dot, L.red);
+        const double t = wg_sum(dot, L.red);
         if (threadIdx.x == 0) *io.part = t;
     }
     __syncthreads();
 }
 
-// FD transforms for a factor precision fixed at compile time
-// (0: FP64 factors, 1: FP32 factors, 2: BF16 factors with FP32 accumulation).
-template <int FDP>
-__device__ __forceinline__ void fd_fwd_p(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    if constexpr (FDP == 0) fd_fwd_2d<double, double>(P, g, blk, io, lds);
-    else if constexpr (FDP == 1) fd_fwd_2d<float, float>(P, g, blk, io, lds);
-    else fd_fwd_2d<uint16_t, float>(P, g, blk, io, lds);
-}
-template <int FDP>
-__device__ __forceinline__ void fd_bwd_p(const Params& P, const Grid& g, int blk, const FdIO& io, double* lds) {
-    if constexpr (FDP == 0) fd_bwd_2d<double, double>(P, g, blk, io, lds);
-    else if constexpr (FDP == 1) fd_bwd_2d<float, float>(P, g, blk, io, lds);
-    else fd_bwd_2d<uint16_t, float>(P, g, blk, io, lds);
+// Factor element types of the FD precisions
+// (0: FP64, 1: FP32, 2: BF16 factors with FP32 accumulation).
+template <int FDP> struct FdTypes;
+template <> struct FdTypes<0> { using TU = double; using TC = double; };
+template <> struct FdTypes<1> { using TU = float; using TC = float; };
+template <> struct FdTypes<2> { using TU = uint16_t; using TC = float; };
+
+// Copy the description of task tk into an LDS slot (all threads; ends synchronised).
+__device__ __forceinline__ void meta_fill(const Params& P, const Task& tk, TaskMeta* M) {
+    __syncthreads();
+    constexpr int GW = sizeof(Grid) / 8, TW = sizeof(Tab1D) / 8;
+    const uint64_t* gsrc = reinterpret_cast<const uint64_t*>(P.grids + tk.grid);
+    uint64_t* gdst = reinterpret_cast<uint64_t*>(&M->g);
+    for (int i = threadIdx.x; i < GW; i += kBlock) gdst[i] = gsrc[i];
+    if (threadIdx.x == 0) {
+        M->grid = tk.grid;
+        M->local = tk.local;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * TW; i += kBlock) {
+        const int k = i / TW, w = i % TW;
+        const int ti = M->g.tab[k];
+        uint64_t* tdst = reinterpret_cast<uint64_t*>(&M->t[k]);
+        tdst[w] = ti >= 0 ? reinterpret_cast<const uint64_t*>(P.tabs + ti)[w] : 0ull;
+    }
+    __syncthreads();
 }
 
 // ===========================================================================
@@ -609,9 +759,9 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nwg) {
 //
 // One sweep = three phases separated by grid-wide barriers:
 //   1 operator   ITER: p = z + beta p, q = A p (inner precision), p.q
-//                RESID: r = b - A x (FP64), ||r||^2
+//                RESID: r = b - A (x + d) (FP64), ||r||^2
 //   2 update     ITER: alpha, d += alpha p, r -= alpha q, FD forward of r
-//                XUPD: x += d, d = 0;  RESID: FD forward of r
+//                RESID: x += d, d = 0, FD forward of r
 //   3 commit     FD backward -> z, r.z; next state written by block 0
 // Convergence tests use the preconditioned residual r.P^-1 r (relative to
 // b.P^-1 b for the FP64 outer test, to its value at the start of an inner
@@ -623,6 +773,7 @@ struct SolveArgs {
     int ndone_target;             // grids in this launch
     int prec;                     // inner precision (IGA_PREC_*)
     int maxit, max_refine, max_sweeps;
+    int continue_cg;              // keep the search direction across residual replacements
     double tol2, tol_in2;
     unsigned long long* trace;    // phase timestamps (or nullptr)
     int trace_sweeps;
@@ -644,7 +795,7 @@ __device__ __forceinline__ double* part_ptr(const Params& P, int kind, int parit
     return P.part + static_cast<int64_t>(kind * 2 + parity) * P.part_stride;
 }
 enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3 };
-enum { ACT_SKIP = 0, ACT_RESID, ACT_ITER, ACT_XUPD, ACT_DONE };
+enum { ACT_SKIP = 0, ACT_RESID, ACT_ITER, ACT_DONE };
 
 struct Decision {
     int act, status;
@@ -670,8 +821,6 @@ __device__ inline Decision decide(const SolveArgs& A, const GState& st, double r
         D.act = ACT_SKIP;
     } else if (st.stage == STAGE_RESID) {
         D.act = ACT_RESID;
-    } else if (st.stage == STAGE_XUPD) {
-        D.act = ACT_XUPD;
     } else if (!isfinite(rho) || rho < 0.0) {
         D.act = ACT_DONE;
         D.status = GS_BREAKDOWN;
@@ -688,8 +837,10 @@ __device__ inline Decision decide(const SolveArgs& A, const GState& st, double r
             D.act = ACT_ITER;
             D.rho0 = rho;
         }
-    } else if (rho <= A.tol_in2 * st.rho0 || st.it >= A.maxit) {
-        D.act = ACT_XUPD;
+    } else if (rho <= A.tol_in2 * st.rho0 || rho <= A.tol2 * st.rhob || st.it >= A.maxit) {
+        // inner solve done (its own tolerance, or the outer target reached by the
+        // recursive residual): x += d and replace r by the FP64 residual
+        D.act = ACT_RESID;
     } else {
         D.act = ACT_ITER;
     }
@@ -704,52 +855,89 @@ struct TaskCtx {
     double pq;    // p.Ap of the current iteration (phases 2-3)
     double rn2;   // ||b - A x||^2 of a residual sweep (phase 3)
 };
-constexpr int kCtxDoubles = 32;  // LDS slots reserved for TaskCtx
-static_assert(sizeof(TaskCtx) <= kCtxDoubles * sizeof(double), "TaskCtx too large");
+static_assert(sizeof(TaskCtx) <= kCtxBytes, "TaskCtx too large");
 
-__device__ __forceinline__ void task_context(const Params& P, const SolveArgs& A, const Grid& g,
-                                             const GState* S0, int gi, int cur, int nxt, int phase,
-                                             TaskCtx* ctx) {
-    __syncthreads();  // previous users of the LDS context are done
-    if (threadIdx.x < 64) {
-        // every load is issued before any is used: one memory round trip
-        const GState st = S0[gi];
-        const int lane = threadIdx.x;
-        double vrz = 0.0, vpq = 0.0, vres = 0.0;
-        const double* prz = part_ptr(P, PK_RZ, nxt) + g.blk_off;
-        const double* ppq = part_ptr(P, PK_PQ, cur) + g.tile_off;
-        const double* pres = part_ptr(P, PK_RES, cur) + g.tile_off;
-        for (int i = lane; i < g.nblk; i += 64) vrz += prz[i];
-        if (phase >= 2)
-            for (int i = lane; i < g.ntile; i += 64) {
-                vpq += ppq[i];
-                vres += pres[i];
-            }
-        for (int o = 32; o > 0; o >>= 1) {
-            vrz += __shfl_xor(vrz, o, 64);
-            vpq += __shfl_xor(vpq, o, 64);
-            vres += __shfl_xor(vres, o, 64);
-        }
-        const Decision D = decide(A, st, st.stage == STAGE_ITER ? vrz : 0.0);
-        if (threadIdx.x == 0) {
-            ctx->st = st;
-            ctx->D = D;
-            ctx->pq = (phase >= 2 && D.act == ACT_ITER) ? vpq : 0.0;
-            ctx->rn2 = (phase == 3 && D.act == ACT_RESID) ? vres : 0.0;
-        }
+// Wavefront-0 registers of a task context between issue and finish.
+struct CtxLoads {
+    GState st;
+    double vrz, vpq, vres;
+};
+
+__device__ __forceinline__ double sum_strided(const double* p, int count) {
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = lane + 64 * s;
+        if (i < count) v += p[i];
     }
-    __syncthreads();
+    for (int i = lane + 256; i < count; i += 64) v += p[i];
+    return v;
+}
+
+// Issue the loads of a task context (wavefront 0 only): the grid state and
+// the partial sums of the previous phases.
+__device__ __forceinline__ void ctx_issue(const Params& P, const Grid& g, const GState* S0, int gi, int cur, int nxt,
+                                          int phase, CtxLoads& c) {
+    c.st = S0[gi];
+    c.vrz = sum_strided(part_ptr(P, PK_RZ, nxt) + g.blk_off, g.nblk);
+    c.vpq = 0.0;
+    c.vres = 0.0;
+    if (phase >= 2) {
+        c.vpq = sum_strided(part_ptr(P, PK_PQ, cur) + g.tile_off, g.ntile);
+        c.vres = sum_strided(part_ptr(P, PK_RES, cur) + g.tile_off, g.ntile);
+    }
+}
+
+// Reduce and decide (wavefront 0 only); lane 0 writes the context to LDS.
+__device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int phase, TaskCtx* ctx) {
+    for (int o = 32; o > 0; o >>= 1) {
+        c.vrz += __shfl_xor(c.vrz, o, 64);
+        c.vpq += __shfl_xor(c.vpq, o, 64);
+        c.vres += __shfl_xor(c.vres, o, 64);
+    }
+    const Decision D = decide(A, c.st, c.st.stage == STAGE_ITER ? c.vrz : 0.0);
+    if (threadIdx.x == 0) {
+        ctx->st = c.st;
+        ctx->D = D;
+        ctx->pq = (phase >= 2 && D.act == ACT_ITER) ? c.vpq : 0.0;
+        ctx->rn2 = (phase == 3 && D.act == ACT_RESID) ? c.vres : 0.0;
+    }
 }
 
 template <int PP, int FDP>
 __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
+    using TU = typename FdTypes<FDP>::TU;
+    using TC = typename FdTypes<FDP>::TC;
     extern __shared__ double lds_all[];
     TaskCtx* ctx = reinterpret_cast<TaskCtx*>(lds_all);
-    double* lds = lds_all + kCtxDoubles;  // task work arrays
+    TaskMeta* meta = reinterpret_cast<TaskMeta*>(reinterpret_cast<char*>(lds_all) + kCtxBytes);
+    TaskMeta* meta_op = meta;             // kMetaOp slots
+    TaskMeta* meta_fd = meta + kMetaOp;   // kMetaFd slots
+    TaskMeta* meta_sp = meta + kMetaSlots - 1;
+    double* lds = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + kSolveLdsHead);  // task work arrays
     const unsigned nwg = gridDim.x;
     const int64_t N = P.ndof_total;
     const int lowp = FDP != 0;
+    const bool wave0 = threadIdx.x < 64;
     if (A.trace && blockIdx.x == 0 && threadIdx.x == 0) A.trace[0] = wall_clock64();
+    // cache the descriptions of this workgroup's tasks
+    {
+        int k = 0;
+        for (int t = A.op_b + blockIdx.x; t < A.op_e && k < kMetaOp; t += nwg, ++k) meta_fill(P, P.optask[t], meta_op + k);
+        k = 0;
+        for (int t = A.fd_b + blockIdx.x; t < A.fd_e && k < kMetaFd; t += nwg, ++k) meta_fill(P, P.fdtask[t], meta_fd + k);
+    }
+    auto op_meta = [&](int t, int k) -> const TaskMeta& {
+        if (k < kMetaOp) return meta_op[k];
+        meta_fill(P, P.optask[t], meta_sp);
+        return *meta_sp;
+    };
+    auto fd_meta = [&](int t, int k) -> const TaskMeta& {
+        if (k < kMetaFd) return meta_fd[k];
+        meta_fill(P, P.fdtask[t], meta_sp);
+        return *meta_sp;
+    };
     for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
         const int cur = sweep & 1, nxt = cur ^ 1;
         unsigned long long tb = A.trace ? wall_clock64() : 0ull;
@@ -760,65 +948,71 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         double* p_new = P.p2 + cur * N;
         double* p_old = P.p2 + nxt * N;
         // ---------------- phase 1: operator -------------------------------------
-        for (int t = A.op_b + blockIdx.x; t < A.op_e; t += nwg) {
-            const Task tk = P.optask[t];
-            const Grid& g = P.grids[tk.grid];
-            task_context(P, A, g, S0, tk.grid, cur, nxt, 1, ctx);
+        for (int t = A.op_b + blockIdx.x, k = 0; t < A.op_e; t += nwg, ++k) {
+            const TaskMeta& M = op_meta(t, k);
+            const Grid& g = M.g;
+            __syncthreads();  // the previous task is done with the LDS context
+            if (wave0) {
+                CtxLoads c;
+                ctx_issue(P, g, S0, M.grid, cur, nxt, 1, c);
+                ctx_finish(A, c, 1, ctx);
+            }
+            __syncthreads();
             const int act = ctx->D.act;
             if (act == ACT_SKIP) {
-                if (tk.local == 0 && threadIdx.x == 0) S1[tk.grid] = ctx->st;  // carry DONE forward
+                if (M.local == 0 && threadIdx.x == 0) S1[M.grid] = ctx->st;  // carry DONE forward
                 continue;
             }
             OpIO io;
             if (act == ACT_ITER) {
                 io.in_a = P.z;
                 io.in_b = p_old;
-                io.beta = ctx->st.it == 0 ? 0.0 : ctx->D.rho / ctx->st.rho;
+                // beta = 0 at the start of a solve; after a residual replacement
+                // either restart (0) or continue with the previous rho (continue_cg)
+                const bool fresh = ctx->st.it == 0 && (!A.continue_cg || ctx->st.refine <= 1);
+                io.beta = fresh ? 0.0 : ctx->D.rho / ctx->st.rho;
                 io.out_in = p_new;
                 io.out = P.q;
                 io.rhs = nullptr;
-                io.part = part_ptr(P, PK_PQ, cur) + g.tile_off + tk.local;
+                io.part = part_ptr(P, PK_PQ, cur) + g.tile_off + M.local;
                 io.lowp = lowp;
             } else if (act == ACT_RESID) {
+                // r = b - A (x + d): the pending update d is folded into x in phase 2
                 io.in_a = P.x;
-                io.in_b = nullptr;
-                io.beta = 0.0;
+                io.in_b = P.d;
+                io.beta = 1.0;
                 io.out_in = nullptr;
                 io.out = r_new;
                 io.rhs = P.b;
-                io.part = part_ptr(P, PK_RES, cur) + g.tile_off + tk.local;
+                io.part = part_ptr(P, PK_RES, cur) + g.tile_off + M.local;
                 io.lowp = 0;
             } else {
                 continue;
             }
-            op_tile_2d<PP>(P, g, tk.local, io, lds);
+            op_tile_2d<PP>(P, g, M.t[0], M.t[1], M.local, io, lds);
         }
         trace_busy(A, sweep, 0, tb);
         grid_barrier(P.bar, nwg);
         trace_mark(A, sweep, 0);
         if (A.trace) tb = wall_clock64();
         // ---------------- phase 2: update + FD forward ---------------------------
-        for (int t = A.fd_b + blockIdx.x; t < A.fd_e; t += nwg) {
-            const Task tk = P.fdtask[t];
-            const Grid& g = P.grids[tk.grid];
-            task_context(P, A, g, S0, tk.grid, cur, nxt, 2, ctx);
+        for (int t = A.fd_b + blockIdx.x, k = 0; t < A.fd_e; t += nwg, ++k) {
+            const TaskMeta& M = fd_meta(t, k);
+            const Grid& g = M.g;
+            __syncthreads();
+            CtxLoads c;
+            if (wave0) ctx_issue(P, g, S0, M.grid, cur, nxt, 2, c);
+            // operands of an iteration step, copied to LDS together with the context loads
+            fd_issue_fwd<TU>(P, M, M.local, r_old, P.q, p_new, P.d, lds);
+            if (wave0) ctx_finish(A, c, 2, ctx);
+            g2l_wait_sync();
             const int act = ctx->D.act;
-            if (act == ACT_XUPD) {
-                const int n1 = g.ni[0];
-                for (int i = threadIdx.x; i < g.ndof; i += kBlock) {
-                    if (!owned_2d(g, tk.local, i % n1, i / n1)) continue;
-                    const int64_t k = g.dof_off + i;
-                    P.x[k] += P.d[k];
-                    P.d[k] = 0.0;
-                }
-                continue;
-            }
             FdIO io;
             io.rt = P.rt;
             io.prec = FDP;
             io.z = nullptr;
             io.rdot = nullptr;
-            io.part = part_ptr(P, PK_RR, cur) + g.blk_off + tk.local;
+            io.part = part_ptr(P, PK_RR, cur) + g.blk_off + M.local;
             if (act == ACT_ITER) {
                 const double pq = ctx->pq;
                 if (!(pq > 0.0) || !isfinite(ctx->D.rho / pq)) continue;  // breakdown: committed in phase 3
@@ -835,21 +1029,40 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.r_out = nullptr;
                 io.dvec = nullptr;
                 io.pvec = nullptr;
+                // x += d, d = 0 on the owned unknowns (phase 1 has read both); a
+                // continued CG carries its search direction into this sweep's buffer
+                {
+                    const FdBlock B(g, M.local);
+                    for (int o = threadIdx.x; o < B.nown; o += kBlock) {
+                        const int64_t kk = g.dof_off + B.gi(o);
+                        P.x[kk] += P.d[kk];
+                        P.d[kk] = 0.0;
+                        if (A.continue_cg) p_new[kk] = p_old[kk];
+                    }
+                }
+                // the residual sweep transforms r_new, not the prefetched r_old
+                g2l_vec(r_new + g.dof_off, g.ndof, fd_lds<TU>(M, lds).R);
+                g2l_wait_sync();
             } else {
                 continue;
             }
-            fd_fwd_p<FDP>(P, g, tk.local, io, lds);
+            fd_fwd_run<TU, TC>(P, M, M.local, io, lds);
         }
         trace_busy(A, sweep, 1, tb);
         grid_barrier(P.bar, nwg);
         trace_mark(A, sweep, 1);
         if (A.trace) tb = wall_clock64();
         // ---------------- phase 3: FD backward and commit ---------------------------
-        for (int t = A.fd_b + blockIdx.x; t < A.fd_e; t += nwg) {
-            const Task tk = P.fdtask[t];
-            const int gi = tk.grid;
-            const Grid& g = P.grids[gi];
-            task_context(P, A, g, S0, gi, cur, nxt, 3, ctx);
+        for (int t = A.fd_b + blockIdx.x, k = 0; t < A.fd_e; t += nwg, ++k) {
+            const TaskMeta& M = fd_meta(t, k);
+            const Grid& g = M.g;
+            const int gi = M.grid;
+            __syncthreads();
+            CtxLoads c;
+            if (wave0) ctx_issue(P, g, S0, gi, cur, nxt, 3, c);
+            fd_issue_bwd<TU>(P, M, M.local, P.rt, r_new, lds);
+            if (wave0) ctx_finish(A, c, 3, ctx);
+            g2l_wait_sync();
             const int act = ctx->D.act;
             if (act == ACT_SKIP) continue;
             bool run_bwd = act == ACT_RESID || (act == ACT_ITER && ctx->pq > 0.0 && isfinite(ctx->D.rho / ctx->pq));
@@ -859,10 +1072,10 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.z = P.z;
                 io.rdot = r_new;
                 io.prec = FDP;
-                io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + tk.local;
-                fd_bwd_p<FDP>(P, g, tk.local, io, lds);
+                io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
+                fd_bwd_run<TU, TC>(P, M, M.local, io, lds);
             }
-            if (tk.local == 0 && threadIdx.x == 0) {
+            if (M.local == 0 && threadIdx.x == 0) {
                 const GState& st = ctx->st;
                 const Decision& D = ctx->D;
                 GState ns = st;
@@ -880,11 +1093,11 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                         ns.it = st.it + 1;
                         ns.rho = D.rho;
                     }
-                } else if (act == ACT_XUPD) {
-                    ns.stage = STAGE_RESID;
-                    ns.total_it += st.it;
-                    ns.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
                 } else if (act == ACT_RESID) {
+                    if (st.stage == STAGE_ITER) {  // end of an inner solve
+                        ns.total_it += st.it;
+                        ns.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
+                    }
                     const double rn2 = ctx->rn2;
                     const double bn2 = st.refine == 0 ? rn2 : st.bn2;
                     ns.bn2 = bn2;
@@ -909,6 +1122,25 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         if (A.trace && blockIdx.x == 0 && threadIdx.x == 0) P.bar[3] = sweep + 1;
         const unsigned done = __hip_atomic_load(&P.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (static_cast<int>(done) >= A.ndone_target) break;
+    }
+}
+
+// One FD transform of block blk of a grid outside the solve (single-operation
+// kernels): description in LDS slot M.
+template <int FDP>
+__device__ __forceinline__ void fd_apply_block(const Params& P, const TaskMeta& M, int blk, const FdIO& io,
+                                               double* lds, bool fwd) {
+    using TU = typename FdTypes<FDP>::TU;
+    using TC = typename FdTypes<FDP>::TC;
+    __syncthreads();
+    if (fwd) {
+        fd_issue_fwd<TU>(P, M, blk, io.r_old, io.q, io.pvec, io.dvec, lds);
+        g2l_wait_sync();
+        fd_fwd_run<TU, TC>(P, M, blk, io, lds);
+    } else {
+        fd_issue_bwd<TU>(P, M, blk, io.rt, io.rdot, lds);
+        g2l_wait_sync();
+        fd_bwd_run<TU, TC>(P, M, blk, io, lds);
     }
 }
 
