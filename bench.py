@@ -38,8 +38,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16fd", "fp64"])
-    ap.add_argument("--tol", type=float, default=1e-11)
-    ap.add_argument("--tol-inner", type=float, default=1e-5)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--tol-inner", type=float, default=1e-4)
+    ap.add_argument("--restart", action="store_true",
+                    help="classic refinement: restart CG at each FP64 residual replacement")
     ap.add_argument("--lattice", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator run")
@@ -84,7 +86,8 @@ def run_mode(S, W, torch, precision, args, xi):
     stream = P.stream
     xi_t = torch.as_tensor(xi, device="cuda:0").contiguous()
     kw = dict(precision=precision, tol=args.tol, tol_inner=args.tol_inner, maxit=400,
-              max_refine=8 if precision != "fp64" else 3, batched=True)
+              max_refine=12 if precision != "fp64" else 3, batched=True,
+              continue_cg=not args.restart)
 
     def step():
         P.assemble()

@@ -20,8 +20,9 @@ constexpr int kMaxDim = 3;
 constexpr int kMaxP = 4;          // solution degree limit (register arrays)
 constexpr int kMaxPg = 4;         // geometry degree limit
 constexpr int kMaxPatch = 4;
-constexpr int kBlock = 256;       // threads per workgroup in every kernel
-constexpr int kBigRed = 1024;     // doubles of LDS for cross-wavefront partial sums of FD tasks
+constexpr int kBlock = 512;       // threads per workgroup in every kernel (8 wavefronts)
+constexpr int kWaves = kBlock / 64;
+constexpr int kBigRed = 2048;     // doubles of LDS for cross-wavefront partial sums of FD tasks
 
 // Grid stages of the persistent refinement/CG state machine.
 enum Stage : int { STAGE_RESID = 0, STAGE_ITER = 1, STAGE_DONE = 2 };
@@ -131,14 +132,14 @@ constexpr int kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
 //   Own       three FP64 values per owned unknown (fetched operands)
 //   Us, Ub    staged factor rows (short direction; long direction of a
 //             single-block grid) in the factor precision, row stride ldu
-//   Slab      long-direction factor rows of a blocked grid: rows x 256
+//   Slab      long-direction factor rows of a blocked grid: rows x kBlock
 //             threads x 16 bytes, in the order the threads consume them
 struct FdLayout {
     int R, S, red, Out, Own, Us, Ub, Slab, rows, total;
 };
 // rows of the slab per thread for block width bs (16-byte chunks of 16/usize values)
 inline IGA_HD int fd_slab_rows(int nbig, int bs, int usize) {
-    const int rpt = 256 * (16 / usize) / bs;  // rows per workgroup pass
+    const int rpt = kBlock * (16 / usize) / bs;  // rows per workgroup pass
     return (nbig + rpt - 1) / rpt;
 }
 inline IGA_HD FdLayout fd_layout(const Grid& g, int ldu_s, int ldu_b, int usize) {
@@ -166,7 +167,7 @@ inline IGA_HD FdLayout fd_layout(const Grid& g, int ldu_s, int ldu_b, int usize)
     o = (o + 15) & ~15;
     L.Slab = o;
     L.rows = wide ? fd_slab_rows(nbig, bs, usize) : 0;
-    o += L.rows * 256 * 16;
+    o += L.rows * kBlock * 16;
     L.total = o;
     return L;
 }
@@ -174,12 +175,12 @@ constexpr size_t kSolveLdsHead = kCtxBytes + kMetaSlots * sizeof(TaskMeta);
 
 // Workspace layout: byte offsets of every device array.
 struct Layout {
-    size_t tabs, grids, dpool, ipool, fpool, hpool, ctrl;
+    size_t tabs, grids, grids_lp, dpool, ipool, fpool, hpool, ctrl;
     size_t G64, G32, Fq;          // operator coefficients and load density at Gauss points
     size_t b, x, d, r2, z, p2, q, rt;
     size_t st2;                   // GState[2][ngrid]
     size_t part;                  // partial sums
-    size_t optask, fdtask;
+    size_t optask, fdtask, fdtask_lp;
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t total;

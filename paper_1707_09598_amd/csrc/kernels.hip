@@ -520,13 +520,13 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
     }
 }
 
-Params make_params(iga_sg_plan_s* P) {
+Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     Params K;
     std::memset(&K, 0, sizeof(K));
     char* base = static_cast<char*>(P->ws);
     const Layout& L = P->lay;
     K.tabs = reinterpret_cast<const Tab1D*>(base + L.tabs);
-    K.grids = reinterpret_cast<const Grid*>(base + L.grids);
+    K.grids = reinterpret_cast<const Grid*>(base + (lowp_fd ? L.grids_lp : L.grids));
     K.dpool = reinterpret_cast<const double*>(base + L.dpool);
     K.ipool = reinterpret_cast<const int*>(base + L.ipool);
     K.fpool = reinterpret_cast<const float*>(base + L.fpool);
@@ -550,7 +550,7 @@ Params make_params(iga_sg_plan_s* P) {
     K.ncompG = P->ncompG;
     K.ngrid = static_cast<int>(P->grids.size());
     K.nop = static_cast<int>(P->optask.size());
-    K.nfd = static_cast<int>(P->fdtask.size());
+    K.nfd = static_cast<int>((lowp_fd ? P->fdtask_lp : P->fdtask).size());
     K.nqp_total = P->nqp_total;
     K.ndof_total = P->ndof_total;
     K.G64 = reinterpret_cast<double*>(base + L.G64);
@@ -566,9 +566,9 @@ Params make_params(iga_sg_plan_s* P) {
     K.rt = reinterpret_cast<double*>(base + L.rt);
     K.st2 = reinterpret_cast<GState*>(base + L.st2);
     K.part = reinterpret_cast<double*>(base + L.part);
-    K.part_stride = static_cast<int64_t>(std::max(P->optask.size(), P->fdtask.size()));
+    K.part_stride = static_cast<int64_t>(std::max(P->optask.size(), std::max(P->fdtask.size(), P->fdtask_lp.size())));
     K.optask = reinterpret_cast<const Task*>(base + L.optask);
-    K.fdtask = reinterpret_cast<const Task*>(base + L.fdtask);
+    K.fdtask = reinterpret_cast<const Task*>(base + (lowp_fd ? L.fdtask_lp : L.fdtask));
     K.bar = reinterpret_cast<unsigned*>(base + L.bar);
     for (int i = 0; i < P->nq && i < 8; ++i) {
         K.gx[i] = P->gauss_x[i];
@@ -649,6 +649,7 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     const Layout& L = P->lay;
     HIP_OK(hipMemcpyAsync(base + L.tabs, P->tabs.data(), sizeof(Tab1D) * P->tabs.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(base + L.grids, P->grids.data(), sizeof(Grid) * P->grids.size(), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(base + L.grids_lp, P->grids_lp.data(), sizeof(Grid) * P->grids_lp.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(base + L.dpool, P->dpool.data(), sizeof(double) * P->dpool.size(), hipMemcpyHostToDevice, st));
     if (!P->ipool.empty())
         HIP_OK(hipMemcpyAsync(base + L.ipool, P->ipool.data(), sizeof(int) * P->ipool.size(), hipMemcpyHostToDevice, st));
@@ -657,6 +658,7 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     HIP_OK(hipMemcpyAsync(base + L.ctrl, P->ctrl.data(), sizeof(double) * P->ctrl.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(base + L.optask, P->optask.data(), sizeof(Task) * P->optask.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(base + L.fdtask, P->fdtask.data(), sizeof(Task) * P->fdtask.size(), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(base + L.fdtask_lp, P->fdtask_lp.data(), sizeof(Task) * P->fdtask_lp.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(base + L.bar, 0, 256, st));
     Params K = make_params(P);
     int maxQ = 0;
@@ -751,7 +753,10 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         return IGA_ERR_INVALID_ARG;
     }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
-    Params K = make_params(P);
+    const bool lp = o->precision != IGA_PREC_FP64;  // FD blocking of the factor precision
+    Params K = make_params(P, lp);
+    const std::vector<Grid>& grids = lp ? P->grids_lp : P->grids;
+    const size_t nfd = (lp ? P->fdtask_lp : P->fdtask).size();
     const int ng = static_cast<int>(P->grids.size());
     SolveArgs A;
     A.prec = o->precision;
@@ -790,11 +795,11 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         return IGA_OK;
     };
     if (o->batched) {
-        iga_status s = launch(0, ng, 0, static_cast<int>(P->optask.size()), 0, static_cast<int>(P->fdtask.size()));
+        iga_status s = launch(0, ng, 0, static_cast<int>(P->optask.size()), 0, static_cast<int>(nfd));
         if (s != IGA_OK) return s;
     } else {
         for (int gi = 0; gi < ng; ++gi) {
-            const Grid& g = P->grids[gi];
+            const Grid& g = grids[gi];
             iga_status s = launch(gi, gi + 1, g.tile_off, g.tile_off + g.ntile, g.blk_off, g.blk_off + g.nblk);
             if (s != IGA_OK) return s;
         }
@@ -960,9 +965,10 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)
         if (P->grids[i].comp == comp) gi = i;
-    const Grid& g = P->grids[gi];
+    const bool lp = which >= 3;  // FD with FP32/BF16 factors uses their blocking
+    const Grid& g = (lp ? P->grids_lp : P->grids)[gi];
     hipStream_t st = static_cast<hipStream_t>(P->stream);
-    Params K = make_params(P);
+    Params K = make_params(P, lp);
     // the hooks read/write the caller's vectors shifted to the grid's offset
     const double* xs = x - g.dof_off;
     double* ys = y - g.dof_off;

@@ -560,35 +560,42 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 size_t lds = (halo + nel * pl + kBlock) * sizeof(double);
                 lds_max = std::max(lds_max, lds);
             }
-            // fast-diagonalisation blocks (2D: split the longest direction)
+            // fast-diagonalisation blocks (2D: split the longest direction).  Long
+            // directions are cut into blocks of 8, 16 or 32 columns whose factor
+            // slab (about 64 KiB) is staged in LDS; FP32/BF16 factors allow wider
+            // blocks, so each precision class has its own blocking.
+            Grid glp = g;
             if (d == 2) {
-                g.big = g.ni[1] > g.ni[0] ? 1 : 0;
-                const int nbig = g.ni[g.big], nsm = g.ni[1 - g.big];
-                const size_t n = static_cast<size_t>(g.ndof);
-                // long directions: blocks of 8, 16 or 32 columns, about 64 KB of the
-                // FP64 factor per block, streamed by the whole workgroup
-                int bs = nbig;
-                const int wide_min = env_int("IGA_FD_WIDE", 16);
-                if (nbig >= wide_min) {
-                    int b = 8;
-                    while (b < 32 && static_cast<size_t>(2 * b) * nbig * sizeof(double) <= 65536) b *= 2;
-                    if (b < nbig) bs = b;
+                for (int cls = 0; cls < 2; ++cls) {
+                    Grid& gc = cls == 0 ? g : glp;
+                    const int usize = cls == 0 ? 8 : 4;
+                    gc.big = gc.ni[1] > gc.ni[0] ? 1 : 0;
+                    const int nbig = gc.ni[gc.big];
+                    int bs = nbig;
+                    const int wide_min = env_int("IGA_FD_WIDE", 100);
+                    if (nbig >= wide_min) {
+                        int b = 8;
+                        while (b < 32 && static_cast<size_t>(2 * b) * nbig * usize <= 66000) b *= 2;
+                        if (b < nbig) bs = b;
+                    }
+                    gc.blk = bs;
+                    gc.nblk = (nbig + bs - 1) / bs;
+                    const bool wide = gc.nblk > 1;
+                    const int ls = P->tabs[gc.tab[1 - gc.big]].ldu, lb = P->tabs[gc.tab[gc.big]].ldu;
+                    // single-block grids stage the long factor as well when it fits
+                    gc.fdstage = wide ? 0 : 1;
+                    if (!wide && fd_layout(gc, ls, lb, usize).total + kSolveLdsHead > kLdsLimit) gc.fdstage = 0;
+                    lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(gc, ls, lb, usize).total));
                 }
-                g.blk = bs;
-                g.nblk = (nbig + bs - 1) / bs;
-                const bool wide = g.nblk > 1;
-                const int ls = P->tabs[g.tab[1 - g.big]].ldu, lb = P->tabs[g.tab[g.big]].ldu;
-                // single-block grids stage the long factor as well when it fits
-                g.fdstage = wide ? 0 : 1;
-                if (!wide && fd_layout(g, ls, lb, 8).total + kSolveLdsHead > kLdsLimit) g.fdstage = 0;
-                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(g, ls, lb, 8).total));
             } else {
                 g.big = 0;
                 g.blk = g.ni[0];
                 g.nblk = 1;
+                glp = g;
                 size_t lds = (3 * static_cast<size_t>(g.ndof) + kBlock) * sizeof(double);
                 lds_max = std::max(lds_max, lds);
             }
+            P->grids_lp.push_back(glp);
             P->grids.push_back(g);
         }
     if (lds_max + kSolveLdsHead > kLdsLimit) {
@@ -605,9 +612,27 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     for (int gi : ord) {
         Grid& g = P->grids[gi];
         g.tile_off = static_cast<int>(P->optask.size());
+        P->grids_lp[gi].tile_off = g.tile_off;
         for (int t = 0; t < g.ntile; ++t) P->optask.push_back({gi, t});
-        g.blk_off = static_cast<int>(P->fdtask.size());
-        for (int t = 0; t < g.nblk; ++t) P->fdtask.push_back({gi, t});
+    }
+    // FD tasks: the blocks of a grid are contiguous (partial sums), grids in
+    // decreasing cost of one block, so that the costliest blocks are taken
+    // first by the persistent workgroups.  Cost ~ unknowns x (short length +
+    // block width): the short-direction product plus the block's long product.
+    for (int cls = 0; cls < 2; ++cls) {
+        std::vector<Grid>& gv = cls == 0 ? P->grids : P->grids_lp;
+        std::vector<Task>& tv = cls == 0 ? P->fdtask : P->fdtask_lp;
+        auto cost = [&](int gi) {
+            const Grid& g = gv[gi];
+            const int nsm = d == 2 ? g.ni[1 - g.big] : 1;
+            return static_cast<double>(g.ndof) * (nsm + std::min(g.blk, g.ni[g.big]));
+        };
+        std::vector<int> fo(ord);
+        std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        for (int gi : fo) {
+            gv[gi].blk_off = static_cast<int>(tv.size());
+            for (int t = 0; t < gv[gi].nblk; ++t) tv.push_back({gi, t});
+        }
     }
     // ---- workspace layout ----------------------------------------------------
     Layout& L = P->lay;
@@ -621,6 +646,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                  nqp = static_cast<size_t>(P->nqp_total);
     L.tabs = take(sizeof(Tab1D) * P->tabs.size());
     L.grids = take(sizeof(Grid) * ng);
+    L.grids_lp = take(sizeof(Grid) * ng);
     L.dpool = take(sizeof(double) * P->dpool.size());
     L.ipool = take(sizeof(int) * P->ipool.size());
     L.fpool = take(sizeof(float) * P->fpool.size());
@@ -638,10 +664,11 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.q = take(sizeof(double) * nd);
     L.rt = take(sizeof(double) * nd);
     L.st2 = take(sizeof(GState) * ng * 2);
-    size_t pst = std::max(P->optask.size(), P->fdtask.size());
+    size_t pst = std::max(P->optask.size(), std::max(P->fdtask.size(), P->fdtask_lp.size()));
     L.part = take(sizeof(double) * pst * 8);
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
+    L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());
     L.bar = take(256);
     L.trace = take(sizeof(unsigned long long) * (1 + 6 * 4096));
     L.total = off;

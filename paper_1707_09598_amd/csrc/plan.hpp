@@ -51,8 +51,9 @@ struct iga_sg_plan_s {
     std::vector<double> gauss_x, gauss_w;
     // per (patch, dir, level) 1D interior matrices (dense, host only)
     std::vector<std::vector<double>> K1d, M1d;
-    std::vector<igasg::Grid> grids;
-    std::vector<igasg::Task> optask, fdtask;
+    std::vector<igasg::Grid> grids;      // FD blocking for FP64 factors
+    std::vector<igasg::Grid> grids_lp;   // same grids, FD blocking for FP32/BF16 factors
+    std::vector<igasg::Task> optask, fdtask, fdtask_lp;
     std::vector<double> ctrl;  // homogeneous control points, concatenated per patch
     int64_t ctrl_off[igasg::kMaxPatch] = {0, 0, 0, 0};
     int ncompG = 0;
@@ -72,5 +73,5 @@ struct iga_sg_plan_s {
 
 namespace igasg {
 int tab_index(const iga_sg_plan_s* P, int patch, int dir, int lev);
-Params make_params(iga_sg_plan_s* P);
+Params make_params(iga_sg_plan_s* P, bool lowp_fd = false);
 }  // namespace igasg

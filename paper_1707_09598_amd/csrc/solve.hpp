@@ -32,84 +32,73 @@ struct OpIO {
     int lowp;             // 1: FP32 coefficients and arithmetic
 };
 
+// One row j2 of Gauss points of one element, by sum factorisation: the
+// element's (p+1)^2 output contributions from that row,
+//   y[a1][a2] = sum_j1 B2[j2][a2] (B1[j1][a1] F0 + D1[j1][a1] F1) + D2[j2][a2] B1[j1][a1] F2,
+// with (F0, F1, F2) = G (v, dv/dxi1, dv/dxi2) at the point (the rational basis
+// adds the value component F0; G holds the symmetric coefficient matrix).
 template <int PP, bool RAT, typename T>
-__device__ __forceinline__ void elem_apply_2d(const double* X, int nh1, int x1, int x2, const double* B1,
-                                              const double* D1, const double* B2, const double* D2,
-                                              const T* G, int64_t nqp, int64_t qrow0, int Q1, double* Y) {
+__device__ __forceinline__ void elem_row_2d(const double* X, int nh1, int x1, int x2, const double* B1,
+                                            const double* D1, const double* B2r, const double* D2r, const T* Gr,
+                                            int64_t nqp, T (&y)[PP + 1][PP + 1]) {
     constexpr int NQ = PP + 1;
-    T c[PP + 1][PP + 1], y[PP + 1][PP + 1];
+    T b2[PP + 1], d2[PP + 1], tb[PP + 1], td[PP + 1], sb[PP + 1], sd[PP + 1];
 #pragma unroll
-    for (int a2 = 0; a2 <= PP; ++a2)
+    for (int a = 0; a <= PP; ++a) {
+        b2[a] = static_cast<T>(B2r[a]);
+        d2[a] = static_cast<T>(D2r[a]);
+    }
 #pragma unroll
-        for (int a1 = 0; a1 <= PP; ++a1) {
-            c[a1][a2] = static_cast<T>(X[(x2 + a2) * nh1 + x1 + a1]);
-            y[a1][a2] = T(0);
+    for (int a1 = 0; a1 <= PP; ++a1) {
+        T u = T(0), v = T(0);
+#pragma unroll
+        for (int a2 = 0; a2 <= PP; ++a2) {
+            const T c = static_cast<T>(X[(x2 + a2) * nh1 + x1 + a1]);
+            u += b2[a2] * c;
+            v += d2[a2] * c;
         }
+        tb[a1] = u;
+        td[a1] = v;
+        sb[a1] = T(0);
+        sd[a1] = T(0);
+    }
 #pragma unroll
-    for (int j2 = 0; j2 < NQ; ++j2) {
-        T b2[PP + 1], d2[PP + 1];
+    for (int j1 = 0; j1 < NQ; ++j1) {
+        T b1[PP + 1], d1[PP + 1];
 #pragma unroll
         for (int a = 0; a <= PP; ++a) {
-            b2[a] = static_cast<T>(B2[j2 * (PP + 1) + a]);
-            d2[a] = static_cast<T>(D2[j2 * (PP + 1) + a]);
+            b1[a] = static_cast<T>(B1[j1 * (PP + 1) + a]);
+            d1[a] = static_cast<T>(D1[j1 * (PP + 1) + a]);
         }
-        T tb[PP + 1], td[PP + 1], sb[PP + 1], sd[PP + 1];
+        T v0 = T(0), v1 = T(0), v2 = T(0);
 #pragma unroll
         for (int a1 = 0; a1 <= PP; ++a1) {
-            T u = T(0), v = T(0);
-#pragma unroll
-            for (int a2 = 0; a2 <= PP; ++a2) {
-                u += b2[a2] * c[a1][a2];
-                v += d2[a2] * c[a1][a2];
-            }
-            tb[a1] = u;
-            td[a1] = v;
-            sb[a1] = T(0);
-            sd[a1] = T(0);
+            if (RAT) v0 += b1[a1] * tb[a1];
+            v1 += d1[a1] * tb[a1];
+            v2 += b1[a1] * td[a1];
         }
-        const T* Gr = G + qrow0 + static_cast<int64_t>(j2) * Q1;
-#pragma unroll
-        for (int j1 = 0; j1 < NQ; ++j1) {
-            T b1[PP + 1], d1[PP + 1];
-#pragma unroll
-            for (int a = 0; a <= PP; ++a) {
-                b1[a] = static_cast<T>(B1[j1 * (PP + 1) + a]);
-                d1[a] = static_cast<T>(D1[j1 * (PP + 1) + a]);
-            }
-            T v0 = T(0), v1 = T(0), v2 = T(0);
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) {
-                if (RAT) v0 += b1[a1] * tb[a1];
-                v1 += d1[a1] * tb[a1];
-                v2 += b1[a1] * td[a1];
-            }
-            T F0 = T(0), F1, F2;
-            if (RAT) {
-                T g00 = Gr[j1], g01 = Gr[nqp + j1], g02 = Gr[2 * nqp + j1];
-                T g11 = Gr[3 * nqp + j1], g12 = Gr[4 * nqp + j1], g22 = Gr[5 * nqp + j1];
-                F0 = g00 * v0 + g01 * v1 + g02 * v2;
-                F1 = g01 * v0 + g11 * v1 + g12 * v2;
-                F2 = g02 * v0 + g12 * v1 + g22 * v2;
-            } else {
-                T g11 = Gr[j1], g12 = Gr[nqp + j1], g22 = Gr[2 * nqp + j1];
-                F1 = g11 * v1 + g12 * v2;
-                F2 = g12 * v1 + g22 * v2;
-            }
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) {
-                sb[a1] += (RAT ? b1[a1] * F0 : T(0)) + d1[a1] * F1;
-                sd[a1] += b1[a1] * F2;
-            }
+        T F0 = T(0), F1, F2;
+        if (RAT) {
+            const T g00 = Gr[j1], g01 = Gr[nqp + j1], g02 = Gr[2 * nqp + j1];
+            const T g11 = Gr[3 * nqp + j1], g12 = Gr[4 * nqp + j1], g22 = Gr[5 * nqp + j1];
+            F0 = g00 * v0 + g01 * v1 + g02 * v2;
+            F1 = g01 * v0 + g11 * v1 + g12 * v2;
+            F2 = g02 * v0 + g12 * v1 + g22 * v2;
+        } else {
+            const T g11 = Gr[j1], g12 = Gr[nqp + j1], g22 = Gr[2 * nqp + j1];
+            F1 = g11 * v1 + g12 * v2;
+            F2 = g12 * v1 + g22 * v2;
         }
 #pragma unroll
-        for (int a2 = 0; a2 <= PP; ++a2)
-#pragma unroll
-            for (int a1 = 0; a1 <= PP; ++a1) y[a1][a2] += b2[a2] * sb[a1] + d2[a2] * sd[a1];
+        for (int a1 = 0; a1 <= PP; ++a1) {
+            sb[a1] += (RAT ? b1[a1] * F0 : T(0)) + d1[a1] * F1;
+            sd[a1] += b1[a1] * F2;
+        }
     }
 #pragma unroll
     for (int a2 = 0; a2 <= PP; ++a2)
 #pragma unroll
-        for (int a1 = 0; a1 <= PP; ++a1) Y[a1 + (PP + 1) * a2] = static_cast<double>(y[a1][a2]);
+        for (int a1 = 0; a1 <= PP; ++a1) y[a1][a2] = b2[a2] * sb[a1] + d2[a2] * sd[a1];
 }
 
 template <int PP>
@@ -146,29 +135,64 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
         X[idx] = v;
     }
     __syncthreads();
-    const int nqp1 = P.nq * (p + 1);
+    // items: (element, row j2 of Gauss points), NG lanes per element (NG the
+    // power of two >= p+1); the rows of an element are summed by a fixed
+    // butterfly over its lanes
+    constexpr int NQ = PP + 1;
+    constexpr int NG = NQ <= 2 ? 2 : (NQ <= 4 ? 4 : 8);
+    const int nqp1 = NQ * NQ;
     const int64_t nqp = g.nqp;
     const FDiv de(ne1);
-    for (int el = threadIdx.x; el < ne1 * ne2; el += kBlock) {
+    const bool rat = P.rational[g.patch] != 0;
+    const int nitem = ne1 * ne2 * NG;
+    for (int it = threadIdx.x; it < nitem; it += kBlock) {
+        const int el = it / NG, j2 = it & (NG - 1);
         int r1;
         const int q1 = de.div(el, &r1);
-        int e1 = el1 + r1, e2 = el2 + q1;
+        const int e1 = el1 + r1, e2 = el2 + q1;
+        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2;
+        const int jr = j2 < NQ ? j2 : 0;
         const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
         const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
-        const double* B2 = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1;
-        const double* D2 = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1;
-        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2;
-        const int64_t qrow0 = static_cast<int64_t>(e2) * P.nq * g.Q[0] + static_cast<int64_t>(e1) * P.nq;
-        double* Ye = Y + el * (p + 1) * (p + 1);
-        const bool rat = P.rational[g.patch] != 0;
+        const double* B2r = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1 + jr * NQ;
+        const double* D2r = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1 + jr * NQ;
+        const int64_t qrow = static_cast<int64_t>(e2 * NQ + jr) * g.Q[0] + static_cast<int64_t>(e1) * NQ;
+        double yv[NQ][NQ];
         if (io.lowp) {
-            const float* G = P.G32 + g.qp_off * P.ncompG;
-            if (rat) elem_apply_2d<PP, true, float>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-            else elem_apply_2d<PP, false, float>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
+            float y[NQ][NQ];
+            const float* Gr = P.G32 + g.qp_off * P.ncompG + qrow;
+            if (rat) elem_row_2d<PP, true, float>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
+            else elem_row_2d<PP, false, float>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
+#pragma unroll
+            for (int a1 = 0; a1 < NQ; ++a1)
+#pragma unroll
+                for (int a2 = 0; a2 < NQ; ++a2) {
+                    float v = j2 < NQ ? y[a1][a2] : 0.0f;
+#pragma unroll
+                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
+                    yv[a1][a2] = static_cast<double>(v);
+                }
         } else {
-            const double* G = P.G64 + g.qp_off * P.ncompG;
-            if (rat) elem_apply_2d<PP, true, double>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
-            else elem_apply_2d<PP, false, double>(X, nh1, x1, x2, B1, D1, B2, D2, G, nqp, qrow0, g.Q[0], Ye);
+            double y[NQ][NQ];
+            const double* Gr = P.G64 + g.qp_off * P.ncompG + qrow;
+            if (rat) elem_row_2d<PP, true, double>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
+            else elem_row_2d<PP, false, double>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
+#pragma unroll
+            for (int a1 = 0; a1 < NQ; ++a1)
+#pragma unroll
+                for (int a2 = 0; a2 < NQ; ++a2) {
+                    double v = j2 < NQ ? y[a1][a2] : 0.0;
+#pragma unroll
+                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
+                    yv[a1][a2] = v;
+                }
+        }
+        if (j2 == 0) {
+            double* Ye = Y + el * nqp1;
+#pragma unroll
+            for (int a2 = 0; a2 < NQ; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < NQ; ++a1) Ye[a1 + NQ * a2] = yv[a1][a2];
         }
     }
     __syncthreads();
@@ -209,12 +233,16 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
 // fast diagonalisation: z = (U1 (x) U2) diag(1/(c1 l1 + c2 l2)) (U1 (x) U2)^T r
 // as mode products
 // ===========================================================================
-// Small dense product in LDS or global memory, C = A B (M x N, inner K):
-// threads take the longer output index and a chunk of 8 of the other one, so
-// every operand value read is used up to 8 times and nothing is split over K.
+// Small dense product in LDS or global memory, C = A B (M x N, inner K).
+// Items are (index of the longer output dimension, chunk of 4 of the other,
+// slice of K): every operand value read is used up to 4 times, and K is cut
+// into KS slices when there are too few outputs to occupy the workgroup; the
+// slices' partial sums go through red (KS * M * N <= kBigRed doubles) and are
+// added in slice order (deterministic).
 template <typename TA, typename TB, typename TC>
 __device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
-                                           int sBn, double* C, int sCm, int sCn) {
+                                           int sBn, double* C, int sCm, int sCn, double* red) {
+    constexpr int CH = 4;
     auto ld = [](auto* p, int i) -> TC {
         using V = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
         if constexpr (std::is_same<V, uint16_t>::value) return static_cast<TC>(bf16_to_f32(p[i]));
@@ -222,41 +250,59 @@ __device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int
     };
     const bool cols = N >= M;
     const int L = cols ? N : M, S = cols ? M : N;
-    const int nch = (S + 7) >> 3;
-    const FDiv dl(L);
-    for (int it = threadIdx.x; it < L * nch; it += kBlock) {
-        int l;
-        const int s0 = dl.div(it, &l) * 8;
-        int sq[8];
+    const int nch = (S + CH - 1) / CH;
+    const int base_items = L * nch;
+    int KS = 1;
+    while (KS < 8 && base_items * KS < kBlock && 2 * KS * M * N <= kBigRed && K >= 16 * KS) KS *= 2;
+    const int kc = (K + KS - 1) / KS;
+    const FDiv dl(L), dn(nch);
+    for (int it = threadIdx.x; it < base_items * KS; it += kBlock) {
+        int rem, l;
+        const int ks = dn.div(dl.div(it, &l), &rem);
+        const int s0 = rem * CH;
+        int sq[CH];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sq[q] = min(s0 + q, S - 1);  // clamped: loads stay in range
-        TC acc[8];
+        for (int q = 0; q < CH; ++q) sq[q] = min(s0 + q, S - 1);  // clamped: loads stay in range
+        TC acc[CH];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = TC(0);
+        for (int q = 0; q < CH; ++q) acc[q] = TC(0);
+        const int k0 = ks * kc, k1 = min(K, k0 + kc);
         if (cols) {
 #pragma unroll 4
-            for (int k = 0; k < K; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 const TC b = ld(B, k * sBk + l * sBn);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] += ld(A, sq[q] * sAm + k * sAk) * b;
+                for (int q = 0; q < CH; ++q) acc[q] += ld(A, sq[q] * sAm + k * sAk) * b;
             }
         } else {
 #pragma unroll 4
-            for (int k = 0; k < K; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 const TC a = ld(A, l * sAm + k * sAk);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] += a * ld(B, k * sBk + sq[q] * sBn);
+                for (int q = 0; q < CH; ++q) acc[q] += a * ld(B, k * sBk + sq[q] * sBn);
             }
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < CH; ++q) {
             if (s0 + q < S) {
-                if (cols) C[(s0 + q) * sCm + l * sCn] = static_cast<double>(acc[q]);
-                else C[l * sCm + (s0 + q) * sCn] = static_cast<double>(acc[q]);
+                const int m = cols ? s0 + q : l, n = cols ? l : s0 + q;
+                if (KS == 1) C[m * sCm + n * sCn] = static_cast<double>(acc[q]);
+                else red[(ks * M + m) * N + n] = static_cast<double>(acc[q]);
             }
         }
     }
     __syncthreads();
+    if (KS > 1) {
+        const FDiv dN(N);
+        for (int o = threadIdx.x; o < M * N; o += kBlock) {
+            int n;
+            const int m = dN.div(o, &n);
+            double t = 0.0;
+            for (int ks = 0; ks < KS; ++ks) t += red[ks * M * N + o];
+            C[m * sCm + n * sCn] = t;
+        }
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ double load_val(const double* p, int i) { return p[i]; }
@@ -471,7 +517,7 @@ __device__ __forceinline__ void fd_issue_factors(const Params& P, const TaskMeta
         constexpr int CPL = VecU<TU>::CPL;
         const int lpr = M.g.blk / CPL;  // lanes per row segment (power of two)
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        const int rpw = 64 / lpr, rpt = 4 * rpw;
+        const int rpw = 64 / lpr, rpt = kWaves * rpw;
         const int jc = (lane & (lpr - 1)) * CPL;
         const int r0 = wave * rpw + lane / lpr;
         if (jc < B.bs) {
@@ -527,9 +573,9 @@ __device__ __forceinline__ void fd_big_t(int K, int msm, int bsa, const double* 
     constexpr int CPL = VecU<TU>::CPL;
     constexpr int LPR = BS / CPL;  // lanes per row segment
     constexpr int RPW = 64 / LPR;  // rows per wavefront copy
-    constexpr int RPT = 4 * RPW;   // rows per workgroup pass
+    constexpr int RPT = kWaves * RPW;  // rows per workgroup pass
     constexpr int ACC = (sizeof(TC) == 8 ? 32 : 64) / CPL;
-    constexpr int MMC = ACC < kBigRed / (4 * BS) ? ACC : kBigRed / (4 * BS);
+    constexpr int MMC = ACC < kBigRed / (kWaves * BS) ? ACC : kBigRed / (kWaves * BS);
     static_assert(LPR >= 1 && LPR <= 64 && MMC >= 1, "block shape");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int jc = (lane % LPR) * CPL;
@@ -578,8 +624,9 @@ __device__ __forceinline__ void fd_big_t(int K, int msm, int bsa, const double* 
         for (int o = threadIdx.x; o < mc * BS; o += kBlock) {
             const int m = o / BS, j = o % BS;
             if (j < bsa) {
-                const double t = red[m * BS + j] + red[(MMC + m) * BS + j] + red[(2 * MMC + m) * BS + j] +
-                                 red[(3 * MMC + m) * BS + j];
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) t += red[(w * MMC + m) * BS + j];
                 C[(m0 + m) * sCm + j * sCj] = t;
             }
         }
@@ -632,24 +679,24 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // S[k2][i1] = sum_i2 UT2[k2][i2] R[i2][i1]
-        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1);
+        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1, L.red);
         // Rt[k2][k1] = sum_i1 S[k2][i1] U1[i1][k1], k1 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n1, n2, bs, L.S, n1, 1, L.Slab, L.red, L.Out, bs, 1);
         else if (B.sbig)
-            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
+            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, L.red);
         else
-            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
+            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, L.red);
     } else {
         // S[i2][k1] = sum_i1 R[i2][i1] U1[i1][k1]
-        small_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1);
+        small_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1, L.red);
         // Rt[k2][k1] = sum_i2 U2[i2][k2] S[i2][k1], k2 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n2, n1, bs, L.S, 1, n1, L.Slab, L.red, L.Out, 1, n1);
         else if (B.sbig)
-            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
+            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, L.red);
         else
-            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
+            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, L.red);
     }
     for (int o = threadIdx.x; o < B.nown; o += kBlock) io.rt[off + B.gi(o)] = L.Out[o] * Iw[o];
     __syncthreads();
@@ -672,24 +719,24 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // T[i2][k1] = sum_k2 U2[i2][k2] Rt[k2][k1]
-        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1);
+        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1, L.red);
         // Z[i2][i1] = sum_k1 T[i2][k1] UT1[k1][i1], i1 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n1, n2, bs, Tm, n1, 1, L.Slab, L.red, L.Out, bs, 1);
         else if (B.sbig)
-            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
+            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, L.red);
         else
-            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
+            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, L.red);
     } else {
         // T[k2][i1] = sum_k1 Rt[k2][k1] UT1[k1][i1]
-        small_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1);
+        small_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1, L.red);
         // Z[i2][i1] = sum_k2 UT2[k2][i2] T[k2][i1], i2 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n2, n1, bs, Tm, 1, n1, L.Slab, L.red, L.Out, 1, n1);
         else if (B.sbig)
-            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
+            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, L.red);
         else
-            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
+            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, L.red);
     }
     double dot = 0.0;
     const double* Rd = L.Own;
@@ -871,7 +918,7 @@ __device__ __forceinline__ double sum_strided(const double* p, int count) {
         const int i = lane + 64 * s;
         if (i < count) v += p[i];
     }
-    for (int i = lane + 256; i < count; i += 64) v += p[i];
+    for (int i = lane + 256; i < count; i += 64) v += p[i];  // beyond the unrolled 4 x 64
     return v;
 }
 
