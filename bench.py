@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-trace", action="store_true", help="skip the phase-traced extra solve")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -119,10 +122,12 @@ def run_mode(S, W, torch, precision, args, xi):
     P.assemble()
     rep = P.solve(**kw)
     u = P.combine(xi_t).cpu().numpy()
-    P.assemble()
-    tr = P.solve(timing=2, **kw)
-    trace = {"sweeps": tr["sweeps"], "phase_wall_us": [round(v, 2) for v in tr["phase_us"][:3]],
-             "phase_busy_us": [round(v, 2) for v in tr["phase_us"][3:]]}
+    trace = None
+    if not args.no_trace:
+        P.assemble()
+        tr = P.solve(timing=2, **kw)
+        trace = {"sweeps": tr["sweeps"], "phase_wall_us": [round(v, 2) for v in tr["phase_us"][:3]],
+                 "phase_busy_us": [round(v, 2) for v in tr["phase_us"][3:]]}
     return {
         "plan": P, "u": u, "rep": rep, "wall_ms": 1e3 * wall / K, "t_asm": t_asm, "t_sol": t_sol,
         "t_cmb": t_cmb, "t_plan_s": t_plan, "ndof": int(P.ndof.sum()), "trace": trace,
@@ -172,6 +177,15 @@ def main():
     import paper_1707_09598_amd as S
     import workloads as W
     S.lib()  # fail loudly if the HIP library is missing
+    if args.calibrate_copy > 0:
+        # plain copy of a known size: reads and writes calibrate the HBM counters
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     xi, _ = W.eval_points(2, 65536, lattice=args.lattice, seed=12345)
 
     main_run = run_mode(S, W, torch, args.precision, args, xi)

@@ -9,32 +9,55 @@ namespace igasg {
 
 // de Boor's triangular scheme (values and first derivatives of the p+1
 // B-splines non-zero on knot interval s), as on the host.
-__device__ __forceinline__ void d_basis_funs(int p, const double* U, int s, double x, double* N,
-                                             double* dN) {
-    double left[kMaxPg + 2], right[kMaxPg + 2];
-    double t[kMaxPg + 1][kMaxPg + 1];
+// Cox-de Boor values (and first derivatives) of the p+1 B-splines that are
+// non-zero on knot span s, by the triangular scheme (left/right differences).
+// Loops run to the compile-time bound PMAX with p <= PMAX masked at run time,
+// so every array index is a constant and the arrays stay in registers.
+template <int PMAX>
+__device__ __forceinline__ void d_basis_funs_m(int p, const double* U, int s, double x, double* N, double* dN) {
+    double left[PMAX + 2], right[PMAX + 2];
+    double t[PMAX + 1][PMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= PMAX; ++i)
+#pragma unroll
+        for (int j = 0; j <= PMAX; ++j) t[i][j] = 0.0;
     t[0][0] = 1.0;
-    for (int j = 1; j <= p; ++j) {
+#pragma unroll
+    for (int j = 1; j <= PMAX; ++j) {
+        if (j > p) break;
         left[j] = x - U[s + 1 - j];
         right[j] = U[s + j] - x;
         double saved = 0.0;
+#pragma unroll
         for (int r = 0; r < j; ++r) {
             t[j][r] = right[r + 1] + left[j - r];
-            double tmp = t[r][j - 1] / t[j][r];
+            const double tmp = t[r][j - 1] / t[j][r];
             t[r][j] = saved + right[r + 1] * tmp;
             saved = left[j - r] * tmp;
         }
         t[j][j] = saved;
     }
-    for (int r = 0; r <= p; ++r) N[r] = t[r][p];
-    if (dN) {
-        for (int r = 0; r <= p; ++r) {
-            double v = 0.0;
-            if (r >= 1) v += t[r - 1][p - 1] / t[p][r - 1];
-            if (r <= p - 1) v -= t[r][p - 1] / t[p][r];
-            dN[r] = p * v;
+    // N[r] = t[r][p]; dN from the degree p-1 functions and the knot differences
+    // t[p][r] (selected by a compile-time degree so that indices stay constant)
+#pragma unroll
+    for (int pp = 0; pp <= PMAX; ++pp) {
+        if (pp != p) continue;
+#pragma unroll
+        for (int r = 0; r <= pp; ++r) {
+            N[r] = t[r][pp];
+            if (dN) {
+                double v = 0.0;
+                if (pp >= 1) {
+                    if (r >= 1) v += t[r - 1][pp - 1] / t[pp][r - 1];
+                    if (r <= pp - 1) v -= t[r][pp - 1] / t[pp][r];
+                }
+                dN[r] = pp * v;
+            }
         }
     }
+}
+__device__ __forceinline__ void d_basis_funs(int p, const double* U, int s, double x, double* N, double* dN) {
+    d_basis_funs_m<kMaxPg>(p, U, s, x, N, dN);
 }
 
 __device__ __forceinline__ int d_find_interval(int p, int nk, const double* U, double x) {

@@ -436,15 +436,21 @@ __global__ void __launch_bounds__(kBlock) k_apply_fd(Params P, int gi, FdIO io, 
 // ===========================================================================
 // combination / evaluation: u(xi) = sum_c coef_c (sum_j x_j B_j(xi)) / W(xi)
 // ===========================================================================
+template <int PP>
 __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, const int* patch, int64_t n,
                                                    double* u, int g0, int g1, int use_coef) {
-    const int d = P.dim, p = P.p;
+    // loops run to compile-time bounds (dimension 3, degree PP, geometry
+    // degree kMaxPg) with run-time masks, so the local arrays stay in registers
+    const int d = P.dim;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kBlock) {
         double xv[3] = {0, 0, 0};
-        for (int k = 0; k < d; ++k) {
-            double t = xi[i * d + k];
-            xv[k] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k < d) {
+                const double t = xi[i * d + k];
+                xv[k] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            }
         }
         const int pt = patch ? patch[i] : 0;
         // weight function W(xi) of the geometry
@@ -453,60 +459,81 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
             double Ng[3][kMaxPg + 1];
             int fg[3] = {0, 0, 0};
             int pgk[3] = {0, 0, 0};
-            for (int k = 0; k < d; ++k) {
-                const Tab1D& T = P.tabs[P.grids[g0].tab[k]];
-                const double* gk = P.dpool + T.oGkn;
-                pgk[k] = T.pg;
-                int s = d_find_interval(T.pg, T.ngk, gk, xv[k]);
-                d_basis_funs(T.pg, gk, s, xv[k], Ng[k], nullptr);
-                fg[k] = s - T.pg;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+#pragma unroll
+                for (int a = 0; a <= kMaxPg; ++a) Ng[k][a] = a == 0 ? 1.0 : 0.0;
+                if (k < d) {
+                    const Tab1D& T = P.tabs[P.grids[g0].tab[k]];
+                    const double* gk = P.dpool + T.oGkn;
+                    pgk[k] = T.pg;
+                    const int s = d_find_interval(T.pg, T.ngk, gk, xv[k]);
+                    d_basis_funs_m<kMaxPg>(T.pg, gk, s, xv[k], Ng[k], nullptr);
+                    fg[k] = s - T.pg;
+                }
             }
             W = 0.0;
             const double* C = P.ctrl + P.ctrl_off[pt];
-            const int lim2 = d > 2 ? pgk[2] : 0;
-            for (int c = 0; c <= lim2; ++c)
-                for (int b = 0; b <= pgk[1]; ++b)
-                    for (int a = 0; a <= pgk[0]; ++a) {
-                        int64_t idx = (fg[0] + a) + static_cast<int64_t>(P.gn[pt][0]) *
-                                                        ((fg[1] + b) + static_cast<int64_t>(P.gn[pt][1]) * (d > 2 ? fg[2] + c : 0));
-                        W += C[idx * 4 + 3] * Ng[0][a] * Ng[1][b] * (d > 2 ? Ng[2][c] : 1.0);
+#pragma unroll
+            for (int c = 0; c <= kMaxPg; ++c) {
+                if (c > pgk[2]) break;
+#pragma unroll
+                for (int b = 0; b <= kMaxPg; ++b) {
+                    if (b > pgk[1]) break;
+#pragma unroll
+                    for (int a = 0; a <= kMaxPg; ++a) {
+                        if (a > pgk[0]) break;
+                        const int64_t idx = (fg[0] + a) + static_cast<int64_t>(P.gn[pt][0]) *
+                                                              ((fg[1] + b) + static_cast<int64_t>(P.gn[pt][1]) * (fg[2] + c));
+                        W += C[idx * 4 + 3] * Ng[0][a] * Ng[1][b] * Ng[2][c];
                     }
+                }
+            }
         }
         double acc = 0.0;
         for (int gi = g0; gi < g1; ++gi) {
             const Grid& g = P.grids[gi];
             if (g.patch != pt) continue;
-            double N[3][kMaxPg + 1];
+            double N[3][PP + 1];
             int f[3] = {0, 0, 0};
-            for (int k = 0; k < d; ++k) {
-                const Tab1D& T = P.tabs[g.tab[k]];
-                int e;
-                if (T.uniform) {
-                    e = static_cast<int>(xv[k] * T.E);
-                    e = e > T.E - 1 ? T.E - 1 : e;
-                } else {
-                    const double* brk = P.dpool + T.oBrk;
-                    int lo = 0, hi = T.E;
-                    while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
-                        if (xv[k] < brk[mid]) hi = mid;
-                        else lo = mid;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+#pragma unroll
+                for (int a = 0; a <= PP; ++a) N[k][a] = a == 0 ? 1.0 : 0.0;
+                if (k < d) {
+                    const Tab1D& T = P.tabs[g.tab[k]];
+                    int e;
+                    if (T.uniform) {
+                        e = static_cast<int>(xv[k] * T.E);
+                        e = e > T.E - 1 ? T.E - 1 : e;
+                    } else {
+                        const double* brk = P.dpool + T.oBrk;
+                        int lo = 0, hi = T.E;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (xv[k] < brk[mid]) hi = mid;
+                            else lo = mid;
+                        }
+                        e = lo;
                     }
-                    e = lo;
+                    d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + e * T.m, xv[k], N[k], nullptr);
+                    f[k] = e * T.m - 1;  // interior index of the first local function
                 }
-                d_basis_funs(p, P.dpool + T.oKn, p + e * T.m, xv[k], N[k], nullptr);
-                f[k] = e * T.m - 1;  // interior index of the first local function
             }
             double v = 0.0;
             const double* X = P.x + g.dof_off;
-            const int lim2 = d > 2 ? p : 0;
-            for (int c = 0; c <= lim2; ++c) {
+            const int lim2 = d > 2 ? PP : 0;
+#pragma unroll
+            for (int c = 0; c <= PP; ++c) {
+                if (c > lim2) break;
                 const int i3 = d > 2 ? f[2] + c : 0;
                 if (i3 < 0 || i3 >= g.ni[2]) continue;
-                for (int b = 0; b <= p; ++b) {
+#pragma unroll
+                for (int b = 0; b <= PP; ++b) {
                     const int i2 = f[1] + b;
                     if (i2 < 0 || i2 >= g.ni[1]) continue;
-                    for (int a = 0; a <= p; ++a) {
+#pragma unroll
+                    for (int a = 0; a <= PP; ++a) {
                         const int i1 = f[0] + a;
                         if (i1 < 0 || i1 >= g.ni[0]) continue;
                         v += X[i1 + static_cast<int64_t>(g.ni[0]) * (i2 + static_cast<int64_t>(g.ni[1]) * i3)] *
@@ -518,6 +545,17 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
         }
         u[i] = acc;
     }
+}
+
+hipError_t launch_combine(int p, int blocks, hipStream_t st, const Params& K, const double* xi, const int* patch,
+                          int64_t n, double* u, int g0, int g1, int use_coef) {
+    switch (p) {
+        case 1: hipLaunchKernelGGL(k_combine<1>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        case 2: hipLaunchKernelGGL(k_combine<2>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        case 3: hipLaunchKernelGGL(k_combine<3>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        default: hipLaunchKernelGGL(k_combine<4>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+    }
+    return hipGetLastError();
 }
 
 Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
@@ -886,8 +924,7 @@ iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int
     if (n == 0) return IGA_OK;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
-    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, K, xi, patch, n, u, 0,
-                       static_cast<int>(P->grids.size()), 1);
+    HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u, 0, static_cast<int>(P->grids.size()), 1));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
@@ -910,7 +947,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
         }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
-    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n)), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, 0);
+    HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
