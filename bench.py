@@ -31,6 +31,35 @@ sys.path.insert(0, ROOT)
 METRIC = "sparse-grid DOF/s to 1e-9 rel L2: batched mixed/learned PCG vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 
+# Memory traffic of the solve kernel (k_solve<3, FP32 factors> on this workload)
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
+# scaled by what the same counters read for a plain 256 MiB device copy in the
+# same runs (fetch 131088 KiB, write 262144 KiB).  Valid only for the kernel
+# sources it was measured on: their hash is checked at run time.
+SOLVE_TRAFFIC = {
+    "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
+                "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp"],
+    "sha256": None,
+    "fetch_kib": None, "write_kib": None,
+    "fetch_factor": 262144.0 / 131088.0, "write_factor": 262144.0 / 262144.0,
+}
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def solve_traffic_bytes():
+    T = SOLVE_TRAFFIC
+    if T["sha256"] is None or T["fetch_kib"] is None or sources_sha256(T["sources"]) != T["sha256"]:
+        return None
+    return 1024.0 * (T["fetch_kib"] * T["fetch_factor"] + T["write_kib"] * T["write_factor"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -244,7 +273,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_solve (persistent refinement + FD-PCG)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": solve_traffic_bytes(),
             "algorithmic_bytes_per_launch": algo, "avg_launch_ms": main_run["t_sol"],
         },
         "cpu_baseline": cpu,
