@@ -115,7 +115,7 @@ struct Task {
 // the tasks of a sweep read their description without a memory round trip.
 struct TaskMeta {
     Grid g;
-    Tab1D t[2];
+    Tab1D t[kMaxDim];
     int grid, local;
 };
 static_assert(sizeof(Grid) % 8 == 0 && sizeof(Tab1D) % 8 == 0 && sizeof(TaskMeta) % 8 == 0, "8-byte words");
@@ -168,6 +168,41 @@ inline IGA_HD FdLayout fd_layout(const Grid& g, int ldu_s, int ldu_b, int usize)
     L.Slab = o;
     L.rows = wide ? fd_slab_rows(nbig, bs, usize) : 0;
     o += L.rows * kBlock * 16;
+    L.total = o;
+    return L;
+}
+
+// LDS layout (byte offsets) of a 3D fast-diagonalisation task (one task per
+// grid): three grid-sized FP64 work tensors R, S, T; red; three FP64 values
+// per unknown (fetched operands); the factors U1, U2, U3 in the factor
+// precision (row strides ld[k]) for the directions whose bit is set in
+// g.fdstage (the others are read from global memory).  Reuses FdLayout: Us
+// holds U1, Ub U2, Slab U3, Out the third work tensor.
+inline IGA_HD FdLayout fd_layout_3d(const Grid& g, const int* ld, int usize) {
+    const int n = g.ni[0] * g.ni[1] * g.ni[2];
+    FdLayout L;
+    int o = 0;
+    L.R = o;
+    o += 8 * n;
+    L.S = o;
+    o += 8 * n;
+    L.Out = o;  // third work tensor T
+    o += 8 * n;
+    L.red = o;
+    o += 8 * kBigRed;
+    L.Own = o;
+    o += 8 * 3 * n;
+    o = (o + 15) & ~15;
+    L.Us = o;
+    if (g.fdstage & 1) o += g.ni[0] * ld[0] * usize;
+    o = (o + 15) & ~15;
+    L.Ub = o;
+    if (g.fdstage & 2) o += g.ni[1] * ld[1] * usize;
+    o = (o + 15) & ~15;
+    L.Slab = o;
+    if (g.fdstage & 4) o += g.ni[2] * ld[2] * usize;
+    o = (o + 15) & ~15;
+    L.rows = 0;
     L.total = o;
     return L;
 }

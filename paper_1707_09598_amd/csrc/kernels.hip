@@ -419,7 +419,10 @@ __global__ void __launch_bounds__(kBlock) k_apply_op(Params P, int gi, OpIO io) 
     meta_fill(P, Task{gi, 0}, M);
     OpIO a = io;
     a.part = nullptr;
-    for (int t = blockIdx.x; t < M->g.ntile; t += gridDim.x) op_tile_2d<PP>(P, M->g, M->t[0], M->t[1], t, a, lds);
+    for (int t = blockIdx.x; t < M->g.ntile; t += gridDim.x) {
+        if (P.dim == 3) op_tile_3d<PP>(P, M->g, M->t[0], M->t[1], M->t[2], t, a, lds);
+        else op_tile_2d<PP>(P, M->g, M->t[0], M->t[1], t, a, lds);
+    }
 }
 __global__ void __launch_bounds__(kBlock) k_apply_fd(Params P, int gi, FdIO io, int fwd) {
     extern __shared__ double lds_all[];
@@ -616,17 +619,17 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
 }
 
 // k_solve<PP, *> lives in one translation unit per degree (solve_p*.hip)
-const void* solve_kernel_p1(int prec);
-const void* solve_kernel_p2(int prec);
-const void* solve_kernel_p3(int prec);
-const void* solve_kernel_p4(int prec);
+const void* solve_kernel_p1(int prec, int dim);
+const void* solve_kernel_p2(int prec, int dim);
+const void* solve_kernel_p3(int prec, int dim);
+const void* solve_kernel_p4(int prec, int dim);
 
-const void* solve_kernel(int p, int prec) {
+const void* solve_kernel(int p, int prec, int dim) {
     switch (p) {
-        case 1: return solve_kernel_p1(prec);
-        case 2: return solve_kernel_p2(prec);
-        case 3: return solve_kernel_p3(prec);
-        default: return solve_kernel_p4(prec);
+        case 1: return solve_kernel_p1(prec, dim);
+        case 2: return solve_kernel_p2(prec, dim);
+        case 3: return solve_kernel_p3(prec, dim);
+        default: return solve_kernel_p4(prec, dim);
     }
 }
 
@@ -723,13 +726,13 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
         for (const void* k : ks)
             HIP_OK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
         for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD})
-            HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec), hipFuncAttributeMaxDynamicSharedMemorySize,
+            HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec, P->dim), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(P->lds_bytes)));
     }
     int occ = 1 << 20;
     for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD}) {
         int o = 0;
-        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec), kBlock, P->lds_bytes));
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec, P->dim), kBlock, P->lds_bytes));
         occ = std::min(occ, o);
     }
     P->max_wg = std::max(1, occ) * P->num_cu;
@@ -786,10 +789,6 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         set_error("invalid solve options");
         return IGA_ERR_INVALID_ARG;
     }
-    if (P->dim != 2) {
-        set_error("the GPU solve path currently supports dim = 2");
-        return IGA_ERR_INVALID_ARG;
-    }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     const bool lp = o->precision != IGA_PREC_FP64;  // FD blocking of the factor precision
     Params K = make_params(P, lp);
@@ -828,7 +827,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         if (o->workgroups > 0) want = o->workgroups;
         int nwg = std::max(1, std::min(want, P->max_wg));
         void* args[] = {&K, &A};
-        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision), dim3(nwg), dim3(kBlock), args,
+        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(kBlock), args,
                                           static_cast<unsigned>(lds), st));
         return IGA_OK;
     };
@@ -994,10 +993,6 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     if (!P->assembled) {
         set_error("iga_sg_apply before iga_sg_assemble");
         return IGA_ERR_STATE;
-    }
-    if (P->dim != 2) {
-        set_error("iga_sg_apply currently supports dim = 2");
-        return IGA_ERR_INVALID_ARG;
     }
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)

@@ -533,9 +533,36 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
                 g.tile[2] = 1;
             } else {
+                // 3D: tiles of about TT unknowns whose halo and element outputs fit in LDS
+                const int TT = env_int("IGA_OP_TILE3", 256);
+                const size_t pl = static_cast<size_t>(p + 1) * (p + 1) * (p + 1);
+                double best = -1.0;
                 g.tile[0] = g.ni[0];
                 g.tile[1] = g.ni[1];
                 g.tile[2] = g.ni[2];
+                for (int t3 = 1; t3 <= std::min(g.ni[2], 64); ++t3)
+                    for (int t2 = 1; t2 <= std::min(g.ni[1], 64); ++t2) {
+                        const int t1 = std::min(g.ni[0], std::max(1, TT / (t2 * t3)));
+                        const int t[3] = {t1, t2, t3};
+                        size_t nel = 1, halo = 1, ntl = 1;
+                        for (int k = 0; k < 3; ++k) {
+                            int lo, hi;
+                            elem_range(0, t[k], p, m, g.E[k], &lo, &hi);
+                            const int ne = hi - lo + 1 + (t[k] < g.ni[k] ? 1 : 0);
+                            nel *= ne;
+                            halo *= static_cast<size_t>(ne - 1) * m + p + 1;
+                            ntl *= (g.ni[k] + t[k] - 1) / t[k];
+                        }
+                        const size_t lds = (halo + nel * pl + kWaves) * sizeof(double);
+                        if (lds + kSolveLdsHead > kLdsLimit) continue;
+                        const double work = static_cast<double>(ntl) * (nel + 64.0);
+                        if (best < 0 || work < best) {
+                            best = work;
+                            g.tile[0] = t1;
+                            g.tile[1] = t2;
+                            g.tile[2] = t3;
+                        }
+                    }
             }
             g.ntile = 1;
             for (int k = 0; k < 3; ++k) {
@@ -543,6 +570,21 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.ntile *= g.ntd[k];
             }
             // LDS of one operator tile: halo unknowns + element outputs
+            if (d == 3) {
+                size_t halo = 1, nel = 1;
+                for (int k = 0; k < 3; ++k) {
+                    int lo, hi, bestk = 0;
+                    for (int t = 0; t < g.ntd[k]; ++t) {
+                        int a = t * g.tile[k], b = std::min(g.ni[k], a + g.tile[k]);
+                        elem_range(a, b, p, m, g.E[k], &lo, &hi);
+                        bestk = std::max(bestk, hi - lo + 1);
+                    }
+                    nel *= bestk;
+                    halo *= static_cast<size_t>(bestk - 1) * m + p + 1;
+                }
+                const size_t pl = static_cast<size_t>(p + 1) * (p + 1) * (p + 1);
+                lds_max = std::max(lds_max, (halo + nel * pl + kWaves) * sizeof(double));
+            }
             if (d == 2) {
                 size_t halo = 1, nel = 1;
                 for (int k = 0; k < d; ++k) {
@@ -588,12 +630,21 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(gc, ls, lb, usize).total));
                 }
             } else {
+                // 3D: one task per grid with the three factors staged in LDS
                 g.big = 0;
                 g.blk = g.ni[0];
                 g.nblk = 1;
+                const int ld[3] = {P->tabs[g.tab[0]].ldu, P->tabs[g.tab[1]].ldu, P->tabs[g.tab[2]].ldu};
+                // stage the factors in LDS, smallest first, while they fit (FP64 sizes)
+                int ord3[3] = {0, 1, 2};
+                std::sort(ord3, ord3 + 3, [&](int a, int b) { return g.ni[a] < g.ni[b]; });
+                g.fdstage = 0;
+                for (int k : ord3) {
+                    g.fdstage |= 1 << k;
+                    if (fd_layout_3d(g, ld, 8).total + kSolveLdsHead > kLdsLimit) g.fdstage &= ~(1 << k);
+                }
                 glp = g;
-                size_t lds = (3 * static_cast<size_t>(g.ndof) + kBlock) * sizeof(double);
-                lds_max = std::max(lds_max, lds);
+                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
             }
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);

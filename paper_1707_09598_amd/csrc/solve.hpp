@@ -229,6 +229,251 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// operator application (3D).  Items are (element, layer j3 of Gauss points);
+// one item computes the element's (p+1)^3 output contributions of its layer by
+// sum factorisation through the directions 3, 2, 1 and back; the NG lanes of
+// an element add their layers by a fixed butterfly.
+// ---------------------------------------------------------------------------
+template <int PP, bool RAT, typename T>
+__device__ __forceinline__ void elem_layer_3d(const double* X, int nh1, int nh2, int x1, int x2, int x3,
+                                              const double* B1, const double* D1, const double* B2,
+                                              const double* D2, const double* B3r, const double* D3r,
+                                              const T* Gl, int64_t nqp, int Q1, T (&Zb)[PP + 1][PP + 1],
+                                              T (&Zd)[PP + 1][PP + 1], T (&b3)[PP + 1], T (&d3)[PP + 1]) {
+    constexpr int NQ = PP + 1;
+    T tb[PP + 1][PP + 1], td[PP + 1][PP + 1];
+#pragma unroll
+    for (int a = 0; a <= PP; ++a) {
+        b3[a] = static_cast<T>(B3r[a]);
+        d3[a] = static_cast<T>(D3r[a]);
+    }
+    // contract direction 3: tb = sum_a3 b3 c, td = sum_a3 d3 c
+#pragma unroll
+    for (int a2 = 0; a2 <= PP; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) {
+            T u = T(0), v = T(0);
+#pragma unroll
+            for (int a3 = 0; a3 <= PP; ++a3) {
+                const T c = static_cast<T>(X[((x3 + a3) * nh2 + x2 + a2) * nh1 + x1 + a1]);
+                u += b3[a3] * c;
+                v += d3[a3] * c;
+            }
+            tb[a1][a2] = u;
+            td[a1][a2] = v;
+            Zb[a1][a2] = T(0);
+            Zd[a1][a2] = T(0);
+        }
+    // one row j2 at a time (not unrolled): bounds the loads in flight and the registers
+#pragma unroll 1
+    for (int j2 = 0; j2 < NQ; ++j2) {
+        T b2[PP + 1], d2[PP + 1];
+#pragma unroll
+        for (int a = 0; a <= PP; ++a) {
+            b2[a] = static_cast<T>(B2[j2 * NQ + a]);
+            d2[a] = static_cast<T>(D2[j2 * NQ + a]);
+        }
+        // contract direction 2
+        T ub[PP + 1], u2[PP + 1], u3[PP + 1];
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) {
+            T s0 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+            for (int a2 = 0; a2 <= PP; ++a2) {
+                s0 += b2[a2] * tb[a1][a2];
+                s2 += d2[a2] * tb[a1][a2];
+                s3 += b2[a2] * td[a1][a2];
+            }
+            ub[a1] = s0;
+            u2[a1] = s2;
+            u3[a1] = s3;
+        }
+        T w0[PP + 1], w2[PP + 1], w3[PP + 1];
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) w0[a1] = w2[a1] = w3[a1] = T(0);
+        const T* Gr = Gl + static_cast<int64_t>(j2) * Q1;
+#pragma unroll
+        for (int j1 = 0; j1 < NQ; ++j1) {
+            T b1[PP + 1], d1[PP + 1];
+#pragma unroll
+            for (int a = 0; a <= PP; ++a) {
+                b1[a] = static_cast<T>(B1[j1 * NQ + a]);
+                d1[a] = static_cast<T>(D1[j1 * NQ + a]);
+            }
+            T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+#pragma unroll
+            for (int a1 = 0; a1 <= PP; ++a1) {
+                if (RAT) v0 += b1[a1] * ub[a1];
+                v1 += d1[a1] * ub[a1];
+                v2 += b1[a1] * u2[a1];
+                v3 += b1[a1] * u3[a1];
+            }
+            T F0 = T(0), F1, F2, F3;
+            if (RAT) {
+                const T g00 = Gr[j1], g01 = Gr[nqp + j1], g02 = Gr[2 * nqp + j1], g03 = Gr[3 * nqp + j1];
+                const T g11 = Gr[4 * nqp + j1], g12 = Gr[5 * nqp + j1], g13 = Gr[6 * nqp + j1];
+                const T g22 = Gr[7 * nqp + j1], g23 = Gr[8 * nqp + j1], g33 = Gr[9 * nqp + j1];
+                F0 = g00 * v0 + g01 * v1 + g02 * v2 + g03 * v3;
+                F1 = g01 * v0 + g11 * v1 + g12 * v2 + g13 * v3;
+                F2 = g02 * v0 + g12 * v1 + g22 * v2 + g23 * v3;
+                F3 = g03 * v0 + g13 * v1 + g23 * v2 + g33 * v3;
+            } else {
+                const T g11 = Gr[j1], g12 = Gr[nqp + j1], g13 = Gr[2 * nqp + j1];
+                const T g22 = Gr[3 * nqp + j1], g23 = Gr[4 * nqp + j1], g33 = Gr[5 * nqp + j1];
+                F1 = g11 * v1 + g12 * v2 + g13 * v3;
+                F2 = g12 * v1 + g22 * v2 + g23 * v3;
+                F3 = g13 * v1 + g23 * v2 + g33 * v3;
+            }
+#pragma unroll
+            for (int a1 = 0; a1 <= PP; ++a1) {
+                w0[a1] += (RAT ? b1[a1] * F0 : T(0)) + d1[a1] * F1;  // tested by B2 B3 (value in 2, 3)
+                w2[a1] += b1[a1] * F2;                               // tested by D2 B3
+                w3[a1] += b1[a1] * F3;                               // tested by B2 D3
+            }
+        }
+#pragma unroll
+        for (int a2 = 0; a2 <= PP; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 <= PP; ++a1) {
+                Zb[a1][a2] += b2[a2] * w0[a1] + d2[a2] * w2[a1];
+                Zd[a1][a2] += b2[a2] * w3[a1];
+            }
+    }
+}
+
+template <int PP>
+__device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const Tab1D& T1, const Tab1D& T2,
+                                           const Tab1D& T3, int tile, const OpIO& io, double* lds) {
+    constexpr int NQ = PP + 1;
+    constexpr int NG = NQ <= 2 ? 2 : (NQ <= 4 ? 4 : 8);
+    constexpr int NE = NQ * NQ * NQ;
+    const int p = PP;
+    const int m1 = T1.m, m2 = T2.m, m3 = T3.m;
+    int r12;
+    const int t3 = FDiv(g.ntd[0] * g.ntd[1]).div(tile, &r12);
+    int t1;
+    const int t2 = FDiv(g.ntd[0]).div(r12, &t1);
+    const int a1 = t1 * g.tile[0], b1 = min(g.ni[0], a1 + g.tile[0]);
+    const int a2 = t2 * g.tile[1], b2 = min(g.ni[1], a2 + g.tile[1]);
+    const int a3 = t3 * g.tile[2], b3 = min(g.ni[2], a3 + g.tile[2]);
+    int el1, eh1, el2, eh2, el3, eh3;
+    d_elem_range(a1, b1, p, m1, g.E[0], &el1, &eh1);
+    d_elem_range(a2, b2, p, m2, g.E[1], &el2, &eh2);
+    d_elem_range(a3, b3, p, m3, g.E[2], &el3, &eh3);
+    const int ne1 = eh1 - el1 + 1, ne2 = eh2 - el2 + 1, ne3 = eh3 - el3 + 1;
+    const int hl1 = el1 * m1 - 1, hl2 = el2 * m2 - 1, hl3 = el3 * m3 - 1;
+    const int nh1 = eh1 * m1 + p - hl1, nh2 = eh2 * m2 + p - hl2, nh3 = eh3 * m3 + p - hl3;
+    double* X = lds;
+    double* Y = lds + nh1 * nh2 * nh3;
+    double* red = Y + ne1 * ne2 * ne3 * NE;
+    const int64_t off = g.dof_off;
+    const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2];
+    {
+        const FDiv dh1(nh1), dh12(nh1 * nh2);
+        for (int idx = threadIdx.x; idx < nh1 * nh2 * nh3; idx += kBlock) {
+            int r, q1;
+            const int q2 = dh12.div(idx, &r);
+            q1 = dh1.div(r, &r);
+            const int i1 = hl1 + r, i2 = hl2 + q1, i3 = hl3 + q2;
+            double v = 0.0;
+            if (i1 >= 0 && i1 < n1 && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3) {
+                const int64_t gi = off + (static_cast<int64_t>(i3) * n2 + i2) * n1 + i1;
+                v = io.in_a[gi];
+                if (io.in_b) v += io.beta * io.in_b[gi];
+                if (io.out_in && i1 >= a1 && i1 < b1 && i2 >= a2 && i2 < b2 && i3 >= a3 && i3 < b3)
+                    io.out_in[gi] = v;
+            }
+            X[idx] = v;
+        }
+    }
+    __syncthreads();
+    const int nqp1 = NQ * NQ;
+    const int64_t nqp = g.nqp;
+    const FDiv de1(ne1), de12(ne1 * ne2);
+    const bool rat = P.rational[g.patch] != 0;
+    const int nitem = ne1 * ne2 * ne3 * NG;
+    for (int it = threadIdx.x; it < nitem; it += kBlock) {
+        const int el = it / NG, j3 = it & (NG - 1);
+        int r, q1;
+        const int q2 = de12.div(el, &r);
+        q1 = de1.div(r, &r);
+        const int e1 = el1 + r, e2 = el2 + q1, e3 = el3 + q2;
+        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2, x3 = e3 * m3 - 1 - hl3;
+        const int jr = j3 < NQ ? j3 : 0;
+        const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
+        const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
+        const double* B2 = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1;
+        const double* D2 = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1;
+        const double* B3r = P.dpool + T3.oB + static_cast<int64_t>(e3) * nqp1 + jr * NQ;
+        const double* D3r = P.dpool + T3.oD + static_cast<int64_t>(e3) * nqp1 + jr * NQ;
+        // Gauss point (e1 NQ + j1, e2 NQ + j2, e3 NQ + j3), direction 1 fastest
+        const int64_t ql = (static_cast<int64_t>(e3 * NQ + jr) * g.Q[1] + e2 * NQ) * g.Q[0] + e1 * NQ;
+        double* Ye = Y + el * NE;
+        auto finish = [&](auto& Zb, auto& Zd, auto& b3v, auto& d3v) {
+#pragma unroll
+            for (int a3 = 0; a3 < NQ; ++a3)
+#pragma unroll
+                for (int a2 = 0; a2 < NQ; ++a2)
+#pragma unroll
+                    for (int a1 = 0; a1 < NQ; ++a1) {
+                        auto v = b3v[a3] * Zb[a1][a2] + d3v[a3] * Zd[a1][a2];
+                        if (j3 >= NQ) v = 0;
+#pragma unroll
+                        for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
+                        if (j3 == 0) Ye[a1 + NQ * (a2 + NQ * a3)] = static_cast<double>(v);
+                    }
+        };
+        if (io.lowp) {
+            float Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
+            const float* Gl = P.G32 + g.qp_off * P.ncompG + ql;
+            if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+            else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+            finish(Zb, Zd, b3v, d3v);
+        } else {
+            double Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
+            const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
+            if (rat) elem_layer_3d<PP, true, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+            else elem_layer_3d<PP, false, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+            finish(Zb, Zd, b3v, d3v);
+        }
+    }
+    __syncthreads();
+    const int w1 = b1 - a1, w2 = b2 - a2, nown = w1 * w2 * (b3 - a3);
+    double dot = 0.0;
+    const FDiv dw1(w1), dw12(w1 * w2);
+    for (int o = threadIdx.x; o < nown; o += kBlock) {
+        int r, q1;
+        const int q2 = dw12.div(o, &r);
+        q1 = dw1.div(r, &r);
+        const int i1 = a1 + r, i2 = a2 + q1, i3 = a3 + q2;
+        int lo1, hi1, lo2, hi2, lo3, hi3;
+        d_elem_range(i1, i1 + 1, p, m1, g.E[0], &lo1, &hi1);
+        d_elem_range(i2, i2 + 1, p, m2, g.E[1], &lo2, &hi2);
+        d_elem_range(i3, i3 + 1, p, m3, g.E[2], &lo3, &hi3);
+        double s = 0.0;
+        for (int e3 = lo3; e3 <= hi3; ++e3)
+            for (int e2 = lo2; e2 <= hi2; ++e2)
+                for (int e1 = lo1; e1 <= hi1; ++e1) {
+                    const int el = ((e3 - el3) * ne2 + (e2 - el2)) * ne1 + (e1 - el1);
+                    s += Y[el * NE + (i1 + 1 - e1 * m1) + NQ * ((i2 + 1 - e2 * m2) + NQ * (i3 + 1 - e3 * m3))];
+                }
+        const int64_t gi = off + (static_cast<int64_t>(i3) * n2 + i2) * n1 + i1;
+        if (io.rhs) {
+            s = io.rhs[gi] - s;
+            dot += s * s;
+        } else {
+            dot += X[((i3 - hl3) * nh2 + (i2 - hl2)) * nh1 + (i1 - hl1)] * s;
+        }
+        io.out[gi] = s;
+    }
+    if (io.part) {
+        const double t = wg_sum(dot, red);
+        if (threadIdx.x == 0) *io.part = t;
+    }
+    __syncthreads();
+}
+
 // ===========================================================================
 // fast diagonalisation: z = (U1 (x) U2) diag(1/(c1 l1 + c2 l2)) (U1 (x) U2)^T r
 // as mode products
@@ -241,7 +486,8 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
 // added in slice order (deterministic).
 template <typename TA, typename TB, typename TC>
 __device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
-                                           int sBn, double* C, int sCm, int sCn, double* red) {
+                                           int sBn, double* C, int sCm, int sCn, double* red, int nb = 1,
+                                           int sAb = 0, int sBb = 0, int sCb = 0) {
     constexpr int CH = 4;
     auto ld = [](auto* p, int i) -> TC {
         using V = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
@@ -252,13 +498,21 @@ __device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int
     const int L = cols ? N : M, S = cols ? M : N;
     const int nch = (S + CH - 1) / CH;
     const int base_items = L * nch;
-    int KS = 1;
-    while (KS < 8 && base_items * KS < kBlock && 2 * KS * M * N <= kBigRed && K >= 16 * KS) KS *= 2;
+    int KS = 1;  // K slices (single product only)
+    while (nb == 1 && KS < 8 && base_items * KS < kBlock && 2 * KS * M * N <= kBigRed && K >= 16 * KS) KS *= 2;
     const int kc = (K + KS - 1) / KS;
     const FDiv dl(L), dn(nch);
-    for (int it = threadIdx.x; it < base_items * KS; it += kBlock) {
+    for (int it = threadIdx.x; it < base_items * KS * nb; it += kBlock) {
         int rem, l;
-        const int ks = dn.div(dl.div(it, &l), &rem);
+        int ks = dn.div(dl.div(it, &l), &rem);
+        int bt = 0;  // batch index (nb > 1 implies KS == 1)
+        if (nb > 1) {
+            bt = ks;
+            ks = 0;
+        }
+        const TA* Ab = A + bt * sAb;
+        const TB* Bb = B + bt * sBb;
+        double* Cb = C + bt * sCb;
         const int s0 = rem * CH;
         int sq[CH];
 #pragma unroll
@@ -270,23 +524,23 @@ __device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int
         if (cols) {
 #pragma unroll 4
             for (int k = k0; k < k1; ++k) {
-                const TC b = ld(B, k * sBk + l * sBn);
+                const TC b = ld(Bb, k * sBk + l * sBn);
 #pragma unroll
-                for (int q = 0; q < CH; ++q) acc[q] += ld(A, sq[q] * sAm + k * sAk) * b;
+                for (int q = 0; q < CH; ++q) acc[q] += ld(Ab, sq[q] * sAm + k * sAk) * b;
             }
         } else {
 #pragma unroll 4
             for (int k = k0; k < k1; ++k) {
-                const TC a = ld(A, l * sAm + k * sAk);
+                const TC a = ld(Ab, l * sAm + k * sAk);
 #pragma unroll
-                for (int q = 0; q < CH; ++q) acc[q] += a * ld(B, k * sBk + sq[q] * sBn);
+                for (int q = 0; q < CH; ++q) acc[q] += a * ld(Bb, k * sBk + sq[q] * sBn);
             }
         }
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
             if (s0 + q < S) {
                 const int m = cols ? s0 + q : l, n = cols ? l : s0 + q;
-                if (KS == 1) C[m * sCm + n * sCn] = static_cast<double>(acc[q]);
+                if (KS == 1) Cb[m * sCm + n * sCn] = static_cast<double>(acc[q]);
                 else red[(ks * M + m) * N + n] = static_cast<double>(acc[q]);
             }
         }
@@ -752,6 +1006,125 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// 3D fast diagonalisation: one task per grid, the three factors staged in LDS,
+// six mode products (small_gemm; the middle one batched over direction 3).
+// ---------------------------------------------------------------------------
+template <typename TU>
+struct Fd3Lds {
+    double *R, *S, *T, *red, *Own;
+    const TU *U1, *U2, *U3;  // LDS copies, or the tables in global memory when not staged
+    int ld1, ld2, ld3;
+};
+template <typename TU>
+__device__ __forceinline__ Fd3Lds<TU> fd3_lds(const Params& P, const TaskMeta& M, double* lds) {
+    const int ld[3] = {M.t[0].ldu, M.t[1].ldu, M.t[2].ldu};
+    const FdLayout Y = fd_layout_3d(M.g, ld, sizeof(TU));
+    char* base = reinterpret_cast<char*>(lds);
+    Fd3Lds<TU> L;
+    L.R = reinterpret_cast<double*>(base + Y.R);
+    L.S = reinterpret_cast<double*>(base + Y.S);
+    L.T = reinterpret_cast<double*>(base + Y.Out);
+    L.red = reinterpret_cast<double*>(base + Y.red);
+    L.Own = reinterpret_cast<double*>(base + Y.Own);
+    const int st = M.g.fdstage;
+    L.U1 = (st & 1) ? reinterpret_cast<const TU*>(base + Y.Us) : u_ptr<TU>(P, M.t[0], false);
+    L.U2 = (st & 2) ? reinterpret_cast<const TU*>(base + Y.Ub) : u_ptr<TU>(P, M.t[1], false);
+    L.U3 = (st & 4) ? reinterpret_cast<const TU*>(base + Y.Slab) : u_ptr<TU>(P, M.t[2], false);
+    L.ld1 = ld[0];
+    L.ld2 = ld[1];
+    L.ld3 = ld[2];
+    return L;
+}
+template <typename TU>
+__device__ __forceinline__ void fd3_issue_factors(const Params& P, const TaskMeta& M, const Fd3Lds<TU>& L) {
+    const int us = static_cast<int>(sizeof(TU));
+    const int st = M.g.fdstage;
+    if (st & 1) g2l_bytes(u_ptr<TU>(P, M.t[0], false), M.g.ni[0] * L.ld1 * us, const_cast<TU*>(L.U1));
+    if (st & 2) g2l_bytes(u_ptr<TU>(P, M.t[1], false), M.g.ni[1] * L.ld2 * us, const_cast<TU*>(L.U2));
+    if (st & 4) g2l_bytes(u_ptr<TU>(P, M.t[2], false), M.g.ni[2] * L.ld3 * us, const_cast<TU*>(L.U3));
+}
+template <typename TU>
+__device__ __forceinline__ void fd3_issue_fwd(const Params& P, const TaskMeta& M, const double* r_src,
+                                              const double* q_src, const double* p_src, const double* d_src,
+                                              double* lds) {
+    const Grid& g = M.g;
+    const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
+    const int n = static_cast<int>(g.ndof);
+    const int64_t off = g.dof_off;
+    g2l_vec(r_src + off, n, L.R);
+    if (q_src) g2l_vec(q_src + off, n, L.S);
+    if (p_src) g2l_vec(p_src + off, n, L.Own);
+    if (d_src) g2l_vec(d_src + off, n, L.Own + n);
+    g2l_vec(P.dpool + g.oDinv, n, L.Own + 2 * n);
+    fd3_issue_factors<TU>(P, M, L);
+}
+template <typename TU>
+__device__ __forceinline__ void fd3_issue_bwd(const Params& P, const TaskMeta& M, const double* rt_src,
+                                              const double* rdot, double* lds) {
+    const Grid& g = M.g;
+    const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
+    const int n = static_cast<int>(g.ndof);
+    g2l_vec(rt_src + g.dof_off, n, L.R);
+    if (rdot) g2l_vec(rdot + g.dof_off, n, L.Own);
+    fd3_issue_factors<TU>(P, M, L);
+}
+// forward: r update (whole grid owned), then Rt = (U1 (x) U2 (x) U3)^T r / lambda
+template <typename TU, typename TC>
+__device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, const FdIO& io, double* lds) {
+    const Grid& g = M.g;
+    const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
+    const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
+    const int64_t off = g.dof_off;
+    if (io.q)
+        for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
+    __syncthreads();
+    double nrm = 0.0;
+    for (int o = threadIdx.x; o < n; o += kBlock) {
+        const double v = L.R[o];
+        if (io.r_out) io.r_out[off + o] = v;
+        if (io.dvec) io.dvec[off + o] = L.Own[n + o] + io.alpha * L.Own[o];
+        nrm += v * v;
+    }
+    if (io.part) {
+        const double t = wg_sum(nrm, L.red);
+        if (threadIdx.x == 0) *io.part = t;
+    }
+    __syncthreads();
+    // S[i3 i2][k1] = sum_i1 R[i3 i2][i1] U1[i1][k1]
+    small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1, L.red);
+    // T[i3][k2][k1] = sum_i2 U2[i2][k2] S[i3][i2][k1]
+    small_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, L.red, n3, 0, n12, n12);
+    // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1]
+    small_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, L.red);
+    for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
+    __syncthreads();
+}
+// backward: z = (U1 (x) U2 (x) U3) Rt; part = rdot . z
+template <typename TU, typename TC>
+__device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, const FdIO& io, double* lds) {
+    const Grid& g = M.g;
+    const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
+    const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
+    const int64_t off = g.dof_off;
+    // T[i3][k2 k1] = sum_k3 U3[i3][k3] Rt[k3][k2 k1]
+    small_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1, L.red);
+    // S[i3][i2][k1] = sum_k2 U2[i2][k2] T[i3][k2][k1]
+    small_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, L.red, n3, 0, n12, n12);
+    // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
+    small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, L.red);
+    double dot = 0.0;
+    for (int o = threadIdx.x; o < n; o += kBlock) {
+        io.z[off + o] = L.R[o];
+        if (io.rdot) dot += L.Own[o] * L.R[o];
+    }
+    if (io.part) {
+        const double t = wg_sum(dot, L.red);
+        if (threadIdx.x == 0) *io.part = t;
+    }
+    __syncthreads();
+}
+
 // Factor element types of the FD precisions
 // (0: FP64, 1: FP32, 2: BF16 factors with FP32 accumulation).
 template <int FDP> struct FdTypes;
@@ -771,7 +1144,7 @@ __device__ __forceinline__ void meta_fill(const Params& P, const Task& tk, TaskM
         M->local = tk.local;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * TW; i += kBlock) {
+    for (int i = threadIdx.x; i < kMaxDim * TW; i += kBlock) {
         const int k = i / TW, w = i % TW;
         const int ti = M->g.tab[k];
         uint64_t* tdst = reinterpret_cast<uint64_t*>(&M->t[k]);
@@ -952,7 +1325,7 @@ __device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int 
     }
 }
 
-template <int PP, int FDP>
+template <int PP, int FDP, int DIM>
 __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
     using TU = typename FdTypes<FDP>::TU;
     using TC = typename FdTypes<FDP>::TC;
@@ -1036,7 +1409,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             } else {
                 continue;
             }
-            op_tile_2d<PP>(P, g, M.t[0], M.t[1], M.local, io, lds);
+            if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], M.local, io, lds);
+            else op_tile_2d<PP>(P, g, M.t[0], M.t[1], M.local, io, lds);
         }
         trace_busy(A, sweep, 0, tb);
         grid_barrier(P.bar, nwg);
@@ -1050,7 +1424,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             CtxLoads c;
             if (wave0) ctx_issue(P, g, S0, M.grid, cur, nxt, 2, c);
             // operands of an iteration step, copied to LDS together with the context loads
-            fd_issue_fwd<TU>(P, M, M.local, r_old, P.q, p_new, P.d, lds);
+            if constexpr (DIM == 3) fd3_issue_fwd<TU>(P, M, r_old, P.q, p_new, P.d, lds);
+            else fd_issue_fwd<TU>(P, M, M.local, r_old, P.q, p_new, P.d, lds);
             if (wave0) ctx_finish(A, c, 2, ctx);
             g2l_wait_sync();
             const int act = ctx->D.act;
@@ -1078,7 +1453,14 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.pvec = nullptr;
                 // x += d, d = 0 on the owned unknowns (phase 1 has read both); a
                 // continued CG carries its search direction into this sweep's buffer
-                {
+                if constexpr (DIM == 3) {  // one task owns the grid
+                    for (int o = threadIdx.x; o < g.ndof; o += kBlock) {
+                        const int64_t kk = g.dof_off + o;
+                        P.x[kk] += P.d[kk];
+                        P.d[kk] = 0.0;
+                        if (A.continue_cg) p_new[kk] = p_old[kk];
+                    }
+                } else {
                     const FdBlock B(g, M.local);
                     for (int o = threadIdx.x; o < B.nown; o += kBlock) {
                         const int64_t kk = g.dof_off + B.gi(o);
@@ -1093,7 +1475,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             } else {
                 continue;
             }
-            fd_fwd_run<TU, TC>(P, M, M.local, io, lds);
+            if constexpr (DIM == 3) fd3_fwd_run<TU, TC>(P, M, io, lds);
+            else fd_fwd_run<TU, TC>(P, M, M.local, io, lds);
         }
         trace_busy(A, sweep, 1, tb);
         grid_barrier(P.bar, nwg);
@@ -1107,7 +1490,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             __syncthreads();
             CtxLoads c;
             if (wave0) ctx_issue(P, g, S0, gi, cur, nxt, 3, c);
-            fd_issue_bwd<TU>(P, M, M.local, P.rt, r_new, lds);
+            if constexpr (DIM == 3) fd3_issue_bwd<TU>(P, M, P.rt, r_new, lds);
+            else fd_issue_bwd<TU>(P, M, M.local, P.rt, r_new, lds);
             if (wave0) ctx_finish(A, c, 3, ctx);
             g2l_wait_sync();
             const int act = ctx->D.act;
@@ -1120,7 +1504,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.rdot = r_new;
                 io.prec = FDP;
                 io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
-                fd_bwd_run<TU, TC>(P, M, M.local, io, lds);
+                if constexpr (DIM == 3) fd3_bwd_run<TU, TC>(P, M, io, lds);
+                else fd_bwd_run<TU, TC>(P, M, M.local, io, lds);
             }
             if (M.local == 0 && threadIdx.x == 0) {
                 const GState& st = ctx->st;
@@ -1180,6 +1565,18 @@ __device__ __forceinline__ void fd_apply_block(const Params& P, const TaskMeta& 
     using TU = typename FdTypes<FDP>::TU;
     using TC = typename FdTypes<FDP>::TC;
     __syncthreads();
+    if (P.dim == 3) {
+        if (fwd) {
+            fd3_issue_fwd<TU>(P, M, io.r_old, io.q, io.pvec, io.dvec, lds);
+            g2l_wait_sync();
+            fd3_fwd_run<TU, TC>(P, M, io, lds);
+        } else {
+            fd3_issue_bwd<TU>(P, M, io.rt, io.rdot, lds);
+            g2l_wait_sync();
+            fd3_bwd_run<TU, TC>(P, M, io, lds);
+        }
+        return;
+    }
     if (fwd) {
         fd_issue_fwd<TU>(P, M, blk, io.r_old, io.q, io.pvec, io.dvec, lds);
         g2l_wait_sync();

@@ -1,13 +1,20 @@
-// solve_p2.hip -- k_solve for spline degree 2 in each inner precision.
+// solve_p2.hip -- k_solve for spline degree 2: each inner precision, 2D and 3D.
 #include "solve.hpp"
 
 namespace igasg {
 
-const void* solve_kernel_p2(int prec) {
+const void* solve_kernel_p2(int prec, int dim) {
+    if (dim == 3) {
+        switch (prec) {
+            case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 3>);
+            case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1, 3>);
+            default: return reinterpret_cast<const void*>(k_solve<2, 2, 3>);
+        }
+    }
     switch (prec) {
-        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0>);
-        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1>);
-        default: return reinterpret_cast<const void*>(k_solve<2, 2>);
+        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 2>);
+        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1, 2>);
+        default: return reinterpret_cast<const void*>(k_solve<2, 2, 2>);
     }
 }
 

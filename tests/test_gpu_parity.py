@@ -36,13 +36,22 @@ def S():
 
 def oracle_perm(nb):
     """GPU interior lexicographic index (direction 1 fastest) -> index of the
-    oracle's dense assembly (single patch: shorter direction fastest)."""
-    n1, n2 = nb[0] - 2, nb[1] - 2
-    i = np.arange(n1 * n2)
-    i1, i2 = i % n1, i // n1
-    if nb[1] < nb[0]:
-        return i2 + n2 * i1
-    return i1 + n1 * i2
+    oracle's dense assembly: single patch, directions ordered by basis count
+    (the oracle's exchange sort), the first one fastest."""
+    d = len(nb)
+    ni = [n - 2 for n in nb]
+    order = list(range(d))
+    for a in range(d):
+        for b in range(a + 1, d):
+            if nb[order[b]] < nb[order[a]]:
+                order[a], order[b] = order[b], order[a]
+    idx = np.arange(int(np.prod(ni)))
+    ik = [idx % ni[0], (idx // ni[0]) % ni[1]] + ([idx // (ni[0] * ni[1])] if d == 3 else [])
+    out, mult = np.zeros_like(idx), 1
+    for k in order:
+        out += ik[k] * mult
+        mult *= ni[k]
+    return out
 
 
 def rel(a, b):
@@ -56,10 +65,21 @@ def _bound(S, wl):
     return P
 
 
+def _config(name, w):
+    """Workload by name; the random-field cube takes its first coefficient sample
+    (a = exp(g) on a 24^3 vertex grid, seed 0)."""
+    if name == "cfg5":
+        a = W.grf_samples(1, n=24)[0]
+        return W.config(name, w=w, a=W._field("grid3d", data=a))
+    return W.config(name, w=w)
+
+
 @pytest.mark.parametrize("name,w,comps", [("cfg1", 4, None), ("cfg2", 5, None), ("cfg2", 7, None),
-                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20])])
+                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20]),
+                                          ("cfg3", 5, None), ("cfg3", 7, [0, 1, 2, 5, 9, 14]),
+                                          ("cfg5", 4, [0, 3, 6, 10])])
 def test_rhs_and_operator_parity(S, name, w, comps):
-    wl = W.config(name, w=w)
+    wl = _config(name, w)
     log(f"case rhs/operator {name} w={w}")
     P = _bound(S, wl)
     Po = O.Problem(wl)
@@ -79,17 +99,24 @@ def test_rhs_and_operator_parity(S, name, w, comps):
 
 
 @pytest.mark.parametrize("name,w,comps", [("cfg1", 5, None), ("cfg2", 7, None),
-                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20])])
+                                          ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20]),
+                                          ("cfg3", 6, None), ("cfg3", 8, [0, 4, 11, 20, 45])])
 def test_fast_diagonalisation_parity(S, name, w, comps):
     wl = W.config(name, w=w)
     log(f"case fd {name} w={w}")
     P = _bound(S, wl)
+    d = len(P.levels[0])
     for c, lv in enumerate(P.levels):
         if comps is not None and c not in comps:
             continue
-        K1, M1 = P.matrices_1d(0, int(lv[0]))
-        K2, M2 = P.matrices_1d(1, int(lv[1]))
-        Pk = np.kron(M2, K1) + np.kron(K2, M1)  # direction 1 fastest
+        KM = [P.matrices_1d(k, int(lv[k])) for k in range(d)]
+        if d == 2:
+            (K1, M1), (K2, M2) = KM
+            Pk = np.kron(M2, K1) + np.kron(K2, M1)  # direction 1 fastest
+        else:
+            (K1, M1), (K2, M2), (K3, M3) = KM
+            Pk = (np.kron(M3, np.kron(M2, K1)) + np.kron(M3, np.kron(K2, M1)) +
+                  np.kron(K3, np.kron(M2, M1)))
         x = W.random_vector(len(Pk), seed=7 + c)
         # dense reference with one refinement step (residual in extended
         # precision) so that its own error stays well below the FP64 bar
@@ -98,9 +125,8 @@ def test_fast_diagonalisation_parity(S, name, w, comps):
         ref = ref + np.linalg.solve(Pk, res)
         # the transform is backward stable: its forward error is about
         # kappa(P) eps, with kappa(P) from the 1D eigenvalues
-        l1 = P.fd_factor(0, int(lv[0]))[1]
-        l2 = P.fd_factor(1, int(lv[1]))[1]
-        kappa = (l1.max() + l2.max()) / (l1.min() + l2.min())
+        lam = [P.fd_factor(k, int(lv[k]))[1] for k in range(d)]
+        kappa = sum(l.max() for l in lam) / sum(l.min() for l in lam)
         tol64 = max(1e-12, 100 * 2.2e-16 * kappa)
         for which, tol in (("fd64", tol64), ("fd32", 1e-5), ("fd16", 2e-2)):
             z = P.apply(c, which, x).cpu().numpy()
@@ -121,11 +147,12 @@ def _solve_and_compare(S, wl, precision, batched, tol_coef, tol_sg, npts=4096):
     worst = 0.0
     for c, (lv, co) in enumerate(zip(P.levels, Po.split(coefs))):
         g = P.coeffs(c).cpu().numpy()
-        ref = co[0][1:-1, 1:-1].reshape(-1)
+        ref = co[0][(slice(1, -1),) * len(lv)].reshape(-1)
         e = rel(g, ref)
         worst = max(worst, e)
         assert e < tol_coef, (c, lv, e)
-    xi, _ = W.eval_points(2, npts, lattice=32, seed=12345)
+    dim = len(P.levels[0])
+    xi, _ = W.eval_points(dim, npts, lattice=32 if dim == 2 else 8, seed=12345)
     u = P.combine(xi).cpu().numpy()
     u_ref = Po.sg_eval(coefs, xi)
     e_sg = rel(u, u_ref)
@@ -153,6 +180,13 @@ def test_solve_parity_cfg2_fp64(S):
 def test_solve_parity_cfg2_mixed(S, precision):
     log(f"case solve cfg2 {precision}")
     _solve_and_compare(S, W.config("cfg2"), precision, True, 1e-9, 1e-9)
+
+
+@pytest.mark.parametrize("precision,w", [("fp64", 6), ("bf16fd", 6), ("fp64", 8)])
+def test_solve_parity_cube(S, precision, w):
+    log(f"case solve cfg3 w={w} {precision}")
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    _solve_and_compare(S, W.config("cfg3", w=w), precision, True, tol, tol)
 
 
 def test_single_component_edge_case(S):
