@@ -1,0 +1,154 @@
+"""Pins of the learned-preconditioner oracle (CPU): convolution against
+brute-force loops and exact identities, gradients against central
+differences, flexible CG against exactly known behaviour."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import learned as L
+
+
+def _rng(seed=0):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def test_shift_matches_index_definition():
+    x = _rng(1).standard_normal((2, 3, 4, 5))
+    for d3, d2, d1 in itertools.product((-1, 0, 1), repeat=3):
+        y = L.shift(x, d3, d2, d1)
+        for i3, i2, i1 in itertools.product(range(3), range(4), range(5)):
+            j3, j2, j1 = i3 + d3, i2 + d2, i1 + d1
+            want = x[:, j3, j2, j1] if (0 <= j3 < 3 and 0 <= j2 < 4 and 0 <= j1 < 5) else 0.0
+            assert np.all(y[:, i3, i2, i1] == want)
+
+
+def test_conv_brute_force_loops():
+    rng = _rng(2)
+    x = rng.standard_normal((2, 3, 4, 5))
+    w = rng.standard_normal((3, 2, 3, 3, 3))
+    b = rng.standard_normal(3)
+    y = L.conv3d(x, w, b)
+    n3, n2, n1 = x.shape[1:]
+    for co in range(3):
+        for i3, i2, i1 in itertools.product(range(n3), range(n2), range(n1)):
+            s = b[co]
+            for ci, t3, t2, t1 in itertools.product(range(2), range(3), range(3), range(3)):
+                j3, j2, j1 = i3 + t3 - 1, i2 + t2 - 1, i1 + t1 - 1
+                if 0 <= j3 < n3 and 0 <= j2 < n2 and 0 <= j1 < n1:
+                    s += w[co, ci, t3, t2, t1] * x[ci, j3, j2, j1]
+            assert abs(y[co, i3, i2, i1] - s) < 1e-12
+
+
+def test_delta_kernels_identity_and_shift():
+    x = _rng(3).standard_normal((1, 4, 5, 6))
+    w = np.zeros((1, 1, 3, 3, 3))
+    w[0, 0, 1, 1, 1] = 1.0
+    assert np.array_equal(L.conv3d(x, w, np.zeros(1)), x)
+    w[:] = 0.0
+    w[0, 0, 1, 1, 2] = 1.0  # neighbour +1 in direction 1
+    y = L.conv3d(x, w, np.zeros(1))
+    assert np.array_equal(y[0, :, :, :-1], x[0, :, :, 1:]) and np.all(y[0, :, :, -1] == 0.0)
+
+
+def test_adjoint_identity():
+    rng = _rng(4)
+    x = rng.standard_normal((3, 4, 3, 5))
+    y = rng.standard_normal((2, 4, 3, 5))
+    w = rng.standard_normal((2, 3, 3, 3, 3))
+    lhs = np.sum(L.conv3d(x, w, np.zeros(2)) * y)
+    rhs = np.sum(x * L.conv3d_adjoint(y, w))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+
+
+def test_gradients_central_differences():
+    rng = _rng(5)
+    net = L.Net([3, 4, 4, 1], seed=7)
+    x = rng.standard_normal((3, 3, 4, 5))
+    t = rng.standard_normal((1, 3, 4, 5))
+    count = t.size
+    _, grads = net.loss_and_grad(x, t, count)
+    h = 1e-6
+    for li in range(3):
+        w, b = net.layers[li]
+        for idx in [tuple(rng.integers(0, s) for s in w.shape) for _ in range(6)]:
+            w0 = w[idx]
+            w[idx] = w0 + h
+            lp, _ = net.loss_and_grad(x, t, count)
+            w[idx] = w0 - h
+            lm, _ = net.loss_and_grad(x, t, count)
+            w[idx] = w0
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[li][0][idx]) < 1e-6 * max(1.0, abs(fd)), (li, idx)
+        for k in range(b.shape[0]):
+            b0 = b[k]
+            b[k] = b0 + h
+            lp, _ = net.loss_and_grad(x, t, count)
+            b[k] = b0 - h
+            lm, _ = net.loss_and_grad(x, t, count)
+            b[k] = b0
+            assert abs((lp - lm) / (2 * h) - grads[li][1][k]) < 1e-6
+
+
+def test_flat_roundtrip_and_count():
+    net = L.Net([3, 16, 16, 1], seed=0)
+    f = net.flat()
+    assert f.size == 3 * 16 * 27 + 16 + 16 * 16 * 27 + 16 + 16 * 27 + 1
+    net2 = L.Net.from_flat([3, 16, 16, 1], f)
+    for (w, b), (w2, b2) in zip(net.layers, net2.layers):
+        assert np.array_equal(w, w2) and np.array_equal(b, b2)
+
+
+def _spd(n, seed):
+    rng = _rng(seed)
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return q @ np.diag(np.linspace(1.0, 300.0, n)) @ q.T
+
+
+def test_fcg_exact_preconditioner_one_step():
+    A = _spd(30, 6)
+    b = _rng(7).standard_normal(30)
+    x, it, _ = L.fcg(A, b, lambda r: np.linalg.solve(A, r), 1e-12, 50)
+    assert it == 1 and np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
+
+
+def test_fcg_with_linear_spd_preconditioner_equals_pcg():
+    """For a fixed SPD preconditioner z.r_old = 0 in exact arithmetic, so the
+    flexible iteration reproduces plain PCG (Fletcher-Reeves beta)."""
+    A = _spd(40, 8)
+    M = np.diag(np.diag(A))
+    b = _rng(9).standard_normal(40)
+    prec = lambda r: np.linalg.solve(M, r)
+    _, it_f, hist_f = L.fcg(A, b, prec, 1e-10, 200)
+    # plain PCG
+    x = np.zeros(40)
+    r = b.copy()
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [np.linalg.norm(r)]
+    for k in range(200):
+        q = A @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        hist.append(np.linalg.norm(r))
+        if hist[-1] <= 1e-10 * np.linalg.norm(b):
+            break
+        z = prec(r)
+        rzn = r @ z
+        p = z + (rzn / rz) * p
+        rz = rzn
+    assert it_f == len(hist) - 1
+    np.testing.assert_allclose(hist_f, hist, rtol=1e-6, atol=1e-12 * np.linalg.norm(b))
+
+
+def test_preconditioner_scale_equivariant():
+    rng = _rng(10)
+    net = L.Net([3, 4, 4, 1], seed=3)
+    r = rng.standard_normal((3, 4, 5))
+    zfd = rng.standard_normal((3, 4, 5))
+    la = rng.standard_normal((3, 4, 5))
+    z1 = L.precondition(net, r, zfd, la)
+    z2 = L.precondition(net, 7.5 * r, 7.5 * zfd, la)
+    np.testing.assert_allclose(z2, 7.5 * z1, rtol=1e-12, atol=1e-12)
