@@ -135,6 +135,11 @@ typedef struct {
     int continue_cg;   /* refinement steps of the mixed modes: 0 restarts CG from the new FP64
                           residual (classic iterative refinement); 1 replaces the recursive
                           residual by the FP64 one and continues CG with its search direction */
+    int precond;       /* 0: fast diagonalisation; 1: learned correction on top of it inside
+                          flexible CG (3D plans, network attached by iga_sg_set_network) */
+    int learned_iters; /* precond 1: the correction acts on the first learned_iters
+                          preconditionings of each (inner) solve, plain fast diagonalisation
+                          after them; 0 = on every one */
 } iga_sg_solve_opts;
 
 /* Per-component results; arrays are caller-owned host buffers of length
@@ -205,9 +210,10 @@ iga_status iga_sg_eval(iga_sg_plan plan, int comp, const double* xi_dev, const i
  * 1 fastest) to out_dev. */
 iga_status iga_sg_coeffs(iga_sg_plan plan, int comp, double* out_dev);
 
-/* Kernel-level hooks (tests): y = A_comp x (which = 0 FP64 operator, 1 FP32
- * operator) or y = P^-1 x (which = 2 FP64, 3 FP32, 4 BF16 fast
- * diagonalisation); x_dev, y_dev hold the component's interior unknowns. */
+/* Kernel-level hooks (tests, training data): y = A_comp x (which = 0 FP64
+ * operator, 1 FP32 operator), y = P^-1 x (which = 2 FP64, 3 FP32, 4 BF16 fast
+ * diagonalisation) or y = b - A x (which = 5, FP64); x_dev, y_dev hold the
+ * component's interior unknowns. */
 iga_status iga_sg_apply(iga_sg_plan plan, int comp, int which, const double* x_dev, double* y_dev);
 
 /* Load vector of component comp (after iga_sg_assemble) to out_dev. */

@@ -6,12 +6,14 @@ CPU-baseline leg use it; the GPU library shares no code with it.
 A small convolutional network acts on the tensor grid of one component: three
 3x3x3 convolutions with zero padding ("same" size), ReLU between them.  Its
 input channels are the normalised residual, the normalised fast-diagonalisation
-output and the centred log-coefficient at the unknowns; its output is a
-correction added to the fast-diagonalisation output (the preconditioner is
-z = z_FD + s N(r / s, z_FD / s, log a), s = ||r||).  The network is trained by
-minimising the mean squared error against (e - z_FD) / s on pairs (r, e) with
-A e = r taken from the iterates of the plain preconditioned CG.  Flexible CG
-(Polak-Ribiere beta) uses it as a variable preconditioner.
+output and the centred log-coefficient at the unknowns; its output y corrects
+the fast-diagonalisation output z_FD, either additively (head 0:
+z = z_FD + s y, s = ||z_FD||) or as a pointwise log-scale (head 1:
+z = z_FD exp(y)).  A corrected z that is not a descent direction (r.z <= 0) is
+replaced by z_FD.  The network is trained by minimising the mean squared error
+of the predicted z / s against e / s on pairs (r, e) with A e = r taken from
+the iterates of the plain preconditioned CG.  Flexible CG (Polak-Ribiere beta)
+uses it as a variable preconditioner.
 
 Tensors are [channels, n3, n2, n1] (direction 1 fastest), weights
 [c_out, c_in, 3, 3, 3] indexed [.., t3, t2, t1] with tap t acting on the
@@ -112,11 +114,17 @@ class Net:
             acts.append(h)
         return h, acts
 
-    def loss_and_grad(self, x: np.ndarray, t: np.ndarray, count: int):
-        """L = sum (y - t)^2 / (2 count) and its gradients (list of (dw, db))."""
+    def loss_and_grad(self, x: np.ndarray, t: np.ndarray, count: int, head: int = 0):
+        """L = sum (pred - t)^2 / (2 count) and its gradients (list of (dw, db));
+        pred = y (head 0) or x[1] exp(y) (head 1)."""
         y, acts = self.forward(x)
-        d = (y - t) / count
-        loss = 0.5 * float(np.sum((y - t) ** 2)) / count
+        if head == 0:
+            pred, dpred = y, 1.0
+        else:
+            pred = x[1:2] * np.exp(y)
+            dpred = pred  # d pred / d y
+        d = (pred - t) * dpred / count
+        loss = 0.5 * float(np.sum((pred - t) ** 2)) / count
         grads = [None] * len(self.layers)
         for li in range(len(self.layers) - 1, -1, -1):
             w, b = self.layers[li]
@@ -128,18 +136,24 @@ class Net:
 
 
 def features(r: np.ndarray, zfd: np.ndarray, loga: np.ndarray) -> Tuple[np.ndarray, float]:
-    """Network input [3, n3, n2, n1] and the scale s = ||r||."""
-    s = float(np.linalg.norm(r))
+    """Network input [3, n3, n2, n1] and the scale s = ||z_FD||."""
+    sr = float(np.linalg.norm(r))
+    sr = sr if sr > 0 else 1.0
+    s = float(np.linalg.norm(zfd))
     s = s if s > 0 else 1.0
     la = loga - loga.mean()
-    return np.stack([r / s, zfd / s, la]), s
+    return np.stack([r / sr, zfd / s, la]), s
 
 
-def precondition(net: Net, r: np.ndarray, zfd: np.ndarray, loga: np.ndarray) -> np.ndarray:
-    """z = z_FD + s N(r / s, z_FD / s, log a - mean)."""
+def precondition(net: Net, r: np.ndarray, zfd: np.ndarray, loga: np.ndarray, head: int = 0) -> np.ndarray:
+    """z = z_FD + s y (head 0) or z_FD exp(y) (head 1) with
+    y = N(r / ||r||, z_FD / s, log a - mean), s = ||z_FD||; z_FD itself when
+    the corrected z is not a descent direction."""
     x, s = features(r, zfd, loga)
     y, _ = net.forward(x)
-    return zfd + s * y[0]
+    z = zfd + s * y[0] if head == 0 else zfd * np.exp(y[0])
+    rz = float(np.sum(r * z))
+    return z if (rz > 0.0 and np.isfinite(rz)) else zfd
 
 
 def fcg(A: np.ndarray, b: np.ndarray, prec: Callable[[np.ndarray], np.ndarray], tol: float,

@@ -22,13 +22,14 @@ GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
 STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_ERR_OUT_OF_MEMORY",
           4: "IGA_ERR_DEVICE", 5: "IGA_ERR_NOT_CONVERGED", 6: "IGA_ERR_BREAKDOWN", 7: "IGA_ERR_STATE"}
-APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4}
+APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5}
 
 EXPORTS = (
     "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_bind", "iga_sg_components",
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
-    "iga_sg_last_error", "iga_sg_version",
+    "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network",
+    "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
 )
 
 
@@ -67,7 +68,8 @@ class _Field(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("batched", C.c_int), ("tol", C.c_double),
                 ("tol_inner", C.c_double), ("maxit", C.c_int), ("max_refine", C.c_int),
-                ("workgroups", C.c_int), ("timing", C.c_int), ("continue_cg", C.c_int)]
+                ("workgroups", C.c_int), ("timing", C.c_int), ("continue_cg", C.c_int),
+                ("precond", C.c_int), ("learned_iters", C.c_int)]
 
 
 class _Report(C.Structure):
@@ -119,6 +121,16 @@ def lib():
         L.iga_sg_destroy.restype = None
         L.iga_sg_last_error.restype = C.c_char_p
         L.iga_sg_version.restype = C.c_char_p
+        L.iga_sg_loga.argtypes = [vp, C.c_int, vp]
+        L.iga_sg_set_network.argtypes = [vp, _ip, C.c_int, vp, C.c_int]
+        L.iga_nn_param_count.argtypes = [_ip, C.c_int]
+        L.iga_nn_param_count.restype = C.c_int64
+        L.iga_nn_forward.argtypes = [_ip, C.c_int, vp, C.c_int, _ip, vp, vp, vp, vp]
+        L.iga_nn_backward.argtypes = [_ip, C.c_int, vp, C.c_int, _ip, vp, vp, vp, vp, C.c_int, C.c_double, vp,
+                                      vp, vp, vp]
+        L.iga_nn_adam.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                                  C.c_int, vp]
+        L.iga_nn_pair.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_int, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -269,9 +281,10 @@ class Plan:
 
     def solve(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
               maxit: int = 500, max_refine: int = 0, batched: bool = True, workgroups: int = 0,
-              timing: bool = False, check: bool = True, continue_cg: bool = False) -> Dict[str, Any]:
+              timing: bool = False, check: bool = True, continue_cg: bool = False,
+              learned: bool = False, learned_iters: int = 0) -> Dict[str, Any]:
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups,
-                  int(timing), int(continue_cg))
+                  int(timing), int(continue_cg), int(learned), int(learned_iters))
         it = np.zeros(self.ncomp, dtype=np.int32)
         rf = np.zeros(self.ncomp, dtype=np.int32)
         rr = np.zeros(self.ncomp)
@@ -289,10 +302,11 @@ class Plan:
 
     def solve_async(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
                     maxit: int = 500, max_refine: int = 0, batched: bool = True,
-                    workgroups: int = 0, continue_cg: bool = False) -> None:
+                    workgroups: int = 0, continue_cg: bool = False, learned: bool = False,
+                    learned_iters: int = 0) -> None:
         """Enqueue a solve without reading the report back (no host sync)."""
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0,
-                  int(continue_cg))
+                  int(continue_cg), int(learned), int(learned_iters))
         _check(lib().iga_sg_solve(self.h, C.byref(o), C.POINTER(_Report)()))
 
     def combine(self, xi, patch=None):
@@ -331,6 +345,21 @@ class Plan:
         _check(lib().iga_sg_rhs(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
 
+    def loga(self, comp: int):
+        import torch
+        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        _check(lib().iga_sg_loga(self.h, comp, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_network(self, net) -> None:
+        """Attach a Network for learned solves (None detaches)."""
+        if net is None:
+            _check(lib().iga_sg_set_network(self.h, None, 0, None, 0))
+            self._net = None
+            return
+        _check(lib().iga_sg_set_network(self.h, net._ch, net.nl, C.c_void_p(net.params.data_ptr()), net.head))
+        self._net = net
+
     def apply(self, comp: int, which: str, x):
         import torch
         x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
@@ -338,6 +367,86 @@ class Plan:
         _check(lib().iga_sg_apply(self.h, comp, APPLY[which], C.c_void_p(x.data_ptr()),
                                   C.c_void_p(y.data_ptr())))
         return y
+
+
+class Network:
+    """The learned preconditioner's network: parameters (FP32, device) and Adam
+    state; forward, backward and update run in the library's kernels."""
+
+    def __init__(self, channels=(3, 16, 16, 1), params=None, device="cuda:0", stream=None, head: int = 0):
+        import torch
+        self.head = int(head)
+        self.channels = tuple(int(c) for c in channels)
+        self._ch = (C.c_int * len(self.channels))(*self.channels)
+        self.nl = len(self.channels) - 1
+        self.count = int(lib().iga_nn_param_count(self._ch, self.nl))
+        if self.count < 0:
+            raise ValueError("invalid network description")
+        self.device = torch.device(device)
+        self.stream = stream
+        if params is None:
+            params = np.zeros(self.count, dtype=np.float32)
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32), device=self.device).contiguous()
+        if self.params.numel() != self.count:
+            raise ValueError("parameter count mismatch")
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.step = 0
+
+    def _s(self):
+        import torch
+        return C.c_void_p(self.stream.cuda_stream if self.stream is not None
+                          else torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, x, keep: bool = False):
+        """x [nb, 3, n3, n2, n1] FP32 device tensor -> y [nb, 1, n3, n2, n1]
+        (and the hidden activations when keep)."""
+        import torch
+        nb, n3, n2, n1 = int(x.shape[0]), int(x.shape[2]), int(x.shape[3]), int(x.shape[4])
+        n = (C.c_int * 3)(n1, n2, n3)
+        nh = sum(self.channels[1:-1]) * nb * n1 * n2 * n3
+        acts = torch.empty(max(nh, 1), dtype=torch.float32, device=self.device)
+        y = torch.empty((nb, self.channels[-1], n3, n2, n1), dtype=torch.float32, device=self.device)
+        _check(lib().iga_nn_forward(self._ch, self.nl, C.c_void_p(self.params.data_ptr()), nb, n,
+                                    C.c_void_p(x.data_ptr()), C.c_void_p(acts.data_ptr()),
+                                    C.c_void_p(y.data_ptr()), self._s()))
+        return (y, acts) if keep else y
+
+    def gradient(self, x, t):
+        """Loss sum (y - t)^2 / (2 count) and its gradient (into self.grads)."""
+        import torch
+        y, acts = self.forward(x, keep=True)
+        nb, n3, n2, n1 = int(x.shape[0]), int(x.shape[2]), int(x.shape[3]), int(x.shape[4])
+        n = (C.c_int * 3)(n1, n2, n3)
+        scratch = torch.empty(2 * nb * max(self.channels) * n1 * n2 * n3 + 2048, dtype=torch.float32,
+                              device=self.device)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(lib().iga_nn_backward(self._ch, self.nl, C.c_void_p(self.params.data_ptr()), nb, n,
+                                     C.c_void_p(x.data_ptr()), C.c_void_p(acts.data_ptr()),
+                                     C.c_void_p(y.data_ptr()), C.c_void_p(t.data_ptr()), self.head,
+                                     float(t.numel()), C.c_void_p(self.grads.data_ptr()),
+                                     C.c_void_p(loss.data_ptr()), C.c_void_p(scratch.data_ptr()), self._s()))
+        return loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        _check(lib().iga_nn_adam(C.c_void_p(self.params.data_ptr()), C.c_void_p(self.grads.data_ptr()),
+                                 C.c_void_p(self.m.data_ptr()), C.c_void_p(self.v.data_ptr()), self.count,
+                                 lr, beta1, beta2, eps, self.step, self._s()))
+
+
+def make_pair(r, zfd, loga, xs=None, xk=None, head: int = 0):
+    """Network input [3, n] and target [n] of one component (FP32 device
+    tensors) from FP64 device vectors."""
+    import torch
+    n = int(r.numel())
+    x = torch.empty((3, n), dtype=torch.float32, device=r.device)
+    t = torch.empty(n, dtype=torch.float32, device=r.device)
+    ptr = lambda v: C.c_void_p(v.data_ptr()) if v is not None else None
+    _check(lib().iga_nn_pair(ptr(r), ptr(zfd), ptr(loga), ptr(xs), ptr(xk), n, int(head), ptr(x), ptr(t),
+                             C.c_void_p(torch.cuda.current_stream(r.device).cuda_stream)))
+    return x, t
 
 
 def version() -> str:

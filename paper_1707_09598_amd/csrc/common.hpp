@@ -124,6 +124,8 @@ constexpr int kMetaFd = 5;     // cached fast-diagonalisation tasks per workgrou
 constexpr int kMetaSlots = kMetaOp + kMetaFd + 1;  // + one slot for tasks beyond the cache
 constexpr int kCtxBytes = 256;  // LDS for the per-task context
 constexpr int kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kNnHidden = 16;           // hidden channels of the learned preconditioner (max)
+constexpr int kNnFloatsPerDof = 3 + 2 * kNnHidden + 1;  // its LDS activations per unknown
 
 // LDS layout (byte offsets) of a 2D fast-diagonalisation task:
 //   R, S      two grid-sized FP64 work vectors
@@ -216,6 +218,7 @@ struct Layout {
     size_t st2;                   // GState[2][ngrid]
     size_t part;                  // partial sums
     size_t optask, fdtask, fdtask_lp;
+    size_t loga;                  // log a at the Greville points of the unknowns
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t total;
@@ -249,12 +252,16 @@ struct Params {
     double* q;
     double* rt;
     GState* st2;       // two buffers of ngrid
-    double* part;      // partial sums: [4 kinds][2 parity][max(nop, nfd)]
+    double* part;      // partial sums: [5 kinds][2 parity][max(nop, nfd)]
     int64_t part_stride;
     const Task* optask;
     const Task* fdtask;
     unsigned* bar;     // [0] count, [1] generation, [2] done counter
     double gx[8], gw[8];  // Gauss-Legendre rule on [-1, 1]
+    double* loga;      // log a at the Greville points of the unknowns [ndof_total]
+    const float* nn;   // learned preconditioner parameters (or nullptr)
+    int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
+    int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)
 };
 
 }  // namespace igasg

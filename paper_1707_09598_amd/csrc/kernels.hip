@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "iga_nn.h"
 #include "plan.hpp"
 #include "solve.hpp"
 
@@ -373,6 +374,76 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     }
 }
 
+// log a at the Greville point of every interior unknown (feature of the
+// learned preconditioner): xi*_k = (t_{j+1} + ... + t_{j+p}) / p for basis
+// j = i_k + 1 of direction k, mapped through F.
+__global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, int g1) {
+    const int64_t i0 = P.grids[g0].dof_off;
+    const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
+    const int p = P.p, d = P.dim;
+    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
+         gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+        int lo = g0, hi = g1 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.grids[mid].dof_off <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        const Grid& g = P.grids[lo];
+        int64_t l = gi - g.dof_off;
+        double xi[3] = {0, 0, 0};
+        int ik[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) {
+            ik[k] = static_cast<int>(l % g.ni[k]);
+            l /= g.ni[k];
+            const Tab1D& T = P.tabs[g.tab[k]];
+            const double* kn = P.dpool + T.oKn;
+            double s = 0.0;
+            for (int m = 1; m <= p; ++m) s += kn[ik[k] + 1 + m];
+            xi[k] = s / p;
+        }
+        // geometry map F(xi) = sum w P B / sum w B from the coarse geometry
+        const int pt = g.patch;
+        double Ng[3][kMaxPg + 1];
+        int fg[3] = {0, 0, 0}, pgk[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int a = 0; a <= kMaxPg; ++a) Ng[k][a] = a == 0 ? 1.0 : 0.0;
+            if (k < d) {
+                const Tab1D& T = P.tabs[g.tab[k]];
+                const double* gk = P.dpool + T.oGkn;
+                pgk[k] = T.pg;
+                const int sp = d_find_interval(T.pg, T.ngk, gk, xi[k]);
+                d_basis_funs_m<kMaxPg>(T.pg, gk, sp, xi[k], Ng[k], nullptr);
+                fg[k] = sp - T.pg;
+            }
+        }
+        double Xh[4] = {0, 0, 0, 0};
+        const double* C = P.ctrl + P.ctrl_off[pt];
+#pragma unroll
+        for (int c = 0; c <= kMaxPg; ++c) {
+            if (c > pgk[2]) break;
+#pragma unroll
+            for (int b = 0; b <= kMaxPg; ++b) {
+                if (b > pgk[1]) break;
+#pragma unroll
+                for (int a = 0; a <= kMaxPg; ++a) {
+                    if (a > pgk[0]) break;
+                    const int64_t idx = (fg[0] + a) + static_cast<int64_t>(P.gn[pt][0]) *
+                                                          ((fg[1] + b) + static_cast<int64_t>(P.gn[pt][1]) * (fg[2] + c));
+                    const double B = Ng[0][a] * Ng[1][b] * Ng[2][c];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) Xh[t] += C[idx * 4 + t] * B;
+                }
+            }
+        }
+        double x[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) x[k] = Xh[k] / Xh[3];
+        P.loga[gi] = log(field_eval(fa, d, x));
+    }
+}
+
 // Reset solver state and vectors of a grid range before a solve.
 __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1, int64_t i0, int64_t i1) {
     const int64_t N = P.ndof_total;
@@ -611,6 +682,10 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     K.optask = reinterpret_cast<const Task*>(base + L.optask);
     K.fdtask = reinterpret_cast<const Task*>(base + (lowp_fd ? L.fdtask_lp : L.fdtask));
     K.bar = reinterpret_cast<unsigned*>(base + L.bar);
+    K.loga = reinterpret_cast<double*>(base + L.loga);
+    K.nn = P->nn;
+    for (int i = 0; i < 4; ++i) K.nn_ch[i] = P->nn_ch[i];
+    K.nn_head = P->nn_head;
     for (int i = 0; i < P->nq && i < 8; ++i) {
         K.gx[i] = P->gauss_x[i];
         K.gw[i] = P->gauss_w[i];
@@ -771,6 +846,8 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_rhs, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_loga, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, to_dev(a), 0, ng);
+    HIP_OK(hipGetLastError());
     P->assembled = true;
     P->solved = false;
     return IGA_OK;
@@ -806,6 +883,12 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     A.tol_in2 = ti * ti;
     A.max_sweeps = (A.maxit + 2) * (A.max_refine + 1) + 4;
     A.continue_cg = o->continue_cg != 0 && o->precision != IGA_PREC_FP64;
+    A.learned = o->precond == 1 ? 1 : 0;
+    A.learned_iters = o->learned_iters > 0 ? o->learned_iters : 0;
+    if (A.learned && (P->dim != 3 || !P->nn)) {
+        set_error("learned preconditioning needs a three-dimensional plan and an attached network");
+        return IGA_ERR_INVALID_ARG;
+    }
     char* trbase = reinterpret_cast<char*>(P->ws) + P->lay.trace;
     A.trace = o->timing >= 2 ? reinterpret_cast<unsigned long long*>(trbase) : nullptr;
     A.trace_sweeps = kTraceSweeps;
@@ -968,6 +1051,48 @@ iga_status iga_sg_coeffs(iga_sg_plan P, int comp, double* out) {
     return IGA_OK;
 }
 
+iga_status iga_sg_loga(iga_sg_plan P, int comp, double* out) {
+    if (!P || comp < 0 || comp >= P->ncomp || !out) {
+        set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->assembled) {
+        set_error("iga_sg_loga before iga_sg_assemble");
+        return IGA_ERR_STATE;
+    }
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    Params K = make_params(P);
+    for (const Grid& g : P->grids)
+        if (g.comp == comp)
+            HIP_OK(hipMemcpyAsync(out, K.loga + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+    return IGA_OK;
+}
+
+iga_status iga_sg_set_network(iga_sg_plan P, const int* channels, int nlayers, const float* params_dev, int head) {
+    if (!P) {
+        set_error("null plan");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!params_dev) {
+        P->nn = nullptr;
+        return IGA_OK;
+    }
+    if (P->dim != 3 || !channels || nlayers != 3 || channels[0] != 3 || channels[3] != 1 || channels[1] < 1 ||
+        channels[1] > kNnHidden || channels[2] < 1 || channels[2] > kNnHidden) {
+        set_error("the learned preconditioner takes 3 layers, channels 3 -> h1 -> h2 -> 1 (h <= %d), 3D plans",
+                  kNnHidden);
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (head < 0 || head > 1) {
+        set_error("network head must be 0 (additive) or 1 (log-scale)");
+        return IGA_ERR_INVALID_ARG;
+    }
+    P->nn = params_dev;
+    for (int i = 0; i < 4; ++i) P->nn_ch[i] = channels[i];
+    P->nn_head = head;
+    return IGA_OK;
+}
+
 iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
     if (!P || comp < 0 || comp >= P->ncomp || !out) {
         set_error("invalid arguments");
@@ -986,7 +1111,7 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
 }
 
 iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, double* y) {
-    if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 4) {
+    if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 5) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -997,23 +1122,23 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)
         if (P->grids[i].comp == comp) gi = i;
-    const bool lp = which >= 3;  // FD with FP32/BF16 factors uses their blocking
+    const bool lp = which == 3 || which == 4;  // FD with FP32/BF16 factors uses their blocking
     const Grid& g = (lp ? P->grids_lp : P->grids)[gi];
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P, lp);
     // the hooks read/write the caller's vectors shifted to the grid's offset
     const double* xs = x - g.dof_off;
     double* ys = y - g.dof_off;
-    if (which <= 1) {
+    if (which <= 1 || which == 5) {
         OpIO io;
         io.in_a = xs;
         io.in_b = nullptr;
         io.beta = 0.0;
         io.out_in = nullptr;
         io.out = ys;
-        io.rhs = nullptr;
+        io.rhs = which == 5 ? K.b : nullptr;  // residual b - A x
         io.part = nullptr;
-        io.lowp = which;
+        io.lowp = which == 1 ? 1 : 0;
         switch (P->p) {
             case 1: hipLaunchKernelGGL(k_apply_op<1>, dim3(g.ntile), dim3(kBlock), P->lds_bytes, st, K, gi, io); break;
             case 2: hipLaunchKernelGGL(k_apply_op<2>, dim3(g.ntile), dim3(kBlock), P->lds_bytes, st, K, gi, io); break;

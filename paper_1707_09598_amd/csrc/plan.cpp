@@ -639,12 +639,15 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 int ord3[3] = {0, 1, 2};
                 std::sort(ord3, ord3 + 3, [&](int a, int b) { return g.ni[a] < g.ni[b]; });
                 g.fdstage = 0;
+                const size_t nn_bytes = static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float);
                 for (int k : ord3) {
                     g.fdstage |= 1 << k;
-                    if (fd_layout_3d(g, ld, 8).total + kSolveLdsHead > kLdsLimit) g.fdstage &= ~(1 << k);
+                    if (fd_layout_3d(g, ld, 8).total + nn_bytes + kSolveLdsHead > kLdsLimit) g.fdstage &= ~(1 << k);
                 }
                 glp = g;
-                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
+                // + the activations of the learned preconditioner
+                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total) +
+                                                static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float));
             }
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);
@@ -716,7 +719,8 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.rt = take(sizeof(double) * nd);
     L.st2 = take(sizeof(GState) * ng * 2);
     size_t pst = std::max(P->optask.size(), std::max(P->fdtask.size(), P->fdtask_lp.size()));
-    L.part = take(sizeof(double) * pst * 8);
+    L.part = take(sizeof(double) * pst * 10);
+    L.loga = take(sizeof(double) * nd);
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());

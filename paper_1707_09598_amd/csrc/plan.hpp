@@ -69,6 +69,9 @@ struct iga_sg_plan_s {
     int num_cu = 0;
     int max_wg = 0;
     void* ev[8] = {nullptr};  // timing events
+    const float* nn = nullptr;  // learned preconditioner parameters (device, caller-owned)
+    int nn_ch[4] = {0, 0, 0, 0};
+    int nn_head = 0;
 };
 
 namespace igasg {

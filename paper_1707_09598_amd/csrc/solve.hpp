@@ -591,6 +591,10 @@ struct FdIO {
     double* z;            // backward output
     const double* rdot;   // backward: dot partner (or nullptr)
     int prec;             // 0 FP64, 1 FP32, 2 BF16 factors
+    // learned preconditioner (3D backward transform only)
+    int learned;
+    const double* rold;   // previous residual: part2 = z . rold (flexible CG)
+    double* part2;
 };
 
 
@@ -1100,7 +1104,49 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
     __syncthreads();
 }
-// backward: z = (U1 (x) U2 (x) U3) Rt; part = rdot . z
+// One 3x3x3 convolution layer on LDS tensors (zero padding): out[co][i] =
+// b[co] + sum_ci sum_t w[co][ci][t] in[ci](i + t - 1), optional ReLU; weights
+// from global memory (the same for every workgroup).
+__device__ __forceinline__ void cnn_layer(const float* __restrict__ w, const float* __restrict__ b, const float* in,
+                                          int cin, float* out, int cout, int n1, int n2, int n3, bool relu) {
+    const int n = n1 * n2 * n3;
+    const FDiv dn(n), d1(n1), d12(n1 * n2);
+    for (int o = threadIdx.x; o < cout * n; o += kBlock) {
+        int i;
+        const int co = dn.div(o, &i);
+        int r, i1;
+        const int i3 = d12.div(i, &r);
+        const int i2 = d1.div(r, &i1);
+        float s = b[co];
+        for (int ci = 0; ci < cin; ++ci) {
+            const float* wc = w + (co * cin + ci) * 27;
+            const float* xc = in + ci * n;
+#pragma unroll
+            for (int t3 = 0; t3 < 3; ++t3) {
+                const int j3 = i3 + t3 - 1;
+                if (j3 < 0 || j3 >= n3) continue;
+#pragma unroll
+                for (int t2 = 0; t2 < 3; ++t2) {
+                    const int j2 = i2 + t2 - 1;
+                    if (j2 < 0 || j2 >= n2) continue;
+#pragma unroll
+                    for (int t1 = 0; t1 < 3; ++t1) {
+                        const int j1 = i1 + t1 - 1;
+                        if (j1 < 0 || j1 >= n1) continue;
+                        s += wc[(t3 * 3 + t2) * 3 + t1] * xc[(j3 * n2 + j2) * n1 + j1];
+                    }
+                }
+            }
+        }
+        out[o] = relu && s < 0.0f ? 0.0f : s;
+    }
+    __syncthreads();
+}
+
+// backward: z = (U1 (x) U2 (x) U3) Rt; part = rdot . z.  With io.learned the
+// network y = N(r / ||r||, z_FD / s, log a - mean), s = ||z_FD||, corrects
+// z_FD: z = z_FD + s y (additive head) or z = z_FD exp(y) (log-scale head),
+// unless r . z <= 0 (then z = z_FD); part2 (if set) = z . rold.
 template <typename TU, typename TC>
 __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, const FdIO& io, double* lds) {
     const Grid& g = M.g;
@@ -1113,14 +1159,66 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     small_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, L.red, n3, 0, n12, n12);
     // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
     small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, L.red);
-    double dot = 0.0;
+    double scale = 0.0;  // s (additive head), -1 (log-scale head), 0: no learned correction
+    float* Y = nullptr;
+    if (io.learned) {
+        // features in LDS after the factor region: X0 [3][n], H1, H2, Y [n]
+        const int ld[3] = {M.t[0].ldu, M.t[1].ldu, M.t[2].ldu};
+        float* X0 = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + fd_layout_3d(g, ld, sizeof(TU)).total);
+        const int h1 = P.nn_ch[1], h2 = P.nn_ch[2];
+        float* H1 = X0 + 3 * n;
+        float* H2 = H1 + kNnHidden * n;
+        Y = H2 + kNnHidden * n;
+        double r2 = 0.0, z2 = 0.0, sa = 0.0;
+        for (int i = threadIdx.x; i < n; i += kBlock) {
+            r2 += L.Own[i] * L.Own[i];
+            z2 += L.R[i] * L.R[i];
+            sa += P.loga[off + i];
+        }
+        r2 = wg_sum(r2, L.red);
+        z2 = wg_sum(z2, L.red);
+        sa = wg_sum(sa, L.red);
+        const double sr = r2 > 0.0 ? sqrt(r2) : 1.0;
+        const double s = z2 > 0.0 ? sqrt(z2) : 1.0;
+        const double mean = sa / n;
+        for (int i = threadIdx.x; i < n; i += kBlock) {
+            X0[i] = static_cast<float>(L.Own[i] / sr);
+            X0[n + i] = static_cast<float>(L.R[i] / s);
+            X0[2 * n + i] = static_cast<float>(P.loga[off + i] - mean);
+        }
+        __syncthreads();
+        const float* w1 = P.nn;
+        const float* b1 = w1 + h1 * 3 * 27;
+        const float* w2 = b1 + h1;
+        const float* b2 = w2 + h2 * h1 * 27;
+        const float* w3 = b2 + h2;
+        const float* b3 = w3 + h2 * 27;
+        cnn_layer(w1, b1, X0, 3, H1, h1, n1, n2, n3, true);
+        cnn_layer(w2, b2, H1, h1, H2, h2, n1, n2, n3, true);
+        cnn_layer(w3, b3, H2, h2, Y, 1, n1, n2, n3, false);
+        // acceptance: the corrected z must be a descent direction (r . z > 0)
+        const bool mult = P.nn_head == 1;
+        double rz = 0.0;
+        for (int i = threadIdx.x; i < n; i += kBlock)
+            rz += L.Own[i] * (mult ? L.R[i] * exp(static_cast<double>(Y[i])) : L.R[i] + s * Y[i]);
+        rz = wg_sum(rz, L.red);
+        if (rz > 0.0 && isfinite(rz)) scale = mult ? -1.0 : s;
+    }
+    double dot = 0.0, dot2 = 0.0;
     for (int o = threadIdx.x; o < n; o += kBlock) {
-        io.z[off + o] = L.R[o];
-        if (io.rdot) dot += L.Own[o] * L.R[o];
+        const double zo = scale > 0.0 ? L.R[o] + scale * Y[o]
+                                      : (scale < 0.0 ? L.R[o] * exp(static_cast<double>(Y[o])) : L.R[o]);
+        io.z[off + o] = zo;
+        if (io.rdot) dot += L.Own[o] * zo;
+        if (io.part2) dot2 += io.rold[off + o] * zo;
     }
     if (io.part) {
         const double t = wg_sum(dot, L.red);
         if (threadIdx.x == 0) *io.part = t;
+    }
+    if (io.part2) {
+        const double t = wg_sum(dot2, L.red);
+        if (threadIdx.x == 0) *io.part2 = t;
     }
     __syncthreads();
 }
@@ -1194,6 +1292,8 @@ struct SolveArgs {
     int prec;                     // inner precision (IGA_PREC_*)
     int maxit, max_refine, max_sweeps;
     int continue_cg;              // keep the search direction across residual replacements
+    int learned;                  // learned correction inside flexible CG (3D)
+    int learned_iters;            // ... on the first learned_iters preconditionings (0: all)
     double tol2, tol_in2;
     unsigned long long* trace;    // phase timestamps (or nullptr)
     int trace_sweeps;
@@ -1214,7 +1314,7 @@ __device__ __forceinline__ void trace_mark(const SolveArgs& A, int sweep, int ph
 __device__ __forceinline__ double* part_ptr(const Params& P, int kind, int parity) {
     return P.part + static_cast<int64_t>(kind * 2 + parity) * P.part_stride;
 }
-enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3 };
+enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3, PK_ZRO = 4 };
 enum { ACT_SKIP = 0, ACT_RESID, ACT_ITER, ACT_DONE };
 
 struct Decision {
@@ -1274,13 +1374,14 @@ struct TaskCtx {
     Decision D;
     double pq;    // p.Ap of the current iteration (phases 2-3)
     double rn2;   // ||b - A x||^2 of a residual sweep (phase 3)
+    double zro;   // z . r_old of the last preconditioning (flexible CG, phase 1)
 };
 static_assert(sizeof(TaskCtx) <= kCtxBytes, "TaskCtx too large");
 
 // Wavefront-0 registers of a task context between issue and finish.
 struct CtxLoads {
     GState st;
-    double vrz, vpq, vres;
+    double vrz, vpq, vres, vzro;
 };
 
 __device__ __forceinline__ double sum_strided(const double* p, int count) {
@@ -1301,6 +1402,7 @@ __device__ __forceinline__ void ctx_issue(const Params& P, const Grid& g, const 
                                           int phase, CtxLoads& c) {
     c.st = S0[gi];
     c.vrz = sum_strided(part_ptr(P, PK_RZ, nxt) + g.blk_off, g.nblk);
+    c.vzro = phase == 1 ? sum_strided(part_ptr(P, PK_ZRO, nxt) + g.blk_off, g.nblk) : 0.0;
     c.vpq = 0.0;
     c.vres = 0.0;
     if (phase >= 2) {
@@ -1315,6 +1417,7 @@ __device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int 
         c.vrz += __shfl_xor(c.vrz, o, 64);
         c.vpq += __shfl_xor(c.vpq, o, 64);
         c.vres += __shfl_xor(c.vres, o, 64);
+        c.vzro += __shfl_xor(c.vzro, o, 64);
     }
     const Decision D = decide(A, c.st, c.st.stage == STAGE_ITER ? c.vrz : 0.0);
     if (threadIdx.x == 0) {
@@ -1322,6 +1425,7 @@ __device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int 
         ctx->D = D;
         ctx->pq = (phase >= 2 && D.act == ACT_ITER) ? c.vpq : 0.0;
         ctx->rn2 = (phase == 3 && D.act == ACT_RESID) ? c.vres : 0.0;
+        ctx->zro = c.vzro;
     }
 }
 
@@ -1390,7 +1494,9 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 // beta = 0 at the start of a solve; after a residual replacement
                 // either restart (0) or continue with the previous rho (continue_cg)
                 const bool fresh = ctx->st.it == 0 && (!A.continue_cg || ctx->st.refine <= 1);
-                io.beta = fresh ? 0.0 : ctx->D.rho / ctx->st.rho;
+                // flexible CG (variable preconditioner): beta = z.(r - r_old) / rho_old
+                const double num = A.learned && ctx->st.it > 0 ? ctx->D.rho - ctx->zro : ctx->D.rho;
+                io.beta = fresh ? 0.0 : num / ctx->st.rho;
                 io.out_in = p_new;
                 io.out = P.q;
                 io.rhs = nullptr;
@@ -1432,6 +1538,9 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             FdIO io;
             io.rt = P.rt;
             io.prec = FDP;
+            io.learned = 0;
+            io.rold = nullptr;
+            io.part2 = nullptr;
             io.z = nullptr;
             io.rdot = nullptr;
             io.part = part_ptr(P, PK_RR, cur) + g.blk_off + M.local;
@@ -1504,6 +1613,14 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.rdot = r_new;
                 io.prec = FDP;
                 io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
+                // the learned map preconditions the residuals of a (re)started
+                // solve from the first one on, up to learned_iters of them; z . r_old
+                // (flexible CG beta) on every iteration of a learned solve
+                io.learned = DIM == 3 && A.learned && P.nn != nullptr &&
+                             (A.learned_iters == 0 || (act == ACT_ITER ? ctx->st.it + 1 : 0) < A.learned_iters);
+                io.rold = r_old;
+                io.part2 = DIM == 3 && A.learned && act == ACT_ITER ? part_ptr(P, PK_ZRO, cur) + g.blk_off + M.local
+                                                                    : nullptr;
                 if constexpr (DIM == 3) fd3_bwd_run<TU, TC>(P, M, io, lds);
                 else fd_bwd_run<TU, TC>(P, M, M.local, io, lds);
             }

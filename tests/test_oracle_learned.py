@@ -61,31 +61,32 @@ def test_adjoint_identity():
     assert abs(lhs - rhs) < 1e-10 * abs(lhs)
 
 
-def test_gradients_central_differences():
+@pytest.mark.parametrize("head", [0, 1])
+def test_gradients_central_differences(head):
     rng = _rng(5)
     net = L.Net([3, 4, 4, 1], seed=7)
     x = rng.standard_normal((3, 3, 4, 5))
     t = rng.standard_normal((1, 3, 4, 5))
     count = t.size
-    _, grads = net.loss_and_grad(x, t, count)
+    _, grads = net.loss_and_grad(x, t, count, head)
     h = 1e-6
     for li in range(3):
         w, b = net.layers[li]
         for idx in [tuple(rng.integers(0, s) for s in w.shape) for _ in range(6)]:
             w0 = w[idx]
             w[idx] = w0 + h
-            lp, _ = net.loss_and_grad(x, t, count)
+            lp, _ = net.loss_and_grad(x, t, count, head)
             w[idx] = w0 - h
-            lm, _ = net.loss_and_grad(x, t, count)
+            lm, _ = net.loss_and_grad(x, t, count, head)
             w[idx] = w0
             fd = (lp - lm) / (2 * h)
             assert abs(fd - grads[li][0][idx]) < 1e-6 * max(1.0, abs(fd)), (li, idx)
         for k in range(b.shape[0]):
             b0 = b[k]
             b[k] = b0 + h
-            lp, _ = net.loss_and_grad(x, t, count)
+            lp, _ = net.loss_and_grad(x, t, count, head)
             b[k] = b0 - h
-            lm, _ = net.loss_and_grad(x, t, count)
+            lm, _ = net.loss_and_grad(x, t, count, head)
             b[k] = b0
             assert abs((lp - lm) / (2 * h) - grads[li][1][k]) < 1e-6
 
@@ -143,12 +144,39 @@ def test_fcg_with_linear_spd_preconditioner_equals_pcg():
     np.testing.assert_allclose(hist_f, hist, rtol=1e-6, atol=1e-12 * np.linalg.norm(b))
 
 
-def test_preconditioner_scale_equivariant():
+@pytest.mark.parametrize("head", [0, 1])
+def test_preconditioner_scale_equivariant(head):
     rng = _rng(10)
     net = L.Net([3, 4, 4, 1], seed=3)
     r = rng.standard_normal((3, 4, 5))
-    zfd = rng.standard_normal((3, 4, 5))
+    zfd = r + 0.1 * rng.standard_normal((3, 4, 5))
     la = rng.standard_normal((3, 4, 5))
-    z1 = L.precondition(net, r, zfd, la)
-    z2 = L.precondition(net, 7.5 * r, 7.5 * zfd, la)
+    z1 = L.precondition(net, r, zfd, la, head)
+    z2 = L.precondition(net, 7.5 * r, 7.5 * zfd, la, head)
     np.testing.assert_allclose(z2, 7.5 * z1, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("head", [0, 1])
+def test_untrained_last_layer_gives_fd(head):
+    """A zero last layer makes the correction vanish: z = z_FD exactly."""
+    rng = _rng(11)
+    net = L.Net([3, 4, 4, 1], seed=3)
+    w, b = net.layers[-1]
+    w[:] = 0.0
+    b[:] = 0.0
+    r = rng.standard_normal((3, 4, 5))
+    zfd = rng.standard_normal((3, 4, 5))
+    zfd *= np.sign(np.sum(r * zfd)) or 1.0
+    assert np.array_equal(L.precondition(net, r, zfd, rng.standard_normal((3, 4, 5)), head), zfd)
+
+
+def test_rejected_correction_falls_back_to_fd():
+    """A correction that turns z against r (r.z <= 0) is discarded."""
+    rng = _rng(12)
+    net = L.Net([3, 1], seed=0)
+    w, b = net.layers[0]
+    w[:] = 0.0
+    b[:] = -1e3  # additive head: z = z_FD - 1e3 s, r.z < 0 for r = z_FD > 0
+    zfd = np.abs(rng.standard_normal((2, 3, 4))) + 0.1
+    r = zfd.copy()
+    assert np.array_equal(L.precondition(net, r, zfd, np.zeros_like(r), 0), zfd)
