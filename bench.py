@@ -87,7 +87,8 @@ def algorithmic_bytes(P, rep, precision):
     Per CG iteration of a grid: the operator coefficients at every Gauss point
     (ncompG values of 4 B in the FP32 inner operator, 8 B in FP64), the FD
     factors U of both directions read twice (forward and backward; 8/4/2 B),
-    and eight FP64 vector passes over the grid's unknowns.  Each refinement
+    eight FP64 vector passes over the grid's unknowns and two reads of the
+    FP64 diagonal scaling (forward and backward transform).  Each refinement
     step adds one FP64 operator application and one FD application.
     """
     wl = P.wl
@@ -104,8 +105,8 @@ def algorithmic_bytes(P, rep, precision):
         fd_u = 2 * sum(n * n for n in ni)
         it = int(rep["iters"][c])
         rf = int(rep["refinements"][c])
-        total += it * (ncompG * nqp * bop_in + fd_u * bu + 64 * ndof)
-        total += rf * (ncompG * nqp * 8 + fd_u * bu + 64 * ndof)
+        total += it * (ncompG * nqp * bop_in + fd_u * bu + 80 * ndof)
+        total += rf * (ncompG * nqp * 8 + fd_u * bu + 80 * ndof)
     return float(total)
 
 

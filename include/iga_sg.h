@@ -140,6 +140,9 @@ typedef struct {
     int learned_iters; /* precond 1: the correction acts on the first learned_iters
                           preconditionings of each (inner) solve, plain fast diagonalisation
                           after them; 0 = on every one */
+    int plain_fd;      /* 0: the fast-diagonalisation preconditioner with diagonal scaling,
+                          z = S P^-1 S r, S = diag(sqrt(P_ii / A_ii)) (S P S has the
+                          diagonal of A); 1: the unscaled pencil, z = P^-1 r */
 } iga_sg_solve_opts;
 
 /* Per-component results; arrays are caller-owned host buffers of length
@@ -212,8 +215,10 @@ iga_status iga_sg_coeffs(iga_sg_plan plan, int comp, double* out_dev);
 
 /* Kernel-level hooks (tests, training data): y = A_comp x (which = 0 FP64
  * operator, 1 FP32 operator), y = P^-1 x (which = 2 FP64, 3 FP32, 4 BF16 fast
- * diagonalisation) or y = b - A x (which = 5, FP64); x_dev, y_dev hold the
- * component's interior unknowns. */
+ * diagonalisation), y = b - A x (which = 5, FP64) or y = S P^-1 S x (which = 6,
+ * FP64, the diagonally scaled preconditioner of iga_sg_solve_opts.plain_fd = 0,
+ * S from the last iga_sg_assemble); x_dev, y_dev hold the component's interior
+ * unknowns. */
 iga_status iga_sg_apply(iga_sg_plan plan, int comp, int which, const double* x_dev, double* y_dev);
 
 /* Load vector of component comp (after iga_sg_assemble) to out_dev. */

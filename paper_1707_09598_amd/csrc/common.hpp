@@ -52,6 +52,7 @@ struct Tab1D {
     int64_t oGkn;         // [ngk] geometry knots
     int64_t oU, oUT;      // [ni][ni] eigenvectors (U[i][k]) and transpose
     int64_t oLam;         // [ni]
+    int64_t oKd, oMd;     // [ni] diagonals of the 1D stiffness and mass matrices of the pencil
     // int-pool offsets
     int64_t oGs;          // [Q] first geometry basis index at each Gauss point
     // float-pool and bf16-pool offsets
@@ -219,6 +220,7 @@ struct Layout {
     size_t part;                  // partial sums
     size_t optask, fdtask, fdtask_lp;
     size_t loga;                  // log a at the Greville points of the unknowns
+    size_t fdscale;               // diagonal scaling of the preconditioner
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t total;
@@ -259,6 +261,8 @@ struct Params {
     unsigned* bar;     // [0] count, [1] generation, [2] done counter
     double gx[8], gw[8];  // Gauss-Legendre rule on [-1, 1]
     double* loga;      // log a at the Greville points of the unknowns [ndof_total]
+    double* fdscale;   // s = sqrt(diag(P) / diag(A)) per unknown [ndof_total]; nullptr in a
+                       // solve without scaling
     const float* nn;   // learned preconditioner parameters (or nullptr)
     int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
     int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)

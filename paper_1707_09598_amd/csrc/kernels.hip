@@ -374,6 +374,87 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     }
 }
 
+// Diagonal scaling of the fast-diagonalisation preconditioner, one thread per
+// unknown: s_i = sqrt(P_ii / A_ii) with P = sum_k K_k (x) prod_{l != k} M_l the
+// pencil of the 1D matrices and A the assembled operator, so that S P S has
+// the diagonal of A.  A_ii sums, over the Gauss points of the elements in the
+// support of basis function i, the stored coefficients G_uv times the products
+// of its value / first derivatives (u, v) (both orders for u != v).
+__global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
+    const int64_t i0 = P.grids[g0].dof_off;
+    const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
+    const int p = P.p, nq = P.nq, d = P.dim;
+    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
+         gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+        int lo = g0, hi = g1 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.grids[mid].dof_off <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        const Grid& g = P.grids[lo];
+        int64_t l = gi - g.dof_off;
+        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
+        const double* Bt[3] = {nullptr, nullptr, nullptr};
+        const double* Dt[3] = {nullptr, nullptr, nullptr};
+        double pd = 0.0, md[3] = {1.0, 1.0, 1.0}, kd[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < d; ++k) {
+            ik[k] = static_cast<int>(l % g.ni[k]);
+            l /= g.ni[k];
+            const Tab1D& T = P.tabs[g.tab[k]];
+            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi[k]);
+            Bt[k] = P.dpool + T.oB;
+            Dt[k] = P.dpool + T.oD;
+            kd[k] = P.dpool[T.oKd + ik[k]];
+            md[k] = P.dpool[T.oMd + ik[k]];
+        }
+        for (int k = 0; k < d; ++k) {
+            double t = g.fdc[k] * kd[k];
+            for (int j = 0; j < d; ++j)
+                if (j != k) t *= md[j];
+            pd += t;
+        }
+        const bool rat = P.rational[g.patch] != 0;
+        const int ne = rat ? d + 1 : d;  // entries of (v, grad v) or of grad v
+        const int64_t nqp = g.nqp;
+        const double* G = P.G64 + g.qp_off * P.ncompG;
+        double ad = 0.0;
+        const int e3lo = d == 3 ? elo[2] : 0, e3hi = d == 3 ? ehi[2] : 0, nj3 = d == 3 ? nq : 1;
+        for (int e3 = e3lo; e3 <= e3hi; ++e3)
+            for (int j3 = 0; j3 < nj3; ++j3)
+                for (int e2 = elo[1]; e2 <= ehi[1]; ++e2)
+                    for (int j2 = 0; j2 < nq; ++j2)
+                        for (int e1 = elo[0]; e1 <= ehi[0]; ++e1)
+                            for (int j1 = 0; j1 < nq; ++j1) {
+                                const int qk[3] = {e1 * nq + j1, e2 * nq + j2, e3 * nq + j3};
+                                const int ek[3] = {e1, e2, e3};
+                                double bv[3] = {1.0, 1.0, 1.0}, dv[3] = {0.0, 0.0, 0.0};
+                                for (int k = 0; k < d; ++k) {
+                                    const int a = ik[k] + 1 - ek[k] * P.tabs[g.tab[k]].m;
+                                    bv[k] = Bt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
+                                    dv[k] = Dt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
+                                }
+                                // f[u]: the value (rational form only) and the derivatives
+                                double f[4];
+                                int u = 0;
+                                if (rat) f[u++] = bv[0] * bv[1] * bv[2];
+                                for (int k = 0; k < d; ++k) {
+                                    double t = dv[k];
+                                    for (int j = 0; j < d; ++j)
+                                        if (j != k) t *= bv[j];
+                                    f[u++] = t;
+                                }
+                                const int64_t lq =
+                                    qk[0] + static_cast<int64_t>(g.Q[0]) * (qk[1] + static_cast<int64_t>(g.Q[1]) * qk[2]);
+                                int c = 0;
+                                for (int a = 0; a < ne; ++a)
+                                    for (int b = a; b < ne; ++b, ++c)
+                                        ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
+                            }
+        P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
+    }
+}
+
 // log a at the Greville point of every interior unknown (feature of the
 // learned preconditioner): xi*_k = (t_{j+1} + ... + t_{j+p}) / p for basis
 // j = i_k + 1 of direction k, mapped through F.
@@ -683,6 +764,7 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     K.fdtask = reinterpret_cast<const Task*>(base + (lowp_fd ? L.fdtask_lp : L.fdtask));
     K.bar = reinterpret_cast<unsigned*>(base + L.bar);
     K.loga = reinterpret_cast<double*>(base + L.loga);
+    K.fdscale = reinterpret_cast<double*>(base + L.fdscale);
     K.nn = P->nn;
     for (int i = 0; i < 4; ++i) K.nn_ch[i] = P->nn_ch[i];
     K.nn_head = P->nn_head;
@@ -848,6 +930,8 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_loga, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, to_dev(a), 0, ng);
     HIP_OK(hipGetLastError());
+    hipLaunchKernelGGL(k_fdscale, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, 0, ng);
+    HIP_OK(hipGetLastError());
     P->assembled = true;
     P->solved = false;
     return IGA_OK;
@@ -869,6 +953,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     const bool lp = o->precision != IGA_PREC_FP64;  // FD blocking of the factor precision
     Params K = make_params(P, lp);
+    if (o->plain_fd) K.fdscale = nullptr;  // unscaled pencil
     const std::vector<Grid>& grids = lp ? P->grids_lp : P->grids;
     const size_t nfd = (lp ? P->fdtask_lp : P->fdtask).size();
     const int ng = static_cast<int>(P->grids.size());
@@ -1111,7 +1196,7 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
 }
 
 iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, double* y) {
-    if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 5) {
+    if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 6) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1152,7 +1237,8 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
         io.r_old = xs;
         io.rt = K.rt;
         io.z = ys;
-        io.prec = which - 2;
+        io.prec = which == 6 ? 0 : which - 2;
+        io.scale = which == 6 ? K.fdscale : nullptr;
         hipLaunchKernelGGL(k_apply_fd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io, 1);
         HIP_OK(hipGetLastError());
         hipLaunchKernelGGL(k_apply_fd, dim3(g.nblk), dim3(kBlock), P->lds_bytes, st, K, gi, io, 0);

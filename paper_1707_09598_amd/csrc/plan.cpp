@@ -353,7 +353,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     P->tabs.resize(ntab);
     P->K1d.resize(ntab);
     P->M1d.resize(ntab);
-    std::map<std::tuple<int, double, int>, std::array<int64_t, 7>> fd_off;
+    std::map<std::tuple<int, double, int>, std::array<int64_t, 9>> fd_off;
     for (int pt = 0; pt < geom->npatch; ++pt)
         for (int k = 0; k < d; ++k)
             for (int lev = 0; lev <= P->Lmax; ++lev) {
@@ -410,7 +410,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     // U and U^T stored row-major with a padded row stride (a multiple of 8
                     // elements, zero-filled) so that rows start 16-byte aligned in every
                     // precision; the pools are padded to 8 elements before each table
-                    std::array<int64_t, 7> o;
+                    std::array<int64_t, 9> o;
                     const int n = F.n, ld = (n + 7) & ~7;
                     auto Uat = [&](int i, int j, bool tr) {
                         return tr ? F.U[static_cast<size_t>(j) * n + i] : F.U[static_cast<size_t>(i) * n + j];
@@ -423,6 +423,10 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     }
                     o[2] = static_cast<int64_t>(dp.size());
                     dp.insert(dp.end(), F.lam.begin(), F.lam.end());
+                    o[7] = static_cast<int64_t>(dp.size());
+                    for (int i = 0; i < n; ++i) dp.push_back(F.K[static_cast<size_t>(i) * n + i]);
+                    o[8] = static_cast<int64_t>(dp.size());
+                    for (int i = 0; i < n; ++i) dp.push_back(F.M[static_cast<size_t>(i) * n + i]);
                     for (int t = 0; t < 2; ++t) {
                         P->fpool.resize((P->fpool.size() + 7) & ~static_cast<size_t>(7), 0.0f);
                         o[3 + t] = static_cast<int64_t>(P->fpool.size());
@@ -447,6 +451,8 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 T.oUT32 = fit->second[4];
                 T.oU16 = fit->second[5];
                 T.oUT16 = fit->second[6];
+                T.oKd = fit->second[7];
+                T.oMd = fit->second[8];
             }
     // homogeneous control points (w P, w) per patch
     for (int pt = 0; pt < geom->npatch; ++pt) {
@@ -721,6 +727,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     size_t pst = std::max(P->optask.size(), std::max(P->fdtask.size(), P->fdtask_lp.size()));
     L.part = take(sizeof(double) * pst * 10);
     L.loga = take(sizeof(double) * nd);
+    L.fdscale = take(sizeof(double) * nd);
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());

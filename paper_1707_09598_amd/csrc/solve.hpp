@@ -591,6 +591,7 @@ struct FdIO {
     double* z;            // backward output
     const double* rdot;   // backward: dot partner (or nullptr)
     int prec;             // 0 FP64, 1 FP32, 2 BF16 factors
+    const double* scale;  // diagonal scaling s (z = s P^-1 (s r)), or nullptr
     // learned preconditioner (3D backward transform only)
     int learned;
     const double* rold;   // previous residual: part2 = z . rold (flexible CG)
@@ -915,16 +916,25 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
     const int n1 = B.n1, n2 = B.n2;
     const TU *Us, *Ub, *Ubig;
     fd_factor_ptrs<TU>(P, M, true, &Us, &Ub, &Ubig);
-    if (io.q)
+    if (io.scale) {
+        // the update in S (written out below), the scaled residual s r in R
+        for (int i = threadIdx.x; i < B.n; i += kBlock) {
+            const double v = io.q ? L.R[i] - io.alpha * L.S[i] : L.R[i];
+            L.S[i] = v;
+            L.R[i] = v * io.scale[off + i];
+        }
+    } else if (io.q) {
         for (int i = threadIdx.x; i < B.n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
+    }
     __syncthreads();
+    const double* Ru = io.scale ? L.S : L.R;
     const double* Pw = L.Own;
     const double* Dw = L.Own + B.nown;
     const double* Iw = L.Own + 2 * B.nown;
     double nrm = 0.0;
     for (int o = threadIdx.x; o < B.nown; o += kBlock) {
         const int gi = B.gi(o);
-        const double v = L.R[gi];
+        const double v = Ru[gi];
         if (io.r_out) io.r_out[off + gi] = v;
         if (io.dvec) io.dvec[off + gi] = Dw[o] + io.alpha * Pw[o];
         nrm += v * v;
@@ -1000,8 +1010,9 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     const double* Rd = L.Own;
     for (int o = threadIdx.x; o < B.nown; o += kBlock) {
         const int64_t gi = off + B.gi(o);
-        io.z[gi] = L.Out[o];
-        if (io.rdot) dot += Rd[o] * L.Out[o];
+        const double zv = io.scale ? L.Out[o] * io.scale[gi] : L.Out[o];
+        io.z[gi] = zv;
+        if (io.rdot) dot += Rd[o] * zv;
     }
     if (io.part) {
         const double t = wg_sum(dot, L.red);
@@ -1080,12 +1091,21 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
     const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
     const int64_t off = g.dof_off;
-    if (io.q)
+    if (io.scale) {
+        // the update in S (written out below), the scaled residual s r in R
+        for (int i = threadIdx.x; i < n; i += kBlock) {
+            const double v = io.q ? L.R[i] - io.alpha * L.S[i] : L.R[i];
+            L.S[i] = v;
+            L.R[i] = v * io.scale[off + i];
+        }
+    } else if (io.q) {
         for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
+    }
     __syncthreads();
+    const double* Ru = io.scale ? L.S : L.R;
     double nrm = 0.0;
     for (int o = threadIdx.x; o < n; o += kBlock) {
-        const double v = L.R[o];
+        const double v = Ru[o];
         if (io.r_out) io.r_out[off + o] = v;
         if (io.dvec) io.dvec[off + o] = L.Own[n + o] + io.alpha * L.Own[o];
         nrm += v * v;
@@ -1159,6 +1179,11 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     small_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, L.red, n3, 0, n12, n12);
     // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
     small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, L.red);
+    if (io.scale) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] *= io.scale[off + i];
+        __syncthreads();
+    }
     double scale = 0.0;  // s (additive head), -1 (log-scale head), 0: no learned correction
     float* Y = nullptr;
     if (io.learned) {
@@ -1538,6 +1563,7 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
             FdIO io;
             io.rt = P.rt;
             io.prec = FDP;
+            io.scale = P.fdscale;
             io.learned = 0;
             io.rold = nullptr;
             io.part2 = nullptr;
@@ -1612,6 +1638,7 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.z = P.z;
                 io.rdot = r_new;
                 io.prec = FDP;
+                io.scale = P.fdscale;
                 io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
                 // the learned map preconditions the residuals of a (re)started
                 // solve from the first one on, up to learned_iters of them; z . r_old

@@ -30,17 +30,20 @@ def grid_shape(plan, comp: int) -> Tuple[int, int, int]:
 
 
 def collect_pairs(plan, snapshots: Sequence[int] = (0, 1, 2, 3, 4, 6, 8, 12, 16), tol: float = 1e-12,
-                  pairs: Dict[int, List] = None, head: int = 0) -> Dict[int, List]:
+                  pairs: Dict[int, List] = None, head: int = 0, scaled: bool = True) -> Dict[int, List]:
     """Append the pairs of one assembled plan (one coefficient sample) to
-    pairs[comp] as (x [3, n], t [n]) FP32 device tensors."""
+    pairs[comp] as (x [3, n], t [n]) FP32 device tensors.  scaled selects the
+    preconditioner the network corrects (the diagonally scaled one or the
+    plain pencil), as in the solves it is used in."""
     pairs = {} if pairs is None else pairs
-    plan.solve(precision="fp64", tol=tol, maxit=1000, max_refine=3)
+    fd = "fds64" if scaled else "fd64"
+    plan.solve(precision="fp64", tol=tol, maxit=1000, max_refine=3, scaled=scaled)
     xs = [plan.coeffs(c) for c in range(plan.ncomp)]
     la = [plan.loga(c) for c in range(plan.ncomp)]
     for k in snapshots:
         if k > 0:
             # k plain iterations, then the residual replacement ends the solve
-            plan.solve(precision="fp64", tol=1e-30, maxit=k, max_refine=1, check=False)
+            plan.solve(precision="fp64", tol=1e-30, maxit=k, max_refine=1, check=False, scaled=scaled)
         for c in range(plan.ncomp):
             xk = plan.coeffs(c) if k > 0 else None
             if xk is None:
@@ -49,7 +52,7 @@ def collect_pairs(plan, snapshots: Sequence[int] = (0, 1, 2, 3, 4, 6, 8, 12, 16)
                 r = plan.apply(c, "res64", zero)
             else:
                 r = plan.apply(c, "res64", xk)
-            zfd = plan.apply(c, "fd64", r)
+            zfd = plan.apply(c, fd, r)
             x, t = make_pair(r, zfd, la[c], xs[c], xk, head=head)
             pairs.setdefault(c, []).append((x, t))
     return pairs
@@ -75,6 +78,24 @@ def train(net: Network, pairs: Dict[int, List], shapes: Dict[int, Tuple[int, int
         if step % 50 == 0 or step == steps - 1:
             losses.append(float(loss.item()))
     return losses
+
+
+def evaluate(net: Network, pairs: Dict[int, List], shapes: Dict[int, Tuple[int, int, int]],
+             batch: int = 64) -> float:
+    """Mean training loss over every pair (no parameter update), weighted by
+    the number of unknowns."""
+    import torch
+    tot, cnt = 0.0, 0
+    for c in sorted(pairs):
+        n1, n2, n3 = shapes[c]
+        P = pairs[c]
+        for i in range(0, len(P), batch):
+            sel = P[i:i + batch]
+            X = torch.stack([q[0] for q in sel]).view(len(sel), 3, n3, n2, n1).contiguous()
+            T = torch.stack([q[1] for q in sel]).view(len(sel), 1, n3, n2, n1).contiguous()
+            tot += float(net.gradient(X, T).item()) * T.numel()
+            cnt += T.numel()
+    return tot / max(cnt, 1)
 
 
 def init_params(channels: Sequence[int], seed: int = 0) -> np.ndarray:

@@ -133,10 +133,44 @@ def test_fast_diagonalisation_parity(S, name, w, comps):
             assert rel(z, ref) < tol, (c, lv, which, rel(z, ref))
 
 
-def _solve_and_compare(S, wl, precision, batched, tol_coef, tol_sg, npts=4096):
+@pytest.mark.parametrize("name,w,comps", [("cfg1", 5, None), ("cfg2", 7, None),
+                                          ("cfg2", 10, [0, 9, 19, 20]), ("cfg3", 6, [0, 5, 10]),
+                                          ("cfg5", 4, [0, 3, 6, 10, 14])])
+def test_scaled_fast_diagonalisation_parity(S, name, w, comps):
+    """z = S P^-1 S x with S = sqrt(diag(P) / diag(A)): diag(A) from the
+    oracle's dense assembly, P the Kronecker pencil of the 1D matrices."""
+    wl = _config(name, w)
+    log(f"case scaled fd {name} w={w}")
+    P = _bound(S, wl)
+    Po = O.Problem(wl)
+    d = len(P.levels[0])
+    for c, lv in enumerate(P.levels):
+        if comps is not None and c not in comps:
+            continue
+        A, _ = Po.assemble_dense(lv)
+        perm = oracle_perm(Po.nbasis(lv))
+        dA = np.diag(A)[perm]
+        KM = [P.matrices_1d(k, int(lv[k])) for k in range(d)]
+        if d == 2:
+            (K1, M1), (K2, M2) = KM
+            Pk = np.kron(M2, K1) + np.kron(K2, M1)
+        else:
+            (K1, M1), (K2, M2), (K3, M3) = KM
+            Pk = (np.kron(M3, np.kron(M2, K1)) + np.kron(M3, np.kron(K2, M1)) +
+                  np.kron(K3, np.kron(M2, M1)))
+        sc = np.sqrt(np.diag(Pk) / dA)
+        x = W.random_vector(len(Pk), seed=17 + c)
+        ref = sc * np.linalg.solve(Pk, sc * x)
+        lam = [P.fd_factor(k, int(lv[k]))[1] for k in range(d)]
+        kappa = sum(l.max() for l in lam) / sum(l.min() for l in lam)
+        z = P.apply(c, "fds64", x).cpu().numpy()
+        assert rel(z, ref) < max(1e-12, 100 * 2.2e-16 * kappa), (c, lv, rel(z, ref))
+
+
+def _solve_and_compare(S, wl, precision, batched, tol_coef, tol_sg, npts=4096, scaled=True):
     P = _bound(S, wl)
     rep = P.solve(precision=precision, tol=1e-11, tol_inner=1e-5, maxit=400, max_refine=6,
-                  batched=batched, check=False)
+                  batched=batched, check=False, scaled=scaled)
     log(f"  code {rep['code']} status {rep['status'].tolist()}")
     log(f"  iters {rep['iters'].tolist()} refine {rep['refinements'].tolist()}")
     log(f"  relres {np.array2string(rep['relres'], precision=2)}")
@@ -171,9 +205,10 @@ def test_solve_parity_cfg1(S, batched):
     _solve_and_compare(S, W.config("cfg1"), "fp64", batched, 1e-10, 1e-10)
 
 
-def test_solve_parity_cfg2_fp64(S):
-    log("case solve cfg2 fp64")
-    _solve_and_compare(S, W.config("cfg2"), "fp64", True, 1e-10, 1e-10)
+@pytest.mark.parametrize("scaled", [True, False])
+def test_solve_parity_cfg2_fp64(S, scaled):
+    log(f"case solve cfg2 fp64 scaled={scaled}")
+    _solve_and_compare(S, W.config("cfg2"), "fp64", True, 1e-10, 1e-10, scaled=scaled)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16fd"])
