@@ -374,18 +374,21 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     }
 }
 
-// Diagonal scaling of the fast-diagonalisation preconditioner, one thread per
-// unknown: s_i = sqrt(P_ii / A_ii) with P = sum_k K_k (x) prod_{l != k} M_l the
-// pencil of the 1D matrices and A the assembled operator, so that S P S has
-// the diagonal of A.  A_ii sums, over the Gauss points of the elements in the
-// support of basis function i, the stored coefficients G_uv times the products
-// of its value / first derivatives (u, v) (both orders for u != v).
+// Diagonal scaling of the fast-diagonalisation preconditioner, one wavefront
+// per unknown: s_i = sqrt(P_ii / A_ii) with P = sum_k K_k (x) prod_{l != k} M_l
+// the pencil of the 1D matrices and A the assembled operator, so that S P S
+// has the diagonal of A.  A_ii sums, over the Gauss points of the elements in
+// the support of basis function i (split over the lanes, then a fixed lane
+// butterfly), the stored coefficients G_uv times the products of its value /
+// first derivatives (u, v), both orders for u != v.
 __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
     const int64_t i0 = P.grids[g0].dof_off;
     const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
     const int p = P.p, nq = P.nq, d = P.dim;
-    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
-         gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
+    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock / 64) + (threadIdx.x >> 6); gi < i1;
+         gi += nw) {
         int lo = g0, hi = g1 - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -394,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
         }
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
-        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
+        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, nt[3] = {1, 1, 1}, mk[3] = {1, 1, 1};
         const double* Bt[3] = {nullptr, nullptr, nullptr};
         const double* Dt[3] = {nullptr, nullptr, nullptr};
         double pd = 0.0, md[3] = {1.0, 1.0, 1.0}, kd[3] = {0.0, 0.0, 0.0};
@@ -402,7 +405,10 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
             ik[k] = static_cast<int>(l % g.ni[k]);
             l /= g.ni[k];
             const Tab1D& T = P.tabs[g.tab[k]];
-            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi[k]);
+            int ehi;
+            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi);
+            nt[k] = (ehi - elo[k] + 1) * nq;  // Gauss points of the support in direction k
+            mk[k] = T.m;
             Bt[k] = P.dpool + T.oB;
             Dt[k] = P.dpool + T.oD;
             kd[k] = P.dpool[T.oKd + ik[k]];
@@ -418,40 +424,37 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
         const int ne = rat ? d + 1 : d;  // entries of (v, grad v) or of grad v
         const int64_t nqp = g.nqp;
         const double* G = P.G64 + g.qp_off * P.ncompG;
+        const int ntot = nt[0] * nt[1] * nt[2];
         double ad = 0.0;
-        const int e3lo = d == 3 ? elo[2] : 0, e3hi = d == 3 ? ehi[2] : 0, nj3 = d == 3 ? nq : 1;
-        for (int e3 = e3lo; e3 <= e3hi; ++e3)
-            for (int j3 = 0; j3 < nj3; ++j3)
-                for (int e2 = elo[1]; e2 <= ehi[1]; ++e2)
-                    for (int j2 = 0; j2 < nq; ++j2)
-                        for (int e1 = elo[0]; e1 <= ehi[0]; ++e1)
-                            for (int j1 = 0; j1 < nq; ++j1) {
-                                const int qk[3] = {e1 * nq + j1, e2 * nq + j2, e3 * nq + j3};
-                                const int ek[3] = {e1, e2, e3};
-                                double bv[3] = {1.0, 1.0, 1.0}, dv[3] = {0.0, 0.0, 0.0};
-                                for (int k = 0; k < d; ++k) {
-                                    const int a = ik[k] + 1 - ek[k] * P.tabs[g.tab[k]].m;
-                                    bv[k] = Bt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
-                                    dv[k] = Dt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
-                                }
-                                // f[u]: the value (rational form only) and the derivatives
-                                double f[4];
-                                int u = 0;
-                                if (rat) f[u++] = bv[0] * bv[1] * bv[2];
-                                for (int k = 0; k < d; ++k) {
-                                    double t = dv[k];
-                                    for (int j = 0; j < d; ++j)
-                                        if (j != k) t *= bv[j];
-                                    f[u++] = t;
-                                }
-                                const int64_t lq =
-                                    qk[0] + static_cast<int64_t>(g.Q[0]) * (qk[1] + static_cast<int64_t>(g.Q[1]) * qk[2]);
-                                int c = 0;
-                                for (int a = 0; a < ne; ++a)
-                                    for (int b = a; b < ne; ++b, ++c)
-                                        ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
-                            }
-        P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
+        for (int t = lane; t < ntot; t += 64) {
+            const int tk[3] = {t % nt[0], (t / nt[0]) % nt[1], t / (nt[0] * nt[1])};
+            int qk[3] = {0, 0, 0};
+            double bv[3] = {1.0, 1.0, 1.0}, dv[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < d; ++k) {
+                const int e = elo[k] + tk[k] / nq;
+                qk[k] = elo[k] * nq + tk[k];
+                const int a = ik[k] + 1 - e * mk[k];  // local index of the basis function
+                bv[k] = Bt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
+                dv[k] = Dt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
+            }
+            // f[u]: the value (rational form only) and the derivatives
+            double f[4];
+            int u = 0;
+            if (rat) f[u++] = bv[0] * bv[1] * bv[2];
+            for (int k = 0; k < d; ++k) {
+                double v = dv[k];
+                for (int j = 0; j < d; ++j)
+                    if (j != k) v *= bv[j];
+                f[u++] = v;
+            }
+            const int64_t lq = qk[0] + static_cast<int64_t>(g.Q[0]) * (qk[1] + static_cast<int64_t>(g.Q[1]) * qk[2]);
+            int c = 0;
+            for (int a = 0; a < ne; ++a)
+                for (int b = a; b < ne; ++b, ++c) ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ad += __shfl_xor(ad, o, 64);
+        if (lane == 0) P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
     }
 }
 
@@ -930,7 +933,7 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     HIP_OK(hipGetLastError());
     hipLaunchKernelGGL(k_loga, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, to_dev(a), 0, ng);
     HIP_OK(hipGetLastError());
-    hipLaunchKernelGGL(k_fdscale, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, 0, ng);
+    hipLaunchKernelGGL(k_fdscale, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
     P->assembled = true;
     P->solved = false;
