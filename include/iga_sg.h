@@ -176,6 +176,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
 /* Bytes of device workspace the plan needs (256-byte aligned sub-buffers). */
 iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes);
 
+/* Task counts of a batched solve (operator tiles; fast-diagonalisation tasks
+ * with FP64 factors and with FP32/BF16 factors) and the LDS bytes a solve
+ * workgroup takes.  Any pointer may be NULL.  Host only. */
+iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64, int* fd_tasks_lowp,
+                             size_t* lds_bytes);
+
 /* Bind a device workspace of at least iga_sg_workspace_bytes bytes and a HIP
  * stream (hipStream_t, NULL = default).  Uploads the plan tables and computes
  * the basis tables on the device; synchronises the stream before returning. */

@@ -25,7 +25,7 @@ STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_
 APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5, "fds64": 6}
 
 EXPORTS = (
-    "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_bind", "iga_sg_components",
+    "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_plan_stats", "iga_sg_bind", "iga_sg_components",
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network",
@@ -106,6 +106,7 @@ def lib():
         vp = C.c_void_p
         L.iga_sg_plan_create.argtypes = [C.POINTER(_Geometry), C.POINTER(_Disc), C.POINTER(vp)]
         L.iga_sg_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.iga_sg_plan_stats.argtypes = [vp, _ip, _ip, _ip, C.POINTER(C.c_size_t)]
         L.iga_sg_bind.argtypes = [vp, vp, C.c_size_t, vp]
         L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
         L.iga_sg_assemble.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Field)]
@@ -226,6 +227,13 @@ class Plan:
         lam = np.zeros(n.value)
         _check(lib().iga_sg_fd_factor(self.h, direction, level, C.byref(n), _ptr(U), _ptr(lam)))
         return U, lam
+
+    def stats(self) -> Dict[str, int]:
+        """Task counts of a batched solve and the LDS bytes per workgroup."""
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        n = C.c_size_t()
+        _check(lib().iga_sg_plan_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)))
+        return {"op_tasks": a.value, "fd_tasks_fp64": b.value, "fd_tasks_lowp": c.value, "lds_bytes": n.value}
 
     def matrices_1d(self, direction: int, level: int):
         n = C.c_int()

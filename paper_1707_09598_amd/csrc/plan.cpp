@@ -466,6 +466,68 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         }
     }
     P->ncompG = P->rational_any ? (d == 2 ? 6 : 10) : (d == 2 ? 3 : 6);
+    // ---- 2D fast-diagonalisation blocking per precision class ---------------
+    // A long direction of at least wide_min unknowns is cut into blocks of 8, 16
+    // or 32 columns whose factor slab (about 64 KiB) is staged in LDS.  Each
+    // block is one task of the persistent solve, and a phase ends with its
+    // slowest workgroup, so wide_min is raised grid length by grid length while
+    // the FD tasks of a solve outnumber the workgroups of one wave and the
+    // grids it makes single-block fit in LDS with both factors staged.
+    int wide_min_cls[2] = {env_int("IGA_FD_WIDE", 100), env_int("IGA_FD_WIDE", 100)};
+    if (d == 2 && !std::getenv("IGA_FD_WIDE")) {
+        const int target = env_int("IGA_FD_TASKS", 256);
+        struct Shape { int ni0, ni1, ld0, ld1; };
+        std::vector<Shape> shapes;
+        for (int c = 0; c < P->ncomp; ++c)
+            for (int pt = 0; pt < geom->npatch; ++pt) {
+                const Tab1D& T0 = P->tabs[tab_index(P, pt, 0, P->comp_levels[c * d])];
+                const Tab1D& T1 = P->tabs[tab_index(P, pt, 1, P->comp_levels[c * d + 1])];
+                shapes.push_back({T0.ni, T1.ni, T0.ldu, T1.ldu});
+            }
+        for (int cls = 0; cls < 2; ++cls) {
+            const int usize = cls == 0 ? 8 : 4;
+            auto nblocks = [&](const Shape& sh, int wm) {
+                const int nbig = std::max(sh.ni0, sh.ni1);
+                if (nbig < wm) return 1;
+                int b = 8;
+                while (b < 32 && static_cast<size_t>(2 * b) * nbig * usize <= 66000) b *= 2;
+                return b < nbig ? (nbig + b - 1) / b : 1;
+            };
+            auto fits_single = [&](const Shape& sh) {
+                Grid t;
+                std::memset(&t, 0, sizeof(t));
+                t.ni[0] = sh.ni0;
+                t.ni[1] = sh.ni1;
+                t.ni[2] = 1;
+                t.big = sh.ni1 > sh.ni0 ? 1 : 0;
+                t.blk = t.ni[t.big];
+                t.nblk = 1;
+                t.fdstage = 1;
+                const int ls = t.big ? sh.ld0 : sh.ld1, lb = t.big ? sh.ld1 : sh.ld0;
+                return fd_layout(t, ls, lb, usize).total + kSolveLdsHead <= static_cast<size_t>(kLdsLimit);
+            };
+            int wm = wide_min_cls[cls];
+            for (;;) {
+                long ntask = 0;
+                int next = 0;  // shortest long direction still cut into blocks
+                for (const Shape& sh : shapes) {
+                    const int nb = nblocks(sh, wm);
+                    ntask += nb;
+                    if (nb > 1) {
+                        const int nbig = std::max(sh.ni0, sh.ni1);
+                        next = next == 0 ? nbig : std::min(next, nbig);
+                    }
+                }
+                if (ntask <= target || next == 0) break;
+                bool ok = true;
+                for (const Shape& sh : shapes)
+                    if (std::max(sh.ni0, sh.ni1) == next && !fits_single(sh)) ok = false;
+                if (!ok) break;
+                wm = next + 1;
+            }
+            wide_min_cls[cls] = wm;
+        }
+    }
     // ---- grids, tiles, preconditioner blocks --------------------------------
     size_t lds_max = 0;
     for (int c = 0; c < P->ncomp; ++c)
@@ -608,10 +670,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 size_t lds = (halo + nel * pl + kBlock) * sizeof(double);
                 lds_max = std::max(lds_max, lds);
             }
-            // fast-diagonalisation blocks (2D: split the longest direction).  Long
-            // directions are cut into blocks of 8, 16 or 32 columns whose factor
-            // slab (about 64 KiB) is staged in LDS; FP32/BF16 factors allow wider
-            // blocks, so each precision class has its own blocking.
+            // fast-diagonalisation blocks (2D: split the longest direction, see the
+            // blocking above); FP32/BF16 factors allow wider blocks, so each
+            // precision class has its own blocking.
             Grid glp = g;
             if (d == 2) {
                 for (int cls = 0; cls < 2; ++cls) {
@@ -620,8 +681,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     gc.big = gc.ni[1] > gc.ni[0] ? 1 : 0;
                     const int nbig = gc.ni[gc.big];
                     int bs = nbig;
-                    const int wide_min = env_int("IGA_FD_WIDE", 100);
-                    if (nbig >= wide_min) {
+                    if (nbig >= wide_min_cls[cls]) {
                         int b = 8;
                         while (b < 32 && static_cast<size_t>(2 * b) * nbig * usize <= 66000) b *= 2;
                         if (b < nbig) bs = b;
@@ -744,6 +804,19 @@ iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes) {
         return IGA_ERR_INVALID_ARG;
     }
     *bytes = plan->lay.total;
+    return IGA_OK;
+}
+
+iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64, int* fd_tasks_lowp,
+                             size_t* lds_bytes) {
+    if (!plan) {
+        set_error("null plan");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (op_tasks) *op_tasks = static_cast<int>(plan->optask.size());
+    if (fd_tasks_fp64) *fd_tasks_fp64 = static_cast<int>(plan->fdtask.size());
+    if (fd_tasks_lowp) *fd_tasks_lowp = static_cast<int>(plan->fdtask_lp.size());
+    if (lds_bytes) *lds_bytes = plan->lds_bytes;
     return IGA_OK;
 }
 
