@@ -31,17 +31,19 @@ sys.path.insert(0, ROOT)
 METRIC = "sparse-grid DOF/s to 1e-9 rel L2: batched mixed/learned PCG vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 
-# Memory traffic of the solve kernel (k_solve<3, FP32 factors> on this workload)
+# Memory traffic of the solve kernel (k_solve<3, FP32 factors> on this workload,
+# with the plan and launch code that shape it)
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
 # scaled by what the same counters read for a plain 256 MiB device copy in the
 # same runs (fetch 131088 KiB, write 262144 KiB).  Valid only for the kernel
 # sources it was measured on: their hash is checked at run time.
 SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
-                "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp"],
-    "sha256": None,
-    "fetch_kib": None, "write_kib": None,
-    "fetch_factor": 262144.0 / 131088.0, "write_factor": 262144.0 / 262144.0,
+                "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
+                "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
+    "sha256": "707575aa9c51496cc7d5dd1672f9139f425b3af2416238eb20694d57f5cc6ace",
+    "fetch_kib": 1144016.3, "write_kib": 292386.5,
+    "fetch_factor": 262144.0 / 131088.9, "write_factor": 262144.0 / 262144.0,
 }
 
 
