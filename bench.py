@@ -78,6 +78,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-trace", action="store_true", help="skip the phase-traced extra solve")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner comparison on the random-field cube")
+    ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
+    ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -164,6 +168,82 @@ def run_mode(S, W, torch, precision, args, xi):
         "plan": P, "u": u, "rep": rep, "wall_ms": 1e3 * wall / K, "t_asm": t_asm, "t_sol": t_sol,
         "t_cmb": t_cmb, "t_plan_s": t_plan, "ndof": int(P.ndof.sum()), "trace": trace,
     }
+
+
+def run_learned(S, W, torch, args, O):
+    """Modes B (FP64 FD-PCG), C (mixed precision) and D (C with the learned
+    correction inside flexible CG) on held-out samples of the random-field
+    cube, after training the network with the library's kernels on pairs from
+    the plain PCG of the training samples.  Timed region per sample: assembly
+    + solve (HIP events on the solve stream)."""
+    from paper_1707_09598_amd import learn
+    ntr, nte = args.learned_train, args.learned_test
+    fields = W.grf_samples(ntr + nte, n=64)
+
+    def plan_for(a):
+        P = S.Plan(W.config("cfg5", a=W._field("grid3d", data=a)))
+        P.bind(device="cuda:0")
+        P.assemble()
+        return P
+
+    t0 = time.perf_counter()
+    pairs, P0 = {}, None
+    for s in range(ntr):
+        P = plan_for(fields[s])
+        learn.collect_pairs(P, pairs=pairs)
+        P0 = P0 or P
+    shapes = {c: learn.grid_shape(P0, c) for c in range(P0.ncomp)}
+    ch = (3, 16, 16, 1)
+    net = S.Network(ch, learn.init_params(ch, seed=0))
+    before = learn.evaluate(net, pairs, shapes)
+    steps = 1500
+    learn.train(net, pairs, shapes, steps=steps, lr=2e-3, batch=16, seed=1)
+    after = learn.evaluate(net, pairs, shapes)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    modes = {"B_fp64": dict(precision="fp64", learned=False, max_refine=3),
+             "C_mixed": dict(precision="fp32", learned=False, max_refine=12, continue_cg=True),
+             "D_mixed_learned": dict(precision="fp32", learned=True, max_refine=12, continue_cg=True),
+             "D_mixed_learned_first10": dict(precision="fp32", learned=True, learned_iters=10, max_refine=12,
+                                             continue_cg=True)}
+    res = {k: {"ms": [], "iterations": [], "codes": []} for k in modes}
+    ref = None
+    ndof = 0
+    for s in range(ntr, ntr + nte):
+        P = plan_for(fields[s])
+        P.set_network(net)
+        ndof = int(P.ndof.sum())
+        for k, kw in modes.items():
+            kw = dict(kw, tol=1e-11, tol_inner=args.tol_inner, maxit=600)
+            P.assemble()
+            rep = P.solve(check=False, **kw)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(P.stream)
+            P.assemble()
+            P.solve_async(**kw)
+            ev[1].record(P.stream)
+            torch.cuda.synchronize()
+            res[k]["ms"].append(ev[0].elapsed_time(ev[1]))
+            res[k]["iterations"].append(int(rep["total_iters"]))
+            res[k]["codes"].append(int(rep["code"]))
+            if s == ntr:
+                # accuracy of each mode against the oracle on the first held-out sample
+                if ref is None:
+                    Po = O.Problem(P.wl)
+                    xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
+                    ref = (xi3, Po.sg_eval(Po.solve_all(), xi3))
+                u = P.combine(ref[0]).cpu().numpy()
+                res[k]["rel_l2_vs_oracle"] = float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1]))
+    out = {"workload": f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), "
+                       f"f = 1, p=3 C^2, w=7, 85 grids, {ndof} unknowns per sample, tol 1e-11; network "
+                       f"3->16->16->1 trained on {ntr} samples, {nte} held-out samples",
+           "train": {"pairs": sum(len(v) for v in pairs.values()), "steps": steps,
+                     "loss_before": before, "loss_after": after, "seconds": t_train}}
+    for k, r in res.items():
+        out[k] = {"dof_per_s": ndof / (np.mean(r["ms"]) / 1e3), "ms_assemble_solve": float(np.mean(r["ms"])),
+                  "iterations": r["iterations"], "codes": r["codes"],
+                  "rel_l2_vs_oracle": r.get("rel_l2_vs_oracle")}
+    return out
 
 
 def cpu_baseline(O, W, xi, seconds):
@@ -296,6 +376,8 @@ def main():
         cpu.pop("assemble_solve_ms", None)
         cpu.pop("combine_ms_scaled", None)
         line["cpu_baseline"] = cpu
+    if not args.no_learned:
+        line["learned_cfg5"] = run_learned(S, W, torch, args, O)
     print(json.dumps(line), flush=True)
 
 

@@ -136,10 +136,12 @@ typedef struct {
                           residual (classic iterative refinement); 1 replaces the recursive
                           residual by the FP64 one and continues CG with its search direction */
     int precond;       /* 0: fast diagonalisation; 1: learned correction on top of it inside
-                          flexible CG (3D plans, network attached by iga_sg_set_network) */
-    int learned_iters; /* precond 1: the correction acts on the first learned_iters
-                          preconditionings of each (inner) solve, plain fast diagonalisation
-                          after them; 0 = on every one */
+                          flexible CG (3D plans, network attached by iga_sg_set_network); the
+                          FP64 residual of every (re)start and the convergence test keep the
+                          plain preconditioner */
+    int learned_iters; /* precond 1: the correction acts on the residuals of the first
+                          learned_iters - 1 iterations of each (inner) solve, plain fast
+                          diagonalisation after them; 0 = on every iteration */
     int plain_fd;      /* 0: the fast-diagonalisation preconditioner with diagonal scaling,
                           z = S P^-1 S r, S = diag(sqrt(P_ii / A_ii)) (S P S has the
                           diagonal of A); 1: the unscaled pencil, z = P^-1 r */

@@ -157,12 +157,14 @@ def precondition(net: Net, r: np.ndarray, zfd: np.ndarray, loga: np.ndarray, hea
 
 
 def fcg(A: np.ndarray, b: np.ndarray, prec: Callable[[np.ndarray], np.ndarray], tol: float,
-        maxit: int) -> Tuple[np.ndarray, int, List[float]]:
+        maxit: int, prec0: Callable[[np.ndarray], np.ndarray] = None) -> Tuple[np.ndarray, int, List[float]]:
     """Flexible CG with the Polak-Ribiere beta: beta = z_k.(r_k - r_{k-1}) / (z_{k-1}.r_{k-1}).
-    Stops when ||r|| <= tol ||b||.  Returns x, iterations, residual history."""
+    The initial residual is preconditioned by prec0 (default prec): the
+    learned solve keeps the plain preconditioner for it.  Stops when
+    ||r|| <= tol ||b||.  Returns x, iterations, residual history."""
     x = np.zeros_like(b)
     r = b.copy()
-    z = prec(r)
+    z = (prec0 or prec)(r)
     p = z.copy()
     rz = float(r @ z)
     hist = [float(np.linalg.norm(r))]

@@ -1640,11 +1640,14 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 io.prec = FDP;
                 io.scale = P.fdscale;
                 io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
-                // the learned map preconditions the residuals of a (re)started
-                // solve from the first one on, up to learned_iters of them; z . r_old
+                // the learned map preconditions the residuals of the CG iterations
+                // (up to learned_iters of them per inner solve); the FP64 residual
+                // of a residual sweep keeps the plain preconditioner, so that the
+                // convergence test r . P^-1 r and the first search direction of a
+                // (re)started solve are those of the plain method; z . r_old
                 // (flexible CG beta) on every iteration of a learned solve
-                io.learned = DIM == 3 && A.learned && P.nn != nullptr &&
-                             (A.learned_iters == 0 || (act == ACT_ITER ? ctx->st.it + 1 : 0) < A.learned_iters);
+                io.learned = DIM == 3 && A.learned && P.nn != nullptr && act == ACT_ITER &&
+                             (A.learned_iters == 0 || ctx->st.it + 1 < A.learned_iters);
                 io.rold = r_old;
                 io.part2 = DIM == 3 && A.learned && act == ACT_ITER ? part_ptr(P, PK_ZRO, cur) + g.blk_off + M.local
                                                                     : nullptr;

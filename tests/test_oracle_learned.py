@@ -113,6 +113,15 @@ def test_fcg_exact_preconditioner_one_step():
     assert it == 1 and np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
 
 
+def test_fcg_first_step_uses_prec0():
+    """The first direction comes from prec0: with the exact inverse there and
+    a useless prec afterwards, one step solves the system."""
+    A = _spd(25, 13)
+    b = _rng(14).standard_normal(25)
+    x, it, _ = L.fcg(A, b, lambda r: r * 0.0 + r, 1e-12, 50, prec0=lambda r: np.linalg.solve(A, r))
+    assert it == 1 and np.linalg.norm(A @ x - b) < 1e-10 * np.linalg.norm(b)
+
+
 def test_fcg_with_linear_spd_preconditioner_equals_pcg():
     """For a fixed SPD preconditioner z.r_old = 0 in exact arithmetic, so the
     flexible iteration reproduces plain PCG (Fletcher-Reeves beta)."""
