@@ -478,85 +478,73 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
 // fast diagonalisation: z = (U1 (x) U2) diag(1/(c1 l1 + c2 l2)) (U1 (x) U2)^T r
 // as mode products
 // ===========================================================================
-// Small dense product in LDS or global memory, C = A B (M x N, inner K).
-// Items are (index of the longer output dimension, chunk of 4 of the other,
-// slice of K): every operand value read is used up to 4 times, and K is cut
-// into KS slices when there are too few outputs to occupy the workgroup; the
-// slices' partial sums go through red (KS * M * N <= kBigRed doubles) and are
-// added in slice order (deterministic).
+// C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores, operands addressed by
+// strides (A(m, k) = A[m sAm + k sAk], ...), nb independent products at batch
+// strides.  Each wavefront takes 16 x 16 output tiles in turn and walks K in
+// steps of 4 with the 16x16x4 MFMA (FP64 for TC = double, FP32 for TC = float;
+// BF16 operands are widened to FP32), two accumulator chains (even and odd
+// steps) in flight.  Lane l supplies A(16 t_m + l % 16, k + l / 16) and
+// B(k + l / 16, 16 t_n + l % 16); out-of-range operands are zero.  The
+// accumulation order is fixed, so results are reproducible.  Ends with a
+// workgroup barrier.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+template <typename TC> struct Mfma;
+template <> struct Mfma<double> {
+    using V = v4d_t;
+    static __device__ __forceinline__ V step(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of accumulator entry r held by a lane (its column is lane % 16)
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using V = v4f_t;
+    static __device__ __forceinline__ V step(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <typename TC, typename T>
+__device__ __forceinline__ TC mm_ld(const T* p, int i) {
+    if constexpr (std::is_same<T, uint16_t>::value) return static_cast<TC>(bf16_to_f32(p[i]));
+    else return static_cast<TC>(p[i]);
+}
 template <typename TA, typename TB, typename TC>
-__device__ __forceinline__ void small_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
-                                           int sBn, double* C, int sCm, int sCn, double* red, int nb = 1,
-                                           int sAb = 0, int sBb = 0, int sCb = 0) {
-    constexpr int CH = 4;
-    auto ld = [](auto* p, int i) -> TC {
-        using V = typename std::remove_cv<typename std::remove_pointer<decltype(p)>::type>::type;
-        if constexpr (std::is_same<V, uint16_t>::value) return static_cast<TC>(bf16_to_f32(p[i]));
-        else return static_cast<TC>(p[i]);
-    };
-    const bool cols = N >= M;
-    const int L = cols ? N : M, S = cols ? M : N;
-    const int nch = (S + CH - 1) / CH;
-    const int base_items = L * nch;
-    int KS = 1;  // K slices (single product only)
-    while (nb == 1 && KS < 8 && base_items * KS < kBlock && 2 * KS * M * N <= kBigRed && K >= 16 * KS) KS *= 2;
-    const int kc = (K + KS - 1) / KS;
-    const FDiv dl(L), dn(nch);
-    for (int it = threadIdx.x; it < base_items * KS * nb; it += kBlock) {
-        int rem, l;
-        int ks = dn.div(dl.div(it, &l), &rem);
-        int bt = 0;  // batch index (nb > 1 implies KS == 1)
-        if (nb > 1) {
-            bt = ks;
-            ks = 0;
-        }
+__device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
+                                          int sBn, double* C, int sCm, int sCn, int nb = 1, int sAb = 0,
+                                          int sBb = 0, int sCb = 0) {
+    using MF = Mfma<TC>;
+    using V = typename MF::V;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, tmn = tm * tn;
+    for (int u = wave; u < tmn * nb; u += kWaves) {  // uniform per wavefront
+        const int bt = u / tmn, t = u - bt * tmn;
+        const int ti = t / tn, tj = t - ti * tn;
         const TA* Ab = A + bt * sAb;
         const TB* Bb = B + bt * sBb;
         double* Cb = C + bt * sCb;
-        const int s0 = rem * CH;
-        int sq[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q) sq[q] = min(s0 + q, S - 1);  // clamped: loads stay in range
-        TC acc[CH];
-#pragma unroll
-        for (int q = 0; q < CH; ++q) acc[q] = TC(0);
-        const int k0 = ks * kc, k1 = min(K, k0 + kc);
-        if (cols) {
-#pragma unroll 4
-            for (int k = k0; k < k1; ++k) {
-                const TC b = ld(Bb, k * sBk + l * sBn);
-#pragma unroll
-                for (int q = 0; q < CH; ++q) acc[q] += ld(Ab, sq[q] * sAm + k * sAk) * b;
-            }
-        } else {
-#pragma unroll 4
-            for (int k = k0; k < k1; ++k) {
-                const TC a = ld(Ab, l * sAm + k * sAk);
-#pragma unroll
-                for (int q = 0; q < CH; ++q) acc[q] += a * ld(Bb, k * sBk + sq[q] * sBn);
-            }
+        const int i = 16 * ti + li, j = 16 * tj + li;
+        const bool iv = i < M, jv = j < N;
+        V acc0 = {TC(0), TC(0), TC(0), TC(0)};
+        V acc1 = acc0;
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            const int ka = k0 + lk, kb = k0 + 4 + lk;
+            const TC a0 = iv && ka < K ? mm_ld<TC>(Ab, i * sAm + ka * sAk) : TC(0);
+            const TC b0 = jv && ka < K ? mm_ld<TC>(Bb, ka * sBk + j * sBn) : TC(0);
+            const TC a1 = iv && kb < K ? mm_ld<TC>(Ab, i * sAm + kb * sAk) : TC(0);
+            const TC b1 = jv && kb < K ? mm_ld<TC>(Bb, kb * sBk + j * sBn) : TC(0);
+            acc0 = MF::step(a0, b0, acc0);
+            acc1 = MF::step(a1, b1, acc1);
         }
 #pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            if (s0 + q < S) {
-                const int m = cols ? s0 + q : l, n = cols ? l : s0 + q;
-                if (KS == 1) Cb[m * sCm + n * sCn] = static_cast<double>(acc[q]);
-                else red[(ks * M + m) * N + n] = static_cast<double>(acc[q]);
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 16 * ti + MF::row(lane, r);
+            if (ii < M && jv) Cb[ii * sCm + j * sCn] = static_cast<double>(acc0[r] + acc1[r]);
         }
     }
     __syncthreads();
-    if (KS > 1) {
-        const FDiv dN(N);
-        for (int o = threadIdx.x; o < M * N; o += kBlock) {
-            int n;
-            const int m = dN.div(o, &n);
-            double t = 0.0;
-            for (int ks = 0; ks < KS; ++ks) t += red[ks * M * N + o];
-            C[m * sCm + n * sCn] = t;
-        }
-        __syncthreads();
-    }
 }
 
 __device__ __forceinline__ double load_val(const double* p, int i) { return p[i]; }
@@ -947,24 +935,24 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // S[k2][i1] = sum_i2 UT2[k2][i2] R[i2][i1]
-        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1, L.red);
+        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1);
         // Rt[k2][k1] = sum_i1 S[k2][i1] U1[i1][k1], k1 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n1, n2, bs, L.S, n1, 1, L.Slab, L.red, L.Out, bs, 1);
         else if (B.sbig)
-            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, L.red);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
         else
-            small_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, L.red);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
     } else {
         // S[i2][k1] = sum_i1 R[i2][i1] U1[i1][k1]
-        small_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1, L.red);
+        mfma_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1);
         // Rt[k2][k1] = sum_i2 U2[i2][k2] S[i2][k1], k2 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n2, n1, bs, L.S, 1, n1, L.Slab, L.red, L.Out, 1, n1);
         else if (B.sbig)
-            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, L.red);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
         else
-            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, L.red);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
     }
     for (int o = threadIdx.x; o < B.nown; o += kBlock) io.rt[off + B.gi(o)] = L.Out[o] * Iw[o];
     __syncthreads();
@@ -987,24 +975,24 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // T[i2][k1] = sum_k2 U2[i2][k2] Rt[k2][k1]
-        small_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1, L.red);
+        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1);
         // Z[i2][i1] = sum_k1 T[i2][k1] UT1[k1][i1], i1 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n1, n2, bs, Tm, n1, 1, L.Slab, L.red, L.Out, bs, 1);
         else if (B.sbig)
-            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, L.red);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
         else
-            small_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, L.red);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
     } else {
         // T[k2][i1] = sum_k1 Rt[k2][k1] UT1[k1][i1]
-        small_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1, L.red);
+        mfma_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1);
         // Z[i2][i1] = sum_k2 UT2[k2][i2] T[k2][i1], i2 in block
         if (B.wide)
             fd_big<TU, TC>(g.blk, n2, n1, bs, Tm, 1, n1, L.Slab, L.red, L.Out, 1, n1);
         else if (B.sbig)
-            small_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, L.red);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
         else
-            small_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, L.red);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
     }
     double dot = 0.0;
     const double* Rd = L.Own;
@@ -1023,7 +1011,7 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
 
 // ---------------------------------------------------------------------------
 // 3D fast diagonalisation: one task per grid, the three factors staged in LDS,
-// six mode products (small_gemm; the middle one batched over direction 3).
+// six mode products (mfma_gemm; the middle one batched over direction 3).
 // ---------------------------------------------------------------------------
 template <typename TU>
 struct Fd3Lds {
@@ -1116,11 +1104,11 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     }
     __syncthreads();
     // S[i3 i2][k1] = sum_i1 R[i3 i2][i1] U1[i1][k1]
-    small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1, L.red);
+    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1);
     // T[i3][k2][k1] = sum_i2 U2[i2][k2] S[i3][i2][k1]
-    small_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, L.red, n3, 0, n12, n12);
+    mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, n3, 0, n12, n12);
     // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1]
-    small_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, L.red);
+    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1);
     for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
     __syncthreads();
 }
@@ -1174,11 +1162,11 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
     const int64_t off = g.dof_off;
     // T[i3][k2 k1] = sum_k3 U3[i3][k3] Rt[k3][k2 k1]
-    small_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1, L.red);
+    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1);
     // S[i3][i2][k1] = sum_k2 U2[i2][k2] T[i3][k2][k1]
-    small_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, L.red, n3, 0, n12, n12);
+    mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, n3, 0, n12, n12);
     // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
-    small_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, L.red);
+    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1);
     if (io.scale) {
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] *= io.scale[off + i];
