@@ -232,6 +232,13 @@ iga_status iga_sg_apply(iga_sg_plan plan, int comp, int which, const double* x_d
 /* Load vector of component comp (after iga_sg_assemble) to out_dev. */
 iga_status iga_sg_rhs(iga_sg_plan plan, int comp, double* out_dev);
 
+/* Replace the load vector of component comp (after iga_sg_assemble, before
+ * iga_sg_solve) by b_dev (device, the component's interior unknowns in the
+ * layout of iga_sg_rhs): a caller's own right-hand side, or a fault forced
+ * from the host (a non-finite entry ends that component with status 6 and
+ * leaves the others untouched). */
+iga_status iga_sg_set_rhs(iga_sg_plan plan, int comp, const double* b_dev);
+
 /* Host copies of the 1D generalised eigen-decomposition K U = M U diag(lam),
  * U^T M U = I, of direction dir and level lev of patch 0: U_host [n][n]
  * (row i = basis function i, column k = eigenvector k), lam_host [n],

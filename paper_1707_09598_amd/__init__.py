@@ -27,7 +27,7 @@ APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5, "fds
 EXPORTS = (
     "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_plan_stats", "iga_sg_bind", "iga_sg_components",
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
-    "iga_sg_apply", "iga_sg_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
+    "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
 )
@@ -116,6 +116,7 @@ def lib():
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
         L.iga_sg_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         L.iga_sg_rhs.argtypes = [vp, C.c_int, vp]
+        L.iga_sg_set_rhs.argtypes = [vp, C.c_int, vp]
         L.iga_sg_fd_factor.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
         L.iga_sg_matrices_1d.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
         L.iga_sg_destroy.argtypes = [vp]
@@ -352,6 +353,14 @@ class Plan:
         out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
         _check(lib().iga_sg_rhs(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
+
+    def set_rhs(self, comp: int, b) -> None:
+        import torch
+        b = torch.as_tensor(b, dtype=torch.float64, device=self.device).contiguous()
+        if b.numel() != int(self.ndof[comp]):
+            raise ValueError("load vector length does not match the component")
+        self._rhs_keep = b  # the copy is asynchronous on the plan's stream
+        _check(lib().iga_sg_set_rhs(self.h, comp, C.c_void_p(b.data_ptr())))
 
     def loga(self, comp: int):
         import torch

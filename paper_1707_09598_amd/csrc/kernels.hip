@@ -1198,6 +1198,24 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
     return IGA_OK;
 }
 
+iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
+    if (!P || comp < 0 || comp >= P->ncomp || !b) {
+        set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->assembled) {
+        set_error("iga_sg_set_rhs before iga_sg_assemble");
+        return IGA_ERR_STATE;
+    }
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    Params K = make_params(P);
+    for (const Grid& g : P->grids)
+        if (g.comp == comp)
+            HIP_OK(hipMemcpyAsync(K.b + g.dof_off, b, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+    P->solved = false;
+    return IGA_OK;
+}
+
 iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, double* y) {
     if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 6) {
         set_error("invalid arguments");

@@ -113,3 +113,16 @@ def test_workspace_and_tiles_cover_every_unknown(S):
     P = S.Plan(W.config("cfg2"))
     assert P.workspace_bytes() > 0
     assert int(P.ndof.sum()) == 22545
+
+
+def test_bind_rejects_small_null_or_misaligned_workspace(S):
+    """Checked on the host before any device call."""
+    import ctypes as C
+    P = S.Plan(W.config("cfg1"))
+    need = P.workspace_bytes()
+    L = S.lib()
+    assert L.iga_sg_bind(P.h, C.c_void_p(4096), C.c_size_t(need - 1), None) == 3
+    assert "too small" in L.iga_sg_last_error().decode()
+    assert L.iga_sg_bind(P.h, None, C.c_size_t(need), None) == 1
+    assert L.iga_sg_bind(P.h, C.c_void_p(4096 + 8), C.c_size_t(need), None) == 1
+    assert "aligned" in L.iga_sg_last_error().decode()
