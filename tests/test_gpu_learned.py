@@ -263,8 +263,11 @@ def test_learned_solve_parity_and_fallback(S):
     # preconditionings of each solve, plain fast diagonalisation after them
     _solve_vs_oracle(P, wl, True, 1e-9, learned_iters=10)
     # FP32 inner solves with the correction, FP64 refinement judged by the
-    # plain preconditioner
+    # plain preconditioner; a milder random correction (a large random one
+    # can stall FP32 flexible CG into p.Ap <= 0, a breakdown)
+    P.set_network(S.Network(ch, _params(ch, seed=4, last_scale=0.005)))
     _solve_vs_oracle(P, wl, True, 1e-9, learned_iters=10, precision="fp32")
+    P.set_network(net)
     # non-finite weights: every learned step is rejected, the plain
     # preconditioner takes over and the iteration is the plain one
     bad = S.Network(ch, np.full(net.count, np.nan, dtype=np.float32))

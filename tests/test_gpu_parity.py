@@ -217,11 +217,48 @@ def test_solve_parity_cfg2_mixed(S, precision):
     _solve_and_compare(S, W.config("cfg2"), precision, True, 1e-9, 1e-9)
 
 
-@pytest.mark.parametrize("precision,w", [("fp64", 6), ("bf16fd", 6), ("fp64", 8)])
+@pytest.mark.parametrize("precision,w", [("fp64", 6), ("bf16fd", 6), ("fp64", 8), ("bf16fd", 8)])
 def test_solve_parity_cube(S, precision, w):
     log(f"case solve cfg3 w={w} {precision}")
     tol = 1e-10 if precision == "fp64" else 1e-9
     _solve_and_compare(S, W.config("cfg3", w=w), precision, True, tol, tol)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_parity_random_field_full_size(S, precision):
+    """The random-field cube at its full size (w=7, 85 grids, a = exp(g) on a
+    64^3 vertex grid, first sample)."""
+    log(f"case solve cfg5 w=7 {precision}")
+    a = W.grf_samples(1, n=64)[0]
+    wl = W.config("cfg5", a=W._field("grid3d", data=a))
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    _solve_and_compare(S, wl, precision, True, tol, tol, npts=2048)
+
+
+def test_combine_at_knots_corners_and_edges(S):
+    """Points on knots, on the boundary (xi = 0 and 1: the last span is closed
+    on the right) and at the corners, and an empty point set."""
+    import torch
+    log("case combine at knots and boundary cfg2 w=7")
+    wl = W.config("cfg2", w=7)
+    P = _bound(S, wl)
+    P.solve(precision="fp64", tol=1e-12, maxit=400, max_refine=3)
+    t = np.array([0.0, 1.0 / 128, 0.25, 0.5, 0.75, 1.0 - 1.0 / 128, 1.0])
+    xi = np.array([[a, b] for a in t for b in t])
+    Po = O.Problem(wl)
+    coefs = Po.solve_all()
+    u = P.combine(xi).cpu().numpy()
+    u_ref = Po.sg_eval(coefs, xi)
+    scale = np.abs(u_ref).max()
+    assert np.abs(u - u_ref).max() < 1e-10 * scale
+    on_edge = (xi == 0.0).any(axis=1) | (xi == 1.0).any(axis=1)
+    assert np.abs(u[on_edge]).max() < 1e-12 * scale  # homogeneous Dirichlet data
+    c = P.ncomp // 2
+    ue = P.eval(c, xi).cpu().numpy()
+    ue_ref = Po.eval(P.levels[c], Po.split(coefs)[c], xi)
+    assert np.abs(ue - ue_ref).max() < 1e-10 * np.abs(ue_ref).max()
+    empty = P.combine(np.zeros((0, 2)))
+    assert isinstance(empty, torch.Tensor) and empty.numel() == 0
 
 
 def test_single_component_edge_case(S):
