@@ -513,13 +513,20 @@ __device__ __forceinline__ TC mm_ld(const T* p, int i) {
 template <typename TA, typename TB, typename TC>
 __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
                                           int sBn, double* C, int sCm, int sCn, int nb = 1, int sAb = 0,
-                                          int sBb = 0, int sCb = 0) {
+                                          int sBb = 0, int sCb = 0, double* red = nullptr) {
     using MF = Mfma<TC>;
     using V = typename MF::V;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, tmn = tm * tn;
-    for (int u = wave; u < tmn * nb; u += kWaves) {  // uniform per wavefront
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, tmn = tm * tn, units = tmn * nb;
+    // fewer tiles than wavefronts: K is cut into ks slices whose partial tiles
+    // are summed in slice order through red (ks * M * N <= kBigRed doubles)
+    int ks = 1;
+    if (red && nb == 1)
+        while (2 * ks * units <= kWaves && 2 * ks * M * N <= kBigRed && K >= 16 * ks) ks *= 2;
+    const int kc = ((K + ks - 1) / ks + 7) & ~7;
+    for (int w = wave; w < units * ks; w += kWaves) {  // uniform per wavefront
+        const int u = w / ks, sl = w - u * ks;
         const int bt = u / tmn, t = u - bt * tmn;
         const int ti = t / tn, tj = t - ti * tn;
         const TA* Ab = A + bt * sAb;
@@ -527,24 +534,40 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
         double* Cb = C + bt * sCb;
         const int i = 16 * ti + li, j = 16 * tj + li;
         const bool iv = i < M, jv = j < N;
+        const int kb0 = sl * kc, kb1 = min(K, kb0 + kc);
         V acc0 = {TC(0), TC(0), TC(0), TC(0)};
         V acc1 = acc0;
-        for (int k0 = 0; k0 < K; k0 += 8) {
+        for (int k0 = kb0; k0 < kb1; k0 += 8) {
             const int ka = k0 + lk, kb = k0 + 4 + lk;
-            const TC a0 = iv && ka < K ? mm_ld<TC>(Ab, i * sAm + ka * sAk) : TC(0);
-            const TC b0 = jv && ka < K ? mm_ld<TC>(Bb, ka * sBk + j * sBn) : TC(0);
-            const TC a1 = iv && kb < K ? mm_ld<TC>(Ab, i * sAm + kb * sAk) : TC(0);
-            const TC b1 = jv && kb < K ? mm_ld<TC>(Bb, kb * sBk + j * sBn) : TC(0);
+            const TC a0 = iv && ka < kb1 ? mm_ld<TC>(Ab, i * sAm + ka * sAk) : TC(0);
+            const TC b0 = jv && ka < kb1 ? mm_ld<TC>(Bb, ka * sBk + j * sBn) : TC(0);
+            const TC a1 = iv && kb < kb1 ? mm_ld<TC>(Ab, i * sAm + kb * sAk) : TC(0);
+            const TC b1 = jv && kb < kb1 ? mm_ld<TC>(Bb, kb * sBk + j * sBn) : TC(0);
             acc0 = MF::step(a0, b0, acc0);
             acc1 = MF::step(a1, b1, acc1);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = 16 * ti + MF::row(lane, r);
-            if (ii < M && jv) Cb[ii * sCm + j * sCn] = static_cast<double>(acc0[r] + acc1[r]);
+            if (ii < M && jv) {
+                const double v = static_cast<double>(acc0[r] + acc1[r]);
+                if (ks == 1) Cb[ii * sCm + j * sCn] = v;
+                else red[(sl * M + ii) * N + j] = v;
+            }
         }
     }
     __syncthreads();
+    if (ks > 1) {
+        const FDiv dN(N);
+        for (int o = threadIdx.x; o < M * N; o += kBlock) {
+            int n;
+            const int m = dN.div(o, &n);
+            double v = 0.0;
+            for (int sl = 0; sl < ks; ++sl) v += red[sl * M * N + o];
+            C[m * sCm + n * sCn] = v;
+        }
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ double load_val(const double* p, int i) { return p[i]; }
@@ -587,48 +610,22 @@ struct FdIO {
 };
 
 
-// Big-direction mode product of one FD block:
-//   C[m][j] = sum_k V(m, k) U(k, c0 + j),  m < msm, j < bsa <= BS, k < K,
-// V in LDS (V(m,k) = V[m*sVm + k*sVk]), U rows in global memory
-// (U(k, c) = U[k*ldu + c]; ldu and the table base are multiples of 8 elements).
-// Lanes cover a row segment of BS columns with 16-byte loads (CPL columns each),
-// the workgroup walks the rows in strides, so each wavefront load instruction
-// reads whole row segments (coalesced).  Per-thread partial sums for a chunk of
-// MMC rows of V are reduced by a fixed butterfly over the lanes sharing a
-// column group and a fixed-order sum over the four wavefronts (deterministic).
+// 16-byte units of the factor tables (CPL elements each).  The slab of a
+// blocked long direction is copied to LDS by 16-byte lanes, thread t taking
+// row t / (blk / CPL) and column group t % (blk / CPL) of each pass of
+// kBlock * CPL / blk rows, which lays it out row-major, [long index][blk].
 template <typename TU> struct VecU;
 template <> struct VecU<double> {
     static constexpr int CPL = 2;
     using Raw = double2;
-    __device__ static Raw zero() { return make_double2(0.0, 0.0); }
-    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
-        u[0] = static_cast<TC>(v.x);
-        u[1] = static_cast<TC>(v.y);
-    }
 };
 template <> struct VecU<float> {
     static constexpr int CPL = 4;
     using Raw = float4;
-    __device__ static Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
-        u[0] = v.x;
-        u[1] = v.y;
-        u[2] = v.z;
-        u[3] = v.w;
-    }
 };
 template <> struct VecU<uint16_t> {
     static constexpr int CPL = 8;
     using Raw = uint4;
-    __device__ static Raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
-    template <typename TC> __device__ static void unpack(const Raw& v, TC* u) {
-        const unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            u[2 * i] = __uint_as_float(w[i] << 16);
-            u[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
-        }
-    }
 };
 template <typename TU>
 __device__ __forceinline__ typename VecU<TU>::Raw load_raw(const TU* p) {
@@ -807,90 +804,6 @@ __device__ __forceinline__ void fd_issue_bwd(const Params& P, const TaskMeta& M,
     fd_issue_factors<TU>(P, M, B, false, L);
 }
 
-// Long-direction product of a blocked grid from the LDS slab:
-//   C[m][j] = sum_k V(m, k) U(k, k0 + j), m < msm, j < bsa, k < K,
-// V(m,k) = V[m*sVm + k*sVk].  Thread (lane, wave) holds column group
-// jc = (lane % LPR) * CPL of rows r0 + s * RPT; partial sums over a chunk of MMC
-// rows of V are reduced by a fixed butterfly over the lanes of a column group
-// and a fixed-order sum over the four wavefronts (deterministic).
-template <int BS, typename TU, typename TC>
-__device__ __forceinline__ void fd_big_t(int K, int msm, int bsa, const double* V, int sVm, int sVk,
-                                         const typename VecU<TU>::Raw* slab, double* red, double* C, int sCm,
-                                         int sCj) {
-    constexpr int CPL = VecU<TU>::CPL;
-    constexpr int LPR = BS / CPL;  // lanes per row segment
-    constexpr int RPW = 64 / LPR;  // rows per wavefront copy
-    constexpr int RPT = kWaves * RPW;  // rows per workgroup pass
-    constexpr int ACC = (sizeof(TC) == 8 ? 32 : 64) / CPL;
-    constexpr int MMC = ACC < kBigRed / (kWaves * BS) ? ACC : kBigRed / (kWaves * BS);
-    static_assert(LPR >= 1 && LPR <= 64 && MMC >= 1, "block shape");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int jc = (lane % LPR) * CPL;
-    const int r0 = wave * RPW + lane / LPR;
-    const bool live = jc < bsa;
-    const int rows = (K + RPT - 1) / RPT;
-    for (int m0 = 0; m0 < msm; m0 += MMC) {
-        const int mc = min(MMC, msm - m0);
-        TC acc[MMC][CPL];
-#pragma unroll
-        for (int m = 0; m < MMC; ++m)
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) acc[m][j] = TC(0);
-        if (live) {
-#pragma unroll 2
-            for (int s = 0; s < rows; ++s) {
-                const int k = r0 + s * RPT;
-                if (k < K) {
-                    TC u[CPL];
-                    VecU<TU>::unpack(slab[s * kBlock + threadIdx.x], u);
-                    const double* vk = V + static_cast<int64_t>(m0) * sVm + static_cast<int64_t>(k) * sVk;
-#pragma unroll
-                    for (int m = 0; m < MMC; ++m) {
-                        if (m < mc) {
-                            const TC v = static_cast<TC>(vk[m * sVm]);
-#pragma unroll
-                            for (int j = 0; j < CPL; ++j) acc[m][j] += v * u[j];
-                        }
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < MMC; ++m) {
-            if (m < mc) {  // uniform: only the rows of V in use are reduced
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) {
-                    TC v = acc[m][j];
-#pragma unroll
-                    for (int sft = LPR; sft < 64; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                    if (lane < LPR) red[(wave * MMC + m) * BS + jc + j] = static_cast<double>(v);
-                }
-            }
-        }
-        __syncthreads();
-        for (int o = threadIdx.x; o < mc * BS; o += kBlock) {
-            const int m = o / BS, j = o % BS;
-            if (j < bsa) {
-                double t = 0.0;
-#pragma unroll
-                for (int w = 0; w < kWaves; ++w) t += red[(w * MMC + m) * BS + j];
-                C[(m0 + m) * sCm + j * sCj] = t;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// Dispatch on the block width BS of the grid (8, 16 or 32 columns).
-template <typename TU, typename TC>
-__device__ __forceinline__ void fd_big(int BS, int K, int msm, int bsa, const double* V, int sVm, int sVk,
-                                       const typename VecU<TU>::Raw* slab, double* red, double* C, int sCm,
-                                       int sCj) {
-    if (BS <= 8) fd_big_t<8, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
-    else if (BS <= 16) fd_big_t<16, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
-    else fd_big_t<32, TU, TC>(K, msm, bsa, V, sVm, sVk, slab, red, C, sCm, sCj);
-}
-
 // Forward transform of one FD block, after fd_issue_fwd and g2l_wait_sync:
 //   r = r_old - alpha q (grid, LDS), owned: r_out = r, d += alpha p,
 //   part = ||r_owned||^2, Rt = (U1 (x) U2)^T r on the block times 1 / lambda.
@@ -935,24 +848,24 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // S[k2][i1] = sum_i2 UT2[k2][i2] R[i2][i1]
-        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1);
+        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, L.R, n1, 1, L.S, n1, 1, 1, 0, 0, 0, L.red);
         // Rt[k2][k1] = sum_i1 S[k2][i1] U1[i1][k1], k1 in block
         if (B.wide)
-            fd_big<TU, TC>(g.blk, n1, n2, bs, L.S, n1, 1, L.Slab, L.red, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, reinterpret_cast<const TU*>(L.Slab), g.blk, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
         else if (B.sbig)
-            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
         else
-            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, L.S, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
     } else {
         // S[i2][k1] = sum_i1 R[i2][i1] U1[i1][k1]
-        mfma_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1);
+        mfma_gemm<double, TU, TC>(n2, n1, n1, L.R, n1, 1, L.Us, ls, 1, L.S, n1, 1, 1, 0, 0, 0, L.red);
         // Rt[k2][k1] = sum_i2 U2[i2][k2] S[i2][k1], k2 in block
         if (B.wide)
-            fd_big<TU, TC>(g.blk, n2, n1, bs, L.S, 1, n1, L.Slab, L.red, L.Out, 1, n1);
+            mfma_gemm<double, TU, TC>(n1, bs, n2, L.S, 1, n1, reinterpret_cast<const TU*>(L.Slab), g.blk, 1, L.Out, 1, n1, 1, 0, 0, 0, L.red);
         else if (B.sbig)
-            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, 1, 0, 0, 0, L.red);
         else
-            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, L.S, n1, 1, L.Out, n1, 1, 1, 0, 0, 0, L.red);
     }
     for (int o = threadIdx.x; o < B.nown; o += kBlock) io.rt[off + B.gi(o)] = L.Out[o] * Iw[o];
     __syncthreads();
@@ -975,24 +888,24 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     const int k0 = B.k0, bs = B.bs, ls = L.ldu_s, lb = L.ldu_b;
     if (B.big == 0) {
         // T[i2][k1] = sum_k2 U2[i2][k2] Rt[k2][k1]
-        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1);
+        mfma_gemm<TU, double, TC>(n2, n1, n2, L.Us, ls, 1, Rt, n1, 1, Tm, n1, 1, 1, 0, 0, 0, L.red);
         // Z[i2][i1] = sum_k1 T[i2][k1] UT1[k1][i1], i1 in block
         if (B.wide)
-            fd_big<TU, TC>(g.blk, n1, n2, bs, Tm, n1, 1, L.Slab, L.red, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, reinterpret_cast<const TU*>(L.Slab), g.blk, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
         else if (B.sbig)
-            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, L.Ub + k0, lb, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
         else
-            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1);
+            mfma_gemm<double, TU, TC>(n2, bs, n1, Tm, n1, 1, Ubig + k0, lb, 1, L.Out, bs, 1, 1, 0, 0, 0, L.red);
     } else {
         // T[k2][i1] = sum_k1 Rt[k2][k1] UT1[k1][i1]
-        mfma_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1);
+        mfma_gemm<double, TU, TC>(n2, n1, n1, Rt, n1, 1, L.Us, ls, 1, Tm, n1, 1, 1, 0, 0, 0, L.red);
         // Z[i2][i1] = sum_k2 UT2[k2][i2] T[k2][i1], i2 in block
         if (B.wide)
-            fd_big<TU, TC>(g.blk, n2, n1, bs, Tm, 1, n1, L.Slab, L.red, L.Out, 1, n1);
+            mfma_gemm<double, TU, TC>(n1, bs, n2, Tm, 1, n1, reinterpret_cast<const TU*>(L.Slab), g.blk, 1, L.Out, 1, n1, 1, 0, 0, 0, L.red);
         else if (B.sbig)
-            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, L.Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, 1, 0, 0, 0, L.red);
         else
-            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1);
+            mfma_gemm<TU, double, TC>(bs, n1, n2, Ub + static_cast<int64_t>(k0) * lb, lb, 1, Tm, n1, 1, L.Out, n1, 1, 1, 0, 0, 0, L.red);
     }
     double dot = 0.0;
     const double* Rd = L.Own;
@@ -1104,11 +1017,11 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     }
     __syncthreads();
     // S[i3 i2][k1] = sum_i1 R[i3 i2][i1] U1[i1][k1]
-    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1);
+    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1, 1, 0, 0, 0, L.red);
     // T[i3][k2][k1] = sum_i2 U2[i2][k2] S[i3][i2][k1]
     mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, n3, 0, n12, n12);
     // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1]
-    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1);
+    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, 1, 0, 0, 0, L.red);
     for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
     __syncthreads();
 }
@@ -1162,11 +1075,11 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
     const int64_t off = g.dof_off;
     // T[i3][k2 k1] = sum_k3 U3[i3][k3] Rt[k3][k2 k1]
-    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1);
+    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1, 1, 0, 0, 0, L.red);
     // S[i3][i2][k1] = sum_k2 U2[i2][k2] T[i3][k2][k1]
     mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, n3, 0, n12, n12);
     // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
-    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1);
+    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, 1, 0, 0, 0, L.red);
     if (io.scale) {
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] *= io.scale[off + i];
