@@ -212,6 +212,13 @@ inline IGA_HD FdLayout fd_layout_3d(const Grid& g, const int* ld, int usize) {
 constexpr size_t kSolveLdsHead = kCtxBytes + kMetaSlots * sizeof(TaskMeta);
 
 // Workspace layout: byte offsets of every device array.
+// Barrier block (unsigned words): generation, finished-grid count, traced
+// sweeps, the global arrival count on its own 64-byte line, the group arrival
+// counts one line apart; bytes 64..67 hold the assembly error flag.
+constexpr int kBarGen = 1, kBarDone = 2, kBarSweeps = 3, kBarCount = 32, kBarGroup = 64, kBarStride = 16;
+constexpr int kBarGroups = 8;
+constexpr int kBarBytes = 4 * (kBarGroup + kBarStride * kBarGroups);
+
 struct Layout {
     size_t tabs, grids, grids_lp, dpool, ipool, fpool, hpool, ctrl;
     size_t G64, G32, Fq;          // operator coefficients and load density at Gauss points

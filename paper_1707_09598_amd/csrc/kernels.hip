@@ -558,9 +558,10 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
             P.st2[P.ngrid + g] = s;
         }
         if (threadIdx.x == 0) {
-            P.bar[0] = 0u;
-            P.bar[2] = 0u;
+            P.bar[kBarDone] = 0u;
+            P.bar[kBarCount] = 0u;
         }
+        if (threadIdx.x < kBarGroups) P.bar[kBarGroup + kBarStride * threadIdx.x] = 0u;
     }
 }
 
@@ -1062,7 +1063,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             std::vector<unsigned long long> tr(1 + 6 * kTraceSweeps);
             unsigned sweeps = 0;
             HIP_OK(hipMemcpy(tr.data(), A.trace, sizeof(unsigned long long) * tr.size(), hipMemcpyDeviceToHost));
-            HIP_OK(hipMemcpy(&sweeps, reinterpret_cast<char*>(P->ws) + P->lay.bar + 12, sizeof(unsigned),
+            HIP_OK(hipMemcpy(&sweeps, reinterpret_cast<char*>(P->ws) + P->lay.bar + 4 * kBarSweeps, sizeof(unsigned),
                              hipMemcpyDeviceToHost));
             const int ns = std::min<int>(static_cast<int>(sweeps), kTraceSweeps);
             rep->sweeps = static_cast<int>(sweeps);

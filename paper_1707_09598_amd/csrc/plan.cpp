@@ -791,7 +791,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());
-    L.bar = take(256);
+    L.bar = take(kBarBytes);
     L.trace = take(sizeof(unsigned long long) * (1 + 6 * 4096));
     L.total = off;
     *out = P;

@@ -1180,19 +1180,37 @@ __device__ __forceinline__ void meta_fill(const Params& P, const Task& tk, TaskM
 // ===========================================================================
 // grid-wide barrier (all workgroups co-resident: cooperative launch)
 // ===========================================================================
+// Grid-wide barrier of the persistent solve, two levels: the workgroups
+// arrive on one of kBarGroups counters (blockIdx % kBarGroups, each on its own
+// 64-byte line), the last of each group arrives on the global counter, and the
+// last group advances the generation word that every workgroup polls.
+// Counters only grow within a launch (k_solve_init clears them): barrier k
+// takes group g from k gs to (k + 1) gs, so the last arrival is the one that
+// reaches a multiple of gs.  Memory ordering: one agent-scope release fence
+// before arriving, acquire-release fences where an arrival is forwarded, one
+// acquire fence after the generation changes.  Against a flat counter with
+// release/acquire read-modify-writes this halves the L2 write-back and
+// invalidate work and the contention on one address.
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nwg) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned gen = __hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned grp = blockIdx.x % kBarGroups;
+        const unsigned ng = nwg < kBarGroups ? nwg : kBarGroups;
+        const unsigned gs = (nwg - grp + kBarGroups - 1) / kBarGroups;  // workgroups in this group
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
-                __builtin_amdgcn_s_sleep(1);
+        const unsigned a =
+            __hip_atomic_fetch_add(&bar[kBarGroup + kBarStride * grp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((a + 1u) % gs == 0u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const unsigned b = __hip_atomic_fetch_add(&bar[kBarCount], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((b + 1u) % ng == 0u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_store(&bar[kBarGen], gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
+        while (__hip_atomic_load(&bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+            __builtin_amdgcn_s_sleep(1);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -1593,14 +1611,14 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                     finish = true;
                 }
                 S1[gi] = ns;
-                if (finish) atomicAdd(&P.bar[2], 1u);
+                if (finish) atomicAdd(&P.bar[kBarDone], 1u);
             }
         }
         trace_busy(A, sweep, 2, tb);
         grid_barrier(P.bar, nwg);
         trace_mark(A, sweep, 2);
-        if (A.trace && blockIdx.x == 0 && threadIdx.x == 0) P.bar[3] = sweep + 1;
-        const unsigned done = __hip_atomic_load(&P.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (A.trace && blockIdx.x == 0 && threadIdx.x == 0) P.bar[kBarSweeps] = sweep + 1;
+        const unsigned done = __hip_atomic_load(&P.bar[kBarDone], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (static_cast<int>(done) >= A.ndone_target) break;
     }
 }
