@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "abb1499484c18f8d5ef29e781188087067e1a4d9d45e4ae1b3f913f1b2843b4b",
-    "fetch_kib": 1225982.5, "write_kib": 206041.7,
-    "fetch_factor": 262144.0 / 131088.2, "write_factor": 262144.0 / 262144.0,
+    "sha256": "913a7d062e6f137e9955243bb593acf3ea6da09b3b906dff1a8aa4277ddf0861",
+    "fetch_kib": 1223822.5, "write_kib": 207003.5,
+    "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
 }
 
 
