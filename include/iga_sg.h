@@ -88,9 +88,14 @@ typedef struct {
 /* Discretisation (Sec. 2.2 and Sec. 3): degree p in every direction,
  * interior continuity C^r (0 <= r < p), sparse-grid level w, minimum level
  * lmin per direction (components have levels i >= lmin with
- * w-d+1 <= |i| <= w), Gauss points per direction nq (0 => p+1). */
+ * w-d+1 <= |i| <= w), Gauss points per direction nq (0 => p+1).
+ * nsamples (0 or 1 => one) problems that differ only in their field data
+ * (coefficient samples) are planned, assembled and solved together: every
+ * component grid exists once per sample, and "instance" s * ncomp + c names
+ * component c of sample s in the calls below that take a component index. */
 typedef struct {
     int p, r, w, lmin, nq;
+    int nsamples;
 } iga_sg_disc;
 
 /* Fields (right-hand side f, coefficient a, Dirichlet data g). */
@@ -113,6 +118,8 @@ typedef struct {
     double prm[4];
     const double* data_dev;  /* GRID3D only; device memory */
     int n[3];
+    int64_t sample_stride;   /* GRID3D in a plan of several samples: sample s reads
+                                data_dev + s * sample_stride (0 => one field for all) */
 } iga_field;
 
 /* Precision of the inner solver (the outer refinement is always FP64). */
@@ -147,8 +154,8 @@ typedef struct {
                           diagonal of A); 1: the unscaled pencil, z = P^-1 r */
 } iga_sg_solve_opts;
 
-/* Per-component results; arrays are caller-owned host buffers of length
- * ncomp (any may be NULL).  status: 0 converged, 5 maxit, 6 breakdown.
+/* Per-instance results (component c of sample s at s * ncomp + c); arrays
+ * are caller-owned host buffers of length ncomp * nsamples (any may be NULL).  status: 0 converged, 5 maxit, 6 breakdown.
  * relres: ||b - A x||_2 / ||b||_2 of the last FP64 residual;
  * prelres: sqrt(r.P^-1 r / b.P^-1 b), the quantity the stopping test uses
  * (P the fast-diagonalisation preconditioner; about the relative
@@ -189,8 +196,9 @@ iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64
  * the basis tables on the device; synchronises the stream before returning. */
 iga_status iga_sg_bind(iga_sg_plan plan, void* workspace_dev, size_t bytes, void* stream);
 
-/* Component list: levels_host [n][dim], ndof_host [n] (interior unknowns),
- * coef_host [n] (combination coefficients c_i).  Any pointer may be NULL. */
+/* Component list: levels_host [n][dim], ndof_host [n] (interior unknowns of
+ * one sample), coef_host [n] (combination coefficients c_i).  Any pointer may
+ * be NULL. */
 iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t* ndof_host,
                              double* coef_host);
 
@@ -207,13 +215,14 @@ iga_status iga_sg_assemble(iga_sg_plan plan, const iga_field* f, const iga_field
  * component failed; the other components are still solved. */
 iga_status iga_sg_solve(iga_sg_plan plan, const iga_sg_solve_opts* opts, iga_sg_report* report);
 
-/* u_dev[i] = sum_c coef_c u_c(xi_i), eq. (TD-combi-tec), accumulated in FP64
- * in component order.  xi_dev [n][dim] parametric points in [0,1]^dim,
+/* u_dev[s * n + i] = sum_c coef_c u_{s,c}(xi_i), eq. (TD-combi-tec), for every
+ * sample s (u_dev holds nsamples * n values), accumulated in FP64 in
+ * component order.  xi_dev [n][dim] parametric points in [0,1]^dim,
  * patch_dev [n] patch ids or NULL (patch 0). */
 iga_status iga_sg_combine(iga_sg_plan plan, const double* xi_dev, const int* patch_dev, int64_t n,
                           double* u_dev);
 
-/* u_dev[i] = u_comp(xi_i) for one component. */
+/* u_dev[i] = u_comp(xi_i) for one component instance (s * ncomp + c). */
 iga_status iga_sg_eval(iga_sg_plan plan, int comp, const double* xi_dev, const int* patch_dev,
                        int64_t n, double* u_dev);
 

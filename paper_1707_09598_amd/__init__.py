@@ -57,12 +57,13 @@ class _Geometry(C.Structure):
 
 
 class _Disc(C.Structure):
-    _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int)]
+    _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int),
+                ("nsamples", C.c_int)]
 
 
 class _Field(C.Structure):
     _fields_ = [("kind", C.c_int), ("prm", C.c_double * 4), ("data_dev", C.c_void_p),
-                ("n", C.c_int * 3)]
+                ("n", C.c_int * 3), ("sample_stride", C.c_int64)]
 
 
 class _Opts(C.Structure):
@@ -155,9 +156,12 @@ class Plan:
 
     Host-side methods (components, fd_factor, matrices_1d) need no GPU.
     ``bind`` allocates the device workspace with torch on the current device.
+    ``nsamples`` > 1 plans that many problems differing in their field data
+    (a grid3d coefficient given as [nsamples, n3, n2, n1]); component c of
+    sample s is instance s * ncomp + c, combine returns [nsamples, n].
     """
 
-    def __init__(self, wl: Dict[str, Any]):
+    def __init__(self, wl: Dict[str, Any], nsamples: int = 1):
         self.wl = wl
         self.dim = d = int(wl["dim"])
         self._keep = []
@@ -191,7 +195,8 @@ class Plan:
         self._keep.append(iarr)
         G = _Geometry(d, len(pats), C.cast(parr, C.POINTER(_Patch)), len(ifs),
                       C.cast(iarr, C.POINTER(_Iface)))
-        D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0)
+        self.nsamples = int(nsamples)
+        D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0, self.nsamples)
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h
@@ -206,6 +211,7 @@ class Plan:
         _check(lib().iga_sg_components(self.h, C.byref(n), lv.ctypes.data_as(_ip),
                                        nd.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(cf)))
         self.levels, self.ndof, self.coef = lv, nd, cf
+        self.ninst = self.ncomp * self.nsamples
 
     def __del__(self):
         try:
@@ -276,6 +282,8 @@ class Plan:
             shp = tuple(t.shape)[::-1]
             for k in range(3):
                 F.n[k] = int(shp[k])
+            if t.dim() == 4:  # one field per sample
+                F.sample_stride = int(shp[0] * shp[1] * shp[2])
         return F
 
     def assemble(self, f=None, a=None, g=None) -> None:
@@ -294,12 +302,12 @@ class Plan:
               learned: bool = False, learned_iters: int = 0, scaled: bool = True) -> Dict[str, Any]:
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups,
                   int(timing), int(continue_cg), int(learned), int(learned_iters), int(not scaled))
-        it = np.zeros(self.ncomp, dtype=np.int32)
-        rf = np.zeros(self.ncomp, dtype=np.int32)
-        rr = np.zeros(self.ncomp)
-        pr = np.zeros(self.ncomp)
-        stt = np.zeros(self.ncomp, dtype=np.int32)
-        R = _Report(self.ncomp, it.ctypes.data_as(_ip), rf.ctypes.data_as(_ip), _ptr(rr), _ptr(pr),
+        it = np.zeros(self.ninst, dtype=np.int32)
+        rf = np.zeros(self.ninst, dtype=np.int32)
+        rr = np.zeros(self.ninst)
+        pr = np.zeros(self.ninst)
+        stt = np.zeros(self.ninst, dtype=np.int32)
+        R = _Report(self.ninst, it.ctypes.data_as(_ip), rf.ctypes.data_as(_ip), _ptr(rr), _ptr(pr),
                     stt.ctypes.data_as(_ip), 0, 0)
         code = lib().iga_sg_solve(self.h, C.byref(o), C.byref(R))
         rep = {"code": code, "iters": it, "refinements": rf, "relres": rr, "prelres": pr,
@@ -322,13 +330,13 @@ class Plan:
         import torch
         xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
         n = xi.shape[0]
-        u = torch.empty(n, dtype=torch.float64, device=self.device)
+        u = torch.empty(self.nsamples * n, dtype=torch.float64, device=self.device)
         pid = None if patch is None else torch.as_tensor(patch, dtype=torch.int32,
                                                          device=self.device).contiguous()
         _check(lib().iga_sg_combine(self.h, C.c_void_p(xi.data_ptr()),
                                     C.c_void_p(pid.data_ptr() if pid is not None else 0), n,
                                     C.c_void_p(u.data_ptr())))
-        return u
+        return u.view(self.nsamples, n) if self.nsamples > 1 else u
 
     def eval(self, comp: int, xi, patch=None):
         import torch
@@ -344,27 +352,27 @@ class Plan:
 
     def coeffs(self, comp: int):
         import torch
-        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        out = torch.empty(int(self.ndof[comp % self.ncomp]), dtype=torch.float64, device=self.device)
         _check(lib().iga_sg_coeffs(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
 
     def rhs(self, comp: int):
         import torch
-        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        out = torch.empty(int(self.ndof[comp % self.ncomp]), dtype=torch.float64, device=self.device)
         _check(lib().iga_sg_rhs(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
 
     def set_rhs(self, comp: int, b) -> None:
         import torch
         b = torch.as_tensor(b, dtype=torch.float64, device=self.device).contiguous()
-        if b.numel() != int(self.ndof[comp]):
+        if b.numel() != int(self.ndof[comp % self.ncomp]):
             raise ValueError("load vector length does not match the component")
         self._rhs_keep = b  # the copy is asynchronous on the plan's stream
         _check(lib().iga_sg_set_rhs(self.h, comp, C.c_void_p(b.data_ptr())))
 
     def loga(self, comp: int):
         import torch
-        out = torch.empty(int(self.ndof[comp]), dtype=torch.float64, device=self.device)
+        out = torch.empty(int(self.ndof[comp % self.ncomp]), dtype=torch.float64, device=self.device)
         _check(lib().iga_sg_loga(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
 

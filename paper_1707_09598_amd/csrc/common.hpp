@@ -88,7 +88,7 @@ struct Grid {
     int ntd[3];       // tiles per direction
     int ntile;
     int tile_off;     // first operator task
-    int pad_;
+    int sample;       // coefficient sample (plans of several samples)
 };
 
 // Per-grid solver state (double-buffered by sweep parity on the device).

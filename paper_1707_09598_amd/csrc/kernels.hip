@@ -46,7 +46,13 @@ struct FieldDev {
     double prm[4];
     const double* data;
     int n[3];
+    int64_t sample_stride;  // elements between the data of consecutive samples
 };
+// The field of one grid's coefficient sample.
+__device__ __forceinline__ FieldDev field_of_sample(FieldDev f, int sample) {
+    if (f.data) f.data += sample * f.sample_stride;
+    return f;
+}
 
 __device__ __forceinline__ void sincos_coef(const double* prm, const double* x, double* a, double* da) {
     const double tp = 6.283185307179586476925;
@@ -268,8 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
             inv[2][2] = (DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]) / det;
         }
         if (!(det > 0.0)) atomicOr(err, 1);
-        const double av = field_eval(fa, d, x);
-        const double fv = field_eval(ff, d, x);
+        const double av = field_eval(field_of_sample(fa, g.sample), d, x);
+        const double fv = field_eval(field_of_sample(ff, g.sample), d, x);
         const double s = av * wq * fabs(det);
         // parametric coefficients Gp = a w |det| DF^-1 DF^-T (symmetric)
         double Gp[3][3];
@@ -524,7 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
         }
         double x[3] = {0, 0, 0};
         for (int k = 0; k < d; ++k) x[k] = Xh[k] / Xh[3];
-        P.loga[gi] = log(field_eval(fa, d, x));
+        P.loga[gi] = log(field_eval(field_of_sample(fa, g.sample), d, x));
     }
 }
 
@@ -809,6 +815,7 @@ FieldDev to_dev(const iga_field* f) {
         for (int i = 0; i < 4; ++i) F.prm[i] = f->prm[i];
         F.data = f->data_dev;
         for (int k = 0; k < 3; ++k) F.n[k] = f->n[k];
+        F.sample_stride = f->sample_stride;
     }
     return F;
 }
@@ -820,6 +827,10 @@ bool field_ok(const iga_field* f, int dim) {
         return false;
     return true;
 }
+
+// Instance index of a grid: component c of sample s is s * ncomp + c.
+int instance_of(const iga_sg_plan_s* P, const Grid& g) { return g.sample * P->ncomp + g.comp; }
+int ninstances(const iga_sg_plan_s* P) { return P->ncomp * P->nsamples; }
 
 int blocks_for(int64_t n) {
     int64_t b = (n + kBlock - 1) / kBlock;
@@ -1043,11 +1054,11 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         if (s.status == GS_BREAKDOWN) ret = IGA_ERR_BREAKDOWN;
     }
     if (rep) {
-        rep->ncomp = P->ncomp;
+        rep->ncomp = ninstances(P);
         rep->total_iters = total;
         for (int gi = 0; gi < ng; ++gi) {
             const GState& s = stv[gi];
-            const int c = P->grids[gi].comp;
+            const int c = instance_of(P, P->grids[gi]);
             if (rep->iters) rep->iters[c] = s.total_it;
             if (rep->refinements) rep->refinements[c] = s.refine;
             if (rep->relres) rep->relres[c] = s.relres;
@@ -1095,13 +1106,16 @@ iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int
     if (n == 0) return IGA_OK;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
-    HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u, 0, static_cast<int>(P->grids.size()), 1));
+    // the grids of a sample are contiguous (sample-major); sample s writes u + s n
+    const int gps = static_cast<int>(P->grids.size()) / P->nsamples;
+    for (int smp = 0; smp < P->nsamples; ++smp)
+        HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u + smp * n, smp * gps, (smp + 1) * gps, 1));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
 
 iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* patch, int64_t n, double* u) {
-    if (!P || comp < 0 || comp >= P->ncomp || (n > 0 && (!xi || !u)) || n < 0) {
+    if (!P || comp < 0 || comp >= ninstances(P) || (n > 0 && (!xi || !u)) || n < 0) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1112,7 +1126,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
     if (n == 0) return IGA_OK;
     int g0 = -1, g1 = -1;
     for (int gi = 0; gi < static_cast<int>(P->grids.size()); ++gi)
-        if (P->grids[gi].comp == comp) {
+        if (instance_of(P, P->grids[gi]) == comp) {
             if (g0 < 0) g0 = gi;
             g1 = gi + 1;
         }
@@ -1124,7 +1138,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
 }
 
 iga_status iga_sg_coeffs(iga_sg_plan P, int comp, double* out) {
-    if (!P || comp < 0 || comp >= P->ncomp || !out) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !out) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1135,13 +1149,13 @@ iga_status iga_sg_coeffs(iga_sg_plan P, int comp, double* out) {
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
-        if (g.comp == comp)
+        if (instance_of(P, g) == comp)
             HIP_OK(hipMemcpyAsync(out, K.x + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
     return IGA_OK;
 }
 
 iga_status iga_sg_loga(iga_sg_plan P, int comp, double* out) {
-    if (!P || comp < 0 || comp >= P->ncomp || !out) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !out) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1152,7 +1166,7 @@ iga_status iga_sg_loga(iga_sg_plan P, int comp, double* out) {
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
-        if (g.comp == comp)
+        if (instance_of(P, g) == comp)
             HIP_OK(hipMemcpyAsync(out, K.loga + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
     return IGA_OK;
 }
@@ -1183,7 +1197,7 @@ iga_status iga_sg_set_network(iga_sg_plan P, const int* channels, int nlayers, c
 }
 
 iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
-    if (!P || comp < 0 || comp >= P->ncomp || !out) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !out) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1194,13 +1208,13 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
-        if (g.comp == comp)
+        if (instance_of(P, g) == comp)
             HIP_OK(hipMemcpyAsync(out, K.b + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
     return IGA_OK;
 }
 
 iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
-    if (!P || comp < 0 || comp >= P->ncomp || !b) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !b) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1211,14 +1225,14 @@ iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
-        if (g.comp == comp)
+        if (instance_of(P, g) == comp)
             HIP_OK(hipMemcpyAsync(K.b + g.dof_off, b, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
     P->solved = false;
     return IGA_OK;
 }
 
 iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, double* y) {
-    if (!P || comp < 0 || comp >= P->ncomp || !x || !y || which < 0 || which > 6) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !x || !y || which < 0 || which > 6) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1228,7 +1242,7 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     }
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)
-        if (P->grids[i].comp == comp) gi = i;
+        if (instance_of(P, P->grids[i]) == comp) gi = i;
     const bool lp = which == 3 || which == 4;  // FD with FP32/BF16 factors uses their blocking
     const Grid& g = (lp ? P->grids_lp : P->grids)[gi];
     hipStream_t st = static_cast<hipStream_t>(P->stream);

@@ -272,6 +272,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     P->w = disc->w;
     P->lmin = disc->lmin;
     P->nq = nq;
+    if (disc->nsamples < 0 || disc->nsamples > 65536) {
+        set_error("nsamples must be in [0, 65536] (got %d)", disc->nsamples);
+        delete P;
+        return IGA_ERR_INVALID_ARG;
+    }
+    P->nsamples = disc->nsamples > 0 ? disc->nsamples : 1;
     P->gauss_x.resize(nq);
     P->gauss_w.resize(nq);
     gauss_rule(nq, P->gauss_x.data(), P->gauss_w.data());
@@ -518,7 +524,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                         next = next == 0 ? nbig : std::min(next, nbig);
                     }
                 }
-                if (ntask <= target || next == 0) break;
+                if (ntask * P->nsamples <= target || next == 0) break;
                 bool ok = true;
                 for (const Shape& sh : shapes)
                     if (std::max(sh.ni0, sh.ni1) == next && !fits_single(sh)) ok = false;
@@ -718,6 +724,25 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);
         }
+    // further samples: the same grids (tables, blocking and tiles shared) over
+    // their own unknowns and Gauss points, sample-major
+    {
+        const size_t ng1 = P->grids.size();
+        const int64_t nd1 = P->ndof_total, nq1 = P->nqp_total;
+        for (int smp = 1; smp < P->nsamples; ++smp)
+            for (size_t i = 0; i < ng1; ++i) {
+                Grid g = P->grids[i], gl = P->grids_lp[i];
+                g.sample = gl.sample = smp;
+                g.dof_off += smp * nd1;
+                gl.dof_off = g.dof_off;
+                g.qp_off += smp * nq1;
+                gl.qp_off = g.qp_off;
+                P->grids.push_back(g);
+                P->grids_lp.push_back(gl);
+            }
+        P->ndof_total = nd1 * P->nsamples;
+        P->nqp_total = nq1 * P->nsamples;
+    }
     if (lds_max + kSolveLdsHead > kLdsLimit) {
         set_error("a component grid needs %zu bytes of LDS (limit %d)", lds_max + kSolveLdsHead, kLdsLimit);
         delete P;
@@ -834,7 +859,7 @@ iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t
         if (ndof_host) {
             int64_t s = 0;
             for (const Grid& g : plan->grids)
-                if (g.comp == c) s += g.ndof;
+                if (g.comp == c && g.sample == 0) s += g.ndof;  // unknowns of one sample
             ndof_host[c] = s;
         }
     }

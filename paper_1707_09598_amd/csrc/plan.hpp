@@ -39,6 +39,7 @@ struct iga_sg_plan_s {
     std::vector<iga_interface> ifaces;
     // components of the combination technique
     int ncomp = 0;
+    int nsamples = 1;              // coefficient samples planned together
     std::vector<int> comp_levels;  // [ncomp][dim]
     std::vector<double> comp_coef;
     // tables and pools

@@ -1,0 +1,64 @@
+"""Several coefficient samples planned, assembled and solved in one launch
+(through the C-ABI): every instance must equal the single-sample solve of its
+sample bit for bit (each grid's arithmetic is fixed-order and independent of
+which workgroup runs it), and the combination returns one row per sample."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_1707_09598_amd as S
+    S.lib()
+    assert torch.cuda.is_available()
+    return S
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_samples_equal_single_sample_solves(S, precision):
+    import torch
+    ns, w = 3, 4
+    log(f"case batched cfg5 w={w} samples={ns} {precision}")
+    fields = W.grf_samples(ns, n=24)
+    kw = dict(precision=precision, tol=1e-11, maxit=400, max_refine=3 if precision == "fp64" else 8,
+              continue_cg=precision != "fp64")
+    xi, _ = W.eval_points(3, 1024, lattice=4, seed=3)
+    wl = W.config("cfg5", w=w, a=W._field("grid3d", data=fields[0]))
+    B = S.Plan(wl, nsamples=ns)
+    assert B.ninst == ns * B.ncomp
+    B.bind()
+    a_all = torch.as_tensor(fields, device="cuda")
+    B.assemble(a=W._field("grid3d", data=a_all))
+    rep = B.solve(**kw)
+    assert len(rep["iters"]) == ns * B.ncomp and np.all(rep["status"] == 0)
+    ub = B.combine(xi).cpu().numpy()
+    assert ub.shape == (ns, len(xi))
+    for s in range(ns):
+        P = S.Plan(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[s])))
+        P.bind()
+        P.assemble()
+        r1 = P.solve(**kw)
+        for c in range(P.ncomp):
+            assert np.array_equal(P.rhs(c).cpu().numpy(), B.rhs(s * B.ncomp + c).cpu().numpy()), (s, c)
+            assert np.array_equal(P.loga(c).cpu().numpy(), B.loga(s * B.ncomp + c).cpu().numpy()), (s, c)
+        for c in range(P.ncomp):
+            x1 = P.coeffs(c).cpu().numpy()
+            xb = B.coeffs(s * B.ncomp + c).cpu().numpy()
+            assert np.array_equal(x1, xb), (s, c)
+        assert np.array_equal(r1["iters"], rep["iters"][s * B.ncomp:(s + 1) * B.ncomp])
+        assert np.array_equal(P.combine(xi).cpu().numpy(), ub[s])
+        c = P.ncomp // 2
+        assert np.array_equal(P.eval(c, xi).cpu().numpy(), B.eval(s * B.ncomp + c, xi).cpu().numpy())
+    log(f"  {ns} samples x {B.ncomp} grids: iterations {int(rep['total_iters'])}")

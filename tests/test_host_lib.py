@@ -126,3 +126,14 @@ def test_bind_rejects_small_null_or_misaligned_workspace(S):
     assert L.iga_sg_bind(P.h, None, C.c_size_t(need), None) == 1
     assert L.iga_sg_bind(P.h, C.c_void_p(4096 + 8), C.c_size_t(need), None) == 1
     assert "aligned" in L.iga_sg_last_error().decode()
+
+
+def test_batched_plan_scales_tasks_and_workspace(S):
+    one = S.Plan(W.config("cfg5", w=5))
+    many = S.Plan(W.config("cfg5", w=5), nsamples=4)
+    assert many.ncomp == one.ncomp and many.ninst == 4 * one.ncomp
+    s1, s4 = one.stats(), many.stats()
+    assert s4["op_tasks"] == 4 * s1["op_tasks"] and s4["fd_tasks_fp64"] == 4 * s1["fd_tasks_fp64"]
+    assert many.workspace_bytes() > 3 * one.workspace_bytes()
+    with pytest.raises(S.IgaError):
+        S.Plan(W.config("cfg5", w=5), nsamples=-1)
