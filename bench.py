@@ -82,6 +82,8 @@ def parse():
                     help="skip the learned-preconditioner comparison on the random-field cube")
     ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
+    ap.add_argument("--batch-samples", type=int, default=64,
+                    help="coefficient samples of the random-field cube solved in one launch (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -98,12 +100,14 @@ def algorithmic_bytes(P, rep, precision):
     step adds one FP64 operator application and one FD application.
     """
     wl = P.wl
-    ncompG = 6 if any(pt.get("weights") is not None for pt in wl["patches"]) else 3
+    rational = any(pt.get("weights") is not None for pt in wl["patches"])
+    ncompG = {(2, False): 3, (2, True): 6, (3, False): 6, (3, True): 10}[(int(wl["dim"]), rational)]
     p = int(wl["p"])
     bop_in = {"fp64": 8, "fp32": 4, "bf16fd": 4}[precision]
     bu = {"fp64": 8, "fp32": 4, "bf16fd": 2}[precision]
     total = 0.0
-    for c, lv in enumerate(P.levels):
+    for c in range(P.ninst):  # instances: component c % ncomp of sample c // ncomp
+        lv = P.levels[c % P.ncomp]
         nb = [2 ** int(l) + p for l in lv]  # C^{p-1}: 2^l + p basis functions
         ni = [n - 2 for n in nb]
         nqp = np.prod([2 ** int(l) * (p + 1) for l in lv])
@@ -246,6 +250,54 @@ def run_learned(S, W, torch, args, O):
     return out
 
 
+def run_batched(S, W, torch, args, O):
+    """The random-field cube at full size (w=7, a = exp(GRF) on a 64^3 grid)
+    with batch_samples coefficient samples in one plan and one persistent
+    launch: assembly + solve timed by HIP events, FP64 (B) and mixed (C)."""
+    ns = args.batch_samples
+    fields = W.grf_samples(ns, n=64)
+    wl = W.config("cfg5", a=W._field("grid3d", data=fields[0]))
+    P = S.Plan(wl, nsamples=ns)
+    P.bind(device="cuda:0")
+    a_all = W._field("grid3d", data=torch.as_tensor(fields, device="cuda:0"))
+    ndof = int(P.ndof.sum()) * ns
+    out = {"workload": f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), f = 1, "
+                       f"p=3 C^2, w=7, {ns} samples x 85 grids in one launch, {ndof} unknowns, tol 1e-10",
+           "samples": ns, "unknowns": ndof}
+    ref = None
+    for key, kw in (("B_fp64", dict(precision="fp64", max_refine=3)),
+                    ("C_mixed", dict(precision="fp32", max_refine=12, continue_cg=True))):
+        kw = dict(kw, tol=1e-10, tol_inner=args.tol_inner, maxit=600)
+        P.assemble(a=a_all)
+        rep = P.solve(check=False, **kw)
+        ms = []
+        for _ in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(P.stream)
+            P.assemble(a=a_all)
+            ev[1].record(P.stream)
+            P.solve_async(**kw)
+            ev[2].record(P.stream)
+            torch.cuda.synchronize()
+            ms.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+        t_asm, t_sol = float(np.median([m[0] for m in ms])), float(np.median([m[1] for m in ms]))
+        algo = algorithmic_bytes(P, rep, kw["precision"])
+        if ref is None:
+            Po = O.Problem(W.config("cfg5", a=W._field("grid3d", data=fields[0])))
+            xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
+            ref = (xi3, Po.sg_eval(Po.solve_all(), xi3))
+        u = P.combine(ref[0])[0].cpu().numpy()
+        out[key] = {"dof_per_s": ndof / ((t_asm + t_sol) / 1e3), "ms_assemble": t_asm, "ms_solve": t_sol,
+                    "codes": int(rep["code"]), "cg_iterations": int(rep["total_iters"]),
+                    "rel_l2_vs_oracle_sample0": float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1])),
+                    "solve_roofline": {"bound": "hbm", "achieved": algo / (t_sol / 1e3) / 1e9,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": algo / (t_sol / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                       "algorithmic_bytes_per_launch": algo}}
+    out["speedup_C_vs_B"] = out["C_mixed"]["dof_per_s"] / out["B_fp64"]["dof_per_s"]
+    return out
+
+
 def cpu_baseline(O, W, xi, seconds):
     """The oracle (serial C, FP64) on the same workload: assembly + direct
     solves of all 21 components + combination at the first 2^16 points of E
@@ -376,6 +428,8 @@ def main():
         cpu.pop("assemble_solve_ms", None)
         cpu.pop("combine_ms_scaled", None)
         line["cpu_baseline"] = cpu
+    if args.batch_samples > 0:
+        line["batched_cfg5"] = run_batched(S, W, torch, args, O)
     if not args.no_learned:
         line["learned_cfg5"] = run_learned(S, W, torch, args, O)
     print(json.dumps(line), flush=True)
