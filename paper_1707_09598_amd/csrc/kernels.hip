@@ -64,7 +64,7 @@ __device__ __forceinline__ void sincos_coef(const double* prm, const double* x, 
     da[1] = -tp * prm[0] * sx * sy;
 }
 
-__device__ double field_eval(const FieldDev& F, int dim, const double* x) {
+__device__ __forceinline__ double field_eval(const FieldDev& F, int dim, const double* x) {
     const double pi = 3.141592653589793238463;
     switch (F.kind) {
         case IGA_FIELD_CONST:
@@ -146,6 +146,20 @@ __device__ double field_eval(const FieldDev& F, int dim, const double* x) {
     }
 }
 
+// Field of a kind fixed at compile time (the switch of field_eval folds to
+// one branch, which keeps the register use of the assembly kernels low);
+// K < 0: the kind is read at run time.
+template <int K>
+__device__ __forceinline__ double field_eval_k(const FieldDev& F, int dim, const double* x) {
+    if constexpr (K < 0) {
+        return field_eval(F, dim, x);
+    } else {
+        FieldDev G = F;
+        G.kind = K;
+        return field_eval(G, dim, x);
+    }
+}
+
 // ===========================================================================
 // K1: basis tables at the Gauss points of every (patch, direction, level)
 // ===========================================================================
@@ -195,9 +209,11 @@ __device__ __forceinline__ int grid_of_qp(const Params& P, int g0, int g1, int64
 
 // Geometry at a tensor Gauss point from the per-direction geometry tables:
 // homogeneous sums X_c = sum w P_c B, W = sum w B and their derivatives.
+template <int DIM>
 __device__ __forceinline__ void geom_at(const Params& P, const Grid& g, const int* qk, double* x,
                                         double DF[3][3], double* W, double* dW) {
-    const int d = P.dim, pt = g.patch;
+    constexpr int d = DIM;
+    const int pt = g.patch;
     const double* Bg[3];
     const double* Dg[3];
     int f[3] = {0, 0, 0}, pg[3] = {0, 0, 0};
@@ -234,11 +250,12 @@ __device__ __forceinline__ void geom_at(const Params& P, const Grid& g, const in
     for (int k = 0; k < d; ++k) dW[k] = dXh[k][3];
 }
 
+template <int KA, int KF, int DIM>
 __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, FieldDev ff, int g0, int g1,
                                                     int* err) {
     const int64_t q0 = P.grids[g0].qp_off;
     const int64_t q1 = P.grids[g1 - 1].qp_off + P.grids[g1 - 1].nqp;
-    const int d = P.dim;
+    constexpr int d = DIM;
     for (int64_t gq = q0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gq < q1;
          gq += static_cast<int64_t>(gridDim.x) * kBlock) {
         const int gi = grid_of_qp(P, g0, g1, gq);
@@ -249,7 +266,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
         qk[1] = static_cast<int>((l / g.Q[0]) % g.Q[1]);
         qk[2] = static_cast<int>(l / (static_cast<int64_t>(g.Q[0]) * g.Q[1]));
         double x[3] = {0, 0, 0}, DF[3][3], W, dW[3] = {0, 0, 0};
-        geom_at(P, g, qk, x, DF, &W, dW);
+        geom_at<DIM>(P, g, qk, x, DF, &W, dW);
         double wq = 1.0;
         for (int k = 0; k < d; ++k) wq *= P.dpool[P.tabs[g.tab[k]].oWq + qk[k]];
         double det, inv[3][3];
@@ -274,8 +291,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
             inv[2][2] = (DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]) / det;
         }
         if (!(det > 0.0)) atomicOr(err, 1);
-        const double av = field_eval(field_of_sample(fa, g.sample), d, x);
-        const double fv = field_eval(field_of_sample(ff, g.sample), d, x);
+        const double av = field_eval_k<KA>(field_of_sample(fa, g.sample), d, x);
+        const double fv = field_eval_k<KF>(field_of_sample(ff, g.sample), d, x);
         const double s = av * wq * fabs(det);
         // parametric coefficients Gp = a w |det| DF^-1 DF^-T (symmetric)
         double Gp[3][3];
@@ -467,6 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
 // log a at the Greville point of every interior unknown (feature of the
 // learned preconditioner): xi*_k = (t_{j+1} + ... + t_{j+p}) / p for basis
 // j = i_k + 1 of direction k, mapped through F.
+template <int KA>
 __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, int g1) {
     const int64_t i0 = P.grids[g0].dof_off;
     const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
@@ -530,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
         }
         double x[3] = {0, 0, 0};
         for (int k = 0; k < d; ++k) x[k] = Xh[k] / Xh[3];
-        P.loga[gi] = log(field_eval(field_of_sample(fa, g.sample), d, x));
+        P.loga[gi] = log(field_eval_k<KA>(field_of_sample(fa, g.sample), d, x));
     }
 }
 
@@ -710,6 +728,45 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
         }
         u[i] = acc;
     }
+}
+
+// Assembly kernels specialised for the field kinds of the workloads
+// (coefficient: constant, sin-cos, 3D grid; load: constant, sine product,
+// annulus right-hand side), the run-time switch for any other combination.
+template <int KA, int DIM>
+hipError_t launch_assemble_f(int kf, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa,
+                             const FieldDev& ff, int ng, int* err) {
+    switch (kf) {
+        case IGA_FIELD_CONST: hipLaunchKernelGGL((k_assemble<KA, IGA_FIELD_CONST, DIM>), grid, dim3(kBlock), 0, st, K, fa, ff, 0, ng, err); break;
+        case IGA_FIELD_SINPROD: hipLaunchKernelGGL((k_assemble<KA, IGA_FIELD_SINPROD, DIM>), grid, dim3(kBlock), 0, st, K, fa, ff, 0, ng, err); break;
+        case IGA_FIELD_ANNULUS_RHS: hipLaunchKernelGGL((k_assemble<KA, IGA_FIELD_ANNULUS_RHS, DIM>), grid, dim3(kBlock), 0, st, K, fa, ff, 0, ng, err); break;
+        default: hipLaunchKernelGGL((k_assemble<KA, -1, DIM>), grid, dim3(kBlock), 0, st, K, fa, ff, 0, ng, err); break;
+    }
+    return hipGetLastError();
+}
+template <int DIM>
+hipError_t launch_assemble_d(int ka, int kf, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa,
+                             const FieldDev& ff, int ng, int* err) {
+    switch (ka) {
+        case IGA_FIELD_CONST: return launch_assemble_f<IGA_FIELD_CONST, DIM>(kf, grid, st, K, fa, ff, ng, err);
+        case IGA_FIELD_SINCOS: return launch_assemble_f<IGA_FIELD_SINCOS, DIM>(kf, grid, st, K, fa, ff, ng, err);
+        case IGA_FIELD_GRID3D: return launch_assemble_f<IGA_FIELD_GRID3D, DIM>(kf, grid, st, K, fa, ff, ng, err);
+        default: return launch_assemble_f<-1, DIM>(kf, grid, st, K, fa, ff, ng, err);
+    }
+}
+hipError_t launch_assemble(int dim, int ka, int kf, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa,
+                           const FieldDev& ff, int ng, int* err) {
+    return dim == 2 ? launch_assemble_d<2>(ka, kf, grid, st, K, fa, ff, ng, err)
+                    : launch_assemble_d<3>(ka, kf, grid, st, K, fa, ff, ng, err);
+}
+hipError_t launch_loga(int ka, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa, int ng) {
+    switch (ka) {
+        case IGA_FIELD_CONST: hipLaunchKernelGGL((k_loga<IGA_FIELD_CONST>), grid, dim3(kBlock), 0, st, K, fa, 0, ng); break;
+        case IGA_FIELD_SINCOS: hipLaunchKernelGGL((k_loga<IGA_FIELD_SINCOS>), grid, dim3(kBlock), 0, st, K, fa, 0, ng); break;
+        case IGA_FIELD_GRID3D: hipLaunchKernelGGL((k_loga<IGA_FIELD_GRID3D>), grid, dim3(kBlock), 0, st, K, fa, 0, ng); break;
+        default: hipLaunchKernelGGL((k_loga<-1>), grid, dim3(kBlock), 0, st, K, fa, 0, ng); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_combine(int p, int blocks, hipStream_t st, const Params& K, const double* xi, const int* patch,
@@ -938,13 +995,11 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     int* err = reinterpret_cast<int*>(reinterpret_cast<char*>(P->ws) + P->lay.bar + 64);
     HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
     const int ng = static_cast<int>(P->grids.size());
-    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(P->nqp_total)), dim3(kBlock), 0, st, K, to_dev(a), to_dev(f), 0,
-                       ng, err);
-    HIP_OK(hipGetLastError());
+    HIP_OK(launch_assemble(P->dim, a ? a->kind : IGA_FIELD_NONE, f ? f->kind : IGA_FIELD_NONE,
+                           dim3(blocks_for(P->nqp_total)), st, K, to_dev(a), to_dev(f), ng, err));
     hipLaunchKernelGGL(k_rhs, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
-    hipLaunchKernelGGL(k_loga, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, to_dev(a), 0, ng);
-    HIP_OK(hipGetLastError());
+    HIP_OK(launch_loga(a ? a->kind : IGA_FIELD_NONE, dim3(blocks_for(P->ndof_total)), st, K, to_dev(a), ng));
     hipLaunchKernelGGL(k_fdscale, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
     P->assembled = true;
