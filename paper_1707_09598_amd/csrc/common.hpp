@@ -248,6 +248,8 @@ struct Params {
     int rational[kMaxPatch];
     int dim, p, nq, ncompG;  // ncompG: operator coefficients per Gauss point
     int ngrid, nop, nfd;
+    int ngrid1;                // grids of one sample (grids are sample-major)
+    int64_t nqp1, ndof1;       // Gauss points and unknowns of one sample
     int64_t nqp_total, ndof_total;
     double* G64;
     float* G32;

@@ -197,11 +197,35 @@ __global__ void __launch_bounds__(kBlock) k_tables(Params P) {
 // ===========================================================================
 // K2: assembly at the Gauss points
 // ===========================================================================
+// Grid of a Gauss point / of an unknown in [g0, g1): binary search over the
+// grid offsets; over all grids of several samples, over the grids of one
+// sample after the sample is found from the per-sample totals.
 __device__ __forceinline__ int grid_of_qp(const Params& P, int g0, int g1, int64_t gq) {
+    int base = 0;
+    if (g0 == 0 && g1 == P.ngrid && P.ngrid1 < P.ngrid) {
+        const int smp = static_cast<int>(gq / P.nqp1);
+        base = smp * P.ngrid1;
+        g0 = base;
+        g1 = base + P.ngrid1;
+    }
     int lo = g0, hi = g1 - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (P.grids[mid].qp_off <= gq) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+__device__ __forceinline__ int grid_of_dof(const Params& P, int g0, int g1, int64_t gi) {
+    if (g0 == 0 && g1 == P.ngrid && P.ngrid1 < P.ngrid) {
+        const int smp = static_cast<int>(gi / P.ndof1);
+        g0 = smp * P.ngrid1;
+        g1 = g0 + P.ngrid1;
+    }
+    int lo = g0, hi = g1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.grids[mid].dof_off <= gi) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -348,12 +372,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     const int p = P.p, nq = P.nq, d = P.dim;
     for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
          gi += static_cast<int64_t>(gridDim.x) * kBlock) {
-        int lo = g0, hi = g1 - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (P.grids[mid].dof_off <= gi) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = grid_of_dof(P, g0, g1, gi);
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
         int I[3];
@@ -412,12 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
     for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock / 64) + (threadIdx.x >> 6); gi < i1;
          gi += nw) {
-        int lo = g0, hi = g1 - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (P.grids[mid].dof_off <= gi) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = grid_of_dof(P, g0, g1, gi);
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
         int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, nt[3] = {1, 1, 1}, mk[3] = {1, 1, 1};
@@ -491,12 +505,7 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
     const int p = P.p, d = P.dim;
     for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
          gi += static_cast<int64_t>(gridDim.x) * kBlock) {
-        int lo = g0, hi = g1 - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (P.grids[mid].dof_off <= gi) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = grid_of_dof(P, g0, g1, gi);
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
         double xi[3] = {0, 0, 0};
@@ -809,6 +818,9 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     K.nq = P->nq;
     K.ncompG = P->ncompG;
     K.ngrid = static_cast<int>(P->grids.size());
+    K.ngrid1 = K.ngrid / P->nsamples;
+    K.nqp1 = P->nqp_total / P->nsamples;
+    K.ndof1 = P->ndof_total / P->nsamples;
     K.nop = static_cast<int>(P->optask.size());
     K.nfd = static_cast<int>((lowp_fd ? P->fdtask_lp : P->fdtask).size());
     K.nqp_total = P->nqp_total;
