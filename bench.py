@@ -82,6 +82,8 @@ def parse():
                     help="skip the learned-preconditioner comparison on the random-field cube")
     ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner (library default shape)")
     ap.add_argument("--batch-samples", type=int, default=64,
                     help="coefficient samples of the random-field cube solved in one launch (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -122,15 +124,21 @@ def algorithmic_bytes(P, rep, precision):
 
 def run_mode(S, W, torch, precision, args, xi):
     wl = W.config("cfg2")
+    kw = dict(precision=precision, tol=args.tol, tol_inner=args.tol_inner, maxit=400,
+              max_refine=12 if precision != "fp64" else 3, batched=True,
+              continue_cg=not args.restart)
+    shape, tuned = {}, None
+    if not args.no_tune:
+        # launch shape picked by timing the candidates on this workload and mode
+        from paper_1707_09598_amd import tune
+        tuned = tune.autotune(wl, kw, repeats=3)
+        shape = tuned["shape"]
     t0 = time.perf_counter()
-    P = S.Plan(wl)
+    P = S.Plan(wl, shape=shape)
     t_plan = time.perf_counter() - t0
     P.bind(device="cuda:0")
     stream = P.stream
     xi_t = torch.as_tensor(xi, device="cuda:0").contiguous()
-    kw = dict(precision=precision, tol=args.tol, tol_inner=args.tol_inner, maxit=400,
-              max_refine=12 if precision != "fp64" else 3, batched=True,
-              continue_cg=not args.restart)
 
     def step():
         P.assemble()
@@ -171,6 +179,7 @@ def run_mode(S, W, torch, precision, args, xi):
     return {
         "plan": P, "u": u, "rep": rep, "wall_ms": 1e3 * wall / K, "t_asm": t_asm, "t_sol": t_sol,
         "t_cmb": t_cmb, "t_plan_s": t_plan, "ndof": int(P.ndof.sum()), "trace": trace,
+        "shape": shape, "tuned": tuned,
     }
 
 
@@ -396,6 +405,7 @@ def main():
                         f"|E| = {len(xi)} evaluation points",
             "mode": f"batched persistent solve, {args.precision} inner PCG, FP64 refinement",
             "tol": args.tol, "tol_inner": args.tol_inner,
+            "launch_shape": main_run["shape"] or "library default",
         },
         "rel_l2_vs_oracle": err,
         "breakdown_ms": {"assemble": main_run["t_asm"], "solve": main_run["t_sol"],
@@ -405,6 +415,8 @@ def main():
         "cg_iterations": int(main_run["rep"]["total_iters"]),
         "refinements_max": int(main_run["rep"]["refinements"].max()),
         "solve_trace": main_run["trace"],
+        "autotune_ms": ({"{}".format(t["shape"]): round(t["ms"], 3) for t in main_run["tuned"]["tried"]}
+                        if main_run["tuned"] else None),
         "roofline": {
             "bound": "hbm", "kernel": "k_solve (persistent refinement + FD-PCG)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -421,6 +433,7 @@ def main():
                              "combine": fp64_run["t_cmb"]},
             "cg_iterations": int(fp64_run["rep"]["total_iters"]),
             "solve_trace": fp64_run["trace"],
+            "launch_shape": fp64_run["shape"] or "library default",
         }
         line["speedup_vs_fp64"] = line["value"] / line["fp64_comparator"]["value"]
     if cpu is not None:

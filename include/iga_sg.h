@@ -96,6 +96,12 @@ typedef struct {
 typedef struct {
     int p, r, w, lmin, nq;
     int nsamples;
+    /* launch shape (0 => library default): unknowns per operator tile in 2D
+     * (default 128) and in 3D (default 256), and the number of
+     * fast-diagonalisation tasks of a solve below which 2D long directions
+     * are kept in one block when LDS allows (default 256, the MI355X CU
+     * count); the autotuner (tune.py) searches these */
+    int op_tile, op_tile3, fd_tasks;
 } iga_sg_disc;
 
 /* Fields (right-hand side f, coefficient a, Dirichlet data g). */

@@ -58,7 +58,7 @@ class _Geometry(C.Structure):
 
 class _Disc(C.Structure):
     _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int),
-                ("nsamples", C.c_int)]
+                ("nsamples", C.c_int), ("op_tile", C.c_int), ("op_tile3", C.c_int), ("fd_tasks", C.c_int)]
 
 
 class _Field(C.Structure):
@@ -159,9 +159,11 @@ class Plan:
     ``nsamples`` > 1 plans that many problems differing in their field data
     (a grid3d coefficient given as [nsamples, n3, n2, n1]); component c of
     sample s is instance s * ncomp + c, combine returns [nsamples, n].
+    ``shape`` sets the launch shape: {"op_tile", "op_tile3", "fd_tasks"}
+    (missing or 0: library default; see ``tune.autotune``).
     """
 
-    def __init__(self, wl: Dict[str, Any], nsamples: int = 1):
+    def __init__(self, wl: Dict[str, Any], nsamples: int = 1, shape: Optional[Dict[str, int]] = None):
         self.wl = wl
         self.dim = d = int(wl["dim"])
         self._keep = []
@@ -196,7 +198,10 @@ class Plan:
         G = _Geometry(d, len(pats), C.cast(parr, C.POINTER(_Patch)), len(ifs),
                       C.cast(iarr, C.POINTER(_Iface)))
         self.nsamples = int(nsamples)
-        D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0, self.nsamples)
+        self.shape = dict(shape or {})
+        D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0, self.nsamples,
+                  int(self.shape.get("op_tile", 0)), int(self.shape.get("op_tile3", 0)),
+                  int(self.shape.get("fd_tasks", 0)))
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h

@@ -481,7 +481,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     // grids it makes single-block fit in LDS with both factors staged.
     int wide_min_cls[2] = {env_int("IGA_FD_WIDE", 100), env_int("IGA_FD_WIDE", 100)};
     if (d == 2 && !std::getenv("IGA_FD_WIDE")) {
-        const int target = env_int("IGA_FD_TASKS", 256);
+        const int target = disc->fd_tasks > 0 ? disc->fd_tasks : env_int("IGA_FD_TASKS", 256);
         struct Shape { int ni0, ni1, ld0, ld1; };
         std::vector<Shape> shapes;
         for (int c = 0; c < P->ncomp; ++c)
@@ -588,7 +588,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             // operator tiles: minimise the elements processed (halo recompute)
             const int m = p - r;
             if (d == 2) {
-                const int TT = env_int("IGA_OP_TILE", 128);
+                const int TT = disc->op_tile > 0 ? disc->op_tile : env_int("IGA_OP_TILE", 128);
                 long best = -1;
                 for (int t2 = 1; t2 <= std::min(g.ni[1], TT); ++t2) {
                     int t1 = std::min(g.ni[0], std::max(1, TT / t2));
@@ -608,7 +608,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.tile[2] = 1;
             } else {
                 // 3D: tiles of about TT unknowns whose halo and element outputs fit in LDS
-                const int TT = env_int("IGA_OP_TILE3", 256);
+                const int TT = disc->op_tile3 > 0 ? disc->op_tile3 : env_int("IGA_OP_TILE3", 256);
                 const size_t pl = static_cast<size_t>(p + 1) * (p + 1) * (p + 1);
                 double best = -1.0;
                 g.tile[0] = g.ni[0];

@@ -95,3 +95,25 @@ def test_fp64_solve_bitwise_reproducible(S):
     for a, b in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, b)
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_autotuned_shape_solves_the_same_problem(S):
+    """The tuner returns the fastest candidate it timed; a solve with that
+    launch shape agrees with the default one to rounding (the operator tiles
+    change the order of the p.q partial sums)."""
+    from paper_1707_09598_amd import tune
+    log("case autotune cfg2 w=7")
+    wl = W.config("cfg2", w=7)
+    kw = dict(precision="fp64", tol=1e-12, maxit=400, max_refine=3)
+    res = tune.autotune(wl, kw, shapes=[{"op_tile": 64}, {"op_tile": 256, "fd_tasks": 1 << 20}], repeats=2)
+    assert res["shape"] in [t["shape"] for t in res["tried"]]
+    assert res["ms"] == min(t["ms"] for t in res["tried"])
+    A = _bound(S, wl)
+    A.solve(**kw)
+    B = S.Plan(wl, shape=res["shape"])
+    B.bind()
+    B.assemble()
+    B.solve(**kw)
+    for c in range(A.ncomp):
+        a, b = A.coeffs(c).cpu().numpy(), B.coeffs(c).cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a), c

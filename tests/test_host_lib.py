@@ -137,3 +137,13 @@ def test_batched_plan_scales_tasks_and_workspace(S):
     assert many.workspace_bytes() > 3 * one.workspace_bytes()
     with pytest.raises(S.IgaError):
         S.Plan(W.config("cfg5", w=5), nsamples=-1)
+
+
+def test_launch_shape_options(S):
+    base = S.Plan(W.config("cfg2")).stats()
+    small = S.Plan(W.config("cfg2"), shape={"op_tile": 64}).stats()
+    nofit = S.Plan(W.config("cfg2"), shape={"fd_tasks": 1 << 20}).stats()
+    assert small["op_tasks"] > base["op_tasks"]
+    assert nofit["fd_tasks_lowp"] > base["fd_tasks_lowp"]  # long directions kept in blocks
+    t3 = S.Plan(W.config("cfg5", w=5), shape={"op_tile3": 64}).stats()
+    assert t3["op_tasks"] > S.Plan(W.config("cfg5", w=5)).stats()["op_tasks"]
