@@ -82,8 +82,9 @@ def parse():
                     help="skip the learned-preconditioner comparison on the random-field cube")
     ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="skip the launch-shape autotuner (library default shape)")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the launch shape of each mode with the autotuner first (its timing runs "
+                         "add solve dispatches of other shapes to a profile of the run)")
     ap.add_argument("--batch-samples", type=int, default=64,
                     help="coefficient samples of the random-field cube solved in one launch (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -128,7 +129,7 @@ def run_mode(S, W, torch, precision, args, xi):
               max_refine=12 if precision != "fp64" else 3, batched=True,
               continue_cg=not args.restart)
     shape, tuned = {}, None
-    if not args.no_tune:
+    if args.tune:
         # launch shape picked by timing the candidates on this workload and mode
         from paper_1707_09598_amd import tune
         tuned = tune.autotune(wl, kw, repeats=3)
