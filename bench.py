@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "913a7d062e6f137e9955243bb593acf3ea6da09b3b906dff1a8aa4277ddf0861",
-    "fetch_kib": 1223822.5, "write_kib": 207003.5,
-    "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
+    "sha256": "4848ca02537b6e3c3c768c4ccbb986b61963dc6dda980e118df4c34c7761afdf",
+    "fetch_kib": 1224179.8, "write_kib": 207001.8,
+    "fetch_factor": 262144.0 / 131088.4, "write_factor": 262144.0 / 262144.0,
 }
 
 
