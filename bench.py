@@ -41,7 +41,7 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "4848ca02537b6e3c3c768c4ccbb986b61963dc6dda980e118df4c34c7761afdf",
+    "sha256": "32b6665208d0ef37214b12b1f139986777f3200cff2cbb115362a4c92625506c",
     "fetch_kib": 1224179.8, "write_kib": 207001.8,
     "fetch_factor": 262144.0 / 131088.4, "write_factor": 262144.0 / 262144.0,
 }

@@ -627,10 +627,6 @@ template <> struct VecU<uint16_t> {
     static constexpr int CPL = 8;
     using Raw = uint4;
 };
-template <typename TU>
-__device__ __forceinline__ typename VecU<TU>::Raw load_raw(const TU* p) {
-    return *reinterpret_cast<const typename VecU<TU>::Raw*>(p);
-}
 
 // Direct global -> LDS copies (gfx950 global_load_lds): each active lane of
 // a wavefront moves SIZE bytes from its own global address to
