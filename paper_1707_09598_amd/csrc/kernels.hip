@@ -364,55 +364,86 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
 }
 
 
-// Load vector: b_i = sum over Gauss points of the supporting elements of
-// B_i(q) Fq(q) (Fq = f w |det DF| / W), one thread per unknown.
+// Gauss points of the support of one basis function, split over the lanes of
+// a wavefront: lane = a + W0 * row with W0 the power of two >= the points of
+// direction 0 in the support (at most (p + 1) (p + 1) <= 25); a lane takes
+// the direction-0 points a, a + W0, ... of rows row, row + 64 / W0, ... of
+// the direction-1 points, for every direction-2 point.  Shifts and masks
+// only, so no integer division per point.
+struct SupportLanes {
+    int a, row, w0, rstep;
+    __device__ explicit SupportLanes(int nt0) {
+        int lw = 0;
+        while ((1 << lw) < nt0 && lw < 6) ++lw;
+        const int lane = threadIdx.x & 63;
+        w0 = 1 << lw;
+        a = lane & (w0 - 1);
+        row = lane >> lw;
+        rstep = 64 >> lw;
+    }
+};
+
+// Unknown handled by the wavefront, uniform over it (so grid and table
+// descriptors come through scalar loads).
+__device__ __forceinline__ int64_t wave_unknown(int64_t first) {
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    return first + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + w;
+}
+
+// Load vector: b_i = sum over the Gauss points of the elements in the support
+// of B_i of B_i(q) Fq(q) (Fq = f w |det DF| / W, stored by k_assemble), one
+// wavefront per unknown, the points split over the lanes and summed by a
+// fixed lane butterfly.
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
     const int64_t i0 = P.grids[g0].dof_off;
     const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
-    const int p = P.p, nq = P.nq, d = P.dim;
-    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < i1;
-         gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int p = P.p, nq = P.nq, nqm = (65536 + nq - 1) / nq;
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
+    for (int64_t gi = wave_unknown(i0); gi < i1; gi += nw) {
         const int lo = grid_of_dof(P, g0, g1, gi);
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
-        int I[3];
-        I[0] = static_cast<int>(l % g.ni[0]) + 1;
-        I[1] = static_cast<int>((l / g.ni[0]) % g.ni[1]) + 1;
-        I[2] = static_cast<int>(l / (static_cast<int64_t>(g.ni[0]) * g.ni[1])) + 1;
-        int elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
-        const double* B[3] = {nullptr, nullptr, nullptr};
-        int m[3] = {1, 1, 1};
-        for (int k = 0; k < d; ++k) {
+        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, nt[3] = {1, 1, 1}, mk[3] = {1, 1, 1};
+        const double* Bt[3] = {nullptr, nullptr, nullptr};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            ik[k] = static_cast<int>(l % g.ni[k]);
+            l /= g.ni[k];
             const Tab1D& T = P.tabs[g.tab[k]];
-            d_elem_range(I[k] - 1, I[k], p, T.m, T.E, &elo[k], &ehi[k]);
-            B[k] = P.dpool + T.oB;
-            m[k] = T.m;
+            int ehi;
+            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi);
+            nt[k] = (ehi - elo[k] + 1) * nq;
+            mk[k] = T.m;
+            Bt[k] = P.dpool + T.oB;
         }
+        // basis value of B_i at support point t of direction k (t / nq by a
+        // multiply-shift, exact for t < 64 and nq <= 8)
+        auto bval = [&](int k, int t) {
+            const int e = elo[k] + ((t * nqm) >> 16);
+            return Bt[k][static_cast<int64_t>(elo[k] * nq + t) * (p + 1) + (ik[k] + 1 - e * mk[k])];
+        };
+        const SupportLanes S(nt[0]);
         const double* F = P.Fq + g.qp_off;
-        double s3 = 0.0;
-        const int e3lo = d > 2 ? elo[2] : 0, e3hi = d > 2 ? ehi[2] : 0, nq3 = d > 2 ? nq : 1;
-        for (int e3 = e3lo; e3 <= e3hi; ++e3)
-            for (int j3 = 0; j3 < nq3; ++j3) {
-                int q3 = e3 * nq + j3;
-                double w3 = d > 2 ? B[2][static_cast<int64_t>(q3) * (p + 1) + (I[2] - e3 * m[2])] : 1.0;
-                if (d <= 2) q3 = 0;
-                double s2 = 0.0;
-                for (int e2 = elo[1]; e2 <= ehi[1]; ++e2)
-                    for (int j2 = 0; j2 < nq; ++j2) {
-                        int q2 = e2 * nq + j2;
-                        double w2 = B[1][static_cast<int64_t>(q2) * (p + 1) + (I[1] - e2 * m[1])];
-                        double s1 = 0.0;
-                        const double* Fr = F + (static_cast<int64_t>(q3) * g.Q[1] + q2) * g.Q[0];
-                        for (int e1 = elo[0]; e1 <= ehi[0]; ++e1)
-                            for (int j1 = 0; j1 < nq; ++j1) {
-                                int q1 = e1 * nq + j1;
-                                s1 += B[0][static_cast<int64_t>(q1) * (p + 1) + (I[0] - e1 * m[0])] * Fr[q1];
-                            }
-                        s2 += w2 * s1;
-                    }
-                s3 += w3 * s2;
+        double acc = 0.0;
+        for (int t0 = S.a; t0 < nt[0]; t0 += S.w0) {
+            const int64_t q0 = elo[0] * nq + t0;
+            double s0 = 0.0;
+            for (int t2 = 0; t2 < (DIM > 2 ? nt[2] : 1); ++t2) {
+                const double b2 = DIM > 2 ? bval(2, t2) : 1.0;
+                const int64_t q2 = DIM > 2 ? elo[2] * nq + t2 : 0;
+                double s1 = 0.0;
+                for (int t1 = S.row; t1 < nt[1]; t1 += S.rstep) {
+                    const int64_t q1 = elo[1] * nq + t1;
+                    s1 += bval(1, t1) * F[q0 + g.Q[0] * (q1 + static_cast<int64_t>(g.Q[1]) * q2)];
+                }
+                s0 += b2 * s1;
             }
-        P.b[gi] = s3;
+            acc += bval(0, t0) * s0;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if ((threadIdx.x & 63) == 0) P.b[gi] = acc;
     }
 }
 
@@ -423,14 +454,13 @@ __global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
 // the support of basis function i (split over the lanes, then a fixed lane
 // butterfly), the stored coefficients G_uv times the products of its value /
 // first derivatives (u, v), both orders for u != v.
+template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
     const int64_t i0 = P.grids[g0].dof_off;
     const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
-    const int p = P.p, nq = P.nq, d = P.dim;
-    const int lane = threadIdx.x & 63;
+    const int p = P.p, nq = P.nq, nqm = (65536 + nq - 1) / nq;
     const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
-    for (int64_t gi = i0 + blockIdx.x * static_cast<int64_t>(kBlock / 64) + (threadIdx.x >> 6); gi < i1;
-         gi += nw) {
+    for (int64_t gi = wave_unknown(i0); gi < i1; gi += nw) {
         const int lo = grid_of_dof(P, g0, g1, gi);
         const Grid& g = P.grids[lo];
         int64_t l = gi - g.dof_off;
@@ -438,7 +468,8 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
         const double* Bt[3] = {nullptr, nullptr, nullptr};
         const double* Dt[3] = {nullptr, nullptr, nullptr};
         double pd = 0.0, md[3] = {1.0, 1.0, 1.0}, kd[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < d; ++k) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
             ik[k] = static_cast<int>(l % g.ni[k]);
             l /= g.ni[k];
             const Tab1D& T = P.tabs[g.tab[k]];
@@ -451,47 +482,60 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
             kd[k] = P.dpool[T.oKd + ik[k]];
             md[k] = P.dpool[T.oMd + ik[k]];
         }
-        for (int k = 0; k < d; ++k) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
             double t = g.fdc[k] * kd[k];
-            for (int j = 0; j < d; ++j)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j)
                 if (j != k) t *= md[j];
             pd += t;
         }
+        // value and derivative of B_i at support point t of direction k, and
+        // the point's index in the grid's Gauss points of that direction
+        // (t / nq by a multiply-shift, exact for t < 64 and nq <= 8)
+        auto bd = [&](int k, int t, double* bv, double* dv) {
+            const int e = elo[k] + ((t * nqm) >> 16);
+            const int64_t i = static_cast<int64_t>(elo[k] * nq + t) * (p + 1) + (ik[k] + 1 - e * mk[k]);
+            *bv = Bt[k][i];
+            *dv = Dt[k][i];
+            return elo[k] * nq + t;
+        };
         const bool rat = P.rational[g.patch] != 0;
-        const int ne = rat ? d + 1 : d;  // entries of (v, grad v) or of grad v
         const int64_t nqp = g.nqp;
         const double* G = P.G64 + g.qp_off * P.ncompG;
-        const int ntot = nt[0] * nt[1] * nt[2];
+        const SupportLanes S(nt[0]);
         double ad = 0.0;
-        for (int t = lane; t < ntot; t += 64) {
-            const int tk[3] = {t % nt[0], (t / nt[0]) % nt[1], t / (nt[0] * nt[1])};
-            int qk[3] = {0, 0, 0};
+        for (int t0 = S.a; t0 < nt[0]; t0 += S.w0) {
             double bv[3] = {1.0, 1.0, 1.0}, dv[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < d; ++k) {
-                const int e = elo[k] + tk[k] / nq;
-                qk[k] = elo[k] * nq + tk[k];
-                const int a = ik[k] + 1 - e * mk[k];  // local index of the basis function
-                bv[k] = Bt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
-                dv[k] = Dt[k][static_cast<int64_t>(qk[k]) * (p + 1) + a];
+            const int q0 = bd(0, t0, &bv[0], &dv[0]);
+            for (int t2 = 0; t2 < (DIM > 2 ? nt[2] : 1); ++t2) {
+                const int q2 = DIM > 2 ? bd(2, t2, &bv[2], &dv[2]) : 0;
+                for (int t1 = S.row; t1 < nt[1]; t1 += S.rstep) {
+                    const int q1 = bd(1, t1, &bv[1], &dv[1]);
+                    // f[u]: the value (rational form only) and the derivatives
+                    double f[DIM + 1];
+                    int u = 0;
+                    if (rat) f[u++] = bv[0] * bv[1] * (DIM > 2 ? bv[2] : 1.0);
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) {
+                        double v = dv[k];
+#pragma unroll
+                        for (int j = 0; j < DIM; ++j)
+                            if (j != k) v *= bv[j];
+                        f[u++] = v;
+                    }
+                    const int ne = u;  // entries of (v, grad v) or of grad v
+                    const int64_t lq = q0 + static_cast<int64_t>(g.Q[0]) * (q1 + static_cast<int64_t>(g.Q[1]) * q2);
+                    int c = 0;
+                    for (int a = 0; a < ne; ++a)
+                        for (int b = a; b < ne; ++b, ++c)
+                            ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
+                }
             }
-            // f[u]: the value (rational form only) and the derivatives
-            double f[4];
-            int u = 0;
-            if (rat) f[u++] = bv[0] * bv[1] * bv[2];
-            for (int k = 0; k < d; ++k) {
-                double v = dv[k];
-                for (int j = 0; j < d; ++j)
-                    if (j != k) v *= bv[j];
-                f[u++] = v;
-            }
-            const int64_t lq = qk[0] + static_cast<int64_t>(g.Q[0]) * (qk[1] + static_cast<int64_t>(g.Q[1]) * qk[2]);
-            int c = 0;
-            for (int a = 0; a < ne; ++a)
-                for (int b = a; b < ne; ++b, ++c) ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) ad += __shfl_xor(ad, o, 64);
-        if (lane == 0) P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
+        if ((threadIdx.x & 63) == 0) P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
     }
 }
 
@@ -628,21 +672,79 @@ __global__ void __launch_bounds__(kBlock) k_apply_fd(Params P, int gi, FdIO io, 
 // ===========================================================================
 // combination / evaluation: u(xi) = sum_c coef_c (sum_j x_j B_j(xi)) / W(xi)
 // ===========================================================================
+// Cox-de Boor recursion on a uniform open knot vector with simple interior
+// knots (t_i = clamp(i - PP, 0, E) / E), in units of one knot span: with
+// X = x E and element e (span e + PP) the differences x - t and t - x become
+// X minus an integer, and every denominator t_{i+j} - t_i is an integer
+// count c of spans (1 <= c <= PP, at least the element itself), so the
+// divisions become products with 1 / c.
 template <int PP>
+__device__ __forceinline__ void uniform_basis(double X, int e, int E, double* N) {
+    double left[PP + 1], right[PP + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= PP; ++j) {
+        left[j] = X - static_cast<double>(max(e + 1 - j, 0));
+        right[j] = static_cast<double>(min(e + j, E)) - X;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const int c = min(e + r + 1, E) - max(e + 1 - j + r, 0);
+            // 1 / c for c in 1..4: 2^-(c/2) for c = 1, 2, 4 (exact), 1/3 by a select
+            const double rc = c == 3 ? 1.0 / 3.0 : ldexp(1.0, -(c >> 1));
+            const double tmp = N[r] * rc;
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+static_assert(kMaxP <= 4, "uniform_basis holds reciprocals of span counts up to 4");
+
+// Basis functions of degree PP that are nonzero at x in direction k of a
+// grid, and the interior index of the first of them.  UNI: the table is
+// uniform with simple interior knots (checked by the host for every grid).
+template <int PP, bool UNI>
+__device__ __forceinline__ int comb_basis(const Params& P, const Tab1D& T, double x, double* N) {
+    int e;
+    if (UNI || T.uniform) {
+        const double X = x * T.E;
+        e = static_cast<int>(X);
+        e = e > T.E - 1 ? T.E - 1 : e;
+        if (UNI || T.m == 1) {
+            uniform_basis<PP>(X, e, T.E, N);
+            return e - 1;
+        }
+    } else {
+        const double* brk = P.dpool + T.oBrk;
+        int lo = 0, hi = T.E;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (x < brk[mid]) hi = mid;
+            else lo = mid;
+        }
+        e = lo;
+    }
+    d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + e * T.m, x, N, nullptr);
+    return e * T.m - 1;
+}
+
+// u(xi) = sum over the grids g0..g1 of the point's patch of c_g u_g(xi)
+// (c_g = 1 without use_coef), one thread per point; on a rational patch the
+// sum of the B-spline parts is divided once by the weight W(xi).  The basis
+// values of a direction are kept while consecutive grids share its table;
+// functions outside a grid's interior set get weight zero and a clamped
+// index, so the coefficient gathers run without branches.
+template <int PP, int DIM, bool UNI>
 __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, const int* patch, int64_t n,
                                                    double* u, int g0, int g1, int use_coef) {
-    // loops run to compile-time bounds (dimension 3, degree PP, geometry
-    // degree kMaxPg) with run-time masks, so the local arrays stay in registers
-    const int d = P.dim;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * kBlock) {
         double xv[3] = {0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (k < d) {
-                const double t = xi[i * d + k];
-                xv[k] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-            }
+        for (int k = 0; k < DIM; ++k) {
+            const double t = xi[i * DIM + k];
+            xv[k] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
         }
         const int pt = patch ? patch[i] : 0;
         // weight function W(xi) of the geometry
@@ -655,7 +757,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
             for (int k = 0; k < 3; ++k) {
 #pragma unroll
                 for (int a = 0; a <= kMaxPg; ++a) Ng[k][a] = a == 0 ? 1.0 : 0.0;
-                if (k < d) {
+                if (k < DIM) {
                     const Tab1D& T = P.tabs[P.grids[g0].tab[k]];
                     const double* gk = P.dpool + T.oGkn;
                     pgk[k] = T.pg;
@@ -683,59 +785,48 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
             }
         }
         double acc = 0.0;
+        double N[DIM][PP + 1];
+        int ix[DIM][PP + 1];
+        int ctab[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ctab[k] = -1;
         for (int gi = g0; gi < g1; ++gi) {
             const Grid& g = P.grids[gi];
-            if (g.patch != pt) continue;
-            double N[3][PP + 1];
-            int f[3] = {0, 0, 0};
+            // the basis update depends on the grid only (uniform over the
+            // wavefront); the patch test comes after it
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < DIM; ++k) {
+                if (g.tab[k] == ctab[k]) continue;
+                ctab[k] = g.tab[k];
+                const int f = comb_basis<PP, UNI>(P, P.tabs[g.tab[k]], xv[k], N[k]);
+                const int ni = g.ni[k];
 #pragma unroll
-                for (int a = 0; a <= PP; ++a) N[k][a] = a == 0 ? 1.0 : 0.0;
-                if (k < d) {
-                    const Tab1D& T = P.tabs[g.tab[k]];
-                    int e;
-                    if (T.uniform) {
-                        e = static_cast<int>(xv[k] * T.E);
-                        e = e > T.E - 1 ? T.E - 1 : e;
-                    } else {
-                        const double* brk = P.dpool + T.oBrk;
-                        int lo = 0, hi = T.E;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (xv[k] < brk[mid]) hi = mid;
-                            else lo = mid;
-                        }
-                        e = lo;
-                    }
-                    d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + e * T.m, xv[k], N[k], nullptr);
-                    f[k] = e * T.m - 1;  // interior index of the first local function
+                for (int a = 0; a <= PP; ++a) {
+                    const int j = f + a;
+                    const bool in = j >= 0 && j < ni;
+                    N[k][a] = in ? N[k][a] : 0.0;
+                    ix[k][a] = j < 0 ? 0 : (j >= ni ? ni - 1 : j);
                 }
             }
-            double v = 0.0;
+            if (g.patch != pt) continue;
             const double* X = P.x + g.dof_off;
-            const int lim2 = d > 2 ? PP : 0;
+            double v = 0.0;
 #pragma unroll
-            for (int c = 0; c <= PP; ++c) {
-                if (c > lim2) break;
-                const int i3 = d > 2 ? f[2] + c : 0;
-                if (i3 < 0 || i3 >= g.ni[2]) continue;
+            for (int c = 0; c <= (DIM > 2 ? PP : 0); ++c) {
 #pragma unroll
                 for (int b = 0; b <= PP; ++b) {
-                    const int i2 = f[1] + b;
-                    if (i2 < 0 || i2 >= g.ni[1]) continue;
+                    const int64_t row = static_cast<int64_t>(g.ni[0]) *
+                                        (ix[1][b] + (DIM > 2 ? static_cast<int64_t>(g.ni[1]) * ix[2][c] : 0));
+                    const double* Xr = X + row;
+                    double vb = 0.0;
 #pragma unroll
-                    for (int a = 0; a <= PP; ++a) {
-                        const int i1 = f[0] + a;
-                        if (i1 < 0 || i1 >= g.ni[0]) continue;
-                        v += X[i1 + static_cast<int64_t>(g.ni[0]) * (i2 + static_cast<int64_t>(g.ni[1]) * i3)] *
-                             N[0][a] * N[1][b] * (d > 2 ? N[2][c] : 1.0);
-                    }
+                    for (int a = 0; a <= PP; ++a) vb += Xr[ix[0][a]] * N[0][a];
+                    v += vb * N[1][b] * (DIM > 2 ? N[2][c] : 1.0);
                 }
             }
-            acc += (use_coef ? g.ccoef : 1.0) * (v / W);
+            acc += use_coef ? g.ccoef * v : v;
         }
-        u[i] = acc;
+        u[i] = acc / W;
     }
 }
 
@@ -778,13 +869,22 @@ hipError_t launch_loga(int ka, dim3 grid, hipStream_t st, const Params& K, const
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int p, int blocks, hipStream_t st, const Params& K, const double* xi, const int* patch,
-                          int64_t n, double* u, int g0, int g1, int use_coef) {
+template <int PP>
+void launch_combine_p(int dim, bool uni, int blocks, hipStream_t st, const Params& K, const double* xi,
+                      const int* patch, int64_t n, double* u, int g0, int g1, int use_coef) {
+    const dim3 grid(blocks), block(kBlock);
+    if (dim == 2 && uni) hipLaunchKernelGGL((k_combine<PP, 2, true>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
+    else if (dim == 2) hipLaunchKernelGGL((k_combine<PP, 2, false>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
+    else if (uni) hipLaunchKernelGGL((k_combine<PP, 3, true>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
+    else hipLaunchKernelGGL((k_combine<PP, 3, false>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
+}
+hipError_t launch_combine(int dim, int p, bool uni, int blocks, hipStream_t st, const Params& K, const double* xi,
+                          const int* patch, int64_t n, double* u, int g0, int g1, int use_coef) {
     switch (p) {
-        case 1: hipLaunchKernelGGL(k_combine<1>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
-        case 2: hipLaunchKernelGGL(k_combine<2>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
-        case 3: hipLaunchKernelGGL(k_combine<3>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
-        default: hipLaunchKernelGGL(k_combine<4>, dim3(blocks), dim3(kBlock), 0, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        case 1: launch_combine_p<1>(dim, uni, blocks, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        case 2: launch_combine_p<2>(dim, uni, blocks, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        case 3: launch_combine_p<3>(dim, uni, blocks, st, K, xi, patch, n, u, g0, g1, use_coef); break;
+        default: launch_combine_p<4>(dim, uni, blocks, st, K, xi, patch, n, u, g0, g1, use_coef); break;
     }
     return hipGetLastError();
 }
@@ -901,6 +1001,16 @@ bool field_ok(const iga_field* f, int dim) {
 int instance_of(const iga_sg_plan_s* P, const Grid& g) { return g.sample * P->ncomp + g.comp; }
 int ninstances(const iga_sg_plan_s* P) { return P->ncomp * P->nsamples; }
 
+// Every solution table of grids g0..g1 is uniform with simple interior knots.
+bool uniform_tables(const iga_sg_plan_s* P, int g0, int g1) {
+    for (int gi = g0; gi < g1; ++gi)
+        for (int k = 0; k < P->dim; ++k) {
+            const Tab1D& T = P->tabs[P->grids[gi].tab[k]];
+            if (!T.uniform || T.m != 1) return false;
+        }
+    return true;
+}
+
 int blocks_for(int64_t n) {
     int64_t b = (n + kBlock - 1) / kBlock;
     return static_cast<int>(std::min<int64_t>(std::max<int64_t>(b, 1), 65535));
@@ -1009,10 +1119,12 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     const int ng = static_cast<int>(P->grids.size());
     HIP_OK(launch_assemble(P->dim, a ? a->kind : IGA_FIELD_NONE, f ? f->kind : IGA_FIELD_NONE,
                            dim3(blocks_for(P->nqp_total)), st, K, to_dev(a), to_dev(f), ng, err));
-    hipLaunchKernelGGL(k_rhs, dim3(blocks_for(P->ndof_total)), dim3(kBlock), 0, st, K, 0, ng);
+    if (P->dim == 2) hipLaunchKernelGGL(k_rhs<2>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
+    else hipLaunchKernelGGL(k_rhs<3>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
     HIP_OK(launch_loga(a ? a->kind : IGA_FIELD_NONE, dim3(blocks_for(P->ndof_total)), st, K, to_dev(a), ng));
-    hipLaunchKernelGGL(k_fdscale, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
+    if (P->dim == 2) hipLaunchKernelGGL(k_fdscale<2>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
+    else hipLaunchKernelGGL(k_fdscale<3>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
     HIP_OK(hipGetLastError());
     P->assembled = true;
     P->solved = false;
@@ -1176,7 +1288,8 @@ iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int
     // the grids of a sample are contiguous (sample-major); sample s writes u + s n
     const int gps = static_cast<int>(P->grids.size()) / P->nsamples;
     for (int smp = 0; smp < P->nsamples; ++smp)
-        HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u + smp * n, smp * gps, (smp + 1) * gps, 1));
+        HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, smp * gps, (smp + 1) * gps), blocks_for(n), st, K, xi, patch, n,
+                              u + smp * n, smp * gps, (smp + 1) * gps, 1));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
@@ -1199,7 +1312,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
         }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
-    HIP_OK(launch_combine(P->p, blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
+    HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, g0, g1), blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
