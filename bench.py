@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "32b6665208d0ef37214b12b1f139986777f3200cff2cbb115362a4c92625506c",
-    "fetch_kib": 1224179.8, "write_kib": 207001.8,
-    "fetch_factor": 262144.0 / 131088.4, "write_factor": 262144.0 / 262144.0,
+    "sha256": "354cc7f454a888e7f21867c52c20cffe7de32d3c61444e474fba71241c1e9b57",
+    "fetch_kib": 1223714.3, "write_kib": 207001.4,
+    "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
 }
 
 
