@@ -228,6 +228,7 @@ struct Layout {
     size_t optask, fdtask, fdtask_lp;
     size_t loga;                  // log a at the Greville points of the unknowns
     size_t fdscale;               // diagonal scaling of the preconditioner
+    size_t loc;                   // element-local load and diagonal sums [2][nloc][nelem]
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t total;
@@ -272,6 +273,8 @@ struct Params {
     double* loga;      // log a at the Greville points of the unknowns [ndof_total]
     double* fdscale;   // s = sqrt(diag(P) / diag(A)) per unknown [ndof_total]; nullptr in a
                        // solve without scaling
+    double* loc;       // element-local sums: operator diagonal [nloc][nelem], then load [nloc][nelem]
+    int64_t nelem;     // elements over all grids (Gauss points / (p+1)^d)
     const float* nn;   // learned preconditioner parameters (or nullptr)
     int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
     int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)

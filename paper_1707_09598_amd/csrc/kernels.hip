@@ -6,7 +6,10 @@
 //   k_assemble    per Gauss point: NURBS map F (eq. F-B-splines), Jacobian,
 //                 a, f, operator coefficients a w |det DF| DF^-1 DF^-T and the
 //                 load density (Galerkin form of Problem 1)
-//   k_rhs         load vector b_j = sum_q f w |det DF| phi_j
+//   k_elemloc     per element and local basis function: its load and
+//                 operator-diagonal sums over the element's Gauss points
+//   k_gather      load vector b_j = sum_q f w |det DF| phi_j and the
+//                 preconditioner scaling from the operator diagonal
 //   k_solve       persistent refinement + fast-diagonalisation PCG over all
 //                 component grids (grid-wide barrier between phases)
 //   k_combine     u_sg(xi) = sum_i c_i u_i(xi), eq. (TD-combi-tec), FP64
@@ -364,121 +367,164 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
 }
 
 
-// Gauss points of the support of one basis function, split over the lanes of
-// a wavefront: lane = a + W0 * row with W0 the power of two >= the points of
-// direction 0 in the support (at most (p + 1) (p + 1) <= 25); a lane takes
-// the direction-0 points a, a + W0, ... of rows row, row + 64 / W0, ... of
-// the direction-1 points, for every direction-2 point.  Shifts and masks
-// only, so no integer division per point.
-struct SupportLanes {
-    int a, row, w0, rstep;
-    __device__ explicit SupportLanes(int nt0) {
-        int lw = 0;
-        while ((1 << lw) < nt0 && lw < 6) ++lw;
-        const int lane = threadIdx.x & 63;
-        w0 = 1 << lw;
-        a = lane & (w0 - 1);
-        row = lane >> lw;
-        rstep = 64 >> lw;
-    }
+// ---------------------------------------------------------------------------
+// Load vector and diagonal of the operator, element by element.
+//
+// Every Gauss point lies in one element and contributes to the (p+1)^d basis
+// functions that are nonzero there.  k_elemloc visits each element once: lane
+// a of the element's lane group takes local basis function
+// B_a = B_{a0}(xi_0) B_{a1}(xi_1) [B_{a2}(xi_2)] and sums over the element's
+// Gauss points
+//   bl(a) = sum_q Fq(q) B_a(q)                      (Fq = f w |det DF| / W)
+//   dl(a) = sum_q sum_uv G_uv(q) f_u(q) f_v(q)      (f = grad B_a, or
+//           (B_a, grad B_a) for the rational form; both orders for u != v)
+// with the element's coefficients staged once in LDS and read by every lane
+// of the group.  The sums are stored structure-of-arrays by local index,
+// loc[a][element] (dl) and loc[nloc + a][element] (bl), so that the gather
+// reads them with consecutive unknowns on consecutive elements.
+//
+// k_gather, one thread per unknown: b_i = sum of bl over the elements of the
+// support of B_i, A_ii likewise from dl, in a fixed element order (bitwise
+// reproducible), and the preconditioner scaling s_i = sqrt(P_ii / A_ii) with
+// P = sum_k K_k (x) prod_{l != k} M_l the pencil of the 1D matrices, so that
+// S P S has the diagonal of A.
+// ---------------------------------------------------------------------------
+template <int DIM, int PP>
+struct ElemShape {
+    static constexpr int NQ = PP + 1;                                          // Gauss points = local functions per direction
+    static constexpr int NLOC = DIM == 2 ? NQ * NQ : NQ * NQ * NQ;             // per element
+    static constexpr int NLP = NLOC <= 4 ? 4 : NLOC <= 8 ? 8 : NLOC <= 16 ? 16 : NLOC <= 32 ? 32 : 64;
+    static constexpr int EPW = 64 / NLP;                                       // elements per wavefront
+    static constexpr int LPL = (NLOC + 63) / 64;                               // local functions per lane
 };
 
-// Unknown handled by the wavefront, uniform over it (so grid and table
-// descriptors come through scalar loads).
-__device__ __forceinline__ int64_t wave_unknown(int64_t first) {
-    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-    return first + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + w;
-}
-
-// Load vector: b_i = sum over the Gauss points of the elements in the support
-// of B_i of B_i(q) Fq(q) (Fq = f w |det DF| / W, stored by k_assemble), one
-// wavefront per unknown, the points split over the lanes and summed by a
-// fixed lane butterfly.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_rhs(Params P, int g0, int g1) {
-    const int64_t i0 = P.grids[g0].dof_off;
-    const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
-    const int p = P.p, nq = P.nq, nqm = (65536 + nq - 1) / nq;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
-    for (int64_t gi = wave_unknown(i0); gi < i1; gi += nw) {
-        const int lo = grid_of_dof(P, g0, g1, gi);
-        const Grid& g = P.grids[lo];
-        int64_t l = gi - g.dof_off;
-        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, nt[3] = {1, 1, 1}, mk[3] = {1, 1, 1};
-        const double* Bt[3] = {nullptr, nullptr, nullptr};
+template <int DIM, int PP, bool RAT>
+__global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
+    using SH = ElemShape<DIM, PP>;
+    constexpr int NQ = SH::NQ, NLOC = SH::NLOC, NLP = SH::NLP, EPW = SH::EPW, LPL = SH::LPL;
+    constexpr int NE = DIM + (RAT ? 1 : 0);      // entries of f
+    constexpr int NC = NE * (NE + 1) / 2;        // stored coefficients per Gauss point
+    constexpr int NCP = (NC + 2) & ~1;           // + load density, padded to 16 bytes
+    constexpr int WAVES = kBlock / 64;
+    __shared__ double sh[WAVES][EPW][NLOC][NCP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / NLP, la = lane % NLP;
+    const int64_t nelem = P.nelem;
+    for (int64_t blk0 = static_cast<int64_t>(blockIdx.x) * WAVES * EPW; blk0 < nelem;
+         blk0 += static_cast<int64_t>(gridDim.x) * WAVES * EPW) {
+        const int64_t el = blk0 + wave * EPW + slot;
+        const bool live = el < nelem;
+        int gi = 0, ek[3] = {0, 0, 0};
+        int64_t qbase = 0, nqp = 0;
+        if (live) {
+            gi = grid_of_qp(P, 0, P.ngrid, el * NLOC);
+            const Grid& g = P.grids[gi];
+            int64_t r = el - g.qp_off / NLOC;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            ik[k] = static_cast<int>(l % g.ni[k]);
-            l /= g.ni[k];
-            const Tab1D& T = P.tabs[g.tab[k]];
-            int ehi;
-            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi);
-            nt[k] = (ehi - elo[k] + 1) * nq;
-            mk[k] = T.m;
-            Bt[k] = P.dpool + T.oB;
-        }
-        // basis value of B_i at support point t of direction k (t / nq by a
-        // multiply-shift, exact for t < 64 and nq <= 8)
-        auto bval = [&](int k, int t) {
-            const int e = elo[k] + ((t * nqm) >> 16);
-            return Bt[k][static_cast<int64_t>(elo[k] * nq + t) * (p + 1) + (ik[k] + 1 - e * mk[k])];
-        };
-        const SupportLanes S(nt[0]);
-        const double* F = P.Fq + g.qp_off;
-        double acc = 0.0;
-        for (int t0 = S.a; t0 < nt[0]; t0 += S.w0) {
-            const int64_t q0 = elo[0] * nq + t0;
-            double s0 = 0.0;
-            for (int t2 = 0; t2 < (DIM > 2 ? nt[2] : 1); ++t2) {
-                const double b2 = DIM > 2 ? bval(2, t2) : 1.0;
-                const int64_t q2 = DIM > 2 ? elo[2] * nq + t2 : 0;
-                double s1 = 0.0;
-                for (int t1 = S.row; t1 < nt[1]; t1 += S.rstep) {
-                    const int64_t q1 = elo[1] * nq + t1;
-                    s1 += bval(1, t1) * F[q0 + g.Q[0] * (q1 + static_cast<int64_t>(g.Q[1]) * q2)];
-                }
-                s0 += b2 * s1;
+            for (int k = 0; k < DIM; ++k) {
+                ek[k] = static_cast<int>(r % g.E[k]);
+                r /= g.E[k];
             }
-            acc += bval(0, t0) * s0;
-        }
+            nqp = g.nqp;
+            qbase = g.qp_off + ek[0] * NQ + static_cast<int64_t>(g.Q[0]) *
+                                                (ek[1] * NQ + (DIM > 2 ? static_cast<int64_t>(g.Q[1]) * ek[2] * NQ : 0));
+            // stage the element's coefficients: lane la copies Gauss point la
+            // (and la + 64 ... when the element has more than 64)
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if ((threadIdx.x & 63) == 0) P.b[gi] = acc;
+            for (int s = 0; s < LPL; ++s) {
+                const int q = la + 64 * s;
+                if (q < NLOC) {
+                    const int j0 = q % NQ, j1 = (q / NQ) % NQ, j2 = DIM > 2 ? q / (NQ * NQ) : 0;
+                    const int64_t lq = qbase + j0 + static_cast<int64_t>(g.Q[0]) * (j1 + static_cast<int64_t>(g.Q[1]) * j2);
+                    const double* G = P.G64 + g.qp_off * NC + (lq - g.qp_off);
+                    int c = 0;
+#pragma unroll
+                    for (int u = 0; u < NE; ++u)
+#pragma unroll
+                        for (int v = u; v < NE; ++v, ++c) {
+                            const double gv = G[c * nqp];
+                            sh[wave][slot][q][c] = u == v ? gv : 2.0 * gv;
+                        }
+                    sh[wave][slot][q][NC] = P.Fq[lq];
+                }
+            }
+        }
+        __syncthreads();
+        if (live) {
+            const Grid& g = P.grids[gi];
+#pragma unroll
+            for (int s = 0; s < LPL; ++s) {
+                const int a = la + 64 * s;
+                if (a < NLOC) {
+                    const int ak[3] = {a % NQ, (a / NQ) % NQ, DIM > 2 ? a / (NQ * NQ) : 0};
+                    double Bv[DIM][NQ], Dv[DIM][NQ];
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) {
+                        const Tab1D& T = P.tabs[g.tab[k]];
+#pragma unroll
+                        for (int j = 0; j < NQ; ++j) {
+                            const int64_t t = static_cast<int64_t>(ek[k] * NQ + j) * NQ + ak[k];
+                            Bv[k][j] = P.dpool[T.oB + t];
+                            Dv[k][j] = P.dpool[T.oD + t];
+                        }
+                    }
+                    double dl = 0.0, bl = 0.0;
+#pragma unroll
+                    for (int j2 = 0; j2 < (DIM > 2 ? NQ : 1); ++j2)
+#pragma unroll
+                        for (int j1 = 0; j1 < NQ; ++j1) {
+                            // products of the other directions' factors
+                            const double b12 = DIM > 2 ? Bv[1][j1] * Bv[2][j2] : Bv[1][j1];
+                            const double d1b2 = DIM > 2 ? Dv[1][j1] * Bv[2][j2] : Dv[1][j1];
+                            const double b1d2 = DIM > 2 ? Bv[1][j1] * Dv[2][j2] : 0.0;
+#pragma unroll
+                            for (int j0 = 0; j0 < NQ; ++j0) {
+                                const double* c = sh[wave][slot][j0 + NQ * (j1 + NQ * j2)];
+                                double f[NE];
+                                int u = 0;
+                                const double val = Bv[0][j0] * b12;
+                                if (RAT) f[u++] = val;
+                                f[u++] = Dv[0][j0] * b12;
+                                f[u++] = Bv[0][j0] * d1b2;
+                                if (DIM > 2) f[u++] = Bv[0][j0] * b1d2;
+                                int ci = 0;
+#pragma unroll
+                                for (int x = 0; x < NE; ++x) {
+                                    double t = 0.0;
+#pragma unroll
+                                    for (int y = x; y < NE; ++y, ++ci) t += c[ci] * f[y];
+                                    dl += f[x] * t;
+                                }
+                                bl += c[NC] * val;
+                            }
+                        }
+                    P.loc[static_cast<int64_t>(a) * nelem + el] = dl;
+                    P.loc[static_cast<int64_t>(NLOC + a) * nelem + el] = bl;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
-// Diagonal scaling of the fast-diagonalisation preconditioner, one wavefront
-// per unknown: s_i = sqrt(P_ii / A_ii) with P = sum_k K_k (x) prod_{l != k} M_l
-// the pencil of the 1D matrices and A the assembled operator, so that S P S
-// has the diagonal of A.  A_ii sums, over the Gauss points of the elements in
-// the support of basis function i (split over the lanes, then a fixed lane
-// butterfly), the stored coefficients G_uv times the products of its value /
-// first derivatives (u, v), both orders for u != v.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
-    const int64_t i0 = P.grids[g0].dof_off;
-    const int64_t i1 = P.grids[g1 - 1].dof_off + P.grids[g1 - 1].ndof;
-    const int p = P.p, nq = P.nq, nqm = (65536 + nq - 1) / nq;
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * (kBlock / 64);
-    for (int64_t gi = wave_unknown(i0); gi < i1; gi += nw) {
-        const int lo = grid_of_dof(P, g0, g1, gi);
-        const Grid& g = P.grids[lo];
+template <int DIM, int PP>
+__global__ void __launch_bounds__(kBlock) k_gather(Params P) {
+    constexpr int NQ = PP + 1;
+    constexpr int NLOC = ElemShape<DIM, PP>::NLOC;
+    const int64_t nelem = P.nelem;
+    for (int64_t gi = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gi < P.ndof_total;
+         gi += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const Grid& g = P.grids[grid_of_dof(P, 0, P.ngrid, gi)];
         int64_t l = gi - g.dof_off;
-        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, nt[3] = {1, 1, 1}, mk[3] = {1, 1, 1};
-        const double* Bt[3] = {nullptr, nullptr, nullptr};
-        const double* Dt[3] = {nullptr, nullptr, nullptr};
+        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0}, mk[3] = {1, 1, 1};
         double pd = 0.0, md[3] = {1.0, 1.0, 1.0}, kd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             ik[k] = static_cast<int>(l % g.ni[k]);
             l /= g.ni[k];
             const Tab1D& T = P.tabs[g.tab[k]];
-            int ehi;
-            d_elem_range(ik[k], ik[k] + 1, p, T.m, g.E[k], &elo[k], &ehi);
-            nt[k] = (ehi - elo[k] + 1) * nq;  // Gauss points of the support in direction k
+            d_elem_range(ik[k], ik[k] + 1, PP, T.m, g.E[k], &elo[k], &ehi[k]);
             mk[k] = T.m;
-            Bt[k] = P.dpool + T.oB;
-            Dt[k] = P.dpool + T.oD;
             kd[k] = P.dpool[T.oKd + ik[k]];
             md[k] = P.dpool[T.oMd + ik[k]];
         }
@@ -490,52 +536,23 @@ __global__ void __launch_bounds__(kBlock) k_fdscale(Params P, int g0, int g1) {
                 if (j != k) t *= md[j];
             pd += t;
         }
-        // value and derivative of B_i at support point t of direction k, and
-        // the point's index in the grid's Gauss points of that direction
-        // (t / nq by a multiply-shift, exact for t < 64 and nq <= 8)
-        auto bd = [&](int k, int t, double* bv, double* dv) {
-            const int e = elo[k] + ((t * nqm) >> 16);
-            const int64_t i = static_cast<int64_t>(elo[k] * nq + t) * (p + 1) + (ik[k] + 1 - e * mk[k]);
-            *bv = Bt[k][i];
-            *dv = Dt[k][i];
-            return elo[k] * nq + t;
-        };
-        const bool rat = P.rational[g.patch] != 0;
-        const int64_t nqp = g.nqp;
-        const double* G = P.G64 + g.qp_off * P.ncompG;
-        const SupportLanes S(nt[0]);
-        double ad = 0.0;
-        for (int t0 = S.a; t0 < nt[0]; t0 += S.w0) {
-            double bv[3] = {1.0, 1.0, 1.0}, dv[3] = {0.0, 0.0, 0.0};
-            const int q0 = bd(0, t0, &bv[0], &dv[0]);
-            for (int t2 = 0; t2 < (DIM > 2 ? nt[2] : 1); ++t2) {
-                const int q2 = DIM > 2 ? bd(2, t2, &bv[2], &dv[2]) : 0;
-                for (int t1 = S.row; t1 < nt[1]; t1 += S.rstep) {
-                    const int q1 = bd(1, t1, &bv[1], &dv[1]);
-                    // f[u]: the value (rational form only) and the derivatives
-                    double f[DIM + 1];
-                    int u = 0;
-                    if (rat) f[u++] = bv[0] * bv[1] * (DIM > 2 ? bv[2] : 1.0);
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) {
-                        double v = dv[k];
-#pragma unroll
-                        for (int j = 0; j < DIM; ++j)
-                            if (j != k) v *= bv[j];
-                        f[u++] = v;
-                    }
-                    const int ne = u;  // entries of (v, grad v) or of grad v
-                    const int64_t lq = q0 + static_cast<int64_t>(g.Q[0]) * (q1 + static_cast<int64_t>(g.Q[1]) * q2);
-                    int c = 0;
-                    for (int a = 0; a < ne; ++a)
-                        for (int b = a; b < ne; ++b, ++c)
-                            ad += (a == b ? 1.0 : 2.0) * G[c * nqp + lq] * f[a] * f[b];
+        const int64_t e0 = g.qp_off / NLOC;
+        double ad = 0.0, bb = 0.0;
+        for (int c2 = elo[2]; c2 <= ehi[2]; ++c2) {
+            const int a2 = DIM > 2 ? ik[2] + 1 - c2 * mk[2] : 0;
+            for (int c1 = elo[1]; c1 <= ehi[1]; ++c1) {
+                const int a1 = ik[1] + 1 - c1 * mk[1];
+                const int64_t row = e0 + g.E[0] * (c1 + static_cast<int64_t>(g.E[1]) * c2);
+                for (int c0 = elo[0]; c0 <= ehi[0]; ++c0) {
+                    const int a = (ik[0] + 1 - c0 * mk[0]) + NQ * (a1 + NQ * a2);
+                    const int64_t el = row + c0;
+                    ad += P.loc[static_cast<int64_t>(a) * nelem + el];
+                    bb += P.loc[static_cast<int64_t>(NLOC + a) * nelem + el];
                 }
             }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) ad += __shfl_xor(ad, o, 64);
-        if ((threadIdx.x & 63) == 0) P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
+        P.b[gi] = bb;
+        P.fdscale[gi] = ad > 0.0 && pd > 0.0 ? sqrt(pd / ad) : 1.0;
     }
 }
 
@@ -859,6 +876,30 @@ hipError_t launch_assemble(int dim, int ka, int kf, dim3 grid, hipStream_t st, c
     return dim == 2 ? launch_assemble_d<2>(ka, kf, grid, st, K, fa, ff, ng, err)
                     : launch_assemble_d<3>(ka, kf, grid, st, K, fa, ff, ng, err);
 }
+// Element-local sums and their gather (load vector, preconditioner scaling),
+// specialised by dimension, degree and the rational form of the coefficients.
+template <int DIM, int PP>
+void launch_loadiag_p(bool rat, hipStream_t st, const Params& K, int dblocks) {
+    constexpr int64_t epb = (kBlock / 64) * ElemShape<DIM, PP>::EPW;  // elements per workgroup
+    const int eblocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>((K.nelem + epb - 1) / epb, 1), 65535));
+    if (rat) hipLaunchKernelGGL((k_elemloc<DIM, PP, true>), dim3(eblocks), dim3(kBlock), 0, st, K);
+    else hipLaunchKernelGGL((k_elemloc<DIM, PP, false>), dim3(eblocks), dim3(kBlock), 0, st, K);
+    hipLaunchKernelGGL((k_gather<DIM, PP>), dim3(dblocks), dim3(kBlock), 0, st, K);
+}
+template <int DIM>
+void launch_loadiag_d(int p, bool rat, hipStream_t st, const Params& K, int dblocks) {
+    switch (p) {
+        case 1: launch_loadiag_p<DIM, 1>(rat, st, K, dblocks); break;
+        case 2: launch_loadiag_p<DIM, 2>(rat, st, K, dblocks); break;
+        case 3: launch_loadiag_p<DIM, 3>(rat, st, K, dblocks); break;
+        default: launch_loadiag_p<DIM, 4>(rat, st, K, dblocks); break;
+    }
+}
+hipError_t launch_loadiag(int dim, int p, bool rat, hipStream_t st, const Params& K, int dblocks) {
+    if (dim == 2) launch_loadiag_d<2>(p, rat, st, K, dblocks);
+    else launch_loadiag_d<3>(p, rat, st, K, dblocks);
+    return hipGetLastError();
+}
 hipError_t launch_loga(int ka, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa, int ng) {
     switch (ka) {
         case IGA_FIELD_CONST: hipLaunchKernelGGL((k_loga<IGA_FIELD_CONST>), grid, dim3(kBlock), 0, st, K, fa, 0, ng); break;
@@ -944,6 +985,12 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     K.bar = reinterpret_cast<unsigned*>(base + L.bar);
     K.loga = reinterpret_cast<double*>(base + L.loga);
     K.fdscale = reinterpret_cast<double*>(base + L.fdscale);
+    K.loc = reinterpret_cast<double*>(base + L.loc);
+    {
+        int64_t nloc = 1;
+        for (int k = 0; k < P->dim; ++k) nloc *= P->nq;
+        K.nelem = P->nqp_total / nloc;
+    }
     K.nn = P->nn;
     for (int i = 0; i < 4; ++i) K.nn_ch[i] = P->nn_ch[i];
     K.nn_head = P->nn_head;
@@ -1119,13 +1166,9 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     const int ng = static_cast<int>(P->grids.size());
     HIP_OK(launch_assemble(P->dim, a ? a->kind : IGA_FIELD_NONE, f ? f->kind : IGA_FIELD_NONE,
                            dim3(blocks_for(P->nqp_total)), st, K, to_dev(a), to_dev(f), ng, err));
-    if (P->dim == 2) hipLaunchKernelGGL(k_rhs<2>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
-    else hipLaunchKernelGGL(k_rhs<3>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
-    HIP_OK(hipGetLastError());
+    // element-local sums (one lane group per element), then one thread per unknown
+    HIP_OK(launch_loadiag(P->dim, P->p, P->ncompG == (P->dim == 2 ? 6 : 10), st, K, blocks_for(P->ndof_total)));
     HIP_OK(launch_loga(a ? a->kind : IGA_FIELD_NONE, dim3(blocks_for(P->ndof_total)), st, K, to_dev(a), ng));
-    if (P->dim == 2) hipLaunchKernelGGL(k_fdscale<2>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
-    else hipLaunchKernelGGL(k_fdscale<3>, dim3(blocks_for(P->ndof_total * 64)), dim3(kBlock), 0, st, K, 0, ng);
-    HIP_OK(hipGetLastError());
     P->assembled = true;
     P->solved = false;
     return IGA_OK;

@@ -813,6 +813,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.part = take(sizeof(double) * pst * 10);
     L.loga = take(sizeof(double) * nd);
     L.fdscale = take(sizeof(double) * nd);
+    // two sums per local basis function of each element; an element has as
+    // many local functions as Gauss points, (p+1)^d
+    L.loc = take(sizeof(double) * 2 * nqp);
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());

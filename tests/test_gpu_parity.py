@@ -67,17 +67,30 @@ def _bound(S, wl):
 
 def _config(name, w):
     """Workload by name; the random-field cube takes its first coefficient sample
-    (a = exp(g) on a 24^3 vertex grid, seed 0)."""
+    (a = exp(g) on a 24^3 vertex grid, seed 0).  Variants: '_c0' / '_c1'
+    lower the continuity (interior knots of multiplicity p or p - 1),
+    '_graded' uses radical knots (two-sided in direction 1, toward 0 in
+    direction 2; eq. of Sec. 4.3)."""
     if name == "cfg5":
         a = W.grf_samples(1, n=24)[0]
         return W.config(name, w=w, a=W._field("grid3d", data=a))
+    base, _, var = name.partition("_")
+    if var == "c0":
+        return W.config(base, w=w, r=0)
+    if var == "c1":
+        return W.config(base, w=w, r=1)
+    if var == "graded":
+        return W.config(base, w=w, grading=[("radical", 3.0), ("toward0", 2.0)] +
+                        ([("uniform", 1.0)] if base in ("cfg3", "cfg5") else []))
     return W.config(name, w=w)
 
 
 @pytest.mark.parametrize("name,w,comps", [("cfg1", 4, None), ("cfg2", 5, None), ("cfg2", 7, None),
                                           ("cfg2", 10, [0, 1, 9, 10, 11, 19, 20]),
                                           ("cfg3", 5, None), ("cfg3", 7, [0, 1, 2, 5, 9, 14]),
-                                          ("cfg5", 4, [0, 3, 6, 10])])
+                                          ("cfg5", 4, [0, 3, 6, 10]),
+                                          ("cfg1_c0", 4, None), ("cfg2_c1", 5, [0, 2, 5, 8, 10]),
+                                          ("cfg2_graded", 5, [0, 3, 7, 10]), ("cfg3_c1", 4, None)])
 def test_rhs_and_operator_parity(S, name, w, comps):
     wl = _config(name, w)
     log(f"case rhs/operator {name} w={w}")
@@ -135,7 +148,9 @@ def test_fast_diagonalisation_parity(S, name, w, comps):
 
 @pytest.mark.parametrize("name,w,comps", [("cfg1", 5, None), ("cfg2", 7, None),
                                           ("cfg2", 10, [0, 9, 19, 20]), ("cfg3", 6, [0, 5, 10]),
-                                          ("cfg5", 4, [0, 3, 6, 10, 14])])
+                                          ("cfg5", 4, [0, 3, 6, 10, 14]),
+                                          ("cfg1_c0", 4, [0, 2, 5]), ("cfg2_c1", 5, [0, 5, 10]),
+                                          ("cfg2_graded", 5, [0, 3, 7, 10]), ("cfg3_c1", 4, None)])
 def test_scaled_fast_diagonalisation_parity(S, name, w, comps):
     """z = S P^-1 S x with S = sqrt(diag(P) / diag(A)): diag(A) from the
     oracle's dense assembly, P the Kronecker pencil of the 1D matrices."""
