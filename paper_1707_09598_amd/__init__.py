@@ -20,6 +20,7 @@ FIELD = {None: -1, "none": -1, "const": 0, "sinprod": 1, "sincos": 2, "annulus_r
          "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7}
 GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
+SCHED = {"auto": 0, "static": 1, "lists": 2}
 STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_ERR_OUT_OF_MEMORY",
           4: "IGA_ERR_DEVICE", 5: "IGA_ERR_NOT_CONVERGED", 6: "IGA_ERR_BREAKDOWN", 7: "IGA_ERR_STATE"}
 APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5, "fds64": 6}
@@ -70,7 +71,8 @@ class _Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("batched", C.c_int), ("tol", C.c_double),
                 ("tol_inner", C.c_double), ("maxit", C.c_int), ("max_refine", C.c_int),
                 ("workgroups", C.c_int), ("timing", C.c_int), ("continue_cg", C.c_int),
-                ("precond", C.c_int), ("learned_iters", C.c_int), ("plain_fd", C.c_int)]
+                ("precond", C.c_int), ("learned_iters", C.c_int), ("plain_fd", C.c_int),
+                ("schedule", C.c_int)]
 
 
 class _Report(C.Structure):
@@ -304,9 +306,11 @@ class Plan:
     def solve(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
               maxit: int = 500, max_refine: int = 0, batched: bool = True, workgroups: int = 0,
               timing: bool = False, check: bool = True, continue_cg: bool = False,
-              learned: bool = False, learned_iters: int = 0, scaled: bool = True) -> Dict[str, Any]:
+              learned: bool = False, learned_iters: int = 0, scaled: bool = True,
+              schedule: str = "auto") -> Dict[str, Any]:
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups,
-                  int(timing), int(continue_cg), int(learned), int(learned_iters), int(not scaled))
+                  int(timing), int(continue_cg), int(learned), int(learned_iters), int(not scaled),
+                  SCHED[schedule])
         it = np.zeros(self.ninst, dtype=np.int32)
         rf = np.zeros(self.ninst, dtype=np.int32)
         rr = np.zeros(self.ninst)
@@ -325,10 +329,10 @@ class Plan:
     def solve_async(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
                     maxit: int = 500, max_refine: int = 0, batched: bool = True,
                     workgroups: int = 0, continue_cg: bool = False, learned: bool = False,
-                    learned_iters: int = 0, scaled: bool = True) -> None:
+                    learned_iters: int = 0, scaled: bool = True, schedule: str = "auto") -> None:
         """Enqueue a solve without reading the report back (no host sync)."""
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0,
-                  int(continue_cg), int(learned), int(learned_iters), int(not scaled))
+                  int(continue_cg), int(learned), int(learned_iters), int(not scaled), SCHED[schedule])
         _check(lib().iga_sg_solve(self.h, C.byref(o), C.POINTER(_Report)()))
 
     def combine(self, xi, patch=None):

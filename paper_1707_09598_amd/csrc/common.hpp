@@ -215,9 +215,13 @@ constexpr size_t kSolveLdsHead = kCtxBytes + kMetaSlots * sizeof(TaskMeta);
 // Barrier block (unsigned words): generation, finished-grid count, traced
 // sweeps, the global arrival count on its own 64-byte line, the group arrival
 // counts one line apart; bytes 64..67 hold the assembly error flag.
+// The lengths of the active task lists (operator and fast-diagonalisation,
+// by sweep parity) follow on a line of their own.
 constexpr int kBarGen = 1, kBarDone = 2, kBarSweeps = 3, kBarCount = 32, kBarGroup = 64, kBarStride = 16;
 constexpr int kBarGroups = 8;
-constexpr int kBarBytes = 4 * (kBarGroup + kBarStride * kBarGroups);
+constexpr int kBarOpLen = kBarGroup + kBarStride * kBarGroups;  // + parity
+constexpr int kBarFdLen = kBarOpLen + 2;                        // + parity
+constexpr int kBarBytes = 4 * (kBarOpLen + kBarStride);
 
 struct Layout {
     size_t tabs, grids, grids_lp, dpool, ipool, fpool, hpool, ctrl;
@@ -229,6 +233,8 @@ struct Layout {
     size_t loga;                  // log a at the Greville points of the unknowns
     size_t fdscale;               // diagonal scaling of the preconditioner
     size_t loc;                   // element-local load and diagonal sums [2][nloc][nelem]
+    size_t gmeta, gmeta_lp;       // TaskMeta per grid (FP64 / low-precision FD blocking)
+    size_t oplist, fdlist;        // active task lists [2 parities][tasks]
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t total;
@@ -275,6 +281,10 @@ struct Params {
                        // solve without scaling
     double* loc;       // element-local sums: operator diagonal [nloc][nelem], then load [nloc][nelem]
     int64_t nelem;     // elements over all grids (Gauss points / (p+1)^d)
+    const TaskMeta* gmeta;  // description of every grid with its 1D tables (local = 0)
+    Task* oplist;      // active operator tasks [2][op_cap] (by sweep parity)
+    Task* fdlist;      // active fast-diagonalisation tasks [2][fd_cap]
+    int op_cap, fd_cap;
     const float* nn;   // learned preconditioner parameters (or nullptr)
     int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
     int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)

@@ -622,8 +622,10 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
     }
 }
 
-// Reset solver state and vectors of a grid range before a solve.
-__global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1, int64_t i0, int64_t i1) {
+// Reset solver state and vectors of a grid range before a solve; the first
+// sweep's active task lists are the launch's task ranges.
+__global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1, int64_t i0, int64_t i1,
+                                                      int op_b, int op_e, int fd_b, int fd_e) {
     const int64_t N = P.ndof_total;
     for (int64_t i = i0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < i1;
          i += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -632,6 +634,10 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
         P.z[i] = 0.0;
         P.p2[i] = 0.0;
         P.p2[N + i] = 0.0;
+    }
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < op_e - op_b || t < fd_e - fd_b; t += gridDim.x * kBlock) {
+        if (t < op_e - op_b) P.oplist[t] = P.optask[op_b + t];
+        if (t < fd_e - fd_b) P.fdlist[t] = P.fdtask[fd_b + t];
     }
     if (blockIdx.x == 0) {
         for (int g = g0 + threadIdx.x; g < g1; g += kBlock) {
@@ -656,6 +662,12 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
             P.bar[kBarCount] = 0u;
         }
         if (threadIdx.x < kBarGroups) P.bar[kBarGroup + kBarStride * threadIdx.x] = 0u;
+        if (threadIdx.x == 0) {
+            P.bar[kBarOpLen] = static_cast<unsigned>(op_e - op_b);
+            P.bar[kBarOpLen + 1] = 0u;
+            P.bar[kBarFdLen] = static_cast<unsigned>(fd_e - fd_b);
+            P.bar[kBarFdLen + 1] = 0u;
+        }
     }
 }
 
@@ -986,6 +998,11 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     K.loga = reinterpret_cast<double*>(base + L.loga);
     K.fdscale = reinterpret_cast<double*>(base + L.fdscale);
     K.loc = reinterpret_cast<double*>(base + L.loc);
+    K.gmeta = reinterpret_cast<const TaskMeta*>(base + (lowp_fd ? L.gmeta_lp : L.gmeta));
+    K.oplist = reinterpret_cast<Task*>(base + L.oplist);
+    K.fdlist = reinterpret_cast<Task*>(base + L.fdlist);
+    K.op_cap = static_cast<int>(P->optask.size());
+    K.fd_cap = static_cast<int>(std::max(P->fdtask.size(), P->fdtask_lp.size()));
     {
         int64_t nloc = 1;
         for (int k = 0; k < P->dim; ++k) nloc *= P->nq;
@@ -1099,6 +1116,26 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     HIP_OK(hipMemcpyAsync(base + L.fdtask, P->fdtask.data(), sizeof(Task) * P->fdtask.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(base + L.fdtask_lp, P->fdtask_lp.data(), sizeof(Task) * P->fdtask_lp.size(), hipMemcpyHostToDevice, st));
     HIP_OK(hipMemsetAsync(base + L.bar, 0, 256, st));
+    {
+        // every grid's description with its 1D tables, one record per grid, so
+        // that a solve task reads its description in one contiguous copy
+        for (int lp = 0; lp < 2; ++lp) {
+            const std::vector<Grid>& gv = lp ? P->grids_lp : P->grids;
+            std::vector<TaskMeta>& mv = lp ? P->gmeta_lp : P->gmeta;
+            mv.assign(gv.size(), TaskMeta());
+            for (size_t gi = 0; gi < gv.size(); ++gi) {
+                TaskMeta& M = mv[gi];
+                std::memset(&M, 0, sizeof(M));
+                M.g = gv[gi];
+                for (int k = 0; k < kMaxDim; ++k)
+                    if (gv[gi].tab[k] >= 0) M.t[k] = P->tabs[gv[gi].tab[k]];
+                M.grid = static_cast<int>(gi);
+                M.local = 0;
+            }
+            HIP_OK(hipMemcpyAsync(base + (lp ? L.gmeta_lp : L.gmeta), mv.data(), sizeof(TaskMeta) * mv.size(),
+                                  hipMemcpyHostToDevice, st));
+        }
+    }
     Params K = make_params(P);
     int maxQ = 0;
     for (const Tab1D& T : P->tabs) maxQ = std::max(maxQ, T.Q);
@@ -1221,7 +1258,8 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     auto launch = [&](int g0, int g1, int opb, int ope, int fdb, int fde) -> iga_status {
         const int64_t i0 = P->grids[g0].dof_off;
         const int64_t i1 = P->grids[g1 - 1].dof_off + P->grids[g1 - 1].ndof;
-        hipLaunchKernelGGL(k_solve_init, dim3(blocks_for(i1 - i0)), dim3(kBlock), 0, st, K, g0, g1, i0, i1);
+        hipLaunchKernelGGL(k_solve_init, dim3(blocks_for(i1 - i0)), dim3(kBlock), 0, st, K, g0, g1, i0, i1, opb, ope,
+                           fdb, fde);
         HIP_OK(hipGetLastError());
         A.op_b = opb;
         A.op_e = ope;
@@ -1231,6 +1269,12 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         int want = std::max(ope - opb, fde - fdb);
         if (o->workgroups > 0) want = o->workgroups;
         int nwg = std::max(1, std::min(want, P->max_wg));
+        // a few tasks per workgroup: round robin over the launch's tasks with
+        // their descriptions cached for the launch; many: round robin over the
+        // per-sweep lists of the grids still iterating
+        A.dyn = (ope - opb > kMetaOp * nwg || fde - fdb > kMetaFd * nwg) ? 1 : 0;
+        if (o->schedule == 1) A.dyn = 0;
+        if (o->schedule == 2) A.dyn = 1;
         void* args[] = {&K, &A};
         HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(kBlock), args,
                                           static_cast<unsigned>(lds), st));

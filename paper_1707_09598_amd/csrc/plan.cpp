@@ -816,6 +816,10 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     // two sums per local basis function of each element; an element has as
     // many local functions as Gauss points, (p+1)^d
     L.loc = take(sizeof(double) * 2 * nqp);
+    L.gmeta = take(sizeof(TaskMeta) * ng);
+    L.gmeta_lp = take(sizeof(TaskMeta) * ng);
+    L.oplist = take(sizeof(Task) * 2 * P->optask.size());
+    L.fdlist = take(sizeof(Task) * 2 * std::max(P->fdtask.size(), P->fdtask_lp.size()));
     L.optask = take(sizeof(Task) * P->optask.size());
     L.fdtask = take(sizeof(Task) * P->fdtask.size());
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());

@@ -55,6 +55,7 @@ struct iga_sg_plan_s {
     std::vector<igasg::Grid> grids;      // FD blocking for FP64 factors
     std::vector<igasg::Grid> grids_lp;   // same grids, FD blocking for FP32/BF16 factors
     std::vector<igasg::Task> optask, fdtask, fdtask_lp;
+    std::vector<igasg::TaskMeta> gmeta, gmeta_lp;  // host copies of the per-grid task descriptions
     std::vector<double> ctrl;  // homogeneous control points, concatenated per patch
     int64_t ctrl_off[igasg::kMaxPatch] = {0, 0, 0, 0};
     int ncompG = 0;

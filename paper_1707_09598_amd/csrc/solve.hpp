@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1152,23 +1153,20 @@ template <> struct FdTypes<0> { using TU = double; using TC = double; };
 template <> struct FdTypes<1> { using TU = float; using TC = float; };
 template <> struct FdTypes<2> { using TU = uint16_t; using TC = float; };
 
-// Copy the description of task tk into an LDS slot (all threads; ends synchronised).
+// Copy the description of task tk into an LDS slot (all threads; ends
+// synchronised): one contiguous copy of the grid's record (grid and 1D tables),
+// the task's local index in the last word.
 __device__ __forceinline__ void meta_fill(const Params& P, const Task& tk, TaskMeta* M) {
     __syncthreads();
-    constexpr int GW = sizeof(Grid) / 8, TW = sizeof(Tab1D) / 8;
-    const uint64_t* gsrc = reinterpret_cast<const uint64_t*>(P.grids + tk.grid);
-    uint64_t* gdst = reinterpret_cast<uint64_t*>(&M->g);
-    for (int i = threadIdx.x; i < GW; i += kBlock) gdst[i] = gsrc[i];
-    if (threadIdx.x == 0) {
-        M->grid = tk.grid;
-        M->local = tk.local;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kMaxDim * TW; i += kBlock) {
-        const int k = i / TW, w = i % TW;
-        const int ti = M->g.tab[k];
-        uint64_t* tdst = reinterpret_cast<uint64_t*>(&M->t[k]);
-        tdst[w] = ti >= 0 ? reinterpret_cast<const uint64_t*>(P.tabs + ti)[w] : 0ull;
+    constexpr int MW = sizeof(TaskMeta) / 8;
+    static_assert(offsetof(TaskMeta, grid) == 8 * (MW - 1) && offsetof(TaskMeta, local) == 8 * MW - 4,
+                  "grid and local share the last word");
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(P.gmeta + tk.grid);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(M);
+    for (int i = threadIdx.x; i < MW; i += kBlock) {
+        uint64_t v = src[i];
+        if (i == MW - 1) v = static_cast<uint32_t>(tk.grid) | (static_cast<uint64_t>(static_cast<uint32_t>(tk.local)) << 32);
+        dst[i] = v;
     }
     __syncthreads();
 }
@@ -1237,6 +1235,7 @@ struct SolveArgs {
     double tol2, tol_in2;
     unsigned long long* trace;    // phase timestamps (or nullptr)
     int trace_sweeps;
+    int dyn;                      // tasks from the per-sweep active lists (else the launch's ranges)
 };
 
 // Phase tracing (10 ns wall clock): slot 0 kernel start; per sweep s the
@@ -1385,22 +1384,28 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
     const int lowp = FDP != 0;
     const bool wave0 = threadIdx.x < 64;
     if (A.trace && blockIdx.x == 0 && threadIdx.x == 0) A.trace[0] = wall_clock64();
-    // cache the descriptions of this workgroup's tasks
-    {
+    // Task schedule.  Static: workgroup w takes tasks w, w + nwg, ... of the
+    // launch's ranges, with the descriptions of its first tasks cached in LDS
+    // for the whole launch (a few tasks per workgroup).  Active lists (many
+    // tasks per workgroup): the same round robin over per-sweep lists that
+    // hold only the tasks of grids still iterating, rebuilt in phase 3.
+    // Which workgroup runs a task changes no result (partial sums go to the
+    // task's own slot).
+    if (!A.dyn) {
         int k = 0;
         for (int t = A.op_b + blockIdx.x; t < A.op_e && k < kMetaOp; t += nwg, ++k) meta_fill(P, P.optask[t], meta_op + k);
         k = 0;
         for (int t = A.fd_b + blockIdx.x; t < A.fd_e && k < kMetaFd; t += nwg, ++k) meta_fill(P, P.fdtask[t], meta_fd + k);
     }
-    auto op_meta = [&](int t, int k) -> const TaskMeta& {
-        if (k < kMetaOp) return meta_op[k];
-        meta_fill(P, P.optask[t], meta_sp);
+    auto task_meta = [&](const Task* list, int t, int k, TaskMeta* cache, int ncache) -> const TaskMeta& {
+        if (!A.dyn && k < ncache) return cache[k];
+        meta_fill(P, list[t], meta_sp);
         return *meta_sp;
     };
-    auto fd_meta = [&](int t, int k) -> const TaskMeta& {
-        if (k < kMetaFd) return meta_fd[k];
-        meta_fill(P, P.fdtask[t], meta_sp);
-        return *meta_sp;
+    // length of an active list (uniform: read through the first lane)
+    auto list_len = [&](int word) {
+        return static_cast<int>(__builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&P.bar[word], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
     };
     for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
         const int cur = sweep & 1, nxt = cur ^ 1;
@@ -1412,8 +1417,10 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         double* p_new = P.p2 + cur * N;
         double* p_old = P.p2 + nxt * N;
         // ---------------- phase 1: operator -------------------------------------
-        for (int t = A.op_b + blockIdx.x, k = 0; t < A.op_e; t += nwg, ++k) {
-            const TaskMeta& M = op_meta(t, k);
+        const Task* ol = A.dyn ? P.oplist + static_cast<int64_t>(cur) * P.op_cap : P.optask + A.op_b;
+        const int nop = A.dyn ? list_len(kBarOpLen + cur) : A.op_e - A.op_b;
+        for (int t = blockIdx.x, k = 0; t < nop; t += nwg, ++k) {
+            const TaskMeta& M = task_meta(ol, t, k, meta_op, kMetaOp);
             const Grid& g = M.g;
             __syncthreads();  // the previous task is done with the LDS context
             if (wave0) {
@@ -1463,8 +1470,15 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         trace_mark(A, sweep, 0);
         if (A.trace) tb = wall_clock64();
         // ---------------- phase 2: update + FD forward ---------------------------
-        for (int t = A.fd_b + blockIdx.x, k = 0; t < A.fd_e; t += nwg, ++k) {
-            const TaskMeta& M = fd_meta(t, k);
+        const Task* fl = A.dyn ? P.fdlist + static_cast<int64_t>(cur) * P.fd_cap : P.fdtask + A.fd_b;
+        const int nfd = A.dyn ? list_len(kBarFdLen + cur) : A.fd_e - A.fd_b;
+        if (A.dyn && blockIdx.x == 0 && threadIdx.x == 0) {
+            // the next sweep's lists (the previous sweep was their last reader)
+            __hip_atomic_store(&P.bar[kBarOpLen + nxt], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.bar[kBarFdLen + nxt], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        for (int t = blockIdx.x, k = 0; t < nfd; t += nwg, ++k) {
+            const TaskMeta& M = task_meta(fl, t, k, meta_fd, kMetaFd);
             const Grid& g = M.g;
             __syncthreads();
             CtxLoads c;
@@ -1533,8 +1547,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         trace_mark(A, sweep, 1);
         if (A.trace) tb = wall_clock64();
         // ---------------- phase 3: FD backward and commit ---------------------------
-        for (int t = A.fd_b + blockIdx.x, k = 0; t < A.fd_e; t += nwg, ++k) {
-            const TaskMeta& M = fd_meta(t, k);
+        for (int t = blockIdx.x, k = 0; t < nfd; t += nwg, ++k) {
+            const TaskMeta& M = task_meta(fl, t, k, meta_fd, kMetaFd);
             const Grid& g = M.g;
             const int gi = M.grid;
             __syncthreads();
@@ -1607,7 +1621,17 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                     finish = true;
                 }
                 S1[gi] = ns;
-                if (finish) atomicAdd(&P.bar[kBarDone], 1u);
+                if (finish) {
+                    atomicAdd(&P.bar[kBarDone], 1u);
+                } else if (A.dyn) {
+                    // the grid keeps iterating: its tasks go on the next sweep's lists
+                    const unsigned o = atomicAdd(&P.bar[kBarOpLen + nxt], static_cast<unsigned>(g.ntile));
+                    Task* on = P.oplist + static_cast<int64_t>(nxt) * P.op_cap + o;
+                    for (int l = 0; l < g.ntile; ++l) on[l] = Task{gi, l};
+                    const unsigned f = atomicAdd(&P.bar[kBarFdLen + nxt], static_cast<unsigned>(g.nblk));
+                    Task* fn = P.fdlist + static_cast<int64_t>(nxt) * P.fd_cap + f;
+                    for (int l = 0; l < g.nblk; ++l) fn[l] = Task{gi, l};
+                }
             }
         }
         trace_busy(A, sweep, 2, tb);

@@ -62,3 +62,36 @@ def test_batched_samples_equal_single_sample_solves(S, precision):
         c = P.ncomp // 2
         assert np.array_equal(P.eval(c, xi).cpu().numpy(), B.eval(s * B.ncomp + c, xi).cpu().numpy())
     log(f"  {ns} samples x {B.ncomp} grids: iterations {int(rep['total_iters'])}")
+
+
+@pytest.mark.parametrize("name,precision,ns", [("cfg5", "fp64", 6), ("cfg5", "fp32", 6), ("cfg2", "fp32", 1)])
+def test_static_and_dynamic_schedules_agree_bitwise(S, name, precision, ns):
+    """The persistent solve's two task schedules (round robin over the launch's
+    tasks; round robin over per-sweep lists of the grids still iterating) give
+    the same coefficients, iteration counts and statuses bit for bit: each
+    task writes its own partial sums in a fixed order."""
+    import torch
+    w = 4 if name == "cfg5" else 7
+    log(f"case schedules {name} w={w} samples={ns} {precision}")
+    if name == "cfg5":
+        fields = W.grf_samples(ns, n=24)
+        P = S.Plan(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[0])), nsamples=ns)
+        P.bind()
+        P.assemble(a=W._field("grid3d", data=torch.as_tensor(fields, device="cuda")))
+    else:
+        P = S.Plan(W.config(name, w=w))
+        P.bind()
+        P.assemble()
+    kw = dict(precision=precision, tol=1e-11, maxit=400, max_refine=3 if precision == "fp64" else 8,
+              continue_cg=precision != "fp64")
+    out = {}
+    for sched in ("static", "lists"):
+        rep = P.solve(schedule=sched, **kw)
+        assert np.all(rep["status"] == 0), sched
+        out[sched] = (rep, [P.coeffs(c).cpu().numpy() for c in range(P.ninst)])
+    (ra, xa), (rb, xb) = out["static"], out["lists"]
+    assert np.array_equal(ra["iters"], rb["iters"])
+    assert np.array_equal(ra["refinements"], rb["refinements"])
+    assert np.array_equal(ra["relres"], rb["relres"])
+    for c in range(P.ninst):
+        assert np.array_equal(xa[c], xb[c]), c

@@ -103,7 +103,7 @@ def test_call_order_state_errors(S):
     f = S._Field()
     f.kind = 0
     assert L.iga_sg_assemble(P.h, C.byref(f), C.byref(f), None) == 7
-    o = S._Opts(0, 1, 1e-12, 1e-4, 100, 0, 0, 0, 0, 0, 0, 0)
+    o = S._Opts(0, 1, 1e-12, 1e-4, 100, 0, 0, 0, 0, 0, 0, 0, 0)
     assert L.iga_sg_solve(P.h, C.byref(o), None) == 7
     assert L.iga_sg_combine(P.h, C.c_void_p(8), None, 1, C.c_void_p(8)) == 7
     assert b"before" in L.iga_sg_last_error()
