@@ -41,8 +41,8 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "354cc7f454a888e7f21867c52c20cffe7de32d3c61444e474fba71241c1e9b57",
-    "fetch_kib": 1223714.3, "write_kib": 207001.4,
+    "sha256": "b9de56a84aa649fccef3035aca11af9effc9e3eff0e036aed877beaaa6ec4b5f",
+    "fetch_kib": 1128846.1, "write_kib": 325252.5,
     "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
 }
 
@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="pick the launch shape of each mode with the autotuner first (its timing runs "
                          "add solve dispatches of other shapes to a profile of the run)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the unit-square (modes A/B) and unit-cube (modes B/C) measurements")
     ap.add_argument("--batch-samples", type=int, default=64,
                     help="coefficient samples of the random-field cube solved in one launch (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -121,6 +123,19 @@ def algorithmic_bytes(P, rep, precision):
         total += it * (ncompG * nqp * bop_in + fd_u * bu + 80 * ndof)
         total += rf * (ncompG * nqp * 8 + fd_u * bu + 80 * ndof)
     return float(total)
+
+
+def assembly_bytes(P):
+    """Bytes the assembly must write: per Gauss point the operator
+    coefficients in FP64 and FP32 and the FP64 load density, per unknown the
+    load vector, the preconditioner scaling and log a (FP64); the coefficient
+    field and the 1D tables are read on top."""
+    wl = P.wl
+    rational = any(pt.get("weights") is not None for pt in wl["patches"])
+    ncompG = {(2, False): 3, (2, True): 6, (3, False): 6, (3, True): 10}[(int(wl["dim"]), rational)]
+    p = int(wl["p"])
+    nqp = sum(int(np.prod([2 ** int(l) * (p + 1) for l in lv])) for lv in P.levels) * P.nsamples
+    return float(nqp * (12 * ncompG + 8) + int(P.ndof.sum()) * P.nsamples * 24)
 
 
 def run_mode(S, W, torch, precision, args, xi):
@@ -264,20 +279,25 @@ def run_batched(S, W, torch, args, O):
     """The random-field cube at full size (w=7, a = exp(GRF) on a 64^3 grid)
     with batch_samples coefficient samples in one plan and one persistent
     launch: assembly + solve timed by HIP events, FP64 (B) and mixed (C)."""
+    from paper_1707_09598_amd import tune
     ns = args.batch_samples
     fields = W.grf_samples(ns, n=64)
     wl = W.config("cfg5", a=W._field("grid3d", data=fields[0]))
-    P = S.Plan(wl, nsamples=ns)
-    P.bind(device="cuda:0")
     a_all = W._field("grid3d", data=torch.as_tensor(fields, device="cuda:0"))
-    ndof = int(P.ndof.sum()) * ns
-    out = {"workload": f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), f = 1, "
-                       f"p=3 C^2, w=7, {ns} samples x 85 grids in one launch, {ndof} unknowns, tol 1e-10",
-           "samples": ns, "unknowns": ndof}
+    out = {"samples": ns}
     ref = None
     for key, kw in (("B_fp64", dict(precision="fp64", max_refine=3)),
                     ("C_mixed", dict(precision="fp32", max_refine=12, continue_cg=True))):
         kw = dict(kw, tol=1e-10, tol_inner=args.tol_inner, maxit=600)
+        # operator tile picked by the autotuner for this batch and mode
+        tuned = tune.autotune(wl, kw, shapes=[{"op_tile3": t} for t in (256, 512, 1024)], repeats=2,
+                              nsamples=ns, fields={"a": a_all})
+        P = S.Plan(wl, nsamples=ns, shape=tuned["shape"])
+        P.bind(device="cuda:0")
+        ndof = int(P.ndof.sum()) * ns
+        out["workload"] = (f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), "
+                           f"f = 1, p=3 C^2, w=7, {ns} samples x 85 grids in one launch, {ndof} unknowns, tol 1e-10")
+        out["unknowns"] = ndof
         P.assemble(a=a_all)
         rep = P.solve(check=False, **kw)
         ms = []
@@ -297,7 +317,16 @@ def run_batched(S, W, torch, args, O):
             xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
             ref = (xi3, Po.sg_eval(Po.solve_all(), xi3))
         u = P.combine(ref[0])[0].cpu().numpy()
+        # assembly: operator coefficients (FP64 and FP32), load density, load
+        # vector, preconditioner scaling and log a written once, the field read once
+        asm_bytes = assembly_bytes(P) + fields.nbytes
         out[key] = {"dof_per_s": ndof / ((t_asm + t_sol) / 1e3), "ms_assemble": t_asm, "ms_solve": t_sol,
+                    "launch_shape": tuned["shape"],
+                    "autotune_ms": {str(t["shape"]["op_tile3"]): round(t["ms"], 3) for t in tuned["tried"]},
+                    "assembly_roofline": {"bound": "hbm", "achieved": asm_bytes / (t_asm / 1e3) / 1e9,
+                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": asm_bytes / (t_asm / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                          "algorithmic_bytes": asm_bytes},
                     "codes": int(rep["code"]), "cg_iterations": int(rep["total_iters"]),
                     "rel_l2_vs_oracle_sample0": float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1])),
                     "solve_roofline": {"bound": "hbm", "achieved": algo / (t_sol / 1e3) / 1e9,
@@ -305,6 +334,65 @@ def run_batched(S, W, torch, args, O):
                                        "frac": algo / (t_sol / 1e3) / 1e9 / HBM_PEAK_GBS,
                                        "algorithmic_bytes_per_launch": algo}}
     out["speedup_C_vs_B"] = out["C_mixed"]["dof_per_s"] / out["B_fp64"]["dof_per_s"]
+    return out
+
+
+def run_small_configs(S, W, torch, O):
+    """The two other single-patch workloads, each at its full size, measured
+    the same way (assembly + solve, HIP events on the plan's stream, median of
+    five runs after one untimed run) and checked against the oracle at 32768
+    seeded points:
+      cfg1  unit square, p=2 C^1, w=6, FP64 to 1e-12: mode A (one component
+            grid per launch) against mode B (all grids in one launch);
+      cfg3  unit cube, p=3 C^2, w=8, lmin=1: mode B (FP64) against mode C
+            (BF16 fast-diagonalisation factors, FP32 operator, FP64
+            refinement), each with the operator tile picked by the autotuner."""
+    from paper_1707_09598_amd import tune
+    out = {}
+    specs = {
+        "cfg1": ("unit square, identity map, u = sin(pi x) sin(pi y), p=2 C^1, w=6, 13 grids, tol 1e-12",
+                 [("A_fp64_per_grid", dict(precision="fp64", batched=False, tol=1e-12, max_refine=3)),
+                  ("B_fp64_batched", dict(precision="fp64", batched=True, tol=1e-12, max_refine=3))], False),
+        "cfg3": ("unit cube, identity map, u = prod sin(pi x_k), p=3 C^2, w=8, lmin=1, 46 grids, tol 1e-10",
+                 [("B_fp64", dict(precision="fp64", tol=1e-10, max_refine=3)),
+                  ("C_bf16fd", dict(precision="bf16fd", tol=1e-10, tol_inner=1e-2, max_refine=16,
+                                    continue_cg=True))], True),
+    }
+    for name, (desc, modes, tuned) in specs.items():
+        wl = W.config(name)
+        Po = O.Problem(wl)
+        xi, _ = W.eval_points(wl["dim"], 32768, lattice=0, seed=777)
+        u_ref = Po.sg_eval(Po.solve_all(), xi)
+        res = {"workload": f"{name}: {desc}"}
+        for key, kw in modes:
+            kw = dict(kw, maxit=600)
+            shape = {}
+            if tuned:
+                shape = tune.autotune(wl, kw, repeats=3)["shape"]
+            P = S.Plan(wl, shape=shape)
+            P.bind(device="cuda:0")
+            P.assemble()
+            rep = P.solve(check=False, **kw)
+            ms = []
+            for _ in range(5):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(P.stream)
+                P.assemble()
+                P.solve_async(**kw)
+                ev[1].record(P.stream)
+                torch.cuda.synchronize()
+                ms.append(ev[0].elapsed_time(ev[1]))
+            t = float(np.median(ms))
+            u = P.combine(xi).cpu().numpy()
+            ndof = int(P.ndof.sum())
+            res[key] = {"dof_per_s": ndof / (t / 1e3), "ms_assemble_solve": t, "unknowns": ndof,
+                        "codes": int(rep["code"]), "cg_iterations": int(rep["total_iters"]),
+                        "rel_l2_vs_oracle": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
+                        "launch_shape": shape or "library default"}
+        keys = [k for k, _ in modes]
+        res[f"speedup_{keys[1].split('_')[0]}_vs_{keys[0].split('_')[0]}"] = (
+            res[keys[1]]["dof_per_s"] / res[keys[0]]["dof_per_s"])
+        out[name] = res
     return out
 
 
@@ -446,6 +534,8 @@ def main():
         line["batched_cfg5"] = run_batched(S, W, torch, args, O)
     if not args.no_learned:
         line["learned_cfg5"] = run_learned(S, W, torch, args, O)
+    if not args.no_small:
+        line.update(run_small_configs(S, W, torch, O))
     print(json.dumps(line), flush=True)
 
 

@@ -17,7 +17,7 @@ import numpy as np
 from . import IgaError, Plan
 
 OP_TILE_2D = (64, 96, 128, 192, 256)
-OP_TILE_3D = (128, 256, 512)
+OP_TILE_3D = (128, 256, 512, 1024)
 FD_TASKS = (256, 1 << 20)
 
 
