@@ -398,24 +398,36 @@ struct ElemShape {
     static constexpr int LPL = (NLOC + 63) / 64;                               // local functions per lane
 };
 
+// The Gauss-point sums are evaluated by sum factorisation: with f_u f_v a
+// product of one 1D factor per direction (B B, B D or D D of the local
+// function's 1D value B and derivative D, by whether u and v differentiate in
+// that direction; a single B for the load), each coefficient's sum over the
+// element's NQ^d points is d successive contractions over one direction,
+//   T_k(a_0..a_k, q_{k+1}..) = sum_j W_k(a_k, j) T_{k-1}(a_0..a_{k-1}, j, q_{k+1}..),
+// NQ multiply-adds per coefficient and stage for each lane, the stages
+// exchanged through LDS.  Position pos of a lane group is the tensor index
+// with direction 0 fastest (local function index after the last stage).
 template <int DIM, int PP, bool RAT>
 __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
     using SH = ElemShape<DIM, PP>;
     constexpr int NQ = SH::NQ, NLOC = SH::NLOC, NLP = SH::NLP, EPW = SH::EPW, LPL = SH::LPL;
-    constexpr int NE = DIM + (RAT ? 1 : 0);      // entries of f
+    constexpr int NE = DIM + (RAT ? 1 : 0);      // entries of f: (value,) d/dxi_0, ..
     constexpr int NC = NE * (NE + 1) / 2;        // stored coefficients per Gauss point
-    constexpr int NCP = (NC + 2) & ~1;           // + load density, padded to 16 bytes
+    constexpr int NT = NC + 1;                   // + load density
     constexpr int WAVES = kBlock / 64;
-    __shared__ double sh[WAVES][EPW][NLOC][NCP];
+    __shared__ double sh[WAVES][EPW][NLOC][NT];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slot = lane / NLP, la = lane % NLP;
     const int64_t nelem = P.nelem;
+    // 1D factor of entry e in direction k: derivative when e differentiates in k
+    auto is_d = [](int e, int k) { return RAT ? e == k + 1 : e == k; };
     for (int64_t blk0 = static_cast<int64_t>(blockIdx.x) * WAVES * EPW; blk0 < nelem;
          blk0 += static_cast<int64_t>(gridDim.x) * WAVES * EPW) {
         const int64_t el = blk0 + wave * EPW + slot;
         const bool live = el < nelem;
         int gi = 0, ek[3] = {0, 0, 0};
-        int64_t qbase = 0, nqp = 0;
+        double Bv[LPL][DIM][NQ], Dv[LPL][DIM][NQ];
+        double (*T)[NT] = sh[wave][slot];
         if (live) {
             gi = grid_of_qp(P, 0, P.ngrid, el * NLOC);
             const Grid& g = P.grids[gi];
@@ -425,17 +437,16 @@ __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
                 ek[k] = static_cast<int>(r % g.E[k]);
                 r /= g.E[k];
             }
-            nqp = g.nqp;
-            qbase = g.qp_off + ek[0] * NQ + static_cast<int64_t>(g.Q[0]) *
-                                                (ek[1] * NQ + (DIM > 2 ? static_cast<int64_t>(g.Q[1]) * ek[2] * NQ : 0));
-            // stage the element's coefficients: lane la copies Gauss point la
-            // (and la + 64 ... when the element has more than 64)
+            const int64_t nqp = g.nqp;
+            const int64_t qbase = g.qp_off + ek[0] * NQ + static_cast<int64_t>(g.Q[0]) *
+                                      (ek[1] * NQ + (DIM > 2 ? static_cast<int64_t>(g.Q[1]) * ek[2] * NQ : 0));
 #pragma unroll
             for (int s = 0; s < LPL; ++s) {
-                const int q = la + 64 * s;
-                if (q < NLOC) {
-                    const int j0 = q % NQ, j1 = (q / NQ) % NQ, j2 = DIM > 2 ? q / (NQ * NQ) : 0;
-                    const int64_t lq = qbase + j0 + static_cast<int64_t>(g.Q[0]) * (j1 + static_cast<int64_t>(g.Q[1]) * j2);
+                const int pos = la + 64 * s;
+                if (pos < NLOC) {
+                    const int dg[3] = {pos % NQ, (pos / NQ) % NQ, DIM > 2 ? pos / (NQ * NQ) : 0};
+                    // stage Gauss point pos of the element (off-diagonal coefficients doubled)
+                    const int64_t lq = qbase + dg[0] + static_cast<int64_t>(g.Q[0]) * (dg[1] + static_cast<int64_t>(g.Q[1]) * dg[2]);
                     const double* G = P.G64 + g.qp_off * NC + (lq - g.qp_off);
                     int c = 0;
 #pragma unroll
@@ -443,67 +454,72 @@ __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
 #pragma unroll
                         for (int v = u; v < NE; ++v, ++c) {
                             const double gv = G[c * nqp];
-                            sh[wave][slot][q][c] = u == v ? gv : 2.0 * gv;
+                            T[pos][c] = u == v ? gv : 2.0 * gv;
                         }
-                    sh[wave][slot][q][NC] = P.Fq[lq];
-                }
-            }
-        }
-        __syncthreads();
-        if (live) {
-            const Grid& g = P.grids[gi];
-#pragma unroll
-            for (int s = 0; s < LPL; ++s) {
-                const int a = la + 64 * s;
-                if (a < NLOC) {
-                    const int ak[3] = {a % NQ, (a / NQ) % NQ, DIM > 2 ? a / (NQ * NQ) : 0};
-                    double Bv[DIM][NQ], Dv[DIM][NQ];
+                    T[pos][NC] = P.Fq[lq];
+                    // 1D values of local function dg[k] of direction k at the element's points
 #pragma unroll
                     for (int k = 0; k < DIM; ++k) {
-                        const Tab1D& T = P.tabs[g.tab[k]];
+                        const Tab1D& Tb = P.tabs[g.tab[k]];
 #pragma unroll
                         for (int j = 0; j < NQ; ++j) {
-                            const int64_t t = static_cast<int64_t>(ek[k] * NQ + j) * NQ + ak[k];
-                            Bv[k][j] = P.dpool[T.oB + t];
-                            Dv[k][j] = P.dpool[T.oD + t];
+                            const int64_t t = static_cast<int64_t>(ek[k] * NQ + j) * NQ + dg[k];
+                            Bv[s][k][j] = P.dpool[Tb.oB + t];
+                            Dv[s][k][j] = P.dpool[Tb.oD + t];
                         }
                     }
-                    double dl = 0.0, bl = 0.0;
-#pragma unroll
-                    for (int j2 = 0; j2 < (DIM > 2 ? NQ : 1); ++j2)
-#pragma unroll
-                        for (int j1 = 0; j1 < NQ; ++j1) {
-                            // products of the other directions' factors
-                            const double b12 = DIM > 2 ? Bv[1][j1] * Bv[2][j2] : Bv[1][j1];
-                            const double d1b2 = DIM > 2 ? Dv[1][j1] * Bv[2][j2] : Dv[1][j1];
-                            const double b1d2 = DIM > 2 ? Bv[1][j1] * Dv[2][j2] : 0.0;
-#pragma unroll
-                            for (int j0 = 0; j0 < NQ; ++j0) {
-                                const double* c = sh[wave][slot][j0 + NQ * (j1 + NQ * j2)];
-                                double f[NE];
-                                int u = 0;
-                                const double val = Bv[0][j0] * b12;
-                                if (RAT) f[u++] = val;
-                                f[u++] = Dv[0][j0] * b12;
-                                f[u++] = Bv[0][j0] * d1b2;
-                                if (DIM > 2) f[u++] = Bv[0][j0] * b1d2;
-                                int ci = 0;
-#pragma unroll
-                                for (int x = 0; x < NE; ++x) {
-                                    double t = 0.0;
-#pragma unroll
-                                    for (int y = x; y < NE; ++y, ++ci) t += c[ci] * f[y];
-                                    dl += f[x] * t;
-                                }
-                                bl += c[NC] * val;
-                            }
-                        }
-                    P.loc[static_cast<int64_t>(a) * nelem + el] = dl;
-                    P.loc[static_cast<int64_t>(NLOC + a) * nelem + el] = bl;
                 }
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            __syncthreads();  // the previous stage's values are in LDS
+            double out[LPL][NT];
+            if (live) {
+#pragma unroll
+                for (int s = 0; s < LPL; ++s) {
+                    const int pos = la + 64 * s;
+                    if (pos < NLOC) {
+                        constexpr int st[3] = {1, NQ, NQ * NQ};
+                        const int base = pos - ((pos / st[k]) % NQ) * st[k];  // digit k cleared
+#pragma unroll
+                        for (int c = 0; c < NT; ++c) out[s][c] = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NQ; ++j) {
+                            const double* in = T[base + j * st[k]];
+                            const double b = Bv[s][k][j], dv = Dv[s][k][j];
+                            const double w[3] = {b * b, b * dv, dv * dv};
+                            int c = 0;
+#pragma unroll
+                            for (int u = 0; u < NE; ++u)
+#pragma unroll
+                                for (int v = u; v < NE; ++v, ++c) out[s][c] += w[is_d(u, k) + is_d(v, k)] * in[c];
+                            out[s][NC] += b * in[NC];
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // every lane has read this stage's inputs
+            if (live) {
+#pragma unroll
+                for (int s = 0; s < LPL; ++s) {
+                    const int pos = la + 64 * s;
+                    if (pos < NLOC) {
+                        if (k + 1 < DIM) {
+#pragma unroll
+                            for (int c = 0; c < NT; ++c) T[pos][c] = out[s][c];
+                        } else {
+                            double dl = 0.0;
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) dl += out[s][c];
+                            P.loc[static_cast<int64_t>(pos) * nelem + el] = dl;
+                            P.loc[static_cast<int64_t>(NLOC + pos) * nelem + el] = out[s][NC];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // LDS free for the next elements
     }
 }
 
