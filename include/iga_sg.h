@@ -102,6 +102,11 @@ typedef struct {
      * are kept in one block when LDS allows (default 256, the MI355X CU
      * count); the autotuner (tune.py) searches these */
     int op_tile, op_tile3, fd_tasks;
+    /* nonzero: instead of the combination technique, the single full
+     * tensor-product grid with level w in every direction (standard IGA at the
+     * finest level of the sparse grid, the paper's comparison in Sec. 4);
+     * combination coefficient 1, lmin ignored */
+    int full;
 } iga_sg_disc;
 
 /* Fields (right-hand side f, coefficient a, Dirichlet data g). */

@@ -59,7 +59,8 @@ class _Geometry(C.Structure):
 
 class _Disc(C.Structure):
     _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int),
-                ("nsamples", C.c_int), ("op_tile", C.c_int), ("op_tile3", C.c_int), ("fd_tasks", C.c_int)]
+                ("nsamples", C.c_int), ("op_tile", C.c_int), ("op_tile3", C.c_int), ("fd_tasks", C.c_int),
+                ("full", C.c_int)]
 
 
 class _Field(C.Structure):
@@ -163,9 +164,12 @@ class Plan:
     sample s is instance s * ncomp + c, combine returns [nsamples, n].
     ``shape`` sets the launch shape: {"op_tile", "op_tile3", "fd_tasks"}
     (missing or 0: library default; see ``tune.autotune``).
+    ``full`` plans the single full tensor-product grid at level w in every
+    direction (standard IGA) instead of the combination technique.
     """
 
-    def __init__(self, wl: Dict[str, Any], nsamples: int = 1, shape: Optional[Dict[str, int]] = None):
+    def __init__(self, wl: Dict[str, Any], nsamples: int = 1, shape: Optional[Dict[str, int]] = None,
+                 full: bool = False):
         self.wl = wl
         self.dim = d = int(wl["dim"])
         self._keep = []
@@ -203,7 +207,7 @@ class Plan:
         self.shape = dict(shape or {})
         D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0, self.nsamples,
                   int(self.shape.get("op_tile", 0)), int(self.shape.get("op_tile3", 0)),
-                  int(self.shape.get("fd_tasks", 0)))
+                  int(self.shape.get("fd_tasks", 0)), int(full))
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h

@@ -339,7 +339,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     }
     // ---- components (eq. TD-combi-tec), lexicographic, level 1 slowest ----
     const int J = P->w - d * P->lmin;
-    {
+    if (disc->full) {
+        // the full tensor-product space at level w in every direction
+        // (standard IGA, the comparison of Sec. 4): one grid, coefficient 1
+        for (int k = 0; k < d; ++k) P->comp_levels.push_back(P->w);
+        P->comp_coef.push_back(1.0);
+    } else {
         int b[3] = {0, 0, 0};
         int lim1 = d > 1 ? J : 0, lim2 = d > 2 ? J : 0;
         for (b[0] = 0; b[0] <= J; ++b[0])
