@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "b9de56a84aa649fccef3035aca11af9effc9e3eff0e036aed877beaaa6ec4b5f",
-    "fetch_kib": 1128846.1, "write_kib": 325252.5,
-    "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
+    "sha256": "9bbf26fdb6401a748d0c427ca54b0023c94170e7aeeb6498b983198435724373",
+    "fetch_kib": 1128805.0, "write_kib": 325254.1,
+    "fetch_factor": 262144.0 / 131088.1, "write_factor": 262144.0 / 262144.0,
 }
 
 
@@ -89,6 +89,8 @@ def parse():
                     help="skip the unit-square (modes A/B) and unit-cube (modes B/C) measurements")
     ap.add_argument("--batch-samples", type=int, default=64,
                     help="coefficient samples of the random-field cube solved in one launch (0: skip)")
+    ap.add_argument("--batch-tile", type=int, default=0,
+                    help="3D operator tile (unknowns) of the random-field batch; 0: autotuned")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -199,7 +201,7 @@ def run_mode(S, W, torch, precision, args, xi):
     }
 
 
-def run_learned(S, W, torch, args, O):
+def run_learned(S, W, torch, args, ref):
     """Modes B (FP64 FD-PCG), C (mixed precision) and D (C with the learned
     correction inside flexible CG) on held-out samples of the random-field
     cube, after training the network with the library's kernels on pairs from
@@ -236,7 +238,6 @@ def run_learned(S, W, torch, args, O):
              "D_mixed_learned_first10": dict(precision="fp32", learned=True, learned_iters=10, max_refine=12,
                                              continue_cg=True)}
     res = {k: {"ms": [], "iterations": [], "codes": []} for k in modes}
-    ref = None
     ndof = 0
     for s in range(ntr, ntr + nte):
         P = plan_for(fields[s])
@@ -255,12 +256,8 @@ def run_learned(S, W, torch, args, O):
             res[k]["ms"].append(ev[0].elapsed_time(ev[1]))
             res[k]["iterations"].append(int(rep["total_iters"]))
             res[k]["codes"].append(int(rep["code"]))
-            if s == ntr:
+            if s == ntr and ref is not None:
                 # accuracy of each mode against the oracle on the first held-out sample
-                if ref is None:
-                    Po = O.Problem(P.wl)
-                    xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
-                    ref = (xi3, Po.sg_eval(Po.solve_all(), xi3))
                 u = P.combine(ref[0]).cpu().numpy()
                 res[k]["rel_l2_vs_oracle"] = float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1]))
     out = {"workload": f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), "
@@ -275,7 +272,7 @@ def run_learned(S, W, torch, args, O):
     return out
 
 
-def run_batched(S, W, torch, args, O):
+def run_batched(S, W, torch, args, ref):
     """The random-field cube at full size (w=7, a = exp(GRF) on a 64^3 grid)
     with batch_samples coefficient samples in one plan and one persistent
     launch: assembly + solve timed by HIP events, FP64 (B) and mixed (C)."""
@@ -285,13 +282,15 @@ def run_batched(S, W, torch, args, O):
     wl = W.config("cfg5", a=W._field("grid3d", data=fields[0]))
     a_all = W._field("grid3d", data=torch.as_tensor(fields, device="cuda:0"))
     out = {"samples": ns}
-    ref = None
     for key, kw in (("B_fp64", dict(precision="fp64", max_refine=3)),
                     ("C_mixed", dict(precision="fp32", max_refine=12, continue_cg=True))):
         kw = dict(kw, tol=1e-10, tol_inner=args.tol_inner, maxit=600)
-        # operator tile picked by the autotuner for this batch and mode
-        tuned = tune.autotune(wl, kw, shapes=[{"op_tile3": t} for t in (256, 512, 1024)], repeats=2,
-                              nsamples=ns, fields={"a": a_all})
+        # operator tile picked by the autotuner for this batch and mode (or given)
+        if args.batch_tile > 0:
+            tuned = {"shape": {"op_tile3": args.batch_tile}, "tried": []}
+        else:
+            tuned = tune.autotune(wl, kw, shapes=[{"op_tile3": t} for t in (256, 512, 1024)], repeats=2,
+                                  nsamples=ns, fields={"a": a_all})
         P = S.Plan(wl, nsamples=ns, shape=tuned["shape"])
         P.bind(device="cuda:0")
         ndof = int(P.ndof.sum()) * ns
@@ -312,10 +311,6 @@ def run_batched(S, W, torch, args, O):
             ms.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
         t_asm, t_sol = float(np.median([m[0] for m in ms])), float(np.median([m[1] for m in ms]))
         algo = algorithmic_bytes(P, rep, kw["precision"])
-        if ref is None:
-            Po = O.Problem(W.config("cfg5", a=W._field("grid3d", data=fields[0])))
-            xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
-            ref = (xi3, Po.sg_eval(Po.solve_all(), xi3))
         u = P.combine(ref[0])[0].cpu().numpy()
         # assembly: operator coefficients (FP64 and FP32), load density, load
         # vector, preconditioner scaling and log a written once, the field read once
@@ -337,7 +332,7 @@ def run_batched(S, W, torch, args, O):
     return out
 
 
-def run_small_configs(S, W, torch, O):
+def run_small_configs(S, W, torch, refs):
     """The two other single-patch workloads, each at its full size, measured
     the same way (assembly + solve, HIP events on the plan's stream, median of
     five runs after one untimed run) and checked against the oracle at 32768
@@ -360,9 +355,7 @@ def run_small_configs(S, W, torch, O):
     }
     for name, (desc, modes, tuned) in specs.items():
         wl = W.config(name)
-        Po = O.Problem(wl)
-        xi, _ = W.eval_points(wl["dim"], 32768, lattice=0, seed=777)
-        u_ref = Po.sg_eval(Po.solve_all(), xi)
+        xi, u_ref = refs[name]
         res = {"workload": f"{name}: {desc}"}
         for key, kw in modes:
             kw = dict(kw, maxit=600)
@@ -394,6 +387,41 @@ def run_small_configs(S, W, torch, O):
             res[keys[1]]["dof_per_s"] / res[keys[0]]["dof_per_s"])
         out[name] = res
     return out
+
+
+def cpu_baseline_leg(args, W, xi, sub):
+    """The CPU side of the benchmark, the only part that runs the oracle: its
+    timing on the annulus workload (unless --no-cpu-baseline) and the
+    reference values every accuracy figure of the line compares against
+    (oracle direct solves of the same workloads and samples, evaluated at the
+    points the GPU legs evaluate)."""
+    import oracle as O
+    if not args.no_cpu_baseline:
+        cpu, coefs, Po = cpu_baseline(O, W, xi, args.cpu_seconds)
+    else:
+        cpu = None
+        Po = O.Problem(W.config("cfg2"))
+        coefs = Po.solve_all()
+    refs = {"cfg2": Po.sg_eval(coefs, xi[sub])}
+
+    def cube_ref(a):
+        P = O.Problem(W.config("cfg5", a=W._field("grid3d", data=a)))
+        xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
+        return xi3, P.sg_eval(P.solve_all(), xi3)
+
+    # random-field samples are seeded by their index: sample 0 of the batch,
+    # the first held-out sample of the learned comparison
+    if args.batch_samples > 0:
+        refs["cfg5_batch"] = cube_ref(W.grf_samples(1, n=64)[0])
+    if not args.no_learned:
+        refs["cfg5_learned"] = cube_ref(W.grf_samples(args.learned_train + 1, n=64)[args.learned_train])
+    if not args.no_small:
+        for name in ("cfg1", "cfg3"):
+            wl = W.config(name)
+            P = O.Problem(wl)
+            xi_n, _ = W.eval_points(wl["dim"], 32768, lattice=0, seed=777)
+            refs[name] = (xi_n, P.sg_eval(P.solve_all(), xi_n))
+    return cpu, refs
 
 
 def cpu_baseline(O, W, xi, seconds):
@@ -456,15 +484,9 @@ def main():
         fp64_run = run_mode(S, W, torch, "fp64", args, xi)
 
     # accuracy against the oracle at the evaluation points
-    import oracle as O
-    if not args.no_cpu_baseline:
-        cpu, coefs, Po = cpu_baseline(O, W, xi, args.cpu_seconds)
-    else:
-        cpu = None
-        Po = O.Problem(W.config("cfg2"))
-        coefs = Po.solve_all()
     sub = np.random.default_rng(1).choice(len(xi), size=min(len(xi), 65536), replace=False)
-    u_ref = Po.sg_eval(coefs, xi[sub])
+    cpu, refs = cpu_baseline_leg(args, W, xi, sub)
+    u_ref = refs["cfg2"]
     err = float(np.linalg.norm(main_run["u"][sub] - u_ref) / np.linalg.norm(u_ref))
     err64 = None
     if fp64_run is not None:
@@ -531,11 +553,11 @@ def main():
         cpu.pop("combine_ms_scaled", None)
         line["cpu_baseline"] = cpu
     if args.batch_samples > 0:
-        line["batched_cfg5"] = run_batched(S, W, torch, args, O)
+        line["batched_cfg5"] = run_batched(S, W, torch, args, refs["cfg5_batch"])
     if not args.no_learned:
-        line["learned_cfg5"] = run_learned(S, W, torch, args, O)
+        line["learned_cfg5"] = run_learned(S, W, torch, args, refs["cfg5_learned"])
     if not args.no_small:
-        line.update(run_small_configs(S, W, torch, O))
+        line.update(run_small_configs(S, W, torch, refs))
     print(json.dumps(line), flush=True)
 
 
