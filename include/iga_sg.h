@@ -276,6 +276,25 @@ iga_status iga_sg_fd_factor(iga_sg_plan plan, int dir, int lev, int* n, double* 
 iga_status iga_sg_matrices_1d(iga_sg_plan plan, int dir, int lev, int* n, double* K_host,
                               double* M_host);
 
+/* One step as a HIP graph: iga_sg_graph_capture records iga_sg_assemble(f,
+ * a, no Dirichlet data) followed by iga_sg_solve(opts, no report) on the
+ * plan's stream into a graph (the persistent solve as a cooperative kernel
+ * node, so all its workgroups are resident as in the direct launch) and
+ * instantiates it; iga_sg_graph_launch replays it on the plan's stream.  A
+ * replay computes exactly what the two calls compute.  The fields' device
+ * data must stay valid and unchanged in place for as long as the graph is
+ * replayed (their values may change between replays).  opts.timing must be 0,
+ * and the plan must be bound to a created stream (the legacy default stream
+ * cannot be captured: IGA_ERR_STATE).
+ * The instantiated graph (runtime-owned resources) is released by the next
+ * capture or by iga_sg_destroy.  Errors: IGA_ERR_STATE before iga_sg_bind or
+ * a launch before a capture; the errors of iga_sg_assemble / iga_sg_solve;
+ * IGA_ERR_DEVICE when the runtime cannot build the graph (the stream is left
+ * out of capture mode either way). */
+iga_status iga_sg_graph_capture(iga_sg_plan plan, const iga_field* f, const iga_field* a,
+                                const iga_sg_solve_opts* opts);
+iga_status iga_sg_graph_launch(iga_sg_plan plan);
+
 void iga_sg_destroy(iga_sg_plan plan);
 const char* iga_sg_last_error(void);
 /* Library version string. */

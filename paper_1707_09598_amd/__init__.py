@@ -29,7 +29,8 @@ EXPORTS = (
     "iga_sg_plan_create", "iga_sg_workspace_bytes", "iga_sg_plan_stats", "iga_sg_bind", "iga_sg_components",
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
-    "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network",
+    "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
+    "iga_sg_graph_launch",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
 )
 
@@ -123,6 +124,8 @@ def lib():
         L.iga_sg_set_rhs.argtypes = [vp, C.c_int, vp]
         L.iga_sg_fd_factor.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
         L.iga_sg_matrices_1d.argtypes = [vp, C.c_int, C.c_int, _ip, _dp, _dp]
+        L.iga_sg_graph_capture.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Opts)]
+        L.iga_sg_graph_launch.argtypes = [vp]
         L.iga_sg_destroy.argtypes = [vp]
         L.iga_sg_destroy.restype = None
         L.iga_sg_last_error.restype = C.c_char_p
@@ -338,6 +341,27 @@ class Plan:
         o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0,
                   int(continue_cg), int(learned), int(learned_iters), int(not scaled), SCHED[schedule])
         _check(lib().iga_sg_solve(self.h, C.byref(o), C.POINTER(_Report)()))
+
+    def capture(self, f=None, a=None, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
+                maxit: int = 500, max_refine: int = 0, batched: bool = True, workgroups: int = 0,
+                continue_cg: bool = False, learned: bool = False, learned_iters: int = 0,
+                scaled: bool = True, schedule: str = "auto") -> None:
+        """Record assembly + solve (no report) as a HIP graph; ``replay``
+        enqueues it.  The fields' device data is kept alive by the plan.  The
+        plan must be bound to a created stream (``bind(stream=...)``), made
+        torch's current stream wherever torch reads the plan's outputs."""
+        wl = self.wl
+        keep = []
+        Ff = self._field(f if f is not None else wl["f"], keep)
+        Fa = self._field(a if a is not None else wl["a"], keep)
+        o = _Opts(PREC[precision], int(batched), tol, tol_inner, maxit, max_refine, workgroups, 0,
+                  int(continue_cg), int(learned), int(learned_iters), int(not scaled), SCHED[schedule])
+        _check(lib().iga_sg_graph_capture(self.h, C.byref(Ff), C.byref(Fa), C.byref(o)))
+        self._graph_fields = keep
+
+    def replay(self) -> None:
+        """Enqueue the captured step on the plan's stream."""
+        _check(lib().iga_sg_graph_launch(self.h))
 
     def combine(self, xi, patch=None):
         import torch

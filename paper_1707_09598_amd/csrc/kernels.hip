@@ -638,6 +638,11 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
     }
 }
 
+// Clears the assembly error flag.
+__global__ void k_clear_flag(int* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
 // Reset solver state and vectors of a grid range before a solve; the first
 // sweep's active task lists are the launch's task ranges.
 __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1, int64_t i0, int64_t i1,
@@ -1215,7 +1220,7 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     int* err = reinterpret_cast<int*>(reinterpret_cast<char*>(P->ws) + P->lay.bar + 64);
-    HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, err);  // a kernel, so that the step can be captured
     const int ng = static_cast<int>(P->grids.size());
     HIP_OK(launch_assemble(P->dim, a ? a->kind : IGA_FIELD_NONE, f ? f->kind : IGA_FIELD_NONE,
                            dim3(blocks_for(P->nqp_total)), st, K, to_dev(a), to_dev(f), ng, err));
@@ -1566,8 +1571,95 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     return IGA_OK;
 }
 
+iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_field* a, const iga_sg_solve_opts* o) {
+    if (!P || !o) {
+        set_error("null argument");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->bound) {
+        set_error("iga_sg_graph_capture before iga_sg_bind");
+        return IGA_ERR_STATE;
+    }
+    if (o->timing) {
+        set_error("timing reports are not available for a captured step");
+        return IGA_ERR_INVALID_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    if (!st) {
+        set_error("graph capture needs a plan bound to a created stream, not the default stream");
+        return IGA_ERR_STATE;
+    }
+    if (P->gexec) {
+        HIP_OK(hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->gexec)));
+        P->gexec = nullptr;
+    }
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    iga_status s = iga_sg_assemble(P, f, a, nullptr);
+    if (s == IGA_OK) s = iga_sg_solve(P, o, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);  // always leave capture mode
+    if (s != IGA_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (s == IGA_OK) {
+            set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+            s = IGA_ERR_DEVICE;
+        }
+        return s;
+    }
+    // The persistent solve needs all its workgroups resident at once (grid
+    // barrier): its captured node is marked cooperative, as the direct
+    // launch is.
+    size_t nn = 0;
+    hipError_t ge = hipGraphGetNodes(g, nullptr, &nn);
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (ge == hipSuccess && nn) ge = hipGraphGetNodes(g, nodes.data(), &nn);
+    const void* fsolve = solve_kernel(P->p, o->precision, P->dim);
+    int marked = 0;
+    for (size_t i = 0; ge == hipSuccess && i < nn; ++i) {
+        hipGraphNodeType t;
+        ge = hipGraphNodeGetType(nodes[i], &t);
+        if (ge != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        ge = hipGraphKernelNodeGetParams(nodes[i], &kp);
+        if (ge != hipSuccess || kp.func != fsolve) continue;
+        hipLaunchAttributeValue v;
+        std::memset(&v, 0, sizeof(v));
+        v.cooperative = 1;
+        ge = hipGraphKernelNodeSetAttribute(nodes[i], hipKernelNodeAttributeCooperative, &v);
+        ++marked;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ge == hipSuccess && marked == (o->batched ? 1 : static_cast<int>(P->grids.size())))
+        ge = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    else if (ge == hipSuccess)
+        ge = hipErrorInvalidValue;
+    (void)hipGraphDestroy(g);
+    if (ge != hipSuccess) {
+        set_error("graph of the step not built (%s, %d solve nodes marked)", hipGetErrorString(ge), marked);
+        return IGA_ERR_DEVICE;
+    }
+    P->gexec = ex;
+    return IGA_OK;
+}
+
+iga_status iga_sg_graph_launch(iga_sg_plan P) {
+    if (!P) {
+        set_error("null plan");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->gexec) {
+        set_error("iga_sg_graph_launch before iga_sg_graph_capture");
+        return IGA_ERR_STATE;
+    }
+    HIP_OK(hipGraphLaunch(static_cast<hipGraphExec_t>(P->gexec), static_cast<hipStream_t>(P->stream)));
+    P->assembled = true;
+    P->solved = true;
+    return IGA_OK;
+}
+
 void iga_sg_destroy(iga_sg_plan P) {
     if (!P) return;
+    if (P->gexec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->gexec));
     for (int i = 0; i < 8; ++i)
         if (P->ev[i]) (void)hipEventDestroy(static_cast<hipEvent_t>(P->ev[i]));
     delete P;

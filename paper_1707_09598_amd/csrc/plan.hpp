@@ -71,6 +71,7 @@ struct iga_sg_plan_s {
     int num_cu = 0;
     int max_wg = 0;
     void* ev[8] = {nullptr};  // timing events
+    void* gexec = nullptr;    // instantiated graph of one step (iga_sg_graph_capture)
     const float* nn = nullptr;  // learned preconditioner parameters (device, caller-owned)
     int nn_ch[4] = {0, 0, 0, 0};
     int nn_head = 0;

@@ -95,3 +95,47 @@ def test_static_and_dynamic_schedules_agree_bitwise(S, name, precision, ns):
     assert np.array_equal(ra["relres"], rb["relres"])
     for c in range(P.ninst):
         assert np.array_equal(xa[c], xb[c]), c
+
+
+@pytest.mark.parametrize("name,precision,ns,batched", [("cfg2", "fp32", 1, True), ("cfg2", "fp64", 1, False),
+                                                        ("cfg5", "fp32", 3, True)])
+def test_graph_replays_equal_direct_calls(S, name, precision, ns, batched):
+    """Assembly + solve captured as one HIP graph (the persistent solve as a
+    cooperative node): three replays, with eager work of the program between
+    them (a different solve, a device copy, a synchronisation), each give the
+    coefficients of the direct calls bit for bit."""
+    import torch
+    w = 4 if name == "cfg5" else 7
+    log(f"case graph {name} w={w} samples={ns} {precision} batched={batched}")
+    kw = dict(precision=precision, tol=1e-11, maxit=400, max_refine=3 if precision == "fp64" else 8,
+              continue_cg=precision != "fp64", batched=batched)
+    # a created stream (the legacy default stream cannot be captured), made
+    # torch's current stream so that torch's reads follow the library's work
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        if name == "cfg5":
+            fields = W.grf_samples(ns, n=24)
+            P = S.Plan(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[0])), nsamples=ns)
+            fa = W._field("grid3d", data=torch.as_tensor(fields, device="cuda"))
+        else:
+            P = S.Plan(W.config(name, w=w))
+            fa = None
+        P.bind(stream=st)
+        P.assemble(a=fa)
+        rep = P.solve(**kw)
+        assert np.all(rep["status"] == 0)
+        ref = [P.coeffs(c).cpu().numpy() for c in range(P.ninst)]
+        P.capture(a=fa, **kw)
+        other = dict(kw, precision="fp64" if precision != "fp64" else "fp32", max_refine=8)
+        for k in range(3):
+            # eager work between replays: another solve overwrites the solution
+            P.assemble(a=fa)
+            P.solve(**other)
+            junk = torch.arange(1 << 16, device="cuda", dtype=torch.float64) * (k + 1)
+            junk2 = junk.clone()
+            torch.cuda.synchronize()
+            P.replay()
+            torch.cuda.synchronize()
+            for c in range(P.ninst):
+                assert np.array_equal(P.coeffs(c).cpu().numpy(), ref[c]), (k, c)
+            del junk, junk2

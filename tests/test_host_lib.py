@@ -107,6 +107,10 @@ def test_call_order_state_errors(S):
     assert L.iga_sg_solve(P.h, C.byref(o), None) == 7
     assert L.iga_sg_combine(P.h, C.c_void_p(8), None, 1, C.c_void_p(8)) == 7
     assert b"before" in L.iga_sg_last_error()
+    # the graph of a step: capture before bind, launch before capture
+    assert L.iga_sg_graph_capture(P.h, C.byref(f), C.byref(f), C.byref(o)) == 7
+    assert L.iga_sg_graph_launch(P.h) == 7
+    assert b"before" in L.iga_sg_last_error()
 
 
 def test_workspace_and_tiles_cover_every_unknown(S):
