@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--tune", action="store_true",
                     help="pick the launch shape of each mode with the autotuner first (its timing runs "
                          "add solve dispatches of other shapes to a profile of the run)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the run with assembly + solve replayed as one HIP graph")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the unit-square (modes A/B) and unit-cube (modes B/C) measurements")
     ap.add_argument("--batch-samples", type=int, default=64,
@@ -194,10 +196,37 @@ def run_mode(S, W, torch, precision, args, xi):
         tr = P.solve(timing=2, **kw)
         trace = {"sweeps": tr["sweeps"], "phase_wall_us": [round(v, 2) for v in tr["phase_us"][:3]],
                  "phase_busy_us": [round(v, 2) for v in tr["phase_us"][3:]]}
+    # the same step with assembly + solve replayed as one HIP graph (a plan on
+    # a created stream: the default stream cannot be captured)
+    graph = None
+    if not args.no_graph:
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            Pg = S.Plan(wl, shape=shape)
+            Pg.bind(device="cuda:0", stream=gs)
+            Pg.capture(**kw)
+            for _ in range(args.warmup):
+                Pg.replay()
+                Pg.combine(xi_t)
+            torch.cuda.synchronize()
+            evg = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+            t0 = time.perf_counter()
+            for k in range(K):
+                evg[k][0].record(gs)
+                Pg.replay()
+                evg[k][1].record(gs)
+                ug = Pg.combine(xi_t)
+                evg[k][2].record(gs)
+            torch.cuda.synchronize()
+            gwall = time.perf_counter() - t0
+            graph = {"wall_ms": 1e3 * gwall / K,
+                     "t_step": float(np.mean([evg[k][0].elapsed_time(evg[k][1]) for k in range(K)])),
+                     "t_cmb": float(np.mean([evg[k][1].elapsed_time(evg[k][2]) for k in range(K)])),
+                     "u": ug.cpu().numpy()}
     return {
         "plan": P, "u": u, "rep": rep, "wall_ms": 1e3 * wall / K, "t_asm": t_asm, "t_sol": t_sol,
         "t_cmb": t_cmb, "t_plan_s": t_plan, "ndof": int(P.ndof.sum()), "trace": trace,
-        "shape": shape, "tuned": tuned,
+        "shape": shape, "tuned": tuned, "graph": graph,
     }
 
 
@@ -523,6 +552,13 @@ def main():
                          "combine": main_run["t_cmb"], "plan_host_s": main_run["t_plan_s"],
                          "wall_per_step": main_run["wall_ms"]},
         "paper_timed_region_dof_per_s": ndof / ((main_run["t_asm"] + main_run["t_sol"]) / 1e3),
+        "graph_step": (None if main_run["graph"] is None else {
+            "mode": "assembly + solve replayed as one HIP graph (cooperative solve node), combination eager",
+            "dof_per_s": ndof / (main_run["graph"]["wall_ms"] / 1e3),
+            "ms_per_step": main_run["graph"]["wall_ms"],
+            "breakdown_ms": {"assemble_solve": main_run["graph"]["t_step"], "combine": main_run["graph"]["t_cmb"]},
+            "rel_l2_vs_oracle": float(np.linalg.norm(main_run["graph"]["u"][sub] - u_ref) / np.linalg.norm(u_ref)),
+        }),
         "cg_iterations": int(main_run["rep"]["total_iters"]),
         "refinements_max": int(main_run["rep"]["refinements"].max()),
         "solve_trace": main_run["trace"],
