@@ -220,8 +220,11 @@ iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t
 
 /* Assemble every component system: per Gauss point the geometry map, its
  * Jacobian, a, f and the operator coefficients a w |det DF| DF^-1 DF^-T
- * (Sec. 2.2, Galerkin form of Problem 1), then the load vectors.  f and a
- * are required; g may be NULL (homogeneous Dirichlet). */
+ * (Sec. 2.2, Galerkin form of Problem 1), then the load vectors and the
+ * diagonal of each operator (for the preconditioner's scaling), both summed
+ * element by element.  f and a are required; g must be NULL or of kind
+ * IGA_FIELD_NONE (homogeneous Dirichlet: the GPU path has no lifting; other
+ * data returns IGA_ERR_INVALID_ARG).  Enqueued on the plan's stream. */
 iga_status iga_sg_assemble(iga_sg_plan plan, const iga_field* f, const iga_field* a,
                            const iga_field* g);
 

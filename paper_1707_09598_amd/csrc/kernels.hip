@@ -1293,9 +1293,9 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         // a few tasks per workgroup: round robin over the launch's tasks with
         // their descriptions cached for the launch; many: round robin over the
         // per-sweep lists of the grids still iterating
-        A.dyn = (ope - opb > kMetaOp * nwg || fde - fdb > kMetaFd * nwg) ? 1 : 0;
-        if (o->schedule == 1) A.dyn = 0;
-        if (o->schedule == 2) A.dyn = 1;
+        A.active = (ope - opb > kMetaOp * nwg || fde - fdb > kMetaFd * nwg) ? 1 : 0;
+        if (o->schedule == 1) A.active = 0;
+        if (o->schedule == 2) A.active = 1;
         void* args[] = {&K, &A};
         HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(kBlock), args,
                                           static_cast<unsigned>(lds), st));

@@ -1235,7 +1235,7 @@ struct SolveArgs {
     double tol2, tol_in2;
     unsigned long long* trace;    // phase timestamps (or nullptr)
     int trace_sweeps;
-    int dyn;                      // tasks from the per-sweep active lists (else the launch's ranges)
+    int active;                   // tasks from the per-sweep active lists (else the launch's ranges)
 };
 
 // Phase tracing (10 ns wall clock): slot 0 kernel start; per sweep s the
@@ -1391,14 +1391,14 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
     // hold only the tasks of grids still iterating, rebuilt in phase 3.
     // Which workgroup runs a task changes no result (partial sums go to the
     // task's own slot).
-    if (!A.dyn) {
+    if (!A.active) {
         int k = 0;
         for (int t = A.op_b + blockIdx.x; t < A.op_e && k < kMetaOp; t += nwg, ++k) meta_fill(P, P.optask[t], meta_op + k);
         k = 0;
         for (int t = A.fd_b + blockIdx.x; t < A.fd_e && k < kMetaFd; t += nwg, ++k) meta_fill(P, P.fdtask[t], meta_fd + k);
     }
     auto task_meta = [&](const Task* list, int t, int k, TaskMeta* cache, int ncache) -> const TaskMeta& {
-        if (!A.dyn && k < ncache) return cache[k];
+        if (!A.active && k < ncache) return cache[k];
         meta_fill(P, list[t], meta_sp);
         return *meta_sp;
     };
@@ -1417,8 +1417,8 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         double* p_new = P.p2 + cur * N;
         double* p_old = P.p2 + nxt * N;
         // ---------------- phase 1: operator -------------------------------------
-        const Task* ol = A.dyn ? P.oplist + static_cast<int64_t>(cur) * P.op_cap : P.optask + A.op_b;
-        const int nop = A.dyn ? list_len(kBarOpLen + cur) : A.op_e - A.op_b;
+        const Task* ol = A.active ? P.oplist + static_cast<int64_t>(cur) * P.op_cap : P.optask + A.op_b;
+        const int nop = A.active ? list_len(kBarOpLen + cur) : A.op_e - A.op_b;
         for (int t = blockIdx.x, k = 0; t < nop; t += nwg, ++k) {
             const TaskMeta& M = task_meta(ol, t, k, meta_op, kMetaOp);
             const Grid& g = M.g;
@@ -1470,9 +1470,9 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
         trace_mark(A, sweep, 0);
         if (A.trace) tb = wall_clock64();
         // ---------------- phase 2: update + FD forward ---------------------------
-        const Task* fl = A.dyn ? P.fdlist + static_cast<int64_t>(cur) * P.fd_cap : P.fdtask + A.fd_b;
-        const int nfd = A.dyn ? list_len(kBarFdLen + cur) : A.fd_e - A.fd_b;
-        if (A.dyn && blockIdx.x == 0 && threadIdx.x == 0) {
+        const Task* fl = A.active ? P.fdlist + static_cast<int64_t>(cur) * P.fd_cap : P.fdtask + A.fd_b;
+        const int nfd = A.active ? list_len(kBarFdLen + cur) : A.fd_e - A.fd_b;
+        if (A.active && blockIdx.x == 0 && threadIdx.x == 0) {
             // the next sweep's lists (the previous sweep was their last reader)
             __hip_atomic_store(&P.bar[kBarOpLen + nxt], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&P.bar[kBarFdLen + nxt], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1623,7 +1623,7 @@ __global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
                 S1[gi] = ns;
                 if (finish) {
                     atomicAdd(&P.bar[kBarDone], 1u);
-                } else if (A.dyn) {
+                } else if (A.active) {
                     // the grid keeps iterating: its tasks go on the next sweep's lists
                     const unsigned o = atomicAdd(&P.bar[kBarOpLen + nxt], static_cast<unsigned>(g.ntile));
                     Task* on = P.oplist + static_cast<int64_t>(nxt) * P.op_cap + o;
