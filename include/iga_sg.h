@@ -164,7 +164,7 @@ typedef struct {
                           z = S P^-1 S r, S = diag(sqrt(P_ii / A_ii)) (S P S has the
                           diagonal of A); 1: the unscaled pencil, z = P^-1 r */
     int schedule;      /* task schedule of the persistent solve: 0 library choice (1 when each
-                          workgroup has a few tasks per phase, else 2); 1 round robin over the
+                          workgroup has at most one task per phase, else 2); 1 round robin over the
                           launch's tasks; 2 round robin over per-sweep lists that hold only
                           the tasks of grids still iterating.  Results are the same bit for
                           bit */

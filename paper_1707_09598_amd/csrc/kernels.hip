@@ -1290,10 +1290,12 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         int want = std::max(ope - opb, fde - fdb);
         if (o->workgroups > 0) want = o->workgroups;
         int nwg = std::max(1, std::min(want, P->max_wg));
-        // a few tasks per workgroup: round robin over the launch's tasks with
-        // their descriptions cached for the launch; many: round robin over the
-        // per-sweep lists of the grids still iterating
-        A.active = (ope - opb > kMetaOp * nwg || fde - fdb > kMetaFd * nwg) ? 1 : 0;
+        // at most one task per workgroup and phase: round robin over the
+        // launch's tasks with their descriptions cached for the launch; more:
+        // round robin over the per-sweep lists of the grids still iterating
+        // (annulus w=10: FP32-class 245 FD tasks, static 2.73 against 2.85 ms;
+        // FP64-class 453, lists 3.19 against 3.41 ms)
+        A.active = (ope - opb > nwg || fde - fdb > nwg) ? 1 : 0;
         if (o->schedule == 1) A.active = 0;
         if (o->schedule == 2) A.active = 1;
         void* args[] = {&K, &A};
