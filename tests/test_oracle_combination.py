@@ -131,3 +131,27 @@ def test_full_tensor_beats_sparse_grid_error_at_same_level():
     c, _ = P.solve([J, J])
     e_full = P.full_errors([J, J], c, 64)
     assert e_full[0] < e_sg[0] and e_full[1] < e_sg[1]
+
+
+@pytest.mark.slow
+def test_sparse_grid_rate_low_regular_annulus():
+    """SG-IGA on the paper's low-regular problem (quarter annulus, f = 1), d = 2,
+    p = 3, C^2: Table 3 reports an L2 rate of 1.58 against the provable 1.5.
+    There is no exact solution: the L2 error of levels 5-9 is measured
+    against the level-12 solution by Gauss quadrature on 256 x 256 parametric
+    cells (|det DF| of the annulus map in closed form; the quadrature
+    integrates the domain area 3 pi / 4 to rounding)."""
+    from quadrature import annulus_quadrature, low_regular_annulus
+    xi, wq = annulus_quadrature(256)
+    assert abs(wq.sum() - 3 * np.pi / 4) < 1e-12
+    Pr = O.Problem(low_regular_annulus(W, 12))
+    ur = Pr.sg_eval(Pr.solve_all(), xi)
+    nrm = np.sqrt(np.sum(wq * ur ** 2))
+    rows = []
+    for J in range(5, 10):
+        P = O.Problem(low_regular_annulus(W, J))
+        u = P.sg_eval(P.solve_all(), xi)
+        rows.append((J, np.sqrt(np.sum(wq * (u - ur) ** 2)) / nrm))
+    r = np.array(rows)
+    l2 = -np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0]
+    assert abs(l2 - 1.5) < 0.2 and abs(l2 - 1.58) < 0.3
