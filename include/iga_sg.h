@@ -107,6 +107,15 @@ typedef struct {
      * finest level of the sparse grid, the paper's comparison in Sec. 4);
      * combination coefficient 1, lmin ignored */
     int full;
+    /* nindex > 0: instead of the sparse-grid set of level w, the combination
+     * over the caller's downward-closed index set I of nindex multi-indices
+     * (index_host [nindex][dim], absolute levels 0..24, host, copied): the
+     * first line of eq. (TD-combi-tec) with its outer sum over I,
+     * c_b = sum over z in {0,1}^dim with b + z in I of (-1)^|z|; multi-indices
+     * with c_b = 0 get no grid.  A set that is not downward closed, or one
+     * given together with full, returns IGA_ERR_INVALID_ARG. */
+    const int* index_host;
+    int nindex;
 } iga_sg_disc;
 
 /* Fields (right-hand side f, coefficient a, Dirichlet data g). */

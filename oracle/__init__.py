@@ -154,6 +154,24 @@ def basis_all(p: int, U, x: float):
 # problems
 # ---------------------------------------------------------------------------
 
+def combination_coefficients(index_set) -> Dict[tuple, int]:
+    """Combination coefficients over a downward-closed index set I (first line
+    of eq. (TD-combi-tec), its outer sum running over I):
+    c_b = sum over z in {0,1}^d with b + z in I of (-1)^|z|, for every b in I
+    (zeros included).  Plain Python over the set."""
+    I = {tuple(int(v) for v in b) for b in index_set}
+    out = {}
+    for b in sorted(I):
+        d = len(b)
+        c = 0
+        for z in range(1 << d):
+            bz = tuple(b[k] + ((z >> k) & 1) for k in range(d))
+            if bz in I:
+                c += -1 if bin(z).count("1") % 2 else 1
+        out[b] = c
+    return out
+
+
 class Problem:
     """A workload dictionary converted to the oracle's C description."""
 

@@ -61,7 +61,7 @@ class _Geometry(C.Structure):
 class _Disc(C.Structure):
     _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int),
                 ("nsamples", C.c_int), ("op_tile", C.c_int), ("op_tile3", C.c_int), ("fd_tasks", C.c_int),
-                ("full", C.c_int)]
+                ("full", C.c_int), ("index_host", C.POINTER(C.c_int)), ("nindex", C.c_int)]
 
 
 class _Field(C.Structure):
@@ -168,11 +168,13 @@ class Plan:
     ``shape`` sets the launch shape: {"op_tile", "op_tile3", "fd_tasks"}
     (missing or 0: library default; see ``tune.autotune``).
     ``full`` plans the single full tensor-product grid at level w in every
-    direction (standard IGA) instead of the combination technique.
+    direction (standard IGA) instead of the combination technique;
+    ``index_set`` ([n, d] absolute levels, downward closed) the combination
+    over that set instead of the sparse-grid set of level w.
     """
 
     def __init__(self, wl: Dict[str, Any], nsamples: int = 1, shape: Optional[Dict[str, int]] = None,
-                 full: bool = False):
+                 full: bool = False, index_set=None):
         self.wl = wl
         self.dim = d = int(wl["dim"])
         self._keep = []
@@ -211,6 +213,11 @@ class Plan:
         D = _Disc(int(wl["p"]), int(wl["r"]), int(wl["w"]), int(wl["lmin"]), 0, self.nsamples,
                   int(self.shape.get("op_tile", 0)), int(self.shape.get("op_tile3", 0)),
                   int(self.shape.get("fd_tasks", 0)), int(full))
+        if index_set is not None:
+            iset = np.ascontiguousarray(np.asarray(index_set, dtype=np.int32).reshape(-1, d))
+            self._keep.append(iset)
+            D.index_host = iset.ctypes.data_as(_ip)
+            D.nindex = len(iset)
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <array>
 #include <map>
+#include <set>
 #include <mutex>
 #include <tuple>
 
@@ -339,7 +340,52 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     }
     // ---- components (eq. TD-combi-tec), lexicographic, level 1 slowest ----
     const int J = P->w - d * P->lmin;
-    if (disc->full) {
+    int lmax_set = 0;
+    if (disc->nindex > 0) {
+        // a caller's downward-closed index set I (absolute levels): the
+        // combination of eq. (TD-combi-tec) with its outer sum over the set,
+        // c_b = sum over z in {0,1}^d with b + z in I of (-1)^|z|; grids with
+        // c_b = 0 are not planned
+        auto fail = [&](const char* what) {
+            set_error("index set: %s", what);
+            delete P;
+            return IGA_ERR_INVALID_ARG;
+        };
+        if (!disc->index_host || disc->full) return fail("null levels, or combined with full");
+        std::set<std::array<int, 3>> I;
+        for (int i = 0; i < disc->nindex; ++i) {
+            std::array<int, 3> b{0, 0, 0};
+            for (int k = 0; k < d; ++k) {
+                b[k] = disc->index_host[static_cast<size_t>(i) * d + k];
+                if (b[k] < 0 || b[k] > 24) return fail("levels must lie in 0..24");
+                lmax_set = std::max(lmax_set, b[k]);
+            }
+            I.insert(b);
+        }
+        for (const auto& b : I)
+            for (int k = 0; k < d; ++k)
+                if (b[k] > 0) {
+                    std::array<int, 3> c = b;
+                    --c[k];
+                    if (!I.count(c)) return fail("not downward closed");
+                }
+        for (const auto& b : I) {  // lexicographic, direction 1 slowest
+            int c = 0;
+            for (int z = 0; z < (1 << d); ++z) {
+                std::array<int, 3> bz = b;
+                int nz = 0;
+                for (int k = 0; k < d; ++k)
+                    if ((z >> k) & 1) {
+                        ++bz[k];
+                        ++nz;
+                    }
+                if (I.count(bz)) c += (nz & 1) ? -1 : 1;
+            }
+            if (c == 0) continue;
+            for (int k = 0; k < d; ++k) P->comp_levels.push_back(b[k]);
+            P->comp_coef.push_back(static_cast<double>(c));
+        }
+    } else if (disc->full) {
         // the full tensor-product space at level w in every direction
         // (standard IGA, the comparison of Sec. 4): one grid, coefficient 1
         for (int k = 0; k < d; ++k) P->comp_levels.push_back(P->w);
@@ -358,7 +404,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
     }
     P->ncomp = static_cast<int>(P->comp_coef.size());
-    P->Lmax = P->lmin + J;
+    P->Lmax = disc->nindex > 0 ? lmax_set : P->lmin + J;
     // ---- 1D tables per (patch, dir, level) ---------------------------------
     const int ntab = geom->npatch * d * (P->Lmax + 1);
     P->tabs.resize(ntab);

@@ -283,3 +283,28 @@ def test_single_component_edge_case(S):
     P.solve(precision="fp64")
     assert P.ncomp == 1 and int(P.ndof[0]) == 1
     assert abs(P.coeffs(0).item() - 3.774475508788975) < 1e-13
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32", 1e-9)])
+def test_index_set_combination_parity(S, precision, bar):
+    """Combination over a caller's anisotropic downward-closed index set
+    {2 b1 + b2 <= 10} on the annulus (the kind of set the knapsack selection
+    of Sec. 4.2 produces): GPU u_I against the oracle's sum of c_b u_b over
+    its own direct solves, coefficients of the general form."""
+    log(f"case index set {precision}")
+    wl = W.config("cfg2")
+    I = [b for b in np.ndindex(6, 11) if 2 * b[0] + b[1] <= 10]
+    P = S.Plan(wl, index_set=I)
+    P.bind()
+    P.assemble()
+    rep = P.solve(precision=precision, tol=1e-11, tol_inner=1e-5, maxit=400,
+                  max_refine=12 if precision != "fp64" else 3, continue_cg=precision != "fp64")
+    assert np.all(rep["status"] == 0)
+    xi, _ = W.eval_points(2, 4096, seed=21)
+    u = P.combine(xi).cpu().numpy()
+    Po = O.Problem(wl)
+    ref = np.zeros(len(xi))
+    for lv, c in zip(P.levels, P.coef):
+        coef, _ = Po.solve([int(v) for v in lv])
+        ref += c * Po.eval([int(v) for v in lv], coef, xi)
+    assert rel(u, ref) < bar

@@ -151,3 +151,20 @@ def test_launch_shape_options(S):
     assert nofit["fd_tasks_lowp"] > base["fd_tasks_lowp"]  # long directions kept in blocks
     t3 = S.Plan(W.config("cfg5", w=5), shape={"op_tile3": 64}).stats()
     assert t3["op_tasks"] > S.Plan(W.config("cfg5", w=5)).stats()["op_tasks"]
+
+
+def test_index_set_plan(S):
+    """A caller's downward-closed index set: the plan keeps the multi-indices
+    with nonzero coefficient, in lexicographic order, with the coefficients
+    of the general form (checked against the oracle's); a set that is not
+    downward closed is rejected."""
+    import oracle as O
+    I = [b for b in np.ndindex(6, 11) if 2 * b[0] + b[1] <= 10]
+    P = S.Plan(W.config("cfg2", w=10), index_set=I)
+    c = O.combination_coefficients(I)
+    want = sorted((b, v) for b, v in c.items() if v != 0)
+    got = [(tuple(int(x) for x in l), float(v)) for l, v in zip(P.levels.tolist(), P.coef.tolist())]
+    assert got == [(b, float(v)) for b, v in want]
+    with pytest.raises(S.IgaError) as e:
+        S.Plan(W.config("cfg2", w=10), index_set=[(0, 0), (2, 0)])
+    assert e.value.code == 1

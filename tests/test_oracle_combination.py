@@ -155,3 +155,47 @@ def test_sparse_grid_rate_low_regular_annulus():
     r = np.array(rows)
     l2 = -np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0]
     assert abs(l2 - 1.5) < 0.2 and abs(l2 - 1.58) < 0.3
+
+
+def _downward_closure(points):
+    out = set()
+    for p in points:
+        for b in np.ndindex(*[v + 1 for v in p]):
+            out.add(tuple(int(x) for x in b))
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_general_index_set_coefficients_simplex(dim):
+    """On the simplex {|b| <= J} the coefficients of the general form equal the
+    binomial closed form (-1)^(J-|b|) binom(d-1, J-|b|) inside the last d
+    layers and vanish below."""
+    for J in range(0, 7):
+        I = [b for b in np.ndindex(*([J + 1] * dim)) if sum(b) <= J]
+        c = O.combination_coefficients(I)
+        for b, v in c.items():
+            j = J - sum(b)
+            want = (-1) ** j * math.comb(dim - 1, j) if j <= dim - 1 else 0
+            assert v == want, (J, b)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_general_index_set_telescoping(dim):
+    """For any downward-closed set, sum over I of the differences
+    Delta_b(u) = sum_z (-1)^|z| u_(b-z) (u_(b-z) = 0 off the index lattice)
+    equals sum_b c_b u_b (the Delta form of the combination technique), for
+    random integer u_b; with u = 1 the coefficients sum to 1."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        pts = [tuple(rng.integers(0, 6, dim)) for _ in range(rng.integers(1, 5))]
+        I = _downward_closure(pts)
+        u = {b: int(rng.integers(-1000, 1000)) for b in I}
+        lhs = 0
+        for b in I:
+            for z in range(1 << dim):
+                bz = tuple(b[k] - ((z >> k) & 1) for k in range(dim))
+                if min(bz) >= 0:
+                    lhs += (-1) ** bin(z).count("1") * u[bz]
+        c = O.combination_coefficients(I)
+        assert lhs == sum(c[b] * u[b] for b in I)
+        assert sum(c.values()) == 1
