@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "9bbf26fdb6401a748d0c427ca54b0023c94170e7aeeb6498b983198435724373",
-    "fetch_kib": 1128805.0, "write_kib": 325254.1,
-    "fetch_factor": 262144.0 / 131088.1, "write_factor": 262144.0 / 262144.0,
+    "sha256": "24ce58217fce27977c619c03d33a305bb9714143518d8c45ae1951e9f3a5eb91",
+    "fetch_kib": 1128861.7, "write_kib": 325253.8,
+    "fetch_factor": 262144.0 / 131088.4, "write_factor": 262144.0 / 262144.0,
 }
 
 
