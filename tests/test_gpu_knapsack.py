@@ -68,3 +68,28 @@ def test_knapsack_index_set_regular_annulus(S):
         coef, _ = Po.solve([int(v) for v in lv])
         ref += c * Po.eval([int(v) for v in lv], coef, pts)
     assert np.linalg.norm(u - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_knapsack_index_set_low_regular_annulus(S):
+    """On the low-regular problem (f = 1) the paper finds optimal sets closer
+    to a rectangle than to a triangle, with profits decaying more slowly in
+    the second (angular) direction: most mirrored pairs b = (i, j), i < j,
+    have the larger profit on the angular side, and the set chosen for the
+    budget of the level-6 sparse grid is not that simplex but reaches beyond
+    |b| = 6."""
+    from paper_1707_09598_amd import knapsack
+    from quadrature import annulus_quadrature, low_regular_annulus
+    wl = low_regular_annulus(W, 9)
+    xi, wq = annulus_quadrature(128)
+    cand = [b for b in np.ndindex(8, 8) if sum(b) <= 9]
+    kw = dict(precision="fp64", tol=1e-12, maxit=600, max_refine=3)
+    prof = knapsack.profits(wl, cand, xi, wq, kw)
+    pairs = [(i, j) for (i, j) in cand if i < j and (j, i) in prof]
+    angular = sum(prof[(i, j)]["profit"] > prof[(j, i)]["profit"] for (i, j) in pairs)
+    log(f"  angular side larger in {angular} of {len(pairs)} mirrored pairs")
+    assert angular >= 0.7 * len(pairs)
+    sg6 = [b for b in cand if sum(b) <= 6]
+    budget = sum(prof[b]["cost"] for b in sg6)
+    I = knapsack.dantzig(prof, budget)
+    log(f"  chosen set ({len(I)} indices): {I}")
+    assert set(I) != set(sg6) and max(sum(b) for b in I) > 6
