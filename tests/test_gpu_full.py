@@ -73,8 +73,10 @@ def test_full_grid_against_sparse_grid(S):
     """Errors against the exact solution per level: the full grid contains
     every component space, so its error at level J is at most the sparse
     grid's; at matched accuracy the sparse grid uses fewer unknowns (summed
-    over its components).  The table of errors against unknowns is printed
-    (the paper's error-against-DOFs comparison)."""
+    over its components).  The table of errors against unknowns and GPU time
+    (assembly + solve) is printed (the paper's error-against-DOFs and
+    error-against-time comparisons)."""
+    import torch
     rows = []
     for J in range(3, 9):
         wl = _annulus_paper(J)
@@ -87,6 +89,15 @@ def test_full_grid_against_sparse_grid(S):
             P.assemble()
             rep = _solve(P, "fp64")
             assert np.all(rep["status"] == 0)
+            ms = []
+            for _ in range(3):  # assembly + solve, HIP events on the plan's stream
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(P.stream)
+                P.assemble()
+                P.solve_async(precision="fp64", tol=1e-12, maxit=800, max_refine=3)
+                ev[1].record(P.stream)
+                torch.cuda.synchronize()
+                ms.append(ev[0].elapsed_time(ev[1]))
             if full:
                 e = Po.full_errors([J, J], _full_array(P, Po, 0), 128)
             else:
@@ -94,7 +105,7 @@ def test_full_grid_against_sparse_grid(S):
                 e = Po.sg_errors(coefs, 128)
             rows.append((J, full, int(P.ndof.sum()), e[0] / e[2], e[1] / e[3]))
             log(f"  {'IGA   ' if full else 'SG-IGA'} J={J} unknowns={rows[-1][2]:6d} "
-                f"relative L2 {rows[-1][3]:.3e} H1 {rows[-1][4]:.3e}")
+                f"relative L2 {rows[-1][3]:.3e} H1 {rows[-1][4]:.3e} GPU {np.median(ms):.3f} ms")
     for J in range(3, 6):
         sg = [r for r in rows if r[0] == J and not r[1]][0]
         fu = [r for r in rows if r[0] == J and r[1]][0]
