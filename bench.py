@@ -370,7 +370,8 @@ def run_small_configs(S, W, torch, refs):
             grid per launch) against mode B (all grids in one launch);
       cfg3  unit cube, p=3 C^2, w=8, lmin=1: mode B (FP64) against mode C
             (BF16 fast-diagonalisation factors, FP32 operator, FP64
-            refinement), each with the operator tile picked by the autotuner."""
+            refinement; and with FP32 factors), each with the operator tile
+            picked by the autotuner."""
     from paper_1707_09598_amd import tune
     out = {}
     specs = {
@@ -380,7 +381,9 @@ def run_small_configs(S, W, torch, refs):
         "cfg3": ("unit cube, identity map, u = prod sin(pi x_k), p=3 C^2, w=8, lmin=1, 46 grids, tol 1e-10",
                  [("B_fp64", dict(precision="fp64", tol=1e-10, max_refine=3)),
                   ("C_bf16fd", dict(precision="bf16fd", tol=1e-10, tol_inner=1e-2, max_refine=16,
-                                    continue_cg=True))], True),
+                                    continue_cg=True)),
+                  ("C_fp32", dict(precision="fp32", tol=1e-10, tol_inner=1e-5, max_refine=12,
+                                  continue_cg=True))], True),
     }
     for name, (desc, modes, tuned) in specs.items():
         wl = W.config(name)
