@@ -20,7 +20,15 @@ constexpr int kMaxDim = 3;
 constexpr int kMaxP = 4;          // solution degree limit (register arrays)
 constexpr int kMaxPg = 4;         // geometry degree limit
 constexpr int kMaxPatch = 4;
-constexpr int kBlock = 512;       // threads per workgroup in every kernel (8 wavefronts)
+// Threads per workgroup: 512 (8 wavefronts) in every kernel except the 3D
+// persistent solve, whose translation units define IGASG_THREADS 256: one
+// 4-wavefront workgroup per CU gets the whole register file there (the 512
+// thread build held 256 VGPRs and spilled about 1 KB per lane).
+#ifndef IGASG_THREADS
+#define IGASG_THREADS 512
+#endif
+constexpr int kBlock = IGASG_THREADS;
+constexpr int kBlockSolve3 = 256;  // threads of the 3D solve kernels
 constexpr int kWaves = kBlock / 64;
 constexpr int kBigRed = 2048;     // doubles of LDS for cross-wavefront partial sums of FD tasks
 

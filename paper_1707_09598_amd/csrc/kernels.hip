@@ -1045,6 +1045,10 @@ const void* solve_kernel_p2(int prec, int dim);
 const void* solve_kernel_p3(int prec, int dim);
 const void* solve_kernel_p4(int prec, int dim);
 
+// Threads per workgroup of the persistent solve (the 3D kernels are built
+// with 256).
+int solve_threads(int dim) { return dim == 3 ? kBlockSolve3 : kBlock; }
+
 const void* solve_kernel(int p, int prec, int dim) {
     switch (p) {
         case 1: return solve_kernel_p1(prec, dim);
@@ -1188,7 +1192,8 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     int occ = 1 << 20;
     for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD}) {
         int o = 0;
-        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec, P->dim), kBlock, P->lds_bytes));
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec, P->dim),
+                                                            solve_threads(P->dim), P->lds_bytes));
         occ = std::min(occ, o);
     }
     P->max_wg = std::max(1, occ) * P->num_cu;
@@ -1299,7 +1304,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         if (o->schedule == 1) A.active = 0;
         if (o->schedule == 2) A.active = 1;
         void* args[] = {&K, &A};
-        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(kBlock), args,
+        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(solve_threads(P->dim)), args,
                                           static_cast<unsigned>(lds), st));
         return IGA_OK;
     };

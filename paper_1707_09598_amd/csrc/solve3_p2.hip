@@ -1,0 +1,16 @@
+// solve3_p2.hip -- k_solve for spline degree 2 in 3D, each inner precision,
+// built with 256-thread workgroups (see IGASG_THREADS in common.hpp).
+#define IGASG_THREADS 256
+#include "solve.hpp"
+
+namespace igasg {
+
+const void* solve3_kernel_p2(int prec) {
+    switch (prec) {
+        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 3>);
+        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1, 3>);
+        default: return reinterpret_cast<const void*>(k_solve<2, 2, 3>);
+    }
+}
+
+}  // namespace igasg

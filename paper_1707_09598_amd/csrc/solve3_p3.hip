@@ -1,0 +1,16 @@
+// solve3_p3.hip -- k_solve for spline degree 3 in 3D, each inner precision,
+// built with 256-thread workgroups (see IGASG_THREADS in common.hpp).
+#define IGASG_THREADS 256
+#include "solve.hpp"
+
+namespace igasg {
+
+const void* solve3_kernel_p3(int prec) {
+    switch (prec) {
+        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<3, 0, 3>);
+        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<3, 1, 3>);
+        default: return reinterpret_cast<const void*>(k_solve<3, 2, 3>);
+    }
+}
+
+}  // namespace igasg
