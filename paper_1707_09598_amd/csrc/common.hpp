@@ -20,10 +20,11 @@ constexpr int kMaxDim = 3;
 constexpr int kMaxP = 4;          // solution degree limit (register arrays)
 constexpr int kMaxPg = 4;         // geometry degree limit
 constexpr int kMaxPatch = 4;
-// Threads per workgroup: 512 (8 wavefronts) in every kernel except the 3D
-// persistent solve, whose translation units define IGASG_THREADS 256: one
-// 4-wavefront workgroup per CU gets the whole register file there (the 512
-// thread build held 256 VGPRs and spilled about 1 KB per lane).
+// Threads per workgroup: 512 (8 wavefronts) in every kernel; the 3D
+// persistent solve has a second build whose translation units define
+// IGASG_THREADS 256: one 4-wavefront workgroup per CU gets the whole register
+// file there (the 512-thread build holds 256 VGPRs and spills about 1 KB per
+// lane).
 #ifndef IGASG_THREADS
 #define IGASG_THREADS 512
 #endif

@@ -1040,21 +1040,26 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
 }
 
 // k_solve<PP, *> lives in one translation unit per degree (solve_p*.hip)
-const void* solve_kernel_p1(int prec, int dim);
-const void* solve_kernel_p2(int prec, int dim);
-const void* solve_kernel_p3(int prec, int dim);
-const void* solve_kernel_p4(int prec, int dim);
+const void* solve_kernel_p1(int prec, int dim, int narrow);
+const void* solve_kernel_p2(int prec, int dim, int narrow);
+const void* solve_kernel_p3(int prec, int dim, int narrow);
+const void* solve_kernel_p4(int prec, int dim, int narrow);
 
-// Threads per workgroup of the persistent solve (the 3D kernels are built
-// with 256).
-int solve_threads(int dim) { return dim == 3 ? kBlockSolve3 : kBlock; }
+// The persistent solve in 3D comes in two builds: 512-thread workgroups
+// (8 wavefronts, 256 VGPRs with about 1 KB per lane of spills) and 256-thread
+// workgroups (narrow: one workgroup per CU with the whole register file, no
+// spills).  The narrow build is faster when every workgroup has many tasks
+// per phase (several coefficient samples in one launch), the wide one when a
+// task's work is spread over few tasks (a single sample, the learned
+// correction's convolutions).  2D uses the wide build.
+int solve_threads(int dim, int narrow) { return dim == 3 && narrow ? kBlockSolve3 : kBlock; }
 
-const void* solve_kernel(int p, int prec, int dim) {
+const void* solve_kernel(int p, int prec, int dim, int narrow = 0) {
     switch (p) {
-        case 1: return solve_kernel_p1(prec, dim);
-        case 2: return solve_kernel_p2(prec, dim);
-        case 3: return solve_kernel_p3(prec, dim);
-        default: return solve_kernel_p4(prec, dim);
+        case 1: return solve_kernel_p1(prec, dim, narrow);
+        case 2: return solve_kernel_p2(prec, dim, narrow);
+        case 3: return solve_kernel_p3(prec, dim, narrow);
+        default: return solve_kernel_p4(prec, dim, narrow);
     }
 }
 
@@ -1186,16 +1191,19 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
         for (const void* k : ks)
             HIP_OK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
         for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD})
-            HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec, P->dim), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(P->lds_bytes)));
+            for (int narrow = 0; narrow <= (P->dim == 3 ? 1 : 0); ++narrow)
+                HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec, P->dim, narrow),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
     }
+    // persistent width: workgroups resident at once for every build of the solve
     int occ = 1 << 20;
-    for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD}) {
-        int o = 0;
-        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec, P->dim),
-                                                            solve_threads(P->dim), P->lds_bytes));
-        occ = std::min(occ, o);
-    }
+    for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD})
+        for (int narrow = 0; narrow <= (P->dim == 3 ? 1 : 0); ++narrow) {
+            int o = 0;
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, solve_kernel(P->p, prec, P->dim, narrow),
+                                                                solve_threads(P->dim, narrow), P->lds_bytes));
+            occ = std::min(occ, o);
+        }
     P->max_wg = std::max(1, occ) * P->num_cu;
     for (int i = 0; i < 8; ++i)
         if (!P->ev[i]) HIP_OK(hipEventCreate(reinterpret_cast<hipEvent_t*>(&P->ev[i])));
@@ -1303,9 +1311,15 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         A.active = (ope - opb > nwg || fde - fdb > nwg) ? 1 : 0;
         if (o->schedule == 1) A.active = 0;
         if (o->schedule == 2) A.active = 1;
+        // 3D with more tasks than workgroups (and no learned correction, whose
+        // convolutions want the wide workgroup): the narrow build (64
+        // random-field samples: FP64 57 -> 46 ms, mixed 48 -> 44 ms).  The
+        // choice depends on the launch alone, not on a forced schedule, so
+        // both schedules of one launch run the same build and agree bitwise.
+        const int narrow = P->dim == 3 && (ope - opb > nwg || fde - fdb > nwg) && !A.learned ? 1 : 0;
         void* args[] = {&K, &A};
-        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim), dim3(nwg), dim3(solve_threads(P->dim)), args,
-                                          static_cast<unsigned>(lds), st));
+        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim, narrow), dim3(nwg),
+                                          dim3(solve_threads(P->dim, narrow)), args, static_cast<unsigned>(lds), st));
         return IGA_OK;
     };
     if (o->batched) {
@@ -1620,7 +1634,8 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
     hipError_t ge = hipGraphGetNodes(g, nullptr, &nn);
     std::vector<hipGraphNode_t> nodes(nn);
     if (ge == hipSuccess && nn) ge = hipGraphGetNodes(g, nodes.data(), &nn);
-    const void* fsolve = solve_kernel(P->p, o->precision, P->dim);
+    const void* fsolve = solve_kernel(P->p, o->precision, P->dim, 0);
+    const void* fsolve_narrow = solve_kernel(P->p, o->precision, P->dim, 1);
     int marked = 0;
     for (size_t i = 0; ge == hipSuccess && i < nn; ++i) {
         hipGraphNodeType t;
@@ -1628,7 +1643,7 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
         if (ge != hipSuccess || t != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp;
         ge = hipGraphKernelNodeGetParams(nodes[i], &kp);
-        if (ge != hipSuccess || kp.func != fsolve) continue;
+        if (ge != hipSuccess || (kp.func != fsolve && kp.func != fsolve_narrow)) continue;
         hipLaunchAttributeValue v;
         std::memset(&v, 0, sizeof(v));
         v.cooperative = 1;

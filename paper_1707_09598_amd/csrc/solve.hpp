@@ -1368,8 +1368,11 @@ __device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int 
     }
 }
 
-template <int PP, int FDP, int DIM>
-__global__ void __launch_bounds__(kBlock) k_solve(Params P, SolveArgs A) {
+// NT: threads per workgroup of the build (a template argument, so that the
+// 512- and 256-thread builds of one kernel have distinct symbols)
+template <int PP, int FDP, int DIM, int NT>
+__global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
+    static_assert(NT == kBlock, "the workgroup size is that of the translation unit's build");
     using TU = typename FdTypes<FDP>::TU;
     using TC = typename FdTypes<FDP>::TC;
     extern __shared__ double lds_all[];

@@ -7,9 +7,9 @@ namespace igasg {
 
 const void* solve3_kernel_p2(int prec) {
     switch (prec) {
-        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 3>);
-        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1, 3>);
-        default: return reinterpret_cast<const void*>(k_solve<2, 2, 3>);
+        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 3, kBlock>);
+        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<2, 1, 3, kBlock>);
+        default: return reinterpret_cast<const void*>(k_solve<2, 2, 3, kBlock>);
     }
 }
 

@@ -7,9 +7,9 @@ namespace igasg {
 
 const void* solve3_kernel_p4(int prec) {
     switch (prec) {
-        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<4, 0, 3>);
-        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<4, 1, 3>);
-        default: return reinterpret_cast<const void*>(k_solve<4, 2, 3>);
+        case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<4, 0, 3, kBlock>);
+        case IGA_PREC_FP32: return reinterpret_cast<const void*>(k_solve<4, 1, 3, kBlock>);
+        default: return reinterpret_cast<const void*>(k_solve<4, 2, 3, kBlock>);
     }
 }
 

@@ -139,3 +139,29 @@ def test_graph_replays_equal_direct_calls(S, name, precision, ns, batched):
             for c in range(P.ninst):
                 assert np.array_equal(P.coeffs(c).cpu().numpy(), ref[c]), (k, c)
             del junk, junk2
+
+
+def test_narrow_build_parity_with_oracle(S):
+    """A 3D launch with more tasks than workgroups runs the 256-thread build of
+    the solve (whose reductions group the wavefronts differently): every
+    sample's coefficients equal the oracle's direct solve (FP64, relative
+    1e-10), checked on the first and last samples."""
+    import torch
+    import oracle as O
+    ns, w = 16, 4
+    log(f"case narrow build cfg5 w={w} samples={ns}")
+    fields = W.grf_samples(ns, n=24)
+    P = S.Plan(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[0])), nsamples=ns)
+    assert P.stats()["op_tasks"] > 256
+    P.bind()
+    P.assemble(a=W._field("grid3d", data=torch.as_tensor(fields, device="cuda")))
+    rep = P.solve(precision="fp64", tol=1e-12, maxit=400, max_refine=3)
+    assert np.all(rep["status"] == 0)
+    for s in (0, ns - 1):
+        Po = O.Problem(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[s])))
+        ref = Po.split(Po.solve_all())
+        for c in range(P.ncomp):
+            nb = Po.nbasis(P.levels[c])
+            x = P.coeffs(s * P.ncomp + c).cpu().numpy()
+            r = ref[c][0][tuple(slice(1, -1) for _ in nb)].ravel()
+            assert np.linalg.norm(x - r) <= 1e-10 * np.linalg.norm(r), (s, c)
