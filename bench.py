@@ -41,9 +41,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "24ce58217fce27977c619c03d33a305bb9714143518d8c45ae1951e9f3a5eb91",
-    "fetch_kib": 1128861.7, "write_kib": 325253.8,
-    "fetch_factor": 262144.0 / 131088.4, "write_factor": 262144.0 / 262144.0,
+    "sha256": "ce18183dae6c0d85a55f394be9735fa97195510de99a5085d39d3e07a6402b15",
+    "fetch_kib": 1128822.4, "write_kib": 325255.2,
+    "fetch_factor": 262144.0 / 131088.6, "write_factor": 262144.0 / 262144.0,
 }
 
 
