@@ -21,7 +21,7 @@
  *   - the combination technique, eq. (TD-combi-tec):
  *       u_J = sum_{J-d+1 <= |b| <= J} (-1)^(J-|b|) binom(d-1, J-|b|) u_b.
  *
- * Readings where the paper is silent (also listed in the design doc):
+ * Readings where the paper is silent:
  *   - levels start at lmin (default 0); the combination index is w - d*lmin;
  *   - evaluation at the last knot uses the last non-empty interval;
  *   - discrete basis phi_j = B_j / W (W the NURBS weight function of F);

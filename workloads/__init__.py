@@ -165,7 +165,7 @@ CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4", "cfg5")
 
 
 def config(name: str, **override: Any) -> Dict[str, Any]:
-    """The five synthetic workloads (sizes and data as in the survey readings).
+    """The five synthetic workloads (sizes and data of the paper's test problems).
 
     cfg1  unit square Poisson, u = sin(pi x) sin(pi y), p=2 C^1, w=6
     cfg2  quarter annulus, a = 1 + 0.5 sin(2 pi x) cos(2 pi y), u = the paper's
