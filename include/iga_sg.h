@@ -299,7 +299,9 @@ iga_status iga_sg_matrices_1d(iga_sg_plan plan, int dir, int lev, int* n, double
  * and the plan must be bound to a created stream (the legacy default stream
  * cannot be captured: IGA_ERR_STATE).
  * The instantiated graph (runtime-owned resources) is released by the next
- * capture or by iga_sg_destroy.  Errors: IGA_ERR_STATE before iga_sg_bind or
+ * capture, by iga_sg_bind (the graph records the workspace's addresses), by
+ * iga_sg_set_network with another network, or by iga_sg_destroy; a launch
+ * after such a release returns IGA_ERR_STATE.  Errors: IGA_ERR_STATE before iga_sg_bind or
  * a launch before a capture; the errors of iga_sg_assemble / iga_sg_solve;
  * IGA_ERR_DEVICE when the runtime cannot build the graph (the stream is left
  * out of capture mode either way). */

@@ -1127,6 +1127,12 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
         set_error("workspace must be 256-byte aligned");
         return IGA_ERR_INVALID_ARG;
     }
+    // a captured step holds the previous workspace's addresses
+    if (P->gexec) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->gexec));
+        P->gexec = nullptr;
+    }
+    P->bound = false;
     P->ws = ws;
     P->ws_bytes = bytes;
     P->stream = stream;
@@ -1205,8 +1211,6 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
             occ = std::min(occ, o);
         }
     P->max_wg = std::max(1, occ) * P->num_cu;
-    for (int i = 0; i < 8; ++i)
-        if (!P->ev[i]) HIP_OK(hipEventCreate(reinterpret_cast<hipEvent_t*>(&P->ev[i])));
     P->bound = true;
     P->assembled = false;
     P->solved = false;
@@ -1287,6 +1291,9 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     A.trace_sweeps = kTraceSweeps;
     if (A.trace) HIP_OK(hipMemsetAsync(trbase, 0, sizeof(unsigned long long) * (1 + 6 * kTraceSweeps), st));
     const size_t lds = P->lds_bytes;
+    if (o->timing)  // timing events are created on first use (a solve without timing creates nothing)
+        for (int i = 0; i < 2; ++i)
+            if (!P->ev[i]) HIP_OK(hipEventCreate(reinterpret_cast<hipEvent_t*>(&P->ev[i])));
     hipEvent_t e0 = static_cast<hipEvent_t>(P->ev[0]), e1 = static_cast<hipEvent_t>(P->ev[1]);
     if (o->timing) HIP_OK(hipEventRecord(e0, st));
     auto launch = [&](int g0, int g1, int opb, int ope, int fdb, int fde) -> iga_status {
@@ -1485,6 +1492,11 @@ iga_status iga_sg_set_network(iga_sg_plan P, const int* channels, int nlayers, c
         set_error("null plan");
         return IGA_ERR_INVALID_ARG;
     }
+    // a captured step holds the previous network's address
+    if (P->gexec && params_dev != P->nn) {
+        (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(P->gexec));
+        P->gexec = nullptr;
+    }
     if (!params_dev) {
         P->nn = nullptr;
         return IGA_OK;
@@ -1670,7 +1682,8 @@ iga_status iga_sg_graph_launch(iga_sg_plan P) {
         return IGA_ERR_INVALID_ARG;
     }
     if (!P->gexec) {
-        set_error("iga_sg_graph_launch before iga_sg_graph_capture");
+        set_error("no captured step: iga_sg_graph_launch before iga_sg_graph_capture, or after a bind or a "
+                  "network change released it");
         return IGA_ERR_STATE;
     }
     HIP_OK(hipGraphLaunch(static_cast<hipGraphExec_t>(P->gexec), static_cast<hipStream_t>(P->stream)));

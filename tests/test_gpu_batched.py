@@ -165,3 +165,39 @@ def test_narrow_build_parity_with_oracle(S):
             x = P.coeffs(s * P.ncomp + c).cpu().numpy()
             r = ref[c][0][tuple(slice(1, -1) for _ in nb)].ravel()
             assert np.linalg.norm(x - r) <= 1e-10 * np.linalg.norm(r), (s, c)
+
+
+def test_graph_released_by_rebind_and_network_change(S):
+    """A captured step records the workspace (and network) addresses of its
+    capture: binding the plan again, or attaching another network, releases
+    it, and a replay is then refused (IGA_ERR_STATE) instead of touching the
+    old memory."""
+    import torch
+    log("case graph released by rebind cfg2 w=6")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        P = S.Plan(W.config("cfg2", w=6))
+        P.bind(stream=st)
+        P.assemble()
+        P.capture(precision="fp64", tol=1e-11, max_refine=3)
+        P.replay()
+        torch.cuda.synchronize()
+        P.bind(stream=st)
+        with pytest.raises(S.IgaError) as e:
+            P.replay()
+        assert e.value.code == 7
+    log("case graph released by a network change cfg5 w=3")
+    with torch.cuda.stream(st):
+        P = S.Plan(W.config("cfg5", w=3, a=W._field("grid3d", data=W.grf_samples(1, n=24)[0])))
+        P.bind(stream=st)
+        P.assemble()
+        net = S.Network((3, 4, 4, 1), device="cuda", stream=st)
+        P.set_network(net)
+        P.capture(precision="fp64", tol=1e-11, max_refine=3, learned=True)
+        P.replay()
+        torch.cuda.synchronize()
+        P.set_network(S.Network((3, 4, 4, 1), device="cuda", stream=st))
+        with pytest.raises(S.IgaError) as e:
+            P.replay()
+        assert e.value.code == 7
+        torch.cuda.synchronize()
