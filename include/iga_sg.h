@@ -210,6 +210,25 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
 /* Bytes of device workspace the plan needs (256-byte aligned sub-buffers). */
 iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes);
 
+/* Variant of iga_sg_bind for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc): the workspace is an array inside the library, one per device
+ * (128 MiB, 256-byte aligned), held from the device's first static binding
+ * until the process ends.  The call uploads the plan tables and computes the
+ * basis tables as iga_sg_bind does (synchronising the stream) and allocates
+ * nothing: no hipMalloc, no hipFree, no allocating library call.  Inputs
+ * (fields, points) and outputs stay caller buffers.
+ * The array of a device serves one plan at a time: a later
+ * iga_sg_bind_static on the same device takes it over, and every call on a
+ * plan bound before then returns IGA_ERR_STATE (rebind it).  The array keeps
+ * the last binding's contents; everything a call reads is written by the
+ * binding or by the call itself.  Calls of two plans that overlap on one
+ * device race and are not supported.
+ * Errors: IGA_ERR_OUT_OF_MEMORY when iga_sg_workspace_bytes exceeds 128 MiB
+ * (nothing is touched), IGA_ERR_DEVICE when the array's address cannot be
+ * obtained or an upload fails. */
+iga_status iga_sg_bind_static(iga_sg_plan plan, void* stream);
+
 /* Task counts of a batched solve (operator tiles; fast-diagonalisation tasks
  * with FP64 factors and with FP32/BF16 factors) and the LDS bytes a solve
  * workgroup takes.  Any pointer may be NULL.  Host only. */

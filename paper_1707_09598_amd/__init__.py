@@ -30,7 +30,7 @@ EXPORTS = (
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
-    "iga_sg_graph_launch",
+    "iga_sg_graph_launch", "iga_sg_bind_static",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
 )
 
@@ -113,6 +113,7 @@ def lib():
         L.iga_sg_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.iga_sg_plan_stats.argtypes = [vp, _ip, _ip, _ip, C.POINTER(C.c_size_t)]
         L.iga_sg_bind.argtypes = [vp, vp, C.c_size_t, vp]
+        L.iga_sg_bind_static.argtypes = [vp, vp]
         L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
         L.iga_sg_assemble.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Field)]
         L.iga_sg_solve.argtypes = [vp, C.POINTER(_Opts), C.POINTER(_Report)]
@@ -284,6 +285,18 @@ class Plan:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         _check(lib().iga_sg_bind(self.h, C.c_void_p(self.ws_ptr), C.c_size_t(nbytes),
                                  C.c_void_p(self.stream.cuda_stream)))
+
+    def bind_static(self, device=None, stream=None) -> None:
+        """Bind to the library's static workspace of the device (no device
+        allocation; see iga_sg_bind_static)."""
+        import torch
+        dev = torch.device(device if device is not None else "cuda")
+        self.ws = None
+        self.ws_ptr = None
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        with torch.cuda.device(dev):
+            _check(lib().iga_sg_bind_static(self.h, C.c_void_p(self.stream.cuda_stream)))
 
     def _field(self, spec, keep):
         F = _Field()

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1112,6 +1113,37 @@ int blocks_for(int64_t n) {
 
 }  // namespace
 
+// Workspace of iga_sg_bind_static: one array per device, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it only stands in for the symbol); the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticWorkspaceBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};       // device address of scratch, per device
+uint64_t g_static_gen[kMaxDevices] = {};    // static bindings made on each device so far
+
+// A plan bound to the static workspace stays usable until another plan binds
+// the same device's array.
+iga_status check_workspace(const iga_sg_plan_s* P) {
+    if (P->static_dev < 0) return IGA_OK;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_gen[P->static_dev] != P->static_gen) {
+        set_error("the static workspace of device %d was bound to another plan since this plan's "
+                  "iga_sg_bind_static", P->static_dev);
+        return IGA_ERR_STATE;
+    }
+    return IGA_OK;
+}
+
+iga_status bind_impl(iga_sg_plan P, void* ws, size_t bytes, void* stream);
+
+}  // namespace
+
 extern "C" {
 
 iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
@@ -1119,6 +1151,52 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
         set_error("null plan or workspace");
         return IGA_ERR_INVALID_ARG;
     }
+    const iga_status s = bind_impl(P, ws, bytes, stream);
+    if (s == IGA_OK) P->static_dev = -1;
+    return s;
+}
+
+iga_status iga_sg_bind_static(iga_sg_plan P, void* stream) {
+    if (!P) {
+        set_error("null plan");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (P->lay.total > kStaticWorkspaceBytes) {
+        set_error("plan needs %zu bytes of workspace, the static workspace holds %zu", P->lay.total,
+                  kStaticWorkspaceBytes);
+        return IGA_ERR_OUT_OF_MEMORY;
+    }
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d devices the static workspace serves", dev, kMaxDevices);
+        return IGA_ERR_DEVICE;
+    }
+    uint64_t gen = 0;
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void* a = nullptr;
+            HIP_OK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+            g_static_ptr[dev] = a;
+        }
+        ptr = g_static_ptr[dev];
+        gen = ++g_static_gen[dev];
+    }
+    P->static_dev = -1;  // until the binding is complete
+    const iga_status s = bind_impl(P, ptr, kStaticWorkspaceBytes, stream);
+    if (s != IGA_OK) return s;
+    P->static_dev = dev;
+    P->static_gen = gen;
+    return IGA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+iga_status bind_impl(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     if (bytes < P->lay.total) {
         set_error("workspace too small: %zu < %zu bytes", bytes, P->lay.total);
         return IGA_ERR_OUT_OF_MEMORY;
@@ -1217,6 +1295,10 @@ iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
     return IGA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a, const iga_field* g) {
     if (!P) {
         set_error("null plan");
@@ -1234,6 +1316,7 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
         set_error("nonhomogeneous Dirichlet data is not supported by the GPU path");
         return IGA_ERR_INVALID_ARG;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     int* err = reinterpret_cast<int*>(reinterpret_cast<char*>(P->ws) + P->lay.bar + 64);
@@ -1262,6 +1345,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         set_error("invalid solve options");
         return IGA_ERR_INVALID_ARG;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     const bool lp = o->precision != IGA_PREC_FP64;  // FD blocking of the factor precision
     Params K = make_params(P, lp);
@@ -1418,6 +1502,7 @@ iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int
         set_error("iga_sg_combine before iga_sg_solve");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     if (n == 0) return IGA_OK;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
@@ -1439,6 +1524,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
         set_error("iga_sg_eval before iga_sg_solve");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     if (n == 0) return IGA_OK;
     int g0 = -1, g1 = -1;
     for (int gi = 0; gi < static_cast<int>(P->grids.size()); ++gi)
@@ -1462,6 +1548,7 @@ iga_status iga_sg_coeffs(iga_sg_plan P, int comp, double* out) {
         set_error("iga_sg_coeffs before iga_sg_solve");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
@@ -1479,6 +1566,7 @@ iga_status iga_sg_loga(iga_sg_plan P, int comp, double* out) {
         set_error("iga_sg_loga before iga_sg_assemble");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
@@ -1526,6 +1614,7 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
         set_error("iga_sg_rhs before iga_sg_assemble");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
@@ -1543,6 +1632,7 @@ iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
         set_error("iga_sg_set_rhs before iga_sg_assemble");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     for (const Grid& g : P->grids)
@@ -1561,6 +1651,7 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
         set_error("iga_sg_apply before iga_sg_assemble");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)
         if (instance_of(P, P->grids[i]) == comp) gi = i;
@@ -1617,6 +1708,7 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
         set_error("timing reports are not available for a captured step");
         return IGA_ERR_INVALID_ARG;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     if (!st) {
         set_error("graph capture needs a plan bound to a created stream, not the default stream");
@@ -1686,6 +1778,7 @@ iga_status iga_sg_graph_launch(iga_sg_plan P) {
                   "network change released it");
         return IGA_ERR_STATE;
     }
+    if (const iga_status ws = check_workspace(P)) return ws;
     HIP_OK(hipGraphLaunch(static_cast<hipGraphExec_t>(P->gexec), static_cast<hipStream_t>(P->stream)));
     P->assembled = true;
     P->solved = true;

@@ -72,6 +72,8 @@ struct iga_sg_plan_s {
     int max_wg = 0;
     void* ev[8] = {nullptr};  // timing events
     void* gexec = nullptr;    // instantiated graph of one step (iga_sg_graph_capture)
+    int static_dev = -1;      // device whose static workspace the plan is bound to (iga_sg_bind_static)
+    uint64_t static_gen = 0;  // that device's binding count at this plan's binding
     const float* nn = nullptr;  // learned preconditioner parameters (device, caller-owned)
     int nn_ch[4] = {0, 0, 0, 0};
     int nn_head = 0;
