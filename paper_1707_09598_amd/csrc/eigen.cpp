@@ -6,9 +6,10 @@
 // with K (stiffness) and M (mass) symmetric banded.  Method (Golub & Van Loan,
 // "Matrix Computations", Sec. 8.3 and 8.7): Cholesky M = L L^T, the standard
 // problem C = L^-1 K L^-T, Householder reduction of C to tridiagonal form,
-// implicit QL iteration with Wilkinson-type shifts, back-transformation
-// U = L^-T Q Z.  The O(n^3) stages (rotation replay, reflector application,
-// triangular back-substitution) are split over column chunks on host threads.
+// the symmetric QR algorithm (implicit steps with the Wilkinson shift,
+// Alg. 8.3.2, deflation as in Alg. 8.3.3), back-transformation U = L^-T Q Z.
+// The O(n^3) stages (rotation replay, reflector application, triangular
+// back-substitution) are split over column chunks on host threads.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -159,51 +160,46 @@ bool gen_eig_banded(int n, int bw, const double* K, const double* M, double* U, 
     A.clear();
     A.shrink_to_fit();
 
-    // --- implicit QL on (dg, e); rotations recorded, replayed on Z^T ---------
+    // --- symmetric QR on (dg, e): implicit steps with the Wilkinson shift ----
+    // (Golub & Van Loan, Alg. 8.3.2 and 8.3.3).  e[i] couples rows i and i+1.
+    // Each step chases the bulge of one plane rotation R_k (rows k, k+1:
+    // row_k <- c row_k + s row_(k+1), row_(k+1) <- -s row_k + c row_(k+1)) down
+    // the unreduced block [lo, hi]; T <- R_k T R_k^T.  The rotations are
+    // recorded in order and replayed on Z^T = ... R_2 R_1.
     std::vector<Rot> rots;
     rots.reserve(static_cast<size_t>(n) * 8);
     const double eps = 2.220446049250313e-16;
-    for (int l = 0; l < n; ++l) {
-        int iter = 0;
-        int m;
-        do {
-            for (m = l; m < n - 1; ++m) {
-                double dd = std::fabs(dg[m]) + std::fabs(dg[m + 1]);
-                if (std::fabs(e[m]) <= eps * dd) break;
+    int hi = n - 1, steps = 0;
+    while (hi > 0) {
+        // deflate negligible couplings at the bottom, then find the trailing
+        // unreduced block [lo, hi] (couplings inside it tested on the way up)
+        auto small = [&](int i) { return std::fabs(e[i]) <= eps * (std::fabs(dg[i]) + std::fabs(dg[i + 1])); };
+        while (hi > 0 && small(hi - 1)) e[--hi] = 0.0;
+        if (hi == 0) break;
+        int lo = hi - 1;
+        while (lo > 0 && !small(lo - 1)) --lo;
+        if (lo > 0) e[lo - 1] = 0.0;
+        if (++steps > 60 * n) return false;
+        // Wilkinson shift: the eigenvalue of the trailing 2x2 block nearer dg[hi]
+        const double dd = 0.5 * (dg[hi - 1] - dg[hi]);
+        const double bb = e[hi - 1];
+        const double mu = dg[hi] - bb * bb / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, bb));
+        double x = dg[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r > 0.0 ? x / r : 1.0, sn = r > 0.0 ? z / r : 0.0;
+            if (k > lo) e[k - 1] = r;  // the bulge below e[k-1] is rotated away
+            const double p = dg[k], q = dg[k + 1], ek = e[k];
+            dg[k] = c * c * p + 2.0 * c * sn * ek + sn * sn * q;
+            dg[k + 1] = sn * sn * p - 2.0 * c * sn * ek + c * c * q;
+            e[k] = c * sn * (q - p) + (c * c - sn * sn) * ek;
+            rots.push_back({k, c, sn});
+            if (k + 1 < hi) {
+                x = e[k];
+                z = sn * e[k + 1];  // new bulge at (k+2, k)
+                e[k + 1] *= c;
             }
-            if (m != l) {
-                if (++iter > 60) return false;
-                double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
-                g = dg[m] - dg[l] + e[l] / (g + std::copysign(r, g));
-                double s = 1.0, c = 1.0, p = 0.0;
-                int i;
-                bool early = false;
-                for (i = m - 1; i >= l; --i) {
-                    double f = s * e[i], b = c * e[i];
-                    r = std::hypot(f, g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {
-                        dg[i + 1] -= p;
-                        e[m] = 0.0;
-                        early = true;
-                        break;
-                    }
-                    s = f / r;
-                    c = g / r;
-                    g = dg[i + 1] - p;
-                    r = (dg[i] - g) * s + 2.0 * c * b;
-                    p = s * r;
-                    dg[i + 1] = g + p;
-                    g = c * r - b;
-                    rots.push_back({i, c, s});
-                }
-                if (early) continue;
-                dg[l] -= p;
-                e[l] = g;
-                e[m] = 0.0;
-            }
-        } while (m != l);
+        }
     }
     // Z^T rows = columns of Z; start from identity and replay rotations
     std::vector<double> ZT(static_cast<size_t>(n) * n, 0.0);
@@ -213,9 +209,9 @@ bool gen_eig_banded(int n, int bw, const double* K, const double* M, double* U, 
             double* zi = &ZT[static_cast<size_t>(R.i) * n];
             double* zj = &ZT[static_cast<size_t>(R.i + 1) * n];
             for (int c = c0; c < c1; ++c) {
-                double f = zj[c];
-                zj[c] = R.s * zi[c] + R.c * f;
-                zi[c] = R.c * zi[c] - R.s * f;
+                const double u = zi[c], v = zj[c];
+                zi[c] = R.c * u + R.s * v;
+                zj[c] = R.c * v - R.s * u;
             }
         }
     });
