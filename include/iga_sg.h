@@ -51,7 +51,7 @@ typedef enum {
     IGA_ERR_STATE = 7          /* call order violated */
 } iga_status;
 
-/* Knot grading of the solution knot vectors (Sec. 4.3): breakpoint i of
+/* Knot grading of the solution knot vectors (Sec. 4.4): breakpoint i of
  * level l is g(i / 2^l).  RADICAL is the paper's two-sided map
  * g(t) = 2^(gamma-1) t^gamma for t <= 1/2 and 1 - 2^(gamma-1) (1-t)^gamma
  * otherwise; TOWARD0 / TOWARD1 grade toward one end: t^gamma, 1-(1-t)^gamma. */
@@ -202,7 +202,7 @@ typedef struct {
 } iga_sg_report;
 
 /* Build a plan: index set and combination coefficients (eq. TD-combi-tec),
- * knot vectors per level (Sec. 3; grading Sec. 4.3), Gauss rules, 1D
+ * knot vectors per level (Sec. 3; grading Sec. 4.4), Gauss rules, 1D
  * stiffness/mass matrices and their generalised eigen-decompositions for the
  * fast-diagonalisation preconditioner, task lists.  Host only; no GPU call. */
 iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc, iga_sg_plan* out);

@@ -9,7 +9,7 @@
  * What it computes, in the paper's order:
  *   - open knot vectors of the dyadic level sequence (Sec. 3, univariate
  *     sequence Xi_alpha with 2^alpha elements), optionally graded with the
- *     radical map of Sec. 4.3;
+ *     radical map of Sec. 4.4;
  *   - B-splines by the Cox-de Boor recursion, eq. (Bsp), with 0/0 = 0;
  *   - the geometry map F of eq. (F-B-splines), rational (NURBS) when weights
  *     are given;
@@ -76,7 +76,7 @@ int orc_gauss_legendre(int n, double* x, double* w) {
 /* ------------------------------------------------------------------------ */
 /* knot vectors                                                              */
 /* ------------------------------------------------------------------------ */
-/* Breakpoint map t -> xi.  RADICAL is the two-sided map of Sec. 4.3 (the
+/* Breakpoint map t -> xi.  RADICAL is the two-sided map of Sec. 4.4 (the
  * printed fraction t^g / (1/2^(g-1)) equals 2^(g-1) t^g, continuous at 1/2);
  * TOWARD0 / TOWARD1 grade toward one end only. */
 double orc_grade(int gkind, double gamma, double t) {

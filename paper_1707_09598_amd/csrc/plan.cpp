@@ -1,6 +1,6 @@
 // plan.cpp -- host plan of the sparse-grid isogeometric solver: index set and
 // combination coefficients (eq. TD-combi-tec), dyadic knot vectors (Sec. 3)
-// with optional grading (Sec. 4.3), Gauss rules, 1D stiffness/mass matrices
+// with optional grading (Sec. 4.4), Gauss rules, 1D stiffness/mass matrices
 // and their generalised eigen-decompositions (fast diagonalisation), the
 // component grids, operator tiles, preconditioner blocks and the device
 // workspace layout.  No GPU call is made here.

@@ -35,5 +35,5 @@ def annulus_quadrature(nc: int, nq: int = 4):
 
 def low_regular_annulus(W, J, r=2):
     """The paper's low-regular problem: quarter annulus, a = 1, f = 1, no exact
-    solution (Sec. 4.2, Table 3)."""
+    solution (Sec. 4.3, Table 3)."""
     return W.config("cfg2", w=J, r=r, f=W._field("const", 1.0), a=W._field("const", 1.0), exact=None)

@@ -70,7 +70,7 @@ def _config(name, w):
     (a = exp(g) on a 24^3 vertex grid, seed 0).  Variants: '_c0' / '_c1'
     lower the continuity (interior knots of multiplicity p or p - 1),
     '_graded' uses radical knots (two-sided in direction 1, toward 0 in
-    direction 2; eq. of Sec. 4.3)."""
+    direction 2; eq. of Sec. 4.4)."""
     if name == "cfg5":
         a = W.grf_samples(1, n=24)[0]
         return W.config(name, w=w, a=W._field("grid3d", data=a))

@@ -135,7 +135,7 @@ def test_gpu_rate_low_regular_annulus(S, precision, low_regular_reference):
 
 @pytest.mark.parametrize("gamma", [2.0, 3.0])
 def test_gpu_rate_low_regular_annulus_radical_mesh(S, gamma):
-    """Radical knots (Sec. 4.3, two-sided map with exponent gamma in both
+    """Radical knots (Sec. 4.4, two-sided map with exponent gamma in both
     directions) on the low-regular problem: the paper reports that the rate
     grows with gamma up to a maximum (its rate-against-gamma figure).  GPU
     solves at levels 5-9 against the oracle's level-12 solution on the same
