@@ -265,13 +265,18 @@ iga_status iga_sg_solve(iga_sg_plan plan, const iga_sg_solve_opts* opts, iga_sg_
 /* u_dev[s * n + i] = sum_c coef_c u_{s,c}(xi_i), eq. (TD-combi-tec), for every
  * sample s (u_dev holds nsamples * n values), accumulated in FP64 in
  * component order.  xi_dev [n][dim] parametric points in [0,1]^dim,
- * patch_dev [n] patch ids or NULL (patch 0). */
+ * patch_dev [n] patch ids or NULL (patch 0).  grad_dev (NULL: not computed)
+ * receives the physical gradient of the same sum, [nsamples][n][dim]:
+ * grad_x u = DF^-T grad_xi u (the discrete functions are B / W on the
+ * geometry map F of eq. (F-B-splines), so grad_xi (v / W) =
+ * (grad_xi v - (v / W) grad_xi W) / W), FP64 (the H1 errors of Sec. 4). */
 iga_status iga_sg_combine(iga_sg_plan plan, const double* xi_dev, const int* patch_dev, int64_t n,
-                          double* u_dev);
+                          double* u_dev, double* grad_dev);
 
-/* u_dev[i] = u_comp(xi_i) for one component instance (s * ncomp + c). */
+/* u_dev[i] = u_comp(xi_i) (and grad_dev [n][dim] its physical gradient, or
+ * NULL) for one component instance (s * ncomp + c). */
 iga_status iga_sg_eval(iga_sg_plan plan, int comp, const double* xi_dev, const int* patch_dev,
-                       int64_t n, double* u_dev);
+                       int64_t n, double* u_dev, double* grad_dev);
 
 /* Copy the interior coefficients of component comp (lexicographic, direction
  * 1 fastest) to out_dev. */

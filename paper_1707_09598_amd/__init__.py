@@ -117,8 +117,8 @@ def lib():
         L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
         L.iga_sg_assemble.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Field)]
         L.iga_sg_solve.argtypes = [vp, C.POINTER(_Opts), C.POINTER(_Report)]
-        L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp]
-        L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp]
+        L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
         L.iga_sg_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         L.iga_sg_rhs.argtypes = [vp, C.c_int, vp]
@@ -383,29 +383,36 @@ class Plan:
         """Enqueue the captured step on the plan's stream."""
         _check(lib().iga_sg_graph_launch(self.h))
 
-    def combine(self, xi, patch=None):
+    def combine(self, xi, patch=None, grad: bool = False):
+        """u_sg at parametric points xi [n, d] ([nsamples, n] for several
+        samples); with grad also its physical gradient ([.., n, d])."""
         import torch
         xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
         n = xi.shape[0]
         u = torch.empty(self.nsamples * n, dtype=torch.float64, device=self.device)
+        g = torch.empty((self.nsamples * n, self.dim), dtype=torch.float64, device=self.device) if grad else None
         pid = None if patch is None else torch.as_tensor(patch, dtype=torch.int32,
                                                          device=self.device).contiguous()
         _check(lib().iga_sg_combine(self.h, C.c_void_p(xi.data_ptr()),
                                     C.c_void_p(pid.data_ptr() if pid is not None else 0), n,
-                                    C.c_void_p(u.data_ptr())))
-        return u.view(self.nsamples, n) if self.nsamples > 1 else u
+                                    C.c_void_p(u.data_ptr()), C.c_void_p(g.data_ptr() if grad else 0)))
+        if self.nsamples > 1:
+            u = u.view(self.nsamples, n)
+            g = g.view(self.nsamples, n, self.dim) if grad else None
+        return (u, g) if grad else u
 
-    def eval(self, comp: int, xi, patch=None):
+    def eval(self, comp: int, xi, patch=None, grad: bool = False):
         import torch
         xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
         n = xi.shape[0]
         u = torch.empty(n, dtype=torch.float64, device=self.device)
+        g = torch.empty((n, self.dim), dtype=torch.float64, device=self.device) if grad else None
         pid = None if patch is None else torch.as_tensor(patch, dtype=torch.int32,
                                                          device=self.device).contiguous()
         _check(lib().iga_sg_eval(self.h, comp, C.c_void_p(xi.data_ptr()),
                                  C.c_void_p(pid.data_ptr() if pid is not None else 0), n,
-                                 C.c_void_p(u.data_ptr())))
-        return u
+                                 C.c_void_p(u.data_ptr()), C.c_void_p(g.data_ptr() if grad else 0)))
+        return (u, g) if grad else u
 
     def coeffs(self, comp: int):
         import torch

@@ -51,7 +51,7 @@ struct Tab1D {
     int ngk;      // geometry knots
     int uniform;  // breakpoints are i / E
     int ldu;      // row stride of the U tables (multiple of 8 elements)
-    int pad1;
+    int lo;       // basis index of the first unknown (1: the first function is a Dirichlet one)
     // double-pool offsets (in elements)
     int64_t oB, oD;       // [Q][p+1] basis values / derivatives at the Gauss points
     int64_t oBg, oDg;     // [Q][pg+1] geometry basis values / derivatives

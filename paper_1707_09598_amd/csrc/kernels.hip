@@ -881,6 +881,184 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
     }
 }
 
+// Geometry of patch pt at parametric point xv from the coarse NURBS (tables
+// T[k] of any grid of the patch): weight W, its parametric gradient dW and
+// the Jacobian DF of F = sum w P B / W (quotient rule), FP64.
+template <int DIM>
+__device__ __forceinline__ void point_geom(const Params& P, const Tab1D* const* T, int pt, const double* xv,
+                                           double* W, double* dW, double DF[DIM][DIM]) {
+    double Ng[3][kMaxPg + 1], dNg[3][kMaxPg + 1];
+    int fg[3] = {0, 0, 0}, pgk[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int a = 0; a <= kMaxPg; ++a) {
+            Ng[k][a] = a == 0 ? 1.0 : 0.0;
+            dNg[k][a] = 0.0;
+        }
+        if (k < DIM) {
+            const double* gk = P.dpool + T[k]->oGkn;
+            pgk[k] = T[k]->pg;
+            const int s = d_find_interval(T[k]->pg, T[k]->ngk, gk, xv[k]);
+            d_basis_funs_m<kMaxPg>(T[k]->pg, gk, s, xv[k], Ng[k], dNg[k]);
+            fg[k] = s - T[k]->pg;
+        }
+    }
+    double Xh[4] = {0, 0, 0, 0}, dXh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    const double* C = P.ctrl + P.ctrl_off[pt];
+#pragma unroll
+    for (int c = 0; c <= kMaxPg; ++c) {
+        if (c > pgk[2]) break;
+#pragma unroll
+        for (int b = 0; b <= kMaxPg; ++b) {
+            if (b > pgk[1]) break;
+#pragma unroll
+            for (int a = 0; a <= kMaxPg; ++a) {
+                if (a > pgk[0]) break;
+                const int64_t idx = (fg[0] + a) + static_cast<int64_t>(P.gn[pt][0]) *
+                                                      ((fg[1] + b) + static_cast<int64_t>(P.gn[pt][1]) * (fg[2] + c));
+                const double v[3] = {Ng[0][a], Ng[1][b], Ng[2][c]};
+                const double dv[3] = {dNg[0][a], dNg[1][b], dNg[2][c]};
+                const double B = v[0] * v[1] * v[2];
+                const double dB[3] = {dv[0] * v[1] * v[2], v[0] * dv[1] * v[2], v[0] * v[1] * dv[2]};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double cp = C[idx * 4 + t];
+                    Xh[t] += cp * B;
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) dXh[k][t] += cp * dB[k];
+                }
+            }
+        }
+    }
+    *W = Xh[3];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) dW[k] = dXh[k][3];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double x = Xh[c] / Xh[3];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) DF[c][k] = (dXh[k][c] - x * dXh[k][3]) / Xh[3];
+    }
+}
+
+// grad_i = grad sum over the grids g0..g1 of the point's patch of c_g u_g at
+// xi_i (c_g = 1 without use_coef), physical coordinates: with v the sum of
+// the B-spline parts (discrete basis B / W), grad_xi (v / W) =
+// (grad_xi v - (v / W) grad_xi W) / W and grad_x = DF^-T grad_xi, FP64.  One
+// thread per point; general Cox-de Boor values and derivatives (any knots).
+template <int PP, int DIM>
+__global__ void __launch_bounds__(kBlock) k_combine_grad(Params P, const double* xi, const int* patch, int64_t n,
+                                                        double* grad, int g0, int g1, int use_coef) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock) {
+        double xv[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double t = xi[i * DIM + k];
+            xv[k] = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        }
+        const int pt = patch ? patch[i] : 0;
+        int gp = g0;  // a grid of the point's patch (its tables hold the patch geometry)
+        while (gp < g1 - 1 && P.grids[gp].patch != pt) ++gp;
+        const Tab1D* Tg[3] = {nullptr, nullptr, nullptr};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) Tg[k] = P.tabs + P.grids[gp].tab[k];
+        double W, dW[DIM], DF[DIM][DIM];
+        point_geom<DIM>(P, Tg, pt, xv, &W, dW, DF);
+        double acc = 0.0, accd[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) accd[k] = 0.0;
+        for (int gi = g0; gi < g1; ++gi) {
+            const Grid& g = P.grids[gi];
+            if (g.patch != pt) continue;
+            double N[DIM][PP + 1], dN[DIM][PP + 1];
+            int ix[DIM][PP + 1];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const Tab1D& T = P.tabs[g.tab[k]];
+                const double* brk = P.dpool + T.oBrk;
+                int lo = 0, hi = T.E;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (xv[k] < brk[mid]) hi = mid;
+                    else lo = mid;
+                }
+                d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + lo * T.m, xv[k], N[k], dN[k]);
+                const int f = lo * T.m - T.lo;  // unknown index of the first nonzero function
+#pragma unroll
+                for (int a = 0; a <= PP; ++a) {
+                    const int j = f + a;
+                    const bool in = j >= 0 && j < g.ni[k];
+                    N[k][a] = in ? N[k][a] : 0.0;
+                    dN[k][a] = in ? dN[k][a] : 0.0;
+                    ix[k][a] = j < 0 ? 0 : (j >= g.ni[k] ? g.ni[k] - 1 : j);
+                }
+            }
+            const double* X = P.x + g.dof_off;
+            double v = 0.0, dv[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) dv[k] = 0.0;
+#pragma unroll
+            for (int c = 0; c <= (DIM > 2 ? PP : 0); ++c) {
+#pragma unroll
+                for (int b = 0; b <= PP; ++b) {
+                    const int64_t row = static_cast<int64_t>(g.ni[0]) *
+                                        (ix[1][b] + (DIM > 2 ? static_cast<int64_t>(g.ni[1]) * ix[2][c] : 0));
+                    const double* Xr = X + row;
+                    double vb = 0.0, db = 0.0;
+#pragma unroll
+                    for (int a = 0; a <= PP; ++a) {
+                        vb += Xr[ix[0][a]] * N[0][a];
+                        db += Xr[ix[0][a]] * dN[0][a];
+                    }
+                    const double n2 = DIM > 2 ? N[2][c] : 1.0;
+                    v += vb * N[1][b] * n2;
+                    dv[0] += db * N[1][b] * n2;
+                    dv[1] += vb * dN[1][b] * n2;
+                    if (DIM > 2) dv[DIM - 1] += vb * N[1][b] * dN[2][c];
+                }
+            }
+            const double cf = use_coef ? g.ccoef : 1.0;
+            acc += cf * v;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) accd[k] += cf * dv[k];
+        }
+        const double u = acc / W;
+        double gh[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) gh[k] = (accd[k] - u * dW[k]) / W;
+        // grad_x = DF^-T gh: solve DF^T y = gh by the adjugate
+        double y[DIM];
+        if constexpr (DIM == 2) {
+            const double det = DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0];
+            // DF^-T = [[DF11, -DF10], [-DF01, DF00]] / det
+            y[0] = (DF[1][1] * gh[0] - DF[1][0] * gh[1]) / det;
+            y[1] = (-DF[0][1] * gh[0] + DF[0][0] * gh[1]) / det;
+        } else {
+            double cof[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                    cof[r][c] = DF[r1][c1] * DF[r2][c2] - DF[r1][c2] * DF[r2][c1];
+                }
+            const double det = DF[0][0] * cof[0][0] + DF[0][1] * cof[0][1] + DF[0][2] * cof[0][2];
+            // (DF^-1)[k][c] = cof[c][k] / det, so (DF^-T gh)_c = sum_k cof[c][k] gh_k / det
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) t += cof[c][k] * gh[k];
+                y[c] = t / det;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) grad[i * DIM + c] = y[c];
+    }
+}
+
 // Assembly kernels specialised for the field kinds of the workloads
 // (coefficient: constant, sin-cos, 3D grid; load: constant, sine product,
 // annulus right-hand side), the run-time switch for any other combination.
@@ -952,6 +1130,21 @@ void launch_combine_p(int dim, bool uni, int blocks, hipStream_t st, const Param
     else if (dim == 2) hipLaunchKernelGGL((k_combine<PP, 2, false>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
     else if (uni) hipLaunchKernelGGL((k_combine<PP, 3, true>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
     else hipLaunchKernelGGL((k_combine<PP, 3, false>), grid, block, 0, st, K, xi, patch, n, u, g0, g1, use_coef);
+}
+hipError_t launch_combine_grad(int dim, int p, int blocks, hipStream_t st, const Params& K, const double* xi,
+                               const int* patch, int64_t n, double* grad, int g0, int g1, int use_coef) {
+    const dim3 grid(blocks), block(kBlock);
+#define IGASG_CG(PP)                                                                                              \
+    if (dim == 2) hipLaunchKernelGGL((k_combine_grad<PP, 2>), grid, block, 0, st, K, xi, patch, n, grad, g0, g1, use_coef); \
+    else hipLaunchKernelGGL((k_combine_grad<PP, 3>), grid, block, 0, st, K, xi, patch, n, grad, g0, g1, use_coef);
+    switch (p) {
+        case 1: IGASG_CG(1) break;
+        case 2: IGASG_CG(2) break;
+        case 3: IGASG_CG(3) break;
+        default: IGASG_CG(4) break;
+    }
+#undef IGASG_CG
+    return hipGetLastError();
 }
 hipError_t launch_combine(int dim, int p, bool uni, int blocks, hipStream_t st, const Params& K, const double* xi,
                           const int* patch, int64_t n, double* u, int g0, int g1, int use_coef) {
@@ -1493,7 +1686,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     return ret;
 }
 
-iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int64_t n, double* u) {
+iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int64_t n, double* u, double* grad) {
     if (!P || (n > 0 && (!xi || !u)) || n < 0) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
@@ -1508,14 +1701,19 @@ iga_status iga_sg_combine(iga_sg_plan P, const double* xi, const int* patch, int
     Params K = make_params(P);
     // the grids of a sample are contiguous (sample-major); sample s writes u + s n
     const int gps = static_cast<int>(P->grids.size()) / P->nsamples;
-    for (int smp = 0; smp < P->nsamples; ++smp)
+    for (int smp = 0; smp < P->nsamples; ++smp) {
         HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, smp * gps, (smp + 1) * gps), blocks_for(n), st, K, xi, patch, n,
                               u + smp * n, smp * gps, (smp + 1) * gps, 1));
+        if (grad)
+            HIP_OK(launch_combine_grad(P->dim, P->p, blocks_for(n), st, K, xi, patch, n, grad + smp * n * P->dim,
+                                       smp * gps, (smp + 1) * gps, 1));
+    }
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }
 
-iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* patch, int64_t n, double* u) {
+iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* patch, int64_t n, double* u,
+                       double* grad) {
     if (!P || comp < 0 || comp >= ninstances(P) || (n > 0 && (!xi || !u)) || n < 0) {
         set_error("invalid arguments");
         return IGA_ERR_INVALID_ARG;
@@ -1535,6 +1733,7 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
     HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, g0, g1), blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
+    if (grad) HIP_OK(launch_combine_grad(P->dim, P->p, blocks_for(n), st, K, xi, patch, n, grad, g0, g1, 0));
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }

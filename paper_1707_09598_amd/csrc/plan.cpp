@@ -421,6 +421,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 T.nk = static_cast<int>(U.size());
                 T.nb = T.nk - p - 1;
                 T.ni = T.nb - 2;
+                T.lo = 1;
                 T.E = 1 << lev;
                 T.Q = T.E * nq;
                 T.m = p - r;

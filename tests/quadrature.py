@@ -1,5 +1,6 @@
-"""Quadrature on the quarter annulus for the L2 norm of a difference of two
-solutions (test infrastructure).
+"""Quadrature for L2 norms of differences of solutions (test infrastructure):
+Gauss points of uniform parametric meshes weighted by |det DF| of the
+workload's map; the quarter annulus in closed form.
 
 The map of the quarter annulus with radii 1 and 2 is F(xi) = (1 + xi_1) A(xi_2)
 with A the rational quadratic quarter arc of the unit circle (control points
@@ -9,14 +10,23 @@ parametric cells, weights times |det DF|."""
 import numpy as np
 
 
-def annulus_quadrature(nc: int, nq: int = 4):
+def param_gauss(dim: int, nc: int, nq: int = 4):
+    """Tensor Gauss-Legendre points of a uniform parametric mesh of [0,1]^dim
+    with nc cells per direction (direction 1 fastest) and their parametric
+    weights."""
     g, w = np.polynomial.legendre.leggauss(nq)
     g, w = (g + 1.0) / 2.0, w / 2.0
     t = ((np.arange(nc)[:, None] + g[None, :]) / nc).ravel()
     wt = np.tile(w, nc) / nc
-    X1, X2 = np.meshgrid(t, t, indexing="ij")
-    W1, W2 = np.meshgrid(wt, wt, indexing="ij")
-    xi = np.stack([X1.ravel(), X2.ravel()], axis=1)
+    grids = np.meshgrid(*([t] * dim), indexing="ij")
+    wgs = np.meshgrid(*([wt] * dim), indexing="ij")
+    xi = np.stack([gk.ravel() for gk in grids], axis=1)
+    wq = np.prod(np.stack([wk.ravel() for wk in wgs], axis=1), axis=1)
+    return xi, wq
+
+
+def annulus_detjac(xi):
+    """|det DF| of the quarter annulus map at parametric points xi [n, 2]."""
     s = 1.0 / np.sqrt(2.0)
     u = xi[:, 1]
     B = [(1 - u) ** 2, 2 * u * (1 - u), u ** 2]
@@ -29,8 +39,29 @@ def annulus_quadrature(nc: int, nq: int = 4):
     dN = [sum(wk * b * p[c] for wk, b, p in zip(wts, dB, P)) for c in range(2)]
     A = [n / Wt for n in N]
     dA = [(dn * Wt - n * dW) / Wt ** 2 for n, dn in zip(N, dN)]
-    det = (1.0 + xi[:, 0]) * np.abs(A[0] * dA[1] - A[1] * dA[0])
-    return xi, W1.ravel() * W2.ravel() * det
+    return (1.0 + xi[:, 0]) * np.abs(A[0] * dA[1] - A[1] * dA[0])
+
+
+def annulus_quadrature(nc: int, nq: int = 4):
+    xi, wq = param_gauss(2, nc, nq)
+    return xi, wq * annulus_detjac(xi)
+
+
+def weighted_points(wl, nc: int):
+    """Gauss points (p+1 per direction) of a uniform parametric mesh and the
+    weights w_q |det DF| of the workload's map: the quarter annulus in closed
+    form; identity maps (unit square and cube) have det DF = 1."""
+    d = int(wl["dim"])
+    xi, wq = param_gauss(d, nc, int(wl["p"]) + 1)
+    pt = wl["patches"][0]
+    if len(wl["patches"]) == 1 and pt.get("weights") is not None:
+        wq = wq * annulus_detjac(xi)
+    return xi, wq
+
+
+def weighted_rel(u, ref, wq):
+    """Relative L2 error of u against ref under the quadrature weights wq."""
+    return float(np.sqrt(np.sum(wq * (u - ref) ** 2) / np.sum(wq * ref ** 2)))
 
 
 def low_regular_annulus(W, J, r=2):

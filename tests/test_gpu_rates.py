@@ -67,8 +67,18 @@ def test_gpu_sparse_grid_rates_regular_annulus(S, precision):
                       max_refine=12 if precision != "fp64" else 3, continue_cg=precision != "fp64")
         assert np.all(rep["status"] == 0)
         Po = O.Problem(wl)
+        co = Po.solve_all()
         e_gpu = Po.sg_errors(_oracle_layout(P, Po), 128)
-        e_orc = Po.sg_errors(Po.solve_all(), 128)
+        e_orc = Po.sg_errors(co, 128)
+        # the GPU solution itself, value and gradient, at weighted Gauss points
+        from quadrature import annulus_quadrature, weighted_rel
+        xq, wq = annulus_quadrature(32)
+        ug, gg = P.combine(xq, grad=True)
+        uo, go = Po.sg_eval(co, xq, grad=True)
+        bar_u = 1e-10 if precision == "fp64" else 1e-9
+        assert weighted_rel(ug.cpu().numpy(), uo, wq) <= bar_u
+        gn = np.sqrt(np.sum(wq[:, None] * go ** 2))
+        assert np.sqrt(np.sum(wq[:, None] * (gg.cpu().numpy() - go) ** 2)) <= 10 * bar_u * gn
         # [L2 error, H1 error, L2 norm, H1 norm]: the errors differ by at most
         # the distance between the two solutions (triangle inequality), which
         # the parity bar bounds relative to the norm of u
@@ -87,13 +97,14 @@ def test_gpu_sparse_grid_rates_regular_annulus(S, precision):
 @pytest.fixture(scope="module")
 def low_regular_reference():
     """Oracle solutions of the low-regular annulus problem at the quadrature
-    points: the level-12 reference and levels 5-9."""
+    points, values and physical gradients: the level-12 reference and levels
+    5-9."""
     from quadrature import annulus_quadrature, low_regular_annulus
     xi, wq = annulus_quadrature(256)
     sols = {}
     for J in (12, 5, 6, 7, 8, 9):
         Po = O.Problem(low_regular_annulus(W, J))
-        sols[J] = Po.sg_eval(Po.solve_all(), xi)
+        sols[J] = Po.sg_eval(Po.solve_all(), xi, grad=True)
         log(f"  oracle level {J} evaluated")
     return xi, wq, sols
 
@@ -101,15 +112,19 @@ def low_regular_reference():
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_gpu_rate_low_regular_annulus(S, precision, low_regular_reference):
     """The paper's low-regular problem (quarter annulus, f = 1; Table 3, d = 2,
-    p = 3, C^2: SG-IGA L2 rate 1.58, provable 1.5) solved on the GPU at levels
-    5-9: L2 errors against the oracle's level-12 solution (Gauss quadrature,
-    256 x 256 cells) equal those of the oracle's own solutions to the parity
-    bar, and the fitted rate is within 0.2 of 1.5 and 0.3 of 1.58."""
+    p = 3, C^2: SG-IGA L2 rate 1.58, provable 1.5; H1 rate 1.19, provable 1)
+    solved on the GPU at levels 5-9: the GPU values and gradients at the
+    quadrature points (Gauss, 256 x 256 cells, weights w_q |det DF|) equal
+    the oracle's solution of the same level to the parity bar, the L2 and H1
+    errors against the oracle's level-12 solution equal the oracle's own, and
+    the fitted L2 rate is within 0.2 of 1.5 and 0.3 of 1.58, the H1 rate
+    within 0.3 of 1 and of 1.19."""
     import torch
-    from quadrature import low_regular_annulus
+    from quadrature import low_regular_annulus, weighted_rel
     xi, wq, sols = low_regular_reference
-    ur = sols[12]
+    ur, gr = sols[12]
     nrm = np.sqrt(np.sum(wq * ur ** 2))
+    gnrm = np.sqrt(np.sum(wq[:, None] * gr ** 2))
     xt = torch.as_tensor(xi, device="cuda")
     bar = 1e-10 if precision == "fp64" else 1e-9
     rows = []
@@ -121,16 +136,24 @@ def test_gpu_rate_low_regular_annulus(S, precision, low_regular_reference):
         rep = P.solve(precision=precision, tol=1e-12, tol_inner=1e-4, maxit=600,
                       max_refine=12 if precision != "fp64" else 3, continue_cg=precision != "fp64")
         assert np.all(rep["status"] == 0)
-        u = P.combine(xt).cpu().numpy()
+        u, g = P.combine(xt, grad=True)
+        u, g = u.cpu().numpy(), g.cpu().numpy()
+        uo, go = sols[J]
+        assert weighted_rel(u, uo, wq) <= bar
+        assert np.sqrt(np.sum(wq[:, None] * (g - go) ** 2)) <= 10 * bar * gnrm
         e_gpu = np.sqrt(np.sum(wq * (u - ur) ** 2)) / nrm
-        e_orc = np.sqrt(np.sum(wq * (sols[J] - ur) ** 2)) / nrm
-        assert abs(e_gpu - e_orc) <= bar
-        rows.append((J, e_gpu))
-        log(f"  J={J} ndof={int(P.ndof.sum())} relative L2 {e_gpu:.3e}")
+        e_orc = np.sqrt(np.sum(wq * (uo - ur) ** 2)) / nrm
+        h_gpu = np.sqrt(np.sum(wq[:, None] * (g - gr) ** 2)) / gnrm
+        h_orc = np.sqrt(np.sum(wq[:, None] * (go - gr) ** 2)) / gnrm
+        assert abs(e_gpu - e_orc) <= bar and abs(h_gpu - h_orc) <= 10 * bar
+        rows.append((J, e_gpu, h_gpu))
+        log(f"  J={J} ndof={int(P.ndof.sum())} relative L2 {e_gpu:.3e} H1 {h_gpu:.3e}")
     r = np.array(rows)
     l2 = -np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0]
-    log(f"  L2 rate over J=5..9: {l2:.2f} (Table 3: 1.58, provable 1.5)")
+    h1 = -np.polyfit(r[:, 0], np.log2(r[:, 2]), 1)[0]
+    log(f"  rates over J=5..9: L2 {l2:.2f} (Table 3: 1.58, provable 1.5), H1 {h1:.2f} (Table 3: 1.19, provable 1)")
     assert abs(l2 - 1.5) < 0.2 and abs(l2 - 1.58) < 0.3
+    assert abs(h1 - 1.0) < 0.3 and abs(h1 - 1.19) < 0.3
 
 
 @pytest.mark.parametrize("gamma", [2.0, 3.0])
@@ -164,6 +187,7 @@ def test_gpu_rate_low_regular_annulus_radical_mesh(S, gamma):
         u = P.combine(xt).cpu().numpy()
         Po = O.Problem(wl(J))
         uo = Po.sg_eval(Po.solve_all(), xi)
+        assert np.sqrt(np.sum(wq * (u - uo) ** 2)) <= 1e-10 * np.sqrt(np.sum(wq * uo ** 2))
         e_gpu = np.sqrt(np.sum(wq * (u - ur) ** 2)) / nrm
         e_orc = np.sqrt(np.sum(wq * (uo - ur) ** 2)) / nrm
         assert abs(e_gpu - e_orc) <= 1e-10

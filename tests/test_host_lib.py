@@ -105,7 +105,7 @@ def test_call_order_state_errors(S):
     assert L.iga_sg_assemble(P.h, C.byref(f), C.byref(f), None) == 7
     o = S._Opts(0, 1, 1e-12, 1e-4, 100, 0, 0, 0, 0, 0, 0, 0, 0)
     assert L.iga_sg_solve(P.h, C.byref(o), None) == 7
-    assert L.iga_sg_combine(P.h, C.c_void_p(8), None, 1, C.c_void_p(8)) == 7
+    assert L.iga_sg_combine(P.h, C.c_void_p(8), None, 1, C.c_void_p(8), None) == 7
     assert b"before" in L.iga_sg_last_error()
     # the graph of a step: capture before bind, launch before capture
     assert L.iga_sg_graph_capture(P.h, C.byref(f), C.byref(f), C.byref(o)) == 7

@@ -272,6 +272,12 @@ def test_polynomial_reproduction(dim, p, r, grading, amp, nq):
     assert np.abs(u - ref).max() < tol
     for lv, c in zip(P.components()[0], P.split(coefs)):
         assert np.abs(P.eval(lv, c, pts) - ref).max() < tol
+    # the gradient of the reproduced polynomial is reproduced as well
+    _, g = P.sg_eval(coefs, pts, grad=True)
+    q = pts * (1 - pts)
+    for k in range(dim):
+        dk = (1 - 2 * pts[:, k]) * np.prod(np.delete(q, k, axis=1), axis=1)
+        assert np.abs(g[:, k] - dk).max() < 10 * tol, k
     if amp == 0:
         # the plain p+1 rule with a varying coefficient is not exact
         wl2 = dict(wl, a=_fld("sincos", 0.5, 0.1), f=_fld("poly_rhs", 0.5, 0.1))
@@ -315,3 +321,28 @@ def test_dirichlet_lifting_patch_test():
     off = np.array([[-1, 0], [0, 0], [-1, -1]], float)
     x = pts + off[pid]
     assert np.abs(u - (1 + x[:, 0] + 2 * x[:, 1])).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg5"])
+def test_gradient_chain_rule_by_central_differences(name):
+    """The physical gradient of a discrete solution on a curved rational map
+    (quarter annulus) and on the cube: for every parametric direction k,
+    grad u . dF/dxi_k equals du/dxi_k, both derivatives taken by central
+    differences of the oracle's point values and of the map itself (so a
+    transposed Jacobian or a missing weight-function term fails)."""
+    wl = W.config(name, w=3) if name == "cfg2" else W.config(name, w=2, a=_fld("const", 1.0))
+    P = O.Problem(wl)
+    lv = P.components()[0][len(P.components()[0]) // 2]
+    c, _ = P.solve(lv)
+    d = P.dim
+    pts, _ = W.eval_points(d, 40, seed=21)
+    pts = 0.05 + 0.9 * pts
+    _, g = P.eval(lv, c, pts, grad=True)
+    h = 1e-6
+    for k in range(d):
+        e = np.zeros(d)
+        e[k] = h
+        du = (P.eval(lv, c, pts + e) - P.eval(lv, c, pts - e)) / (2 * h)
+        dF = np.array([(P.geometry(x + e)[0] - P.geometry(x - e)[0]) / (2 * h) for x in pts])
+        lhs = np.sum(g * dF, axis=1)
+        assert np.abs(lhs - du).max() < 1e-6 * max(1.0, np.abs(du).max()), k
