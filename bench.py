@@ -1,19 +1,25 @@
 """Benchmark: sparse-grid DOF/s of the batched mixed-precision solve on one MI355X.
 
-Workload: the quarter annulus (exact rational quadratic NURBS map, radii 1-2)
-with a(x) = 1 + 0.5 sin(2 pi x) cos(2 pi y), the paper's smooth annulus
-solution as manufactured u, degree 3, C^2, combination level w = 10:
-21 anisotropic component grids, 22,545 unknowns.  Synthetic, seeded inputs.
+Headline workload (the largest single-GPU workload of the method's
+benchmarks): the random-field unit cube, -div(a grad u) = 1 with a = exp(g),
+g a seeded Gaussian random field (squared-exponential covariance, correlation
+length 0.2, sigma 1) on a 64^3 vertex grid, degree 3, C^2, combination level
+w = 7: 85 anisotropic component grids per coefficient sample, 256 samples
+planned together and solved in one persistent launch, 4,713,728 unknowns.
+Synthetic, seeded inputs; fields resident in HBM before the timed region.
 
-One step = the whole hot path on the GPU: assembly (geometry, coefficients,
-load vectors) of every component grid, the batched persistent solve (FP64
-refinement around FP32 fast-diagonalisation PCG, or plain FP64), and the
-combination u_sg = sum c_i u_i at the evaluation set E (2^16 seeded random
-points + the 1024^2 cell midpoints of a uniform parametric lattice).  The
-plan (knots, 1D matrices and their eigen-decompositions) is data-independent
-setup and is timed separately.
+One step = the timed region of the paper's cost measurements (Sec. 4.1: setup
+and solve, evaluation excluded): assembly of every component system of every
+sample, then the batched persistent solve.  Mode C (the line's value): FP32
+operator and FP32 fast-diagonalisation factors inside FP64 refinement; mode B
+(fp64_comparator): plain FP64 FD-PCG on the same launch.  Both to the
+preconditioned relative residual tol = 1e-10, checked against the oracle's
+direct solves of sampled coefficient samples (relative L2 of u_sg on weighted
+Gauss points and on random points).  The combination u_sg = sum c_i u_i of
+every sample is timed separately (combine_ms).  The plan (knots, 1D
+matrices, eigen-decompositions) is data-independent setup, timed separately.
 
-value = sum of component unknowns / (ms_per_step / 1e3).
+value = 256 x 18,413 unknowns / (ms_per_step / 1e3).
 """
 from __future__ import annotations
 
@@ -31,19 +37,19 @@ sys.path.insert(0, ROOT)
 METRIC = "sparse-grid DOF/s to 1e-9 rel L2: batched mixed/learned PCG vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 
-# Memory traffic of the solve kernel (k_solve<3, FP32 factors> on this workload,
-# with the plan and launch code that shape it)
-# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
-# scaled by what the same counters read for a plain 256 MiB device copy in the
-# same runs (fetch 131088 KiB, write 262144 KiB).  Valid only for the kernel
-# sources it was measured on: their hash is checked at run time.
+# Memory traffic of the solve kernel of the headline step (k_solve<3, FP32
+# factors, 3D, 256-thread build; mode C on the 256-sample launch) from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by
+# what the same counters read for a plain device copy of known size in the
+# same runs.  Valid only for the kernel sources and tolerances it was
+# measured with: their hash is checked at run time (null otherwise).
 SOLVE_TRAFFIC = {
-    "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve_p3.hip",
+    "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve3_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "ce18183dae6c0d85a55f394be9735fa97195510de99a5085d39d3e07a6402b15",
-    "fetch_kib": 1107423.3, "write_kib": 318550.7,
-    "fetch_factor": 262144.0 / 131088.9, "write_factor": 262144.0 / 262144.0,
+    "sha256": None,
+    "fetch_kib": None, "write_kib": None,
+    "fetch_factor": None, "write_factor": None,
     "tol": 1e-10, "tol_inner": 1e-05,
 }
 
@@ -58,9 +64,9 @@ def sources_sha256(paths):
 
 
 def solve_traffic_bytes(tol, tol_inner):
-    """HBM bytes per launch of the mixed-precision solve from the stored
-    counter runs, or None once the kernel sources or the tolerances (which set
-    the number of iterations a launch runs) differ from the measured ones."""
+    """HBM bytes per launch of the headline solve from the stored counter
+    runs, or None once the kernel sources or the tolerances (which set the
+    number of iterations a launch runs) differ from the measured ones."""
     T = SOLVE_TRAFFIC
     if T["sha256"] is None or T["fetch_kib"] is None or sources_sha256(T["sources"]) != T["sha256"]:
         return None
@@ -74,64 +80,63 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=256, help="coefficient samples in the headline launch")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16fd", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-inner", type=float, default=1e-5)
-    ap.add_argument("--restart", action="store_true",
-                    help="classic refinement: restart CG at each FP64 residual replacement")
-    ap.add_argument("--lattice", type=int, default=1024)
+    ap.add_argument("--tile", type=int, default=1024,
+                    help="3D operator tile (unknowns) of the headline launch; 0: autotuned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=5, help="repetitions of each oracle timing (median)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator run")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-trace", action="store_true", help="skip the phase-traced extra solve")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner comparison on the random-field cube")
     ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
-    ap.add_argument("--tune", action="store_true",
-                    help="pick the launch shape of each mode with the autotuner first (its timing runs "
-                         "add solve dispatches of other shapes to a profile of the run)")
+    ap.add_argument("--no-annulus", action="store_true", help="skip the quarter-annulus (cfg2) measurements")
     ap.add_argument("--no-graph", action="store_true",
-                    help="skip the run with assembly + solve replayed as one HIP graph")
+                    help="skip the annulus run with assembly + solve replayed as one HIP graph")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the unit-square (modes A/B) and unit-cube (modes B/C) measurements")
-    ap.add_argument("--batch-samples", type=int, default=64,
-                    help="coefficient samples of the random-field cube solved in one launch (0: skip)")
-    ap.add_argument("--batch-tile", type=int, default=0,
-                    help="3D operator tile (unknowns) of the random-field batch; 0: autotuned")
+    ap.add_argument("--tune", action="store_true", help="autotune the annulus launch shape")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline step (profiling runs): no extras, no CPU baseline")
     return ap.parse_args()
 
 
-def algorithmic_bytes(P, rep, precision):
-    """Bytes the solve kernel must stream for the iterations it ran.
+def _ncompG(wl):
+    rational = any(pt.get("weights") is not None for pt in wl["patches"])
+    return {(2, False): 3, (2, True): 6, (3, False): 6, (3, True): 10}[(int(wl["dim"]), rational)]
 
-    Per CG iteration of a grid: the operator coefficients at every Gauss point
-    (ncompG values of 4 B in the FP32 inner operator, 8 B in FP64), the FD
-    factors U of both directions read twice (forward and backward; 8/4/2 B),
-    eight FP64 vector passes over the grid's unknowns and two reads of the
-    FP64 diagonal scaling (forward and backward transform).  Each refinement
-    step adds one FP64 operator application and one FD application.
+
+def solve_bytes(P, rep, precision):
+    """Algorithmic bytes of one solve launch: what the method must stream
+    for the CG iterations and refinement sweeps it ran.
+
+    Unit: one grid unknown per CG iteration.  Per CG iteration of grid g the
+    operator coefficients at its Gauss points (ncompG values, 4 B in the
+    FP32 inner operator, 8 B in FP64) and 64 B per unknown of FP64 vectors
+    (eight passes); per refinement sweep the FP64 coefficients and the same
+    vector bytes.  The 1D factors U_l are shared by every grid of a level and
+    charged once per distinct table and sweep (forward and backward reads).
     """
     wl = P.wl
-    rational = any(pt.get("weights") is not None for pt in wl["patches"])
-    ncompG = {(2, False): 3, (2, True): 6, (3, False): 6, (3, True): 10}[(int(wl["dim"]), rational)]
-    p = int(wl["p"])
-    bop_in = {"fp64": 8, "fp32": 4, "bf16fd": 4}[precision]
-    bu = {"fp64": 8, "fp32": 4, "bf16fd": 2}[precision]
+    ncompG, p, d = _ncompG(wl), int(wl["p"]), int(wl["dim"])
+    b_in = {"fp64": 8, "fp32": 4, "bf16fd": 4}[precision]
+    b_u = {"fp64": 8, "fp32": 4, "bf16fd": 2}[precision]
     total = 0.0
     for c in range(P.ninst):  # instances: component c % ncomp of sample c // ncomp
         lv = P.levels[c % P.ncomp]
-        nb = [2 ** int(l) + p for l in lv]  # C^{p-1}: 2^l + p basis functions
-        ni = [n - 2 for n in nb]
-        nqp = np.prod([2 ** int(l) * (p + 1) for l in lv])
-        ndof = np.prod(ni)
-        fd_u = 2 * sum(n * n for n in ni)
-        it = int(rep["iters"][c])
-        rf = int(rep["refinements"][c])
-        total += it * (ncompG * nqp * bop_in + fd_u * bu + 80 * ndof)
-        total += rf * (ncompG * nqp * 8 + fd_u * bu + 80 * ndof)
+        ni = [2 ** int(l) + p - 2 for l in lv]  # C^{p-1}: 2^l + p basis functions, 2 on the boundary
+        nqp = float(np.prod([2 ** int(l) * (p + 1) for l in lv]))
+        ndof = float(np.prod(ni))
+        it, rf = int(rep["iters"][c]), int(rep["refinements"][c])
+        total += it * (ncompG * nqp * b_in + 64 * ndof) + rf * (ncompG * nqp * 8 + 64 * ndof)
+    sweeps = int(np.max(rep["iters"] + 2 * rep["refinements"]))
+    levels = sorted({int(l) for lv in P.levels for l in lv})
+    total += sweeps * sum(2 * (2 ** l + p - 2) ** 2 * b_u for l in levels) * d
     return float(total)
 
 
@@ -141,18 +146,132 @@ def assembly_bytes(P):
     load vector, the preconditioner scaling and log a (FP64); the coefficient
     field and the 1D tables are read on top."""
     wl = P.wl
-    rational = any(pt.get("weights") is not None for pt in wl["patches"])
-    ncompG = {(2, False): 3, (2, True): 6, (3, False): 6, (3, True): 10}[(int(wl["dim"]), rational)]
-    p = int(wl["p"])
+    ncompG, p = _ncompG(wl), int(wl["p"])
     nqp = sum(int(np.prod([2 ** int(l) * (p + 1) for l in lv])) for lv in P.levels) * P.nsamples
     return float(nqp * (12 * ncompG + 8) + int(P.ndof.sum()) * P.nsamples * 24)
 
 
+def cube_points():
+    """Evaluation points of the random-field cube for the accuracy checks:
+    the Gauss points (4 per direction) of a 4^3 uniform parametric mesh with
+    their weights (identity map: |det DF| = 1), and 4096 seeded random
+    points."""
+    g, w = np.polynomial.legendre.leggauss(4)
+    t = ((np.arange(4)[:, None] + (g[None, :] + 1) / 2) / 4).ravel()
+    wt = np.tile(w / 2, 4) / 4
+    X = np.stack([a.ravel() for a in np.meshgrid(t, t, t, indexing="ij")], axis=1)
+    Wq = np.prod(np.stack([a.ravel() for a in np.meshgrid(wt, wt, wt, indexing="ij")], axis=1), axis=1)
+    import workloads as W
+    xr, _ = W.eval_points(3, 4096, seed=12345)
+    return np.ascontiguousarray(X), Wq, xr
+
+
+def accuracy(u_gauss, u_rand, ref):
+    """Relative L2 errors against an oracle reference (weighted Gauss points,
+    plain l2 on the random points); the larger one is reported."""
+    rg, wq, rr = ref
+    eg = float(np.sqrt(np.sum(wq * (u_gauss - rg) ** 2) / np.sum(wq * rg ** 2)))
+    er = float(np.linalg.norm(u_rand - rr) / np.linalg.norm(rr))
+    return max(eg, er)
+
+
+def timed(P, torch, step, K, W):
+    """W untimed steps, then K steps; returns the wall ms per step (host
+    clock over the K steps, bracketed by device synchronisations) and the
+    mean assembly and solve times by HIP events on the plan's stream."""
+    for _ in range(W):
+        step(None)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    t0 = time.perf_counter()
+    for k in range(K):
+        step(ev[k])
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / K
+    t_asm = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)]))
+    t_sol = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)]))
+    return wall, t_asm, t_sol
+
+
+def headline(S, W, torch, args, refs):
+    """Modes C (value) and B (comparator) on the 256-sample launch."""
+    from paper_1707_09598_amd import tune
+    ns = args.samples
+    fields = W.grf_samples(ns, n=64)
+    wl = W.config("cfg5", a=W._field("grid3d", data=fields[0]))
+    a_all = W._field("grid3d", data=torch.as_tensor(fields, device="cuda:0"))
+    del fields
+    modes = [("C", dict(precision=args.precision, max_refine=12, continue_cg=True, tol_inner=args.tol_inner))]
+    if not args.no_fp64 and args.precision != "fp64":
+        modes.append(("B", dict(precision="fp64", max_refine=3)))
+    out = {}
+    xg, wq, xr = cube_points()
+    xg_t = torch.as_tensor(xg, device="cuda:0")
+    xr_t = torch.as_tensor(xr, device="cuda:0")
+    for key, kw in modes:
+        kw = dict(kw, tol=args.tol, maxit=600)
+        if args.tile > 0:
+            shape, tried = {"op_tile3": args.tile}, None
+        else:
+            tu = tune.autotune(wl, kw, shapes=[{"op_tile3": t} for t in (256, 512, 1024)], repeats=2,
+                               nsamples=ns, fields={"a": a_all})
+            shape, tried = tu["shape"], {str(t["shape"]["op_tile3"]): round(t["ms"], 3) for t in tu["tried"]}
+        t0 = time.perf_counter()
+        P = S.Plan(wl, nsamples=ns, shape=shape)
+        t_plan = time.perf_counter() - t0
+        P.bind(device="cuda:0")
+        st = P.stream
+
+        def step(ev):
+            if ev is not None:
+                ev[0].record(st)
+            P.assemble(a=a_all)
+            if ev is not None:
+                ev[1].record(st)
+            P.solve_async(**kw)
+            if ev is not None:
+                ev[2].record(st)
+
+        wall, t_asm, t_sol = timed(P, torch, step, args.steps, args.warmup)
+        # one more step with the report (iterations, refinements, status)
+        P.assemble(a=a_all)
+        rep = P.solve(check=False, **kw)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        ug = P.combine(xg_t)
+        e1.record(st)
+        ur = P.combine(xr_t)
+        torch.cuda.synchronize()
+        t_cmb = e0.elapsed_time(e1)
+        ug, ur = ug.cpu().numpy(), ur.cpu().numpy()
+        err = {str(s): accuracy(ug[s], ur[s], refs[s]) for s in refs if s < ns}
+        ndof = int(P.ndof.sum()) * ns
+        algo = solve_bytes(P, rep, kw["precision"])
+        asm = assembly_bytes(P) + 8 * ns * 64 ** 3
+        out[key] = {
+            "precision": kw["precision"], "wall_ms": wall, "ms_assemble": t_asm, "ms_solve": t_sol,
+            "dof_per_s": ndof / (wall / 1e3), "unknowns": ndof, "plan_host_s": t_plan,
+            "combine_ms": t_cmb, "combine_points_per_sample": len(xg),
+            "codes": int(rep["code"]), "status_nonzero": int(np.count_nonzero(rep["status"])),
+            "cg_iterations": int(rep["total_iters"]), "refinements_max": int(rep["refinements"].max()),
+            "rel_l2_vs_oracle": err, "launch_shape": shape, "autotune_ms": tried,
+            "solve_bytes": algo,
+            "solve_roofline_frac": algo / (t_sol / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "assembly_bytes": asm,
+            "assembly_roofline_frac": asm / (t_asm / 1e3) / 1e9 / HBM_PEAK_GBS,
+        }
+        del P
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_mode(S, W, torch, precision, args, xi):
+    """One mode on the quarter annulus (cfg2): a step is assembly, the
+    batched solve and the combination at E (timed by HIP events per stage)."""
     wl = W.config("cfg2")
     kw = dict(precision=precision, tol=args.tol, tol_inner=args.tol_inner, maxit=400,
               max_refine=12 if precision != "fp64" else 3, batched=True,
-              continue_cg=not args.restart)
+              continue_cg=True)
     shape, tuned = {}, None
     if args.tune:
         # launch shape picked by timing the candidates on this workload and mode
@@ -197,15 +316,10 @@ def run_mode(S, W, torch, precision, args, xi):
     rep = P.solve(**kw)
     u = P.combine(xi_t).cpu().numpy()
     trace = None
-    if not args.no_trace:
-        P.assemble()
-        tr = P.solve(timing=2, **kw)
-        trace = {"sweeps": tr["sweeps"], "phase_wall_us": [round(v, 2) for v in tr["phase_us"][:3]],
-                 "phase_busy_us": [round(v, 2) for v in tr["phase_us"][3:]]}
     # the same step with assembly + solve replayed as one HIP graph (a plan on
     # a created stream: the default stream cannot be captured)
     graph = None
-    if not args.no_graph:
+    if not args.no_graph and precision != "fp64":
         gs = torch.cuda.Stream()
         with torch.cuda.stream(gs):
             Pg = S.Plan(wl, shape=shape)
@@ -234,6 +348,33 @@ def run_mode(S, W, torch, precision, args, xi):
         "t_cmb": t_cmb, "t_plan_s": t_plan, "ndof": int(P.ndof.sum()), "trace": trace,
         "shape": shape, "tuned": tuned, "graph": graph,
     }
+
+
+
+def run_annulus(S, W, torch, args, xi, sub, u_ref):
+    """The quarter annulus (cfg2, 21 grids, 22,545 unknowns): modes C and B
+    with the combination at E = 2^16 random points + the 1024^2 lattice
+    midpoints inside the step, and mode C with assembly + solve replayed as
+    one HIP graph."""
+    res = {"workload": "cfg2: 2D quarter annulus (rational quadratic NURBS), a = 1 + 0.5 sin(2 pi x) "
+                       "cos(2 pi y), p=3 C^2, level w=10, 21 component grids, 22545 unknowns, "
+                       f"|E| = {len(xi)} evaluation points in the step"}
+    for key, prec in (("C_mixed", args.precision), ("B_fp64", "fp64")):
+        r = run_mode(S, W, torch, prec, args, xi)
+        e = float(np.linalg.norm(r["u"][sub] - u_ref) / np.linalg.norm(u_ref)) if u_ref is not None else None
+        res[key] = {"dof_per_s": r["ndof"] / (r["wall_ms"] / 1e3), "ms_per_step": r["wall_ms"],
+                    "breakdown_ms": {"assemble": r["t_asm"], "solve": r["t_sol"], "combine": r["t_cmb"]},
+                    "cg_iterations": int(r["rep"]["total_iters"]), "rel_l2_vs_oracle": e,
+                    "launch_shape": r["shape"] or "library default"}
+        if r["graph"] is not None:
+            g = r["graph"]
+            res[key]["graph_step"] = {
+                "dof_per_s": r["ndof"] / (g["wall_ms"] / 1e3), "ms_per_step": g["wall_ms"],
+                "breakdown_ms": {"assemble_solve": g["t_step"], "combine": g["t_cmb"]},
+                "rel_l2_vs_oracle": (float(np.linalg.norm(g["u"][sub] - u_ref) / np.linalg.norm(u_ref))
+                                     if u_ref is not None else None)}
+    res["speedup_C_vs_B"] = res["C_mixed"]["dof_per_s"] / res["B_fp64"]["dof_per_s"]
+    return res
 
 
 def run_learned(S, W, torch, args, ref):
@@ -307,66 +448,6 @@ def run_learned(S, W, torch, args, ref):
     return out
 
 
-def run_batched(S, W, torch, args, ref):
-    """The random-field cube at full size (w=7, a = exp(GRF) on a 64^3 grid)
-    with batch_samples coefficient samples in one plan and one persistent
-    launch: assembly + solve timed by HIP events, FP64 (B) and mixed (C)."""
-    from paper_1707_09598_amd import tune
-    ns = args.batch_samples
-    fields = W.grf_samples(ns, n=64)
-    wl = W.config("cfg5", a=W._field("grid3d", data=fields[0]))
-    a_all = W._field("grid3d", data=torch.as_tensor(fields, device="cuda:0"))
-    out = {"samples": ns}
-    for key, kw in (("B_fp64", dict(precision="fp64", max_refine=3)),
-                    ("C_mixed", dict(precision="fp32", max_refine=12, continue_cg=True))):
-        kw = dict(kw, tol=1e-10, tol_inner=args.tol_inner, maxit=600)
-        # operator tile picked by the autotuner for this batch and mode (or given)
-        if args.batch_tile > 0:
-            tuned = {"shape": {"op_tile3": args.batch_tile}, "tried": []}
-        else:
-            tuned = tune.autotune(wl, kw, shapes=[{"op_tile3": t} for t in (256, 512, 1024)], repeats=2,
-                                  nsamples=ns, fields={"a": a_all})
-        P = S.Plan(wl, nsamples=ns, shape=tuned["shape"])
-        P.bind(device="cuda:0")
-        ndof = int(P.ndof.sum()) * ns
-        out["workload"] = (f"cfg5: unit cube, a = exp(GRF on a 64^3 vertex grid, corr. length 0.2, sigma 1), "
-                           f"f = 1, p=3 C^2, w=7, {ns} samples x 85 grids in one launch, {ndof} unknowns, tol 1e-10")
-        out["unknowns"] = ndof
-        P.assemble(a=a_all)
-        rep = P.solve(check=False, **kw)
-        ms = []
-        for _ in range(3):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            ev[0].record(P.stream)
-            P.assemble(a=a_all)
-            ev[1].record(P.stream)
-            P.solve_async(**kw)
-            ev[2].record(P.stream)
-            torch.cuda.synchronize()
-            ms.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
-        t_asm, t_sol = float(np.median([m[0] for m in ms])), float(np.median([m[1] for m in ms]))
-        algo = algorithmic_bytes(P, rep, kw["precision"])
-        u = P.combine(ref[0])[0].cpu().numpy()
-        # assembly: operator coefficients (FP64 and FP32), load density, load
-        # vector, preconditioner scaling and log a written once, the field read once
-        asm_bytes = assembly_bytes(P) + fields.nbytes
-        out[key] = {"dof_per_s": ndof / ((t_asm + t_sol) / 1e3), "ms_assemble": t_asm, "ms_solve": t_sol,
-                    "launch_shape": tuned["shape"],
-                    "autotune_ms": {str(t["shape"]["op_tile3"]): round(t["ms"], 3) for t in tuned["tried"]},
-                    "assembly_roofline": {"bound": "hbm", "achieved": asm_bytes / (t_asm / 1e3) / 1e9,
-                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                          "frac": asm_bytes / (t_asm / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                          "algorithmic_bytes": asm_bytes},
-                    "codes": int(rep["code"]), "cg_iterations": int(rep["total_iters"]),
-                    "rel_l2_vs_oracle_sample0": float(np.linalg.norm(u - ref[1]) / np.linalg.norm(ref[1])),
-                    "solve_roofline": {"bound": "hbm", "achieved": algo / (t_sol / 1e3) / 1e9,
-                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                       "frac": algo / (t_sol / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                       "algorithmic_bytes_per_launch": algo}}
-    out["speedup_C_vs_B"] = out["C_mixed"]["dof_per_s"] / out["B_fp64"]["dof_per_s"]
-    return out
-
-
 def run_small_configs(S, W, torch, refs):
     """The two other single-patch workloads, each at its full size, measured
     the same way (assembly + solve, HIP events on the plan's stream, median of
@@ -427,70 +508,128 @@ def run_small_configs(S, W, torch, refs):
     return out
 
 
-def cpu_baseline_leg(args, W, xi, sub):
-    """The CPU side of the benchmark, the only part that runs the oracle: its
-    timing on the annulus workload (unless --no-cpu-baseline) and the
-    reference values every accuracy figure of the line compares against
-    (oracle direct solves of the same workloads and samples, evaluated at the
-    points the GPU legs evaluate)."""
-    import oracle as O
-    if not args.no_cpu_baseline:
-        cpu, coefs, Po = cpu_baseline(O, W, xi, args.cpu_seconds)
-    else:
-        cpu = None
-        Po = O.Problem(W.config("cfg2"))
-        coefs = Po.solve_all()
-    refs = {"cfg2": Po.sg_eval(coefs, xi[sub])}
-
-    def cube_ref(a):
-        P = O.Problem(W.config("cfg5", a=W._field("grid3d", data=a)))
-        xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
-        return xi3, P.sg_eval(P.solve_all(), xi3)
-
-    # random-field samples are seeded by their index: sample 0 of the batch,
-    # the first held-out sample of the learned comparison
-    if args.batch_samples > 0:
-        refs["cfg5_batch"] = cube_ref(W.grf_samples(1, n=64)[0])
-    if not args.no_learned:
-        refs["cfg5_learned"] = cube_ref(W.grf_samples(args.learned_train + 1, n=64)[args.learned_train])
-    if not args.no_small:
-        for name in ("cfg1", "cfg3"):
-            wl = W.config(name)
-            P = O.Problem(wl)
-            xi_n, _ = W.eval_points(wl["dim"], 32768, lattice=0, seed=777)
-            refs[name] = (xi_n, P.sg_eval(P.solve_all(), xi_n))
-    return cpu, refs
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the cores this process may use
+    (capped at 16, the host share of one GPU)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, max(1, min(16, n))
 
 
-def cpu_baseline(O, W, xi, seconds):
-    """The oracle (serial C, FP64) on the same workload: assembly + direct
-    solves of all 21 components + combination at the first 2^16 points of E
-    (a bounded sample of the evaluation step, scaled to the full E)."""
-    wl = W.config("cfg2")
-    Po = O.Problem(wl)
-    n_e = min(len(xi), 65536)
-    reps, t_solve, t_eval = 0, 0.0, 0.0
-    coefs = None
-    t_start = time.perf_counter()
-    while reps == 0 or time.perf_counter() - t_start < seconds:
-        t0 = time.perf_counter()
-        coefs = Po.solve_all()
-        t1 = time.perf_counter()
-        u = Po.sg_eval(coefs, xi[:n_e])
-        t2 = time.perf_counter()
-        t_solve += t1 - t0
-        t_eval += t2 - t1
-        reps += 1
-    t_solve /= reps
-    t_eval = t_eval / reps * (len(xi) / n_e)
-    ndof = sum(int(np.prod([n - 2 for n in Po.nbasis(l)])) for l in Po.components()[0])
+def cpu_baseline(O, W, args):
+    """The oracle (FP64 C, -O3 -march=native on this host) on the headline
+    workload's samples, each (sample, grid) a direct solve: assembly, profile
+    Cholesky, one refinement step (the paper's timed setup + solve).
+
+      serial      one sample, its 85 grids in turn on one core (median of runs)
+      all-core    `cores` samples x 85 grids on `cores` threads, the grids
+                  taken longest first (LPT list scheduling, Sec. 4.1), median
+                  of runs: the reported value
+      LPT-sim     the paper's simulated parallel time: the serial per-grid
+                  times of those samples assigned longest first to the first
+                  free of `cores` cores (makespan)
+    """
+    from concurrent.futures import ThreadPoolExecutor
+    model, cores = host_cpu()
+    fields = W.grf_samples(cores, n=64)
+    probs = [O.Problem(W.config("cfg5", a=W._field("grid3d", data=fields[s]))) for s in range(cores)]
+    levels = probs[0].components()[0]
+    ndof = sum(int(np.prod([n - 2 for n in probs[0].nbasis(l)])) for l in levels)
+    runs = []
+    for _ in range(args.cpu_runs):
+        ts = []
+        for l in levels:
+            t0 = time.perf_counter()
+            probs[0].solve(l)
+            ts.append(time.perf_counter() - t0)
+        runs.append(ts)
+    per_grid = np.median(np.array(runs), axis=0)
+    t_serial = float(np.median([sum(r) for r in runs]))
+    order = sorted(((per_grid[g], s, g) for s in range(cores) for g in range(len(levels))), reverse=True)
+    load = np.zeros(cores)
+    for t, _, _ in order:
+        load[int(np.argmin(load))] += t
+    t_lpt = float(load.max())
+    par = []
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        for _ in range(args.cpu_runs):
+            t0 = time.perf_counter()
+            list(ex.map(lambda o: probs[o[1]].solve(levels[o[2]]), order))
+            par.append(time.perf_counter() - t0)
+    t_par = float(np.median(par))
     return {
-        "value": ndof / (t_solve + t_eval), "unit": "DOF/s", "cores": 1, "kind": "oracle",
-        "sample": (f"full cfg2 assembly + 21 direct solves (profile Cholesky + 1 refinement "
-                   f"step), x{reps} repetitions, plus combination at {n_e} of the {len(xi)} "
-                   f"evaluation points scaled to all of E; serial FP64 C"),
-        "assemble_solve_ms": 1e3 * t_solve, "combine_ms_scaled": 1e3 * t_eval,
-    }, coefs, Po
+        "value": cores * ndof / t_par, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{cores} random-field samples of the headline workload (85 grids, {ndof} unknowns each) "
+                   f"solved by the oracle's direct solver on {cores} threads, grids longest first; "
+                   f"median of {args.cpu_runs} runs; serial C FP64, gcc -O3 -march=native"),
+        "cpu_model": model,
+        "serial": {"value": ndof / t_serial, "seconds_per_sample": t_serial, "cores": 1},
+        "all_cores_lpt_order": {"value": cores * ndof / t_par, "seconds": t_par},
+        "lpt_simulated": {"value": cores * ndof / t_lpt, "makespan_s": t_lpt,
+                          "note": "serial per-grid times scheduled longest first on the cores (Sec. 4.1)"},
+    }
+
+
+def cpu_leg(args, W, xi, sub):
+    """The CPU side of the benchmark, the only part that runs the oracle: its
+    timing (unless --no-cpu-baseline) and the reference values every accuracy
+    figure compares against (oracle direct solves of the same workloads and
+    samples at the points the GPU legs evaluate)."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    O.use_native()
+    cpu = None if args.no_cpu_baseline else cpu_baseline(O, W, args)
+    xg, wq, xr = cube_points()
+
+    def cube_ref(s):
+        a = W.grf_samples(1, n=64, first_seed=s)[0]
+        Po = O.Problem(W.config("cfg5", a=W._field("grid3d", data=a)))
+        co = Po.solve_all()
+        return Po.sg_eval(co, xg), wq, Po.sg_eval(co, xr)
+
+    def annulus_ref():
+        Po = O.Problem(W.config("cfg2"))
+        return Po.sg_eval(Po.solve_all(), xi[sub])
+
+    def learned_ref():
+        s = args.learned_train
+        Po = O.Problem(W.config("cfg5", a=W._field("grid3d", data=W.grf_samples(1, n=64, first_seed=s)[0])))
+        xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
+        return xi3, Po.sg_eval(Po.solve_all(), xi3)
+
+    def small_ref(name):
+        wl = W.config(name)
+        Po = O.Problem(wl)
+        xi_n, _ = W.eval_points(wl["dim"], 32768, lattice=0, seed=777)
+        return xi_n, Po.sg_eval(Po.solve_all(), xi_n)
+
+    _, cores = host_cpu()
+    jobs = {("cube", s): (cube_ref, s) for s in sorted({0, args.samples - 1})}
+    if not args.no_annulus:
+        jobs["cfg2"] = (annulus_ref,)
+    if not args.no_learned:
+        jobs["learned"] = (learned_ref,)
+    if not args.no_small:
+        jobs["cfg1"] = (small_ref, "cfg1")
+        jobs["cfg3"] = (small_ref, "cfg3")
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        fut = {k: ex.submit(v[0], *v[1:]) for k, v in jobs.items()}
+        res = {k: f.result() for k, f in fut.items()}
+    refs = {"cube": {k[1]: v for k, v in res.items() if isinstance(k, tuple)}}
+    for k in ("cfg2", "learned", "cfg1", "cfg3"):
+        refs[k] = res.get(k)
+    return cpu, refs
 
 
 def main():
@@ -505,6 +644,8 @@ def main():
     import paper_1707_09598_amd as S
     import workloads as W
     S.lib()  # fail loudly if the HIP library is missing
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_learned = args.no_annulus = args.no_small = True
     if args.calibrate_copy > 0:
         # plain copy of a known size: reads and writes calibrate the HBM counters
         n = args.calibrate_copy * (1 << 20) // 8
@@ -514,30 +655,24 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    xi, _ = W.eval_points(2, 65536, lattice=args.lattice, seed=12345)
+    xi, _ = W.eval_points(2, 65536, lattice=1024, seed=12345)
+    sub = np.random.default_rng(1).choice(len(xi), size=65536, replace=False)
+    if args.headline_only:
+        cpu, refs = None, {"cube": {}}
+    else:
+        cpu, refs = cpu_leg(args, W, xi, sub)
+        print(f"[bench] oracle leg done", file=sys.stderr, flush=True)
 
-    main_run = run_mode(S, W, torch, args.precision, args, xi)
-    fp64_run = None
-    if not args.no_fp64 and args.precision != "fp64":
-        fp64_run = run_mode(S, W, torch, "fp64", args, xi)
-
-    # accuracy against the oracle at the evaluation points
-    sub = np.random.default_rng(1).choice(len(xi), size=min(len(xi), 65536), replace=False)
-    cpu, refs = cpu_baseline_leg(args, W, xi, sub)
-    u_ref = refs["cfg2"]
-    err = float(np.linalg.norm(main_run["u"][sub] - u_ref) / np.linalg.norm(u_ref))
-    err64 = None
-    if fp64_run is not None:
-        err64 = float(np.linalg.norm(fp64_run["u"][sub] - u_ref) / np.linalg.norm(u_ref))
-
-    ms = main_run["wall_ms"]  # wall clock per step over the timed region
-    ndof = main_run["ndof"]
-    value = ndof / (ms / 1e3)
-    algo = algorithmic_bytes(main_run["plan"], main_run["rep"], args.precision)
-    achieved = algo / (main_run["t_sol"] / 1e3) / 1e9
+    head = headline(S, W, torch, args, refs["cube"])
+    print(f"[bench] headline done", file=sys.stderr, flush=True)
+    C = head["C"]
+    ms = C["wall_ms"]
+    ndof = C["unknowns"]
+    worst = max(C["rel_l2_vs_oracle"].values()) if C["rel_l2_vs_oracle"] else None
+    achieved = C["solve_bytes"] / (C["ms_solve"] / 1e3) / 1e9
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": ndof / (ms / 1e3),
         "unit": "DOF/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -549,60 +684,46 @@ def main():
         "dtype": {"fp32": "f32+f64", "bf16fd": "bf16+f32+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": "cfg2: 2D quarter annulus (rational quadratic NURBS), a = 1 + 0.5 sin(2 pi x) "
-                        "cos(2 pi y), p=3 C^2, level w=10, 21 component grids, 22545 unknowns, "
-                        f"|E| = {len(xi)} evaluation points",
-            "mode": f"batched persistent solve, {args.precision} inner PCG, FP64 refinement",
-            "tol": args.tol, "tol_inner": args.tol_inner,
-            "launch_shape": main_run["shape"] or "library default",
+            "workload": (f"cfg5: unit cube, -div(a grad u) = 1, a = exp(GRF on a 64^3 vertex grid, corr. "
+                         f"length 0.2, sigma 1), p=3 C^2, level w=7; {args.samples} coefficient samples x 85 "
+                         f"component grids in one persistent launch, {ndof} unknowns"),
+            "mode": f"C: batched persistent solve, {args.precision} inner PCG, FP64 refinement",
+            "tol": args.tol, "tol_inner": args.tol_inner, "launch_shape": C["launch_shape"],
+            "step": "assembly + solve of every sample (combination timed separately)",
         },
-        "rel_l2_vs_oracle": err,
-        "breakdown_ms": {"assemble": main_run["t_asm"], "solve": main_run["t_sol"],
-                         "combine": main_run["t_cmb"], "plan_host_s": main_run["t_plan_s"],
-                         "wall_per_step": main_run["wall_ms"]},
-        "paper_timed_region_dof_per_s": ndof / ((main_run["t_asm"] + main_run["t_sol"]) / 1e3),
-        "graph_step": (None if main_run["graph"] is None else {
-            "mode": "assembly + solve replayed as one HIP graph (cooperative solve node), combination eager",
-            "dof_per_s": ndof / (main_run["graph"]["wall_ms"] / 1e3),
-            "ms_per_step": main_run["graph"]["wall_ms"],
-            "breakdown_ms": {"assemble_solve": main_run["graph"]["t_step"], "combine": main_run["graph"]["t_cmb"]},
-            "rel_l2_vs_oracle": float(np.linalg.norm(main_run["graph"]["u"][sub] - u_ref) / np.linalg.norm(u_ref)),
-        }),
-        "cg_iterations": int(main_run["rep"]["total_iters"]),
-        "refinements_max": int(main_run["rep"]["refinements"].max()),
-        "solve_trace": main_run["trace"],
-        "autotune_ms": ({"{}".format(t["shape"]): round(t["ms"], 3) for t in main_run["tuned"]["tried"]}
-                        if main_run["tuned"] else None),
+        "rel_l2_vs_oracle": worst,
+        "rel_l2_vs_oracle_per_sample": C["rel_l2_vs_oracle"],
+        "breakdown_ms": {"assemble": C["ms_assemble"], "solve": C["ms_solve"], "wall_per_step": ms,
+                         "combine_4096_points_per_sample": C["combine_ms"], "plan_host_s": C["plan_host_s"]},
+        "cg_iterations": C["cg_iterations"], "refinements_max": C["refinements_max"],
+        "codes": C["codes"], "status_nonzero": C["status_nonzero"],
+        "assembly_roofline_frac": C["assembly_roofline_frac"],
         "roofline": {
-            "bound": "hbm", "kernel": "k_solve (persistent refinement + FD-PCG)",
+            "bound": "hbm", "kernel": "k_solve (persistent refinement + FD-PCG, 3D, FP32 factors)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": solve_traffic_bytes(args.tol, args.tol_inner),
-            "algorithmic_bytes_per_launch": algo, "avg_launch_ms": main_run["t_sol"],
+            "algorithmic_bytes_per_launch": C["solve_bytes"], "avg_launch_ms": C["ms_solve"],
         },
         "cpu_baseline": cpu,
     }
-    if fp64_run is not None:
-        ms64 = fp64_run["wall_ms"]
+    if "B" in head:
+        B = head["B"]
         line["fp64_comparator"] = {
-            "value": ndof / (ms64 / 1e3), "ms_per_step": ms64, "rel_l2_vs_oracle": err64,
-            "breakdown_ms": {"assemble": fp64_run["t_asm"], "solve": fp64_run["t_sol"],
-                             "combine": fp64_run["t_cmb"]},
-            "cg_iterations": int(fp64_run["rep"]["total_iters"]),
-            "solve_trace": fp64_run["trace"],
-            "launch_shape": fp64_run["shape"] or "library default",
+            "value": B["dof_per_s"], "ms_per_step": B["wall_ms"],
+            "rel_l2_vs_oracle": max(B["rel_l2_vs_oracle"].values()) if B["rel_l2_vs_oracle"] else None,
+            "breakdown_ms": {"assemble": B["ms_assemble"], "solve": B["ms_solve"]},
+            "cg_iterations": B["cg_iterations"], "codes": B["codes"],
+            "solve_roofline_frac": B["solve_roofline_frac"], "launch_shape": B["launch_shape"],
         }
-        line["speedup_vs_fp64"] = line["value"] / line["fp64_comparator"]["value"]
-    if cpu is not None:
-        cpu = dict(cpu)
-        cpu.pop("assemble_solve_ms", None)
-        cpu.pop("combine_ms_scaled", None)
-        line["cpu_baseline"] = cpu
-    if args.batch_samples > 0:
-        line["batched_cfg5"] = run_batched(S, W, torch, args, refs["cfg5_batch"])
+        line["speedup_vs_fp64"] = line["value"] / B["dof_per_s"]
+    if not args.no_annulus:
+        line["annulus_cfg2"] = run_annulus(S, W, torch, args, xi, sub, refs["cfg2"])
+        print(f"[bench] annulus done", file=sys.stderr, flush=True)
     if not args.no_learned:
-        line["learned_cfg5"] = run_learned(S, W, torch, args, refs["cfg5_learned"])
+        line["learned_cfg5"] = run_learned(S, W, torch, args, refs["learned"])
+        print(f"[bench] learned done", file=sys.stderr, flush=True)
     if not args.no_small:
-        line.update(run_small_configs(S, W, torch, refs))
+        line.update(run_small_configs(S, W, torch, {"cfg1": refs["cfg1"], "cfg3": refs["cfg3"]}))
     print(json.dumps(line), flush=True)
 
 

@@ -29,13 +29,31 @@ WITH_BOUNDARY = 1
 MASS = 2
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (portable x86-64 flags, -O3)."""
-    if force or not os.path.exists(_SO):
-        cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-march=x86-64-v2",
-               "-o", _SO + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
+_SO_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc -O3: liboracle.so with portable x86-64
+    flags (the library the tests load), or with native=True
+    liboracle_native.so with -march=native for the host it is built on (the
+    CPU baseline's timing build; the source is the same)."""
+    so = _SO_NATIVE if native else _SO
+    if force or not os.path.exists(so):
+        arch = "-march=native" if native else "-march=x86-64-v2"
+        cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", arch,
+               "-o", so + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_SO + ".tmp", _SO)
+        os.replace(so + ".tmp", so)
+    return so
+
+
+def use_native() -> str:
+    """Build the -march=native oracle on this host and make lib() load it;
+    call before the first lib()."""
+    global _SO
+    if _lib is not None and _SO != _SO_NATIVE:
+        raise RuntimeError("the portable oracle is already loaded")
+    _SO = build(force=True, native=True)
     return _SO
 
 
