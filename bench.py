@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16fd", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--tol-inner", type=float, default=1e-5)
-    ap.add_argument("--tile", type=int, default=1024,
+    ap.add_argument("--tile", type=int, default=0,
                     help="3D operator tile (unknowns) of the headline launch; 0: autotuned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-runs", type=int, default=5, help="repetitions of each oracle timing (median)")

@@ -172,11 +172,17 @@ typedef struct {
     int plain_fd;      /* 0: the fast-diagonalisation preconditioner with diagonal scaling,
                           z = S P^-1 S r, S = diag(sqrt(P_ii / A_ii)) (S P S has the
                           diagonal of A); 1: the unscaled pencil, z = P^-1 r */
-    int schedule;      /* task schedule of the persistent solve: 0 library choice (1 when each
-                          workgroup has at most one task per phase, else 2); 1 round robin over the
-                          launch's tasks; 2 round robin over per-sweep lists that hold only
-                          the tasks of grids still iterating.  Results are the same bit for
-                          bit */
+    int schedule;      /* task schedule of the batched solve: 1 round robin over the launch's
+                          tasks; 2 round robin over per-sweep lists that hold only the tasks
+                          of grids still iterating (1 and 2: one cooperative launch whose
+                          phases are separated by grid-wide barriers; the same results bit for
+                          bit); 3 whole grid per workgroup: one workgroup runs the complete
+                          refinement + CG of a grid and takes the next grid from a counter,
+                          largest first (no grid-wide barrier); 0 library choice: 3 when every
+                          grid has one fast-diagonalisation block and at most four operator
+                          tiles, else 1 when each workgroup has at most one task per phase,
+                          else 2.  Schedule 3 follows the same iteration per grid; its
+                          reductions may group differently (rounding) */
 } iga_sg_solve_opts;
 
 /* Per-instance results (component c of sample s at s * ncomp + c); arrays
@@ -231,9 +237,11 @@ iga_status iga_sg_bind_static(iga_sg_plan plan, void* stream);
 
 /* Task counts of a batched solve (operator tiles; fast-diagonalisation tasks
  * with FP64 factors and with FP32/BF16 factors) and the LDS bytes a solve
- * workgroup takes.  Any pointer may be NULL.  Host only. */
+ * workgroup takes (lds_bytes: with the learned preconditioner's activations
+ * in 3D; lds_plain_bytes: a solve without it).  Any pointer may be NULL.
+ * Host only. */
 iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64, int* fd_tasks_lowp,
-                             size_t* lds_bytes);
+                             size_t* lds_bytes, size_t* lds_plain_bytes);
 
 /* Bind a device workspace of at least iga_sg_workspace_bytes bytes and a HIP
  * stream (hipStream_t, NULL = default).  Uploads the plan tables and computes

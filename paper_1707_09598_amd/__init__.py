@@ -20,7 +20,7 @@ FIELD = {None: -1, "none": -1, "const": 0, "sinprod": 1, "sincos": 2, "annulus_r
          "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7}
 GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
-SCHED = {"auto": 0, "static": 1, "lists": 2}
+SCHED = {"auto": 0, "static": 1, "lists": 2, "grid": 3}
 STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_ERR_OUT_OF_MEMORY",
           4: "IGA_ERR_DEVICE", 5: "IGA_ERR_NOT_CONVERGED", 6: "IGA_ERR_BREAKDOWN", 7: "IGA_ERR_STATE"}
 APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5, "fds64": 6}
@@ -111,7 +111,7 @@ def lib():
         vp = C.c_void_p
         L.iga_sg_plan_create.argtypes = [C.POINTER(_Geometry), C.POINTER(_Disc), C.POINTER(vp)]
         L.iga_sg_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
-        L.iga_sg_plan_stats.argtypes = [vp, _ip, _ip, _ip, C.POINTER(C.c_size_t)]
+        L.iga_sg_plan_stats.argtypes = [vp, _ip, _ip, _ip, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.iga_sg_bind.argtypes = [vp, vp, C.c_size_t, vp]
         L.iga_sg_bind_static.argtypes = [vp, vp]
         L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
@@ -260,9 +260,10 @@ class Plan:
     def stats(self) -> Dict[str, int]:
         """Task counts of a batched solve and the LDS bytes per workgroup."""
         a, b, c = C.c_int(), C.c_int(), C.c_int()
-        n = C.c_size_t()
-        _check(lib().iga_sg_plan_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)))
-        return {"op_tasks": a.value, "fd_tasks_fp64": b.value, "fd_tasks_lowp": c.value, "lds_bytes": n.value}
+        n, m = C.c_size_t(), C.c_size_t()
+        _check(lib().iga_sg_plan_stats(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(n), C.byref(m)))
+        return {"op_tasks": a.value, "fd_tasks_fp64": b.value, "fd_tasks_lowp": c.value, "lds_bytes": n.value,
+                "lds_plain_bytes": m.value}
 
     def matrices_1d(self, direction: int, level: int):
         n = C.c_int()

@@ -222,11 +222,12 @@ constexpr size_t kSolveLdsHead = kCtxBytes + kMetaSlots * sizeof(TaskMeta);
 
 // Workspace layout: byte offsets of every device array.
 // Barrier block (unsigned words): generation, finished-grid count, traced
-// sweeps, the global arrival count on its own 64-byte line, the group arrival
+// sweeps, the next grid of the whole-grid solve, the global arrival count on its own 64-byte line, the group arrival
 // counts one line apart; bytes 64..67 hold the assembly error flag.
 // The lengths of the active task lists (operator and fast-diagonalisation,
 // by sweep parity) follow on a line of their own.
-constexpr int kBarGen = 1, kBarDone = 2, kBarSweeps = 3, kBarCount = 32, kBarGroup = 64, kBarStride = 16;
+constexpr int kBarGen = 1, kBarDone = 2, kBarSweeps = 3, kBarNext = 4, kBarCount = 32, kBarGroup = 64,
+              kBarStride = 16;
 constexpr int kBarGroups = 8;
 constexpr int kBarOpLen = kBarGroup + kBarStride * kBarGroups;  // + parity
 constexpr int kBarFdLen = kBarOpLen + 2;                        // + parity

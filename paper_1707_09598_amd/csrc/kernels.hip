@@ -682,6 +682,7 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
         if (threadIdx.x == 0) {
             P.bar[kBarDone] = 0u;
             P.bar[kBarCount] = 0u;
+            P.bar[kBarNext] = 0u;
         }
         if (threadIdx.x < kBarGroups) P.bar[kBarGroup + kBarStride * threadIdx.x] = 0u;
         if (threadIdx.x == 0) {
@@ -1234,10 +1235,10 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
 }
 
 // k_solve<PP, *> lives in one translation unit per degree (solve_p*.hip)
-const void* solve_kernel_p1(int prec, int dim, int narrow);
-const void* solve_kernel_p2(int prec, int dim, int narrow);
-const void* solve_kernel_p3(int prec, int dim, int narrow);
-const void* solve_kernel_p4(int prec, int dim, int narrow);
+const void* solve_kernel_p1(int prec, int dim, int narrow, int grid);
+const void* solve_kernel_p2(int prec, int dim, int narrow, int grid);
+const void* solve_kernel_p3(int prec, int dim, int narrow, int grid);
+const void* solve_kernel_p4(int prec, int dim, int narrow, int grid);
 
 // The persistent solve in 3D comes in two builds: 512-thread workgroups
 // (8 wavefronts, 256 VGPRs with about 1 KB per lane of spills) and 256-thread
@@ -1248,12 +1249,14 @@ const void* solve_kernel_p4(int prec, int dim, int narrow);
 // correction's convolutions).  2D uses the wide build.
 int solve_threads(int dim, int narrow) { return dim == 3 && narrow ? kBlockSolve3 : kBlock; }
 
-const void* solve_kernel(int p, int prec, int dim, int narrow = 0) {
+// grid: the whole-grid solve k_solve_grid built for 1 or 2 workgroups per CU
+// (0: the cooperative k_solve)
+const void* solve_kernel(int p, int prec, int dim, int narrow = 0, int grid = 0) {
     switch (p) {
-        case 1: return solve_kernel_p1(prec, dim, narrow);
-        case 2: return solve_kernel_p2(prec, dim, narrow);
-        case 3: return solve_kernel_p3(prec, dim, narrow);
-        default: return solve_kernel_p4(prec, dim, narrow);
+        case 1: return solve_kernel_p1(prec, dim, narrow, grid);
+        case 2: return solve_kernel_p2(prec, dim, narrow, grid);
+        case 3: return solve_kernel_p3(prec, dim, narrow, grid);
+        default: return solve_kernel_p4(prec, dim, narrow, grid);
     }
 }
 
@@ -1469,8 +1472,10 @@ iga_status bind_impl(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
             HIP_OK(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
         for (int prec : {IGA_PREC_FP64, IGA_PREC_FP32, IGA_PREC_BF16FD})
             for (int narrow = 0; narrow <= (P->dim == 3 ? 1 : 0); ++narrow)
-                HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec, P->dim, narrow),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(P->lds_bytes)));
+                for (int grid = 0; grid <= 2; ++grid)
+                    HIP_OK(hipFuncSetAttribute(solve_kernel(P->p, prec, P->dim, narrow, grid),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(P->lds_bytes)));
     }
     // persistent width: workgroups resident at once for every build of the solve
     int occ = 1 << 20;
@@ -1534,7 +1539,8 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         set_error("iga_sg_solve before iga_sg_assemble");
         return IGA_ERR_STATE;
     }
-    if (o->precision < IGA_PREC_FP64 || o->precision > IGA_PREC_BF16FD || !(o->tol > 0) || o->maxit < 1) {
+    if (o->precision < IGA_PREC_FP64 || o->precision > IGA_PREC_BF16FD || !(o->tol > 0) || o->maxit < 1 ||
+        o->schedule < 0 || o->schedule > 3) {
         set_error("invalid solve options");
         return IGA_ERR_INVALID_ARG;
     }
@@ -1573,6 +1579,15 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             if (!P->ev[i]) HIP_OK(hipEventCreate(reinterpret_cast<hipEvent_t*>(&P->ev[i])));
     hipEvent_t e0 = static_cast<hipEvent_t>(P->ev[0]), e1 = static_cast<hipEvent_t>(P->ev[1]);
     if (o->timing) HIP_OK(hipEventRecord(e0, st));
+    // Whole-grid solve (one workgroup per grid, no grid barrier) for a batched
+    // launch whose grids are each a few tasks: forced by schedule 3, chosen
+    // when every grid has one FD block and at most four operator tiles.
+    bool whole = false;
+    if (o->batched) {
+        bool small = true;
+        for (const Grid& g : grids) small = small && g.nblk == 1 && g.ntile <= 4;
+        whole = o->schedule == 3 || (o->schedule == 0 && small);
+    }
     auto launch = [&](int g0, int g1, int opb, int ope, int fdb, int fde) -> iga_status {
         const int64_t i0 = P->grids[g0].dof_off;
         const int64_t i1 = P->grids[g1 - 1].dof_off + P->grids[g1 - 1].ndof;
@@ -1602,8 +1617,29 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         // both schedules of one launch run the same build and agree bitwise.
         const int narrow = P->dim == 3 && (ope - opb > nwg || fde - fdb > nwg) && !A.learned ? 1 : 0;
         void* args[] = {&K, &A};
+        if (whole) {
+            // whole-grid solve: a plain launch of as many workgroups as are
+            // resident at once (they take the grids from a counter)
+            const int nar = P->dim == 3 && !A.learned ? 1 : 0;
+            const size_t ldsg = A.learned ? lds : P->lds_plain;  // no activations without the network
+            // the two-workgroup build where two fit a CU by LDS, in the mixed
+            // modes (random-field batch of 256 samples, FP32 inner solve, tile
+            // 256: 77.7 against 107 ms; its FP64 operator spills, so plain
+            // FP64 keeps the one-workgroup build)
+            const int waves =
+                o->precision != IGA_PREC_FP64 && 2 * (ldsg + 1024) <= static_cast<size_t>(kLdsLimit) ? 2 : 1;
+            const void* fk = solve_kernel(P->p, o->precision, P->dim, nar, waves);
+            int occg = 0;
+            HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occg, fk, solve_threads(P->dim, nar), ldsg));
+            int nw = std::max(1, std::min(fde - fdb, std::max(1, occg) * P->num_cu));
+            if (o->workgroups > 0) nw = std::min(nw, o->workgroups);
+            HIP_OK(hipLaunchKernel(fk, dim3(nw), dim3(solve_threads(P->dim, nar)), args, ldsg, st));
+            P->last_solve_coop = 0;
+            return IGA_OK;
+        }
         HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim, narrow), dim3(nwg),
                                           dim3(solve_threads(P->dim, narrow)), args, static_cast<unsigned>(lds), st));
+        P->last_solve_coop = 1;
         return IGA_OK;
     };
     if (o->batched) {
@@ -1939,6 +1975,8 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
     if (ge == hipSuccess && nn) ge = hipGraphGetNodes(g, nodes.data(), &nn);
     const void* fsolve = solve_kernel(P->p, o->precision, P->dim, 0);
     const void* fsolve_narrow = solve_kernel(P->p, o->precision, P->dim, 1);
+    // the whole-grid solve is a plain kernel node: nothing to mark
+    const int want_marked = !P->last_solve_coop ? 0 : (o->batched ? 1 : static_cast<int>(P->grids.size()));
     int marked = 0;
     for (size_t i = 0; ge == hipSuccess && i < nn; ++i) {
         hipGraphNodeType t;
@@ -1954,7 +1992,7 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
         ++marked;
     }
     hipGraphExec_t ex = nullptr;
-    if (ge == hipSuccess && marked == (o->batched ? 1 : static_cast<int>(P->grids.size())))
+    if (ge == hipSuccess && marked == want_marked)
         ge = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     else if (ge == hipSuccess)
         ge = hipErrorInvalidValue;

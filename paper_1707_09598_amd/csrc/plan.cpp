@@ -587,7 +587,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         }
     }
     // ---- grids, tiles, preconditioner blocks --------------------------------
-    size_t lds_max = 0;
+    size_t lds_max = 0, lds_op = 0, lds_fd_plain = 0;
     for (int c = 0; c < P->ncomp; ++c)
         for (int pt = 0; pt < geom->npatch; ++pt) {
             Grid g;
@@ -710,6 +710,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
                 const size_t pl = static_cast<size_t>(p + 1) * (p + 1) * (p + 1);
                 lds_max = std::max(lds_max, (halo + nel * pl + kWaves) * sizeof(double));
+                lds_op = std::max(lds_op, (halo + nel * pl + kWaves) * sizeof(double));
             }
             if (d == 2) {
                 size_t halo = 1, nel = 1;
@@ -772,6 +773,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 // + the activations of the learned preconditioner
                 lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total) +
                                                 static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float));
+                lds_fd_plain = std::max(lds_fd_plain, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
             }
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);
@@ -801,6 +803,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         return IGA_ERR_INVALID_ARG;
     }
     P->lds_bytes = lds_max + kSolveLdsHead;  // + task context and cached task descriptions
+    // without the learned preconditioner's activations (3D): the operator
+    // tiles and the FD layouts alone
+    P->lds_plain = (d == 3 ? std::max(lds_op, lds_fd_plain) : lds_max) + kSolveLdsHead;
     // task lists in decreasing grid size (longest-processing-time order)
     std::vector<int> ord(P->grids.size());
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = static_cast<int>(i);
@@ -892,7 +897,7 @@ iga_status iga_sg_workspace_bytes(iga_sg_plan plan, size_t* bytes) {
 }
 
 iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64, int* fd_tasks_lowp,
-                             size_t* lds_bytes) {
+                             size_t* lds_bytes, size_t* lds_plain_bytes) {
     if (!plan) {
         set_error("null plan");
         return IGA_ERR_INVALID_ARG;
@@ -901,6 +906,7 @@ iga_status iga_sg_plan_stats(iga_sg_plan plan, int* op_tasks, int* fd_tasks_fp64
     if (fd_tasks_fp64) *fd_tasks_fp64 = static_cast<int>(plan->fdtask.size());
     if (fd_tasks_lowp) *fd_tasks_lowp = static_cast<int>(plan->fdtask_lp.size());
     if (lds_bytes) *lds_bytes = plan->lds_bytes;
+    if (lds_plain_bytes) *lds_plain_bytes = plan->lds_plain;
     return IGA_OK;
 }
 

@@ -62,6 +62,7 @@ struct iga_sg_plan_s {
     int rational_any = 0;
     int64_t nqp_total = 0, ndof_total = 0;
     size_t lds_bytes = 0;
+    size_t lds_plain = 0;  // LDS of a solve without the learned preconditioner (3D: no activations)
     igasg::Layout lay{};
     // binding
     void* ws = nullptr;
@@ -72,6 +73,7 @@ struct iga_sg_plan_s {
     int max_wg = 0;
     void* ev[8] = {nullptr};  // timing events
     void* gexec = nullptr;    // instantiated graph of one step (iga_sg_graph_capture)
+    int last_solve_coop = 1;  // the last solve launched the cooperative kernel (else the whole-grid one)
     int static_dev = -1;      // device whose static workspace the plan is bound to (iga_sg_bind_static)
     uint64_t static_gen = 0;  // that device's binding count at this plan's binding
     const float* nn = nullptr;  // learned preconditioner parameters (device, caller-owned)

@@ -1646,6 +1646,239 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
     }
 }
 
+// ===========================================================================
+// whole-grid solve: one workgroup runs the complete refinement + PCG of one
+// grid (all its operator tiles and FD blocks in turn) and takes the next grid
+// from a shared counter, in the launch's cost order (largest first).  Every
+// reduction is a workgroup reduction; there is no grid-wide barrier, so a
+// grid that converges early frees its workgroup at once and the grids of a
+// large batch keep every CU busy.  The refinement / CG state machine, the
+// operator tiles and the FD transforms are those of k_solve (decide,
+// op_tile_*, fd*_run), so a grid follows the same iteration as there.
+// ===========================================================================
+template <int PP, int FDP, int DIM>
+__device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs& A, const TaskMeta& M,
+                                               double* slots, double* lds) {
+    using TU = typename FdTypes<FDP>::TU;
+    using TC = typename FdTypes<FDP>::TC;
+    const Grid& g = M.g;
+    const int gi = M.grid;
+    const int64_t N = P.ndof_total;
+    GState st;
+    st.rho = st.rho0 = st.rhob = st.bn2 = st.relres = st.prelres = 0.0;
+    st.stage = STAGE_RESID;
+    st.it = st.total_it = st.refine = 0;
+    st.status = GS_RUNNING;
+    st.pad = 0;
+    double rz = 0.0, zro = 0.0;
+    int pr = 0, pp = 0;  // buffer parities of r and p
+    double* sl = slots;   // partial sum of one tile / block (written by thread 0)
+    double* sl2 = slots + 1;
+    // sum of the per-tile or per-block partials, in tile order (every thread)
+    auto tiles = [&](auto&& body, int n) {
+        double acc = 0.0;
+        for (int t = 0; t < n; ++t) {
+            body(t);
+            __syncthreads();
+            acc += *sl;
+        }
+        return acc;
+    };
+    for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
+        const Decision D = decide(A, st, st.stage == STAGE_ITER ? rz : 0.0);
+        if (D.act == ACT_DONE) {
+            st.stage = STAGE_DONE;
+            st.status = D.status;
+            st.rhob = D.rhob;
+            st.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
+            break;
+        }
+        double* r_cur = P.r2 + pr * N;
+        double* r_oth = P.r2 + (pr ^ 1) * N;
+        double* p_old = P.p2 + pp * N;
+        double* p_new = P.p2 + (pp ^ 1) * N;
+        FdIO fio;
+        fio.rt = P.rt;
+        fio.prec = FDP;
+        fio.scale = P.fdscale;
+        fio.learned = 0;
+        fio.rold = nullptr;
+        fio.part2 = nullptr;
+        fio.z = nullptr;
+        fio.rdot = nullptr;
+        fio.part = sl;
+        if (D.act == ACT_ITER) {
+            // p = z + beta p, q = A p, p.q
+            const bool fresh = st.it == 0 && (!A.continue_cg || st.refine <= 1);
+            const double num = A.learned && st.it > 0 ? D.rho - zro : D.rho;
+            OpIO io;
+            io.in_a = P.z;
+            io.in_b = p_old;
+            io.beta = fresh ? 0.0 : num / st.rho;
+            io.out_in = p_new;
+            io.out = P.q;
+            io.rhs = nullptr;
+            io.part = sl;
+            io.lowp = FDP != 0;
+            const double pq = tiles([&](int t) {
+                if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
+                else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
+            }, g.ntile);
+            if (!(pq > 0.0) || !isfinite(D.rho / pq)) {
+                st.stage = STAGE_DONE;
+                st.status = GS_BREAKDOWN;
+                st.total_it += st.it;
+                break;
+            }
+            // alpha, d += alpha p, r -= alpha q, forward transform
+            fio.alpha = D.rho / pq;
+            fio.r_old = r_cur;
+            fio.q = P.q;
+            fio.r_out = r_oth;
+            fio.dvec = P.d;
+            fio.pvec = p_new;
+            tiles([&](int b) {
+                if constexpr (DIM == 3) {
+                    fd3_issue_fwd<TU>(P, M, r_cur, P.q, p_new, P.d, lds);
+                    g2l_wait_sync();
+                    fd3_fwd_run<TU, TC>(P, M, fio, lds);
+                } else {
+                    __syncthreads();
+                    fd_issue_fwd<TU>(P, M, b, r_cur, P.q, p_new, P.d, lds);
+                    g2l_wait_sync();
+                    fd_fwd_run<TU, TC>(P, M, b, fio, lds);
+                }
+            }, g.nblk);
+            // backward transform -> z, r.z (and z.r_old for flexible CG)
+            fio.z = P.z;
+            fio.rdot = r_oth;
+            fio.learned = DIM == 3 && A.learned && P.nn != nullptr &&
+                          (A.learned_iters == 0 || st.it + 1 < A.learned_iters);
+            fio.rold = r_cur;
+            fio.part2 = DIM == 3 && A.learned ? sl2 : nullptr;
+            double z2 = 0.0;
+            const double rzn = tiles([&](int b) {
+                if constexpr (DIM == 3) {
+                    fd3_issue_bwd<TU>(P, M, P.rt, r_oth, lds);
+                    g2l_wait_sync();
+                    fd3_bwd_run<TU, TC>(P, M, fio, lds);
+                } else {
+                    __syncthreads();
+                    fd_issue_bwd<TU>(P, M, b, P.rt, r_oth, lds);
+                    g2l_wait_sync();
+                    fd_bwd_run<TU, TC>(P, M, b, fio, lds);
+                }
+                if (fio.part2) {
+                    __syncthreads();
+                    z2 += *sl2;
+                }
+            }, g.nblk);
+            st.rhob = D.rhob;
+            st.rho0 = D.rho0;
+            st.stage = STAGE_ITER;
+            st.it += 1;
+            st.rho = D.rho;
+            rz = rzn;
+            zro = z2;
+            pr ^= 1;
+            pp ^= 1;
+        } else {
+            // FP64 residual r = b - A (x + d), then x += d, d = 0
+            OpIO io;
+            io.in_a = P.x;
+            io.in_b = P.d;
+            io.beta = 1.0;
+            io.out_in = nullptr;
+            io.out = r_cur;
+            io.rhs = P.b;
+            io.part = sl;
+            io.lowp = 0;
+            const double rn2 = tiles([&](int t) {
+                if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
+                else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
+            }, g.ntile);
+            for (int o = threadIdx.x; o < g.ndof; o += kBlock) {
+                const int64_t k = g.dof_off + o;
+                P.x[k] += P.d[k];
+                P.d[k] = 0.0;
+            }
+            __syncthreads();
+            fio.alpha = 0.0;
+            fio.r_old = r_cur;
+            fio.q = nullptr;
+            fio.r_out = nullptr;
+            fio.dvec = nullptr;
+            fio.pvec = nullptr;
+            tiles([&](int b) {
+                if constexpr (DIM == 3) {
+                    fd3_issue_fwd<TU>(P, M, r_cur, nullptr, nullptr, nullptr, lds);
+                    g2l_wait_sync();
+                    fd3_fwd_run<TU, TC>(P, M, fio, lds);
+                } else {
+                    __syncthreads();
+                    fd_issue_fwd<TU>(P, M, b, r_cur, nullptr, nullptr, nullptr, lds);
+                    g2l_wait_sync();
+                    fd_fwd_run<TU, TC>(P, M, b, fio, lds);
+                }
+            }, g.nblk);
+            fio.z = P.z;
+            fio.rdot = r_cur;
+            const double rzn = tiles([&](int b) {
+                if constexpr (DIM == 3) {
+                    fd3_issue_bwd<TU>(P, M, P.rt, r_cur, lds);
+                    g2l_wait_sync();
+                    fd3_bwd_run<TU, TC>(P, M, fio, lds);
+                } else {
+                    __syncthreads();
+                    fd_issue_bwd<TU>(P, M, b, P.rt, r_cur, lds);
+                    g2l_wait_sync();
+                    fd_bwd_run<TU, TC>(P, M, b, fio, lds);
+                }
+            }, g.nblk);
+            if (st.stage == STAGE_ITER) {  // end of an inner solve
+                st.total_it += st.it;
+                st.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
+            }
+            st.bn2 = st.refine == 0 ? rn2 : st.bn2;
+            st.relres = st.bn2 > 0.0 ? sqrt(rn2 / st.bn2) : 0.0;
+            st.stage = STAGE_ITER;
+            st.it = 0;
+            st.refine += 1;
+            rz = rzn;
+        }
+    }
+    if (threadIdx.x == 0) {
+        P.st2[gi] = st;
+        P.st2[P.ngrid + gi] = st;
+    }
+    __syncthreads();
+}
+
+// WAVES: workgroups per CU the build is compiled for (register budget); 2
+// lets two workgroups share a CU when their LDS fits (the FP64 operator
+// tile then spills, so only the mixed modes use it)
+template <int PP, int FDP, int DIM, int NT, int WAVES>
+__global__ void __launch_bounds__(NT, WAVES) k_solve_grid(Params P, SolveArgs A) {
+    static_assert(NT == kBlock, "the workgroup size is that of the translation unit's build");
+    extern __shared__ double lds_all[];
+    double* slots = lds_all;  // the context area: the grid handed out, two partial sums
+    TaskMeta* meta = reinterpret_cast<TaskMeta*>(reinterpret_cast<char*>(lds_all) + kCtxBytes);
+    double* lds = reinterpret_cast<double*>(reinterpret_cast<char*>(lds_all) + kSolveLdsHead);
+    int* next = reinterpret_cast<int*>(slots + 4);
+    const int ntask = A.fd_e - A.fd_b;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) *next = static_cast<int>(atomicAdd(&P.bar[kBarNext], 1u));
+        __syncthreads();
+        const int t = *next;
+        if (t >= ntask) break;
+        const Task tk = P.fdtask[A.fd_b + t];
+        if (tk.local != 0) continue;  // the first block of a grid stands for the grid
+        meta_fill(P, tk, meta);
+        solve_one_grid<PP, FDP, DIM>(P, A, *meta, slots, lds);
+    }
+}
+
 // One FD transform of block blk of a grid outside the solve (single-operation
 // kernels): description in LDS slot M.
 template <int FDP>

@@ -4,10 +4,30 @@
 
 namespace igasg {
 
-const void* solve3_kernel_p2(int prec);
+const void* solve3_kernel_p2(int prec, int grid);
 
-const void* solve_kernel_p2(int prec, int dim, int narrow) {
-    if (dim == 3 && narrow) return solve3_kernel_p2(prec);  // 256-thread build (solve3_p2.hip)
+const void* solve_kernel_p2(int prec, int dim, int narrow, int grid) {
+    if (dim == 3 && narrow) return solve3_kernel_p2(prec, grid);  // 256-thread build (solve3_p2.hip)
+    if (grid && dim == 3) {
+        switch (prec) {
+            case IGA_PREC_FP64: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 0, 3, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 0, 3, kBlock, 1>);
+            case IGA_PREC_FP32: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 1, 3, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 1, 3, kBlock, 1>);
+            default: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 2, 3, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 2, 3, kBlock, 1>);
+        }
+    }
+    if (grid) {
+        switch (prec) {
+            case IGA_PREC_FP64: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 0, 2, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 0, 2, kBlock, 1>);
+            case IGA_PREC_FP32: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 1, 2, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 1, 2, kBlock, 1>);
+            default: return grid == 2 ? reinterpret_cast<const void*>(k_solve_grid<2, 2, 2, kBlock, 2>)
+                             : reinterpret_cast<const void*>(k_solve_grid<2, 2, 2, kBlock, 1>);
+        }
+    }
     if (dim == 3) {
         switch (prec) {
             case IGA_PREC_FP64: return reinterpret_cast<const void*>(k_solve<2, 0, 3, kBlock>);

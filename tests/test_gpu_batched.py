@@ -155,7 +155,7 @@ def test_narrow_build_parity_with_oracle(S):
     assert P.stats()["op_tasks"] > 256
     P.bind()
     P.assemble(a=W._field("grid3d", data=torch.as_tensor(fields, device="cuda")))
-    rep = P.solve(precision="fp64", tol=1e-12, maxit=400, max_refine=3)
+    rep = P.solve(precision="fp64", tol=1e-12, maxit=400, max_refine=3, schedule="lists")
     assert np.all(rep["status"] == 0)
     for s in (0, ns - 1):
         Po = O.Problem(W.config("cfg5", w=w, a=W._field("grid3d", data=fields[s])))
@@ -201,3 +201,48 @@ def test_graph_released_by_rebind_and_network_change(S):
             P.replay()
         assert e.value.code == 7
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,precision,ns,w", [("cfg5", "fp64", 12, 4), ("cfg5", "fp32", 12, 4),
+                                                  ("cfg5", "fp32", 2, 7), ("cfg3", "fp64", 1, 6),
+                                                  ("cfg3", "bf16fd", 1, 6), ("cfg1", "fp64", 1, 6),
+                                                  ("cfg2", "fp64", 1, 6), ("cfg2", "fp32", 1, 6)])
+def test_whole_grid_solve_parity(S, name, precision, ns, w):
+    """The whole-grid solve (one workgroup per grid, schedule 3) against the
+    oracle's direct solves of the first and last samples (relative 1e-10 in
+    FP64, 1e-9 in the mixed modes) and against the cooperative solve of the
+    same launch (schedule 2: the same iteration, iteration counts within one)."""
+    import torch
+    import oracle as O
+    log(f"case whole-grid {name} w={w} samples={ns} {precision}")
+    kw = dict(precision=precision, tol=1e-12 if precision == "fp64" else 1e-11, tol_inner=1e-5, maxit=600,
+              max_refine=3 if precision == "fp64" else 12, continue_cg=precision != "fp64")
+    if name == "cfg5":
+        fields = W.grf_samples(ns, n=24)
+        wl0 = lambda s: W.config("cfg5", w=w, a=W._field("grid3d", data=fields[s]))
+        P = S.Plan(wl0(0), nsamples=ns)
+        P.bind()
+        P.assemble(a=W._field("grid3d", data=torch.as_tensor(fields, device="cuda")))
+    else:
+        wl0 = lambda s: W.config(name, w=w)
+        P = S.Plan(wl0(0))
+        P.bind()
+        P.assemble()
+    rg = P.solve(schedule="grid", **kw)
+    assert np.all(rg["status"] == 0)
+    xg = [P.coeffs(c).cpu().numpy() for c in range(P.ninst)]
+    rl = P.solve(schedule="lists", **kw)
+    assert np.all(np.abs(rg["iters"] - rl["iters"]) <= 1)
+    bar = 1e-10 if precision == "fp64" else 1e-9
+    for c in range(P.ninst):
+        xl = P.coeffs(c).cpu().numpy()
+        assert np.linalg.norm(xg[c] - xl) <= bar * np.linalg.norm(xl), c
+    for s in sorted({0, ns - 1}):
+        Po = O.Problem(wl0(s))
+        ref = Po.split(Po.solve_all())
+        for c in range(P.ncomp):
+            nb = Po.nbasis(P.levels[c])
+            r = ref[c][0][tuple(slice(1, -1) for _ in nb)].ravel()
+            x = xg[s * P.ncomp + c]
+            assert np.linalg.norm(x - r) <= bar * np.linalg.norm(r), (s, c)
+    log(f"  iterations grid {int(rg['total_iters'])} lists {int(rl['total_iters'])}")
