@@ -202,6 +202,11 @@ typedef struct {
     int total_iters;       /* sum of CG iterations over components */
     int sweeps;            /* iterations of the persistent loop (timing = 2) */
     double kernel_ms[4];   /* [1]: solve launch(es) in ms (timing >= 1) */
+    int precision;         /* inner precision the solve ran with (IGA_PREC_*): a mixed mode is
+                              declined (FP64 instead) when the plan's 1D eigenvalue ratio
+                              max lambda / min lambda exceeds 1e7, where FP32 factors cannot
+                              represent the pencil (strongly graded knots) */
+    double lam_ratio;      /* that ratio, the largest over the plan's 1D tables */
     double phase_us[6];    /* timing = 2: mean wall time of the operator, update/forward and
                               backward phases per sweep (barrier included), then the mean
                               longest busy time of any workgroup in each phase */
@@ -297,6 +302,13 @@ iga_status iga_sg_coeffs(iga_sg_plan plan, int comp, double* out_dev);
  * S from the last iga_sg_assemble); x_dev, y_dev hold the component's interior
  * unknowns. */
 iga_status iga_sg_apply(iga_sg_plan plan, int comp, int which, const double* x_dev, double* y_dev);
+
+/* Full coefficient arrays of component comp (after iga_sg_solve): for each
+ * patch in turn, every basis function of its grid ([n_d]..[n_1], direction 1
+ * fastest, basis B / W of Sec. 2.2), the unknowns at their functions and the
+ * Dirichlet lift's values (or 0) at the boundary functions; the function
+ * u_comp on that patch is sum_j out_dev[j] B_j / W.  Parity hook. */
+iga_status iga_sg_coeffs_full(iga_sg_plan plan, int comp, double* out_dev);
 
 /* Load vector of component comp (after iga_sg_assemble) to out_dev. */
 iga_status iga_sg_rhs(iga_sg_plan plan, int comp, double* out_dev);

@@ -30,7 +30,7 @@ EXPORTS = (
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
-    "iga_sg_graph_launch", "iga_sg_bind_static",
+    "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
 )
 
@@ -82,7 +82,7 @@ class _Report(C.Structure):
                 ("refinements", C.POINTER(C.c_int)), ("relres", C.POINTER(C.c_double)),
                 ("prelres", C.POINTER(C.c_double)), ("status", C.POINTER(C.c_int)),
                 ("total_iters", C.c_int), ("sweeps", C.c_int), ("kernel_ms", C.c_double * 4),
-                ("phase_us", C.c_double * 6)]
+                ("precision", C.c_int), ("lam_ratio", C.c_double), ("phase_us", C.c_double * 6)]
 
 
 _lib = None
@@ -120,6 +120,7 @@ def lib():
         L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
+        L.iga_sg_coeffs_full.argtypes = [vp, C.c_int, vp]
         L.iga_sg_apply.argtypes = [vp, C.c_int, C.c_int, vp, vp]
         L.iga_sg_rhs.argtypes = [vp, C.c_int, vp]
         L.iga_sg_set_rhs.argtypes = [vp, C.c_int, vp]
@@ -349,7 +350,9 @@ class Plan:
         code = lib().iga_sg_solve(self.h, C.byref(o), C.byref(R))
         rep = {"code": code, "iters": it, "refinements": rf, "relres": rr, "prelres": pr,
                "status": stt, "total_iters": R.total_iters, "kernel_ms": list(R.kernel_ms),
-               "sweeps": R.sweeps, "phase_us": list(R.phase_us)}
+               "sweeps": R.sweeps, "phase_us": list(R.phase_us),
+               "precision": {v: k for k, v in PREC.items()}.get(R.precision, R.precision),
+               "lam_ratio": R.lam_ratio}
         if check:
             _check(code)
         return rep
@@ -419,6 +422,18 @@ class Plan:
         import torch
         out = torch.empty(int(self.ndof[comp % self.ncomp]), dtype=torch.float64, device=self.device)
         _check(lib().iga_sg_coeffs(self.h, comp, C.c_void_p(out.data_ptr())))
+        return out
+
+    def coeffs_full(self, comp: int):
+        """Full per-patch coefficient arrays of a component instance
+        [npatch, n_d, .., n_1] (unknowns plus Dirichlet lift)."""
+        import torch
+        lv = self.levels[comp % self.ncomp]
+        p, r = int(self.wl["p"]), int(self.wl["r"])
+        nb = [p + 1 + (2 ** int(l) - 1) * (p - r) for l in lv]
+        npat = len(self.wl["patches"])
+        out = torch.empty([npat] + nb[::-1], dtype=torch.float64, device=self.device)
+        _check(lib().iga_sg_coeffs_full(self.h, comp, C.c_void_p(out.data_ptr())))
         return out
 
     def rhs(self, comp: int):

@@ -91,13 +91,27 @@ struct Grid {
     int nblk;
     int blk;          // block length
     int blk_off;      // first FD task
-    int fdstage;      // single-block grids: the long direction's factor is staged in LDS
+    int fdstage;      // 2D single-block grids: the long direction's factor is staged in LDS; blocked
+                      // grids: 0 the block's slab is staged, -1 it is read from memory (long grids)
     // operator tiles
     int tile[3];      // tile size in unknowns per direction
     int ntd[3];       // tiles per direction
     int ntile;
     int tile_off;     // first operator task
     int sample;       // coefficient sample (plans of several samples)
+    // several patches: the grids of one component instance (one per patch,
+    // consecutive) form one linear system with one solver state; its partial
+    // sums span the group's operator tiles and FD blocks
+    int state;        // grid index holding the group's solver state (the first of the group)
+    int gtile_off, gntile, gblk_off, gnblk;
+    // conforming C^0 interfaces (2D): for side s (0: xi1 = 0, 1: xi1 = 1,
+    // 2: xi2 = 0, 3: xi2 = 1) in nbr_on, the unknown of the neighbouring
+    // patch's grid that shares the unknown at tangential index t of that side
+    // sits at dof_off + nbr_base[s] + nbr_stride[s] * t
+    int nbr_on;
+    int nbr_base[4], nbr_stride[4];
+    int pin[4];       // unknowns fixed to their Dirichlet value (a vertex between two interfaces), or -1
+    int64_t lift_off; // offset of the grid's full coefficient array of the Dirichlet lift (2D)
 };
 
 // Per-grid solver state (double-buffered by sweep parity on the device).
@@ -113,7 +127,8 @@ struct GState {
     int total_it;
     int refine;       // inner solves started
     int status;
-    int pad;
+    int op64;         // the inner solve uses the FP64 operator (after an inner breakdown of the
+                      // FP32 operator: it lost positive definiteness on a badly graded grid)
 };
 
 struct Task {
@@ -178,7 +193,7 @@ inline IGA_HD FdLayout fd_layout(const Grid& g, int ldu_s, int ldu_b, int usize)
     if (!wide && g.fdstage) o += nbig * ldu_b * usize;
     o = (o + 15) & ~15;
     L.Slab = o;
-    L.rows = wide ? fd_slab_rows(nbig, bs, usize) : 0;
+    L.rows = wide && g.fdstage >= 0 ? fd_slab_rows(nbig, bs, usize) : 0;  // fdstage -1: slab read from memory
     o += L.rows * kBlock * 16;
     L.total = o;
     return L;
@@ -243,6 +258,7 @@ struct Layout {
     size_t loga;                  // log a at the Greville points of the unknowns
     size_t fdscale;               // diagonal scaling of the preconditioner
     size_t loc;                   // element-local load and diagonal sums [2][nloc][nelem]
+    size_t lift;                  // Dirichlet lift, full coefficient arrays per grid (2D)
     size_t gmeta, gmeta_lp;       // TaskMeta per grid (FP64 / low-precision FD blocking)
     size_t oplist, fdlist;        // active task lists [2 parities][tasks]
     size_t bar;                   // barrier + counters
@@ -295,6 +311,9 @@ struct Params {
     Task* oplist;      // active operator tasks [2][op_cap] (by sweep parity)
     Task* fdlist;      // active fast-diagonalisation tasks [2][fd_cap]
     int op_cap, fd_cap;
+    const double* lift;  // Dirichlet lift coefficients (full arrays per grid), nullptr without data
+    double* lift_rw;     // the lift arrays (written by the assembly)
+    int mp;            // several patches: interface sums and grouped solver states
     const float* nn;   // learned preconditioner parameters (or nullptr)
     int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
     int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)

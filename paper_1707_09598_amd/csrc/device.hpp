@@ -143,13 +143,14 @@ struct FDiv {
 // x / m for the knot multiplicity m (1 for maximal regularity).
 __device__ __forceinline__ int div_mult(int x, int m) { return m == 1 ? x : x / m; }
 
-// Element range touching interior unknowns [a, b) of one direction.
-__device__ __forceinline__ void d_elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
-    int lo_basis = a + 1, hi_basis = b;
-    int lo = (lo_basis - p <= 0) ? 0 : div_mult(lo_basis - p + m - 1, m);
-    int hi = div_mult(hi_basis, m);
-    *elo = lo < 0 ? 0 : lo;
-    *ehi = hi > E - 1 ? E - 1 : hi;
+// Element range touching unknowns [a, b) of one direction whose first
+// unknown is basis function lo (1 after a Dirichlet end, 0 after an interface).
+__device__ __forceinline__ void d_elem_range(int a, int b, int p, int m, int E, int lo, int* elo, int* ehi) {
+    const int lo_basis = a + lo, hi_basis = b - 1 + lo;
+    const int e0 = (lo_basis - p <= 0) ? 0 : div_mult(lo_basis - p + m - 1, m);
+    const int e1 = div_mult(hi_basis, m);
+    *elo = e0 < 0 ? 0 : e0;
+    *ehi = e1 > E - 1 ? E - 1 : e1;
 }
 
 }  // namespace igasg

@@ -533,15 +533,16 @@ __global__ void __launch_bounds__(kBlock) k_gather(Params P) {
          gi += static_cast<int64_t>(gridDim.x) * kBlock) {
         const Grid& g = P.grids[grid_of_dof(P, 0, P.ngrid, gi)];
         int64_t l = gi - g.dof_off;
-        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0}, mk[3] = {1, 1, 1};
+        int ik[3] = {0, 0, 0}, elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0}, mk[3] = {1, 1, 1}, lk[3] = {1, 1, 1};
         double pd = 0.0, md[3] = {1.0, 1.0, 1.0}, kd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             ik[k] = static_cast<int>(l % g.ni[k]);
             l /= g.ni[k];
             const Tab1D& T = P.tabs[g.tab[k]];
-            d_elem_range(ik[k], ik[k] + 1, PP, T.m, g.E[k], &elo[k], &ehi[k]);
+            d_elem_range(ik[k], ik[k] + 1, PP, T.m, g.E[k], T.lo, &elo[k], &ehi[k]);
             mk[k] = T.m;
+            lk[k] = T.lo;
             kd[k] = P.dpool[T.oKd + ik[k]];
             md[k] = P.dpool[T.oMd + ik[k]];
         }
@@ -556,12 +557,12 @@ __global__ void __launch_bounds__(kBlock) k_gather(Params P) {
         const int64_t e0 = g.qp_off / NLOC;
         double ad = 0.0, bb = 0.0;
         for (int c2 = elo[2]; c2 <= ehi[2]; ++c2) {
-            const int a2 = DIM > 2 ? ik[2] + 1 - c2 * mk[2] : 0;
+            const int a2 = DIM > 2 ? ik[2] + lk[2] - c2 * mk[2] : 0;
             for (int c1 = elo[1]; c1 <= ehi[1]; ++c1) {
-                const int a1 = ik[1] + 1 - c1 * mk[1];
+                const int a1 = ik[1] + lk[1] - c1 * mk[1];
                 const int64_t row = e0 + g.E[0] * (c1 + static_cast<int64_t>(g.E[1]) * c2);
                 for (int c0 = elo[0]; c0 <= ehi[0]; ++c0) {
-                    const int a = (ik[0] + 1 - c0 * mk[0]) + NQ * (a1 + NQ * a2);
+                    const int a = (ik[0] + lk[0] - c0 * mk[0]) + NQ * (a1 + NQ * a2);
                     const int64_t el = row + c0;
                     ad += P.loc[static_cast<int64_t>(a) * nelem + el];
                     bb += P.loc[static_cast<int64_t>(NLOC + a) * nelem + el];
@@ -594,7 +595,7 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
             const Tab1D& T = P.tabs[g.tab[k]];
             const double* kn = P.dpool + T.oKn;
             double s = 0.0;
-            for (int m = 1; m <= p; ++m) s += kn[ik[k] + 1 + m];
+            for (int m = 1; m <= p; ++m) s += kn[ik[k] + T.lo + m];
             xi[k] = s / p;
         }
         // geometry map F(xi) = sum w P B / sum w B from the coarse geometry
@@ -675,7 +676,7 @@ __global__ void __launch_bounds__(kBlock) k_solve_init(Params P, int g0, int g1,
             s.total_it = 0;
             s.refine = 0;
             s.status = GS_RUNNING;
-            s.pad = 0;
+            s.op64 = 0;
             P.st2[g] = s;
             P.st2[P.ngrid + g] = s;
         }
@@ -765,7 +766,7 @@ __device__ __forceinline__ int comb_basis(const Params& P, const Tab1D& T, doubl
         e = e > T.E - 1 ? T.E - 1 : e;
         if (UNI || T.m == 1) {
             uniform_basis<PP>(X, e, T.E, N);
-            return e - 1;
+            return e - T.lo;
         }
     } else {
         const double* brk = P.dpool + T.oBrk;
@@ -778,7 +779,7 @@ __device__ __forceinline__ int comb_basis(const Params& P, const Tab1D& T, doubl
         e = lo;
     }
     d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + e * T.m, x, N, nullptr);
-    return e * T.m - 1;
+    return e * T.m - T.lo;
 }
 
 // u(xi) = sum over the grids g0..g1 of the point's patch of c_g u_g(xi)
@@ -810,7 +811,9 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
 #pragma unroll
                 for (int a = 0; a <= kMaxPg; ++a) Ng[k][a] = a == 0 ? 1.0 : 0.0;
                 if (k < DIM) {
-                    const Tab1D& T = P.tabs[P.grids[g0].tab[k]];
+                    int gp = g0;  // a grid of the point's patch (its tables hold the patch geometry)
+                    while (gp < g1 - 1 && P.grids[gp].patch != pt) ++gp;
+                    const Tab1D& T = P.tabs[P.grids[gp].tab[k]];
                     const double* gk = P.dpool + T.oGkn;
                     pgk[k] = T.pg;
                     const int s = d_find_interval(T.pg, T.ngk, gk, xv[k]);
@@ -840,6 +843,8 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
         double N[DIM][PP + 1];
         int ix[DIM][PP + 1];
         int ctab[DIM];
+        double Nf[DIM][PP + 1];  // unmasked values and first basis index (Dirichlet lift, 2D)
+        int Jf[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) ctab[k] = -1;
         for (int gi = g0; gi < g1; ++gi) {
@@ -852,10 +857,12 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
                 ctab[k] = g.tab[k];
                 const int f = comb_basis<PP, UNI>(P, P.tabs[g.tab[k]], xv[k], N[k]);
                 const int ni = g.ni[k];
+                Jf[k] = f + P.tabs[g.tab[k]].lo;
 #pragma unroll
                 for (int a = 0; a <= PP; ++a) {
                     const int j = f + a;
                     const bool in = j >= 0 && j < ni;
+                    Nf[k][a] = N[k][a];
                     N[k][a] = in ? N[k][a] : 0.0;
                     ix[k][a] = j < 0 ? 0 : (j >= ni ? ni - 1 : j);
                 }
@@ -876,6 +883,17 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
                     v += vb * N[1][b] * (DIM > 2 ? N[2][c] : 1.0);
                 }
             }
+            if (DIM == 2 && P.lift) {
+                // the lift's boundary coefficients (zero at the unknowns)
+                const double* Lg = P.lift + g.lift_off;
+#pragma unroll
+                for (int b = 0; b <= PP; ++b) {
+                    double vb = 0.0;
+#pragma unroll
+                    for (int a = 0; a <= PP; ++a) vb += Lg[(Jf[0] + a) + static_cast<int64_t>(g.nb[0]) * (Jf[DIM - 1] + b)] * Nf[0][a];
+                    v += vb * Nf[DIM - 1][b];
+                }
+            }
             acc += use_coef ? g.ccoef * v : v;
         }
         u[i] = acc / W;
@@ -887,7 +905,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(Params P, const double* xi, 
 // the Jacobian DF of F = sum w P B / W (quotient rule), FP64.
 template <int DIM>
 __device__ __forceinline__ void point_geom(const Params& P, const Tab1D* const* T, int pt, const double* xv,
-                                           double* W, double* dW, double DF[DIM][DIM]) {
+                                           double* W, double* dW, double DF[DIM][DIM], double* xo = nullptr) {
     double Ng[3][kMaxPg + 1], dNg[3][kMaxPg + 1];
     int fg[3] = {0, 0, 0}, pgk[3] = {0, 0, 0};
 #pragma unroll
@@ -938,9 +956,225 @@ __device__ __forceinline__ void point_geom(const Params& P, const Tab1D* const* 
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         const double x = Xh[c] / Xh[3];
+        if (xo) xo[c] = x;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) DF[c][k] = (dXh[k][c] - x * dXh[k][3]) / Xh[3];
     }
+}
+
+// ===========================================================================
+// Dirichlet lift (2D, polynomial patches): the boundary coefficients of
+// u_D = sum over the Dirichlet functions of c_j phi_j.  The two end functions
+// of a Dirichlet side interpolate g at the patch corners (open knots); the
+// others are the L2 projection of g on the side's trace space with the ends
+// fixed: M c = (g, B) - M_corner c_corner with the side's 1D mass matrix in
+// arc length, one workgroup per (grid, side), the band of M assembled row by
+// row in LDS (each thread one function, over the elements of its support),
+// then a banded Cholesky solve by one thread.  Values go to the grid's full
+// coefficient array (direction 1 fastest); the others stay 0.
+// ===========================================================================
+template <int PP>
+__global__ void __launch_bounds__(kBlock) k_lift_edges(Params P, FieldDev fg) {
+    extern __shared__ double lsh[];
+    const int gi = blockIdx.x, sd = blockIdx.y;
+    const Grid& g = P.grids[gi];
+    const int k = sd / 2, t = 1 - k;  // fixed and running directions
+    const Tab1D& Tk = P.tabs[g.tab[k]];
+    const Tab1D& Tt = P.tabs[g.tab[t]];
+    const Tab1D* Tg[2] = {P.tabs + g.tab[0], P.tabs + g.tab[1]};
+    if (sd == 0 && threadIdx.x == 0) {
+        // a vertex between two interfaces of this patch that carries Dirichlet
+        // data elsewhere (fixed unknown): its value interpolates g as well
+        for (int e = 0; e < 4; ++e) {
+            if (g.pin[e] < 0) continue;
+            double xi[2] = {static_cast<double>(e & 1), static_cast<double>(e >> 1)}, x[2], W, dW[2], DF[2][2];
+            point_geom<2>(P, Tg, g.patch, xi, &W, dW, DF, x);
+            const int64_t idx = ((e & 1) ? g.nb[0] - 1 : 0) + static_cast<int64_t>(g.nb[0]) * ((e >> 1) ? g.nb[1] - 1 : 0);
+            P.lift_rw[g.lift_off + idx] = field_eval(field_of_sample(fg, g.sample), 2, x);
+        }
+    }
+    const int hik = Tk.nb - Tk.lo - Tk.ni;
+    if ((sd % 2 == 0 && Tk.lo == 0) || (sd % 2 == 1 && hik == 0)) return;  // interface side
+    const int n = Tt.nb, m = n - 2;
+    const int jfix = (sd % 2) ? Tk.nb - 1 : 0;
+    double* Lb = lsh;                            // [m][PP + 1]: M[i][i - d]
+    double* rhs = lsh + static_cast<size_t>(m) * (PP + 1);
+    double* cv = rhs + m;                        // corner values
+    if (threadIdx.x < 2) {
+        double xi[2], x[2], W, dW[2], DF[2][2];
+        xi[k] = static_cast<double>(sd % 2);
+        xi[t] = static_cast<double>(threadIdx.x);
+        point_geom<2>(P, Tg, g.patch, xi, &W, dW, DF, x);
+        cv[threadIdx.x] = field_eval(field_of_sample(fg, g.sample), 2, x);
+    }
+    __syncthreads();
+    const int mult = Tt.m, nq = P.nq;
+    for (int i = 1 + threadIdx.x; i <= m; i += kBlock) {
+        double row[2 * PP + 1], b = 0.0;
+#pragma unroll
+        for (int j = 0; j <= 2 * PP; ++j) row[j] = 0.0;
+        // elements e whose functions e mult .. e mult + p include i
+        const int e0 = max(0, (i - PP + mult - 1) / mult), e1 = min(Tt.E - 1, i / mult);
+        for (int e = e0; e <= e1; ++e) {
+            const int a = i - e * mult;
+            for (int q = 0; q < nq; ++q) {
+                const int qq = e * nq + q;
+                const double* Nq = P.dpool + Tt.oB + static_cast<int64_t>(qq) * (PP + 1);
+                double xi[2], x[2], W, dW[2], DF[2][2];
+                xi[k] = static_cast<double>(sd % 2);
+                xi[t] = P.dpool[Tt.oXq + qq];
+                point_geom<2>(P, Tg, g.patch, xi, &W, dW, DF, x);
+                const double ds = sqrt(DF[0][t] * DF[0][t] + DF[1][t] * DF[1][t]) * P.dpool[Tt.oWq + qq];
+                const double gv = field_eval(field_of_sample(fg, g.sample), 2, x);
+                b += gv * Nq[a] * ds;
+#pragma unroll
+                for (int c = 0; c <= PP; ++c) {
+                    const int j = e * mult + c;
+                    row[j - i + PP] += Nq[a] * Nq[c] * ds;
+                }
+            }
+        }
+        // fixed end values move to the right-hand side
+#pragma unroll
+        for (int c = 0; c <= 2 * PP; ++c) {
+            const int j = i - PP + c;
+            if (j == 0) b -= row[c] * cv[0];
+            if (j == n - 1) b -= row[c] * cv[1];
+        }
+        rhs[i - 1] = b;
+#pragma unroll
+        for (int dd = 0; dd <= PP; ++dd) Lb[static_cast<size_t>(i - 1) * (PP + 1) + dd] = row[PP - dd];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // banded Cholesky M = L L^T in place (L[i][i - d] at Lb[i][d]), then
+        // the two triangular solves
+        for (int i = 0; i < m; ++i) {
+            for (int dd = min(PP, i); dd >= 1; --dd) {
+                const int j = i - dd;
+                double v = Lb[i * (PP + 1) + dd];
+                for (int kk = 1; kk <= PP - dd && j - kk >= 0; ++kk)
+                    v -= Lb[i * (PP + 1) + dd + kk] * Lb[j * (PP + 1) + kk];
+                Lb[i * (PP + 1) + dd] = v / Lb[j * (PP + 1)];
+            }
+            double v = Lb[i * (PP + 1)];
+            for (int dd = 1; dd <= min(PP, i); ++dd) v -= Lb[i * (PP + 1) + dd] * Lb[i * (PP + 1) + dd];
+            Lb[i * (PP + 1)] = sqrt(v);
+        }
+        for (int i = 0; i < m; ++i) {
+            double v = rhs[i];
+            for (int dd = 1; dd <= min(PP, i); ++dd) v -= Lb[i * (PP + 1) + dd] * rhs[i - dd];
+            rhs[i] = v / Lb[i * (PP + 1)];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double v = rhs[i];
+            for (int dd = 1; dd <= PP && i + dd < m; ++dd) v -= Lb[(i + dd) * (PP + 1) + dd] * rhs[i + dd];
+            rhs[i] = v / Lb[i * (PP + 1)];
+        }
+    }
+    __syncthreads();
+    double* L = P.lift_rw + g.lift_off;
+    for (int j = threadIdx.x; j < n; j += kBlock) {
+        const double v = j == 0 ? cv[0] : (j == n - 1 ? cv[1] : rhs[j - 1]);
+        const int64_t idx = k == 0 ? jfix + static_cast<int64_t>(Tk.nb) * j : j + static_cast<int64_t>(Tt.nb) * jfix;
+        L[idx] = v;
+    }
+}
+
+// Load vector correction of the lift, -a(u_D, phi_a) for every local
+// function a of every element (2D, polynomial map): per Gauss point the
+// parametric gradient of u_D from the element's (p+1)^2 lift coefficients,
+// its flux G grad u_D, and the sum of the flux against grad B_a, added to the
+// element-local load sums before the gather.  One thread per element.
+template <int PP>
+__global__ void __launch_bounds__(kBlock) k_lift_rhs(Params P) {
+    constexpr int NQ = PP + 1, NLOC = NQ * NQ;
+    for (int64_t el = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; el < P.nelem;
+         el += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int gi = grid_of_qp(P, 0, P.ngrid, el * NLOC);
+        const Grid& g = P.grids[gi];
+        const int64_t le = el - g.qp_off / NLOC;
+        const int e0 = static_cast<int>(le % g.E[0]), e1 = static_cast<int>(le / g.E[0]);
+        const Tab1D& T0 = P.tabs[g.tab[0]];
+        const Tab1D& T1 = P.tabs[g.tab[1]];
+        const double* L = P.lift + g.lift_off;
+        double c[NQ][NQ];
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < NQ; ++b)
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) {
+                c[a][b] = L[(e0 * T0.m + a) + static_cast<int64_t>(T0.nb) * (e1 * T1.m + b)];
+                any = any || c[a][b] != 0.0;
+            }
+        if (!any) continue;
+        double out[NQ][NQ];
+#pragma unroll
+        for (int b = 0; b < NQ; ++b)
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) out[a][b] = 0.0;
+        for (int q1 = 0; q1 < NQ; ++q1)
+            for (int q0 = 0; q0 < NQ; ++q0) {
+                const int Q0 = e0 * NQ + q0, Q1 = e1 * NQ + q1;
+                const double* B0 = P.dpool + T0.oB + static_cast<int64_t>(Q0) * NQ;
+                const double* D0 = P.dpool + T0.oD + static_cast<int64_t>(Q0) * NQ;
+                const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(Q1) * NQ;
+                const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(Q1) * NQ;
+                double u0 = 0.0, u1 = 0.0;  // parametric gradient of u_D
+#pragma unroll
+                for (int b = 0; b < NQ; ++b)
+#pragma unroll
+                    for (int a = 0; a < NQ; ++a) {
+                        u0 += c[a][b] * D0[a] * B1[b];
+                        u1 += c[a][b] * B0[a] * D1[b];
+                    }
+                const int64_t qi = g.qp_off + static_cast<int64_t>(Q1) * g.Q[0] + Q0;
+                const int64_t nqp = g.nqp;
+                const double* G = P.G64 + g.qp_off * P.ncompG + (qi - g.qp_off);
+                const double f0 = G[0] * u0 + G[nqp] * u1, f1 = G[nqp] * u0 + G[2 * nqp] * u1;
+#pragma unroll
+                for (int b = 0; b < NQ; ++b)
+#pragma unroll
+                    for (int a = 0; a < NQ; ++a) out[a][b] -= f0 * D0[a] * B1[b] + f1 * B0[a] * D1[b];
+            }
+        // element-local load sums: loc[NLOC + a][element]
+#pragma unroll
+        for (int b = 0; b < NQ; ++b)
+#pragma unroll
+            for (int a = 0; a < NQ; ++a) P.loc[static_cast<int64_t>(NLOC + a + NQ * b) * P.nelem + el] += out[a][b];
+    }
+}
+
+// Full coefficient arrays of grids g0..g1 (every basis function, direction 1
+// fastest, one grid after another): the lift's boundary values plus the
+// unknowns at their basis functions.
+__global__ void __launch_bounds__(kBlock) k_full_coeffs(Params P, int g0, int g1, double* out) {
+    int64_t base = 0;
+    for (int gi = g0; gi < g1; ++gi) {
+        const Grid& g = P.grids[gi];
+        const int n0 = g.nb[0], n1 = g.nb[1], n2 = g.nb[2];
+        const int lo0 = P.tabs[g.tab[0]].lo, lo1 = P.tabs[g.tab[1]].lo;
+        const int lo2 = P.dim > 2 ? P.tabs[g.tab[2]].lo : 0;
+        const int64_t nt = static_cast<int64_t>(n0) * n1 * n2;
+        for (int64_t j = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; j < nt;
+             j += static_cast<int64_t>(gridDim.x) * kBlock) {
+            const int j0 = static_cast<int>(j % n0), j1 = static_cast<int>((j / n0) % n1),
+                      j2 = static_cast<int>(j / (static_cast<int64_t>(n0) * n1));
+            const int i0 = j0 - lo0, i1 = j1 - lo1, i2 = j2 - lo2;
+            double v = (P.lift && P.dim == 2) ? P.lift[g.lift_off + j] : 0.0;
+            if (i0 >= 0 && i0 < g.ni[0] && i1 >= 0 && i1 < g.ni[1] && i2 >= 0 && i2 < g.ni[2])
+                v += P.x[g.dof_off + i0 + static_cast<int64_t>(g.ni[0]) * (i1 + static_cast<int64_t>(g.ni[1]) * i2)];
+            out[base + j] = v;
+        }
+        base += nt;
+    }
+}
+
+// Clears the lift arrays (a kernel, so that the assembly can be captured).
+__global__ void __launch_bounds__(kBlock) k_zero(double* v, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock)
+        v[i] = 0.0;
 }
 
 // grad_i = grad sum over the grids g0..g1 of the point's patch of c_g u_g at
@@ -973,8 +1207,8 @@ __global__ void __launch_bounds__(kBlock) k_combine_grad(Params P, const double*
         for (int gi = g0; gi < g1; ++gi) {
             const Grid& g = P.grids[gi];
             if (g.patch != pt) continue;
-            double N[DIM][PP + 1], dN[DIM][PP + 1];
-            int ix[DIM][PP + 1];
+            double N[DIM][PP + 1], dN[DIM][PP + 1], Nf[DIM][PP + 1], dNf[DIM][PP + 1];
+            int ix[DIM][PP + 1], Jf[DIM];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
                 const Tab1D& T = P.tabs[g.tab[k]];
@@ -987,6 +1221,12 @@ __global__ void __launch_bounds__(kBlock) k_combine_grad(Params P, const double*
                 }
                 d_basis_funs_m<PP>(PP, P.dpool + T.oKn, PP + lo * T.m, xv[k], N[k], dN[k]);
                 const int f = lo * T.m - T.lo;  // unknown index of the first nonzero function
+                Jf[k] = lo * T.m;
+#pragma unroll
+                for (int a = 0; a <= PP; ++a) {
+                    Nf[k][a] = N[k][a];
+                    dNf[k][a] = dN[k][a];
+                }
 #pragma unroll
                 for (int a = 0; a <= PP; ++a) {
                     const int j = f + a;
@@ -1019,6 +1259,19 @@ __global__ void __launch_bounds__(kBlock) k_combine_grad(Params P, const double*
                     dv[1] += vb * dN[1][b] * n2;
                     if (DIM > 2) dv[DIM - 1] += vb * N[1][b] * dN[2][c];
                 }
+            }
+            if (DIM == 2 && P.lift) {
+                // the lift's boundary coefficients (zero at the unknowns)
+                const double* Lg = P.lift + g.lift_off;
+#pragma unroll
+                for (int b = 0; b <= PP; ++b)
+#pragma unroll
+                    for (int a = 0; a <= PP; ++a) {
+                        const double cl = Lg[(Jf[0] + a) + static_cast<int64_t>(g.nb[0]) * (Jf[DIM - 1] + b)];
+                        v += cl * Nf[0][a] * Nf[DIM - 1][b];
+                        dv[0] += cl * dNf[0][a] * Nf[DIM - 1][b];
+                        dv[DIM - 1] += cl * Nf[0][a] * dNf[DIM - 1][b];
+                    }
             }
             const double cf = use_coef ? g.ccoef : 1.0;
             acc += cf * v;
@@ -1060,6 +1313,11 @@ __global__ void __launch_bounds__(kBlock) k_combine_grad(Params P, const double*
     }
 }
 
+inline int blocks_for_n(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return static_cast<int>(std::min<int64_t>(std::max<int64_t>(b, 1), 65535));
+}
+
 // Assembly kernels specialised for the field kinds of the workloads
 // (coefficient: constant, sin-cos, 3D grid; load: constant, sine product,
 // annulus right-hand side), the run-time switch for any other combination.
@@ -1092,25 +1350,37 @@ hipError_t launch_assemble(int dim, int ka, int kf, dim3 grid, hipStream_t st, c
 // Element-local sums and their gather (load vector, preconditioner scaling),
 // specialised by dimension, degree and the rational form of the coefficients.
 template <int DIM, int PP>
-void launch_loadiag_p(bool rat, hipStream_t st, const Params& K, int dblocks) {
+void launch_loadiag_p(bool rat, bool lift, hipStream_t st, const Params& K, int dblocks) {
     constexpr int64_t epb = (kBlock / 64) * ElemShape<DIM, PP>::EPW;  // elements per workgroup
     const int eblocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>((K.nelem + epb - 1) / epb, 1), 65535));
     if (rat) hipLaunchKernelGGL((k_elemloc<DIM, PP, true>), dim3(eblocks), dim3(kBlock), 0, st, K);
     else hipLaunchKernelGGL((k_elemloc<DIM, PP, false>), dim3(eblocks), dim3(kBlock), 0, st, K);
+    if constexpr (DIM == 2)
+        if (lift) hipLaunchKernelGGL((k_lift_rhs<PP>), dim3(blocks_for_n(K.nelem)), dim3(kBlock), 0, st, K);
     hipLaunchKernelGGL((k_gather<DIM, PP>), dim3(dblocks), dim3(kBlock), 0, st, K);
 }
 template <int DIM>
-void launch_loadiag_d(int p, bool rat, hipStream_t st, const Params& K, int dblocks) {
+void launch_loadiag_d(int p, bool rat, bool lift, hipStream_t st, const Params& K, int dblocks) {
     switch (p) {
-        case 1: launch_loadiag_p<DIM, 1>(rat, st, K, dblocks); break;
-        case 2: launch_loadiag_p<DIM, 2>(rat, st, K, dblocks); break;
-        case 3: launch_loadiag_p<DIM, 3>(rat, st, K, dblocks); break;
-        default: launch_loadiag_p<DIM, 4>(rat, st, K, dblocks); break;
+        case 1: launch_loadiag_p<DIM, 1>(rat, lift, st, K, dblocks); break;
+        case 2: launch_loadiag_p<DIM, 2>(rat, lift, st, K, dblocks); break;
+        case 3: launch_loadiag_p<DIM, 3>(rat, lift, st, K, dblocks); break;
+        default: launch_loadiag_p<DIM, 4>(rat, lift, st, K, dblocks); break;
     }
 }
-hipError_t launch_loadiag(int dim, int p, bool rat, hipStream_t st, const Params& K, int dblocks) {
-    if (dim == 2) launch_loadiag_d<2>(p, rat, st, K, dblocks);
-    else launch_loadiag_d<3>(p, rat, st, K, dblocks);
+// element-local sums, the lift's load correction (when lift), the gather
+hipError_t launch_loadiag(int dim, int p, bool rat, bool lift, hipStream_t st, const Params& K, int dblocks) {
+    if (dim == 2) launch_loadiag_d<2>(p, rat, lift, st, K, dblocks);
+    else launch_loadiag_d<3>(p, rat, lift, st, K, dblocks);
+    return hipGetLastError();
+}
+hipError_t launch_lift_edges(int p, dim3 grid, size_t lds, hipStream_t st, const Params& K, const FieldDev& fg) {
+    switch (p) {
+        case 1: hipLaunchKernelGGL(k_lift_edges<1>, grid, dim3(kBlock), lds, st, K, fg); break;
+        case 2: hipLaunchKernelGGL(k_lift_edges<2>, grid, dim3(kBlock), lds, st, K, fg); break;
+        case 3: hipLaunchKernelGGL(k_lift_edges<3>, grid, dim3(kBlock), lds, st, K, fg); break;
+        default: hipLaunchKernelGGL(k_lift_edges<4>, grid, dim3(kBlock), lds, st, K, fg); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_loga(int ka, dim3 grid, hipStream_t st, const Params& K, const FieldDev& fa, int ng) {
@@ -1182,6 +1452,9 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
             if (w != P->patches[pt].weights[0]) rat = true;
         K.rational[pt] = rat ? 1 : 0;
     }
+    K.lift_rw = P->nlift > 0 ? reinterpret_cast<double*>(base + L.lift) : nullptr;
+    K.lift = P->lifted ? K.lift_rw : nullptr;
+    K.mp = P->patches.size() > 1 ? 1 : 0;
     K.dim = P->dim;
     K.p = P->p;
     K.nq = P->nq;
@@ -1300,6 +1573,16 @@ bool uniform_tables(const iga_sg_plan_s* P, int g0, int g1) {
             if (!T.uniform || T.m != 1) return false;
         }
     return true;
+}
+
+// Inner precision a solve runs with: FP32 / BF16 factors hold the 1D
+// eigen-decompositions only while max lambda / min lambda stays below about
+// 1 / (FP32 precision); strongly graded knots exceed that (the L-shape with
+// exponent 3 at level 4: 6e7) and the mixed modes then diverge, so the solve
+// runs in FP64 and the report says so.
+constexpr double kLowpLamRatio = 1e7;
+int effective_precision(const iga_sg_plan_s* P, int prec) {
+    return prec != IGA_PREC_FP64 && P->lam_ratio > kLowpLamRatio ? IGA_PREC_FP64 : prec;
 }
 
 int blocks_for(int64_t n) {
@@ -1510,9 +1793,20 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
         set_error("invalid f or a field");
         return IGA_ERR_INVALID_ARG;
     }
-    if (g && g->kind != IGA_FIELD_NONE) {
-        set_error("nonhomogeneous Dirichlet data is not supported by the GPU path");
+    const bool lift = g && g->kind != IGA_FIELD_NONE;
+    if (lift && (P->dim != 2 || P->rational_any || !field_ok(g, P->dim) || g->kind == IGA_FIELD_GRID3D)) {
+        set_error("Dirichlet data: two-dimensional plans with polynomial maps and an analytic field");
         return IGA_ERR_INVALID_ARG;
+    }
+    size_t lift_lds = 0;
+    if (lift) {
+        int nmax = 0;
+        for (const Grid& gr : P->grids) nmax = std::max(nmax, std::max(gr.nb[0], gr.nb[1]));
+        lift_lds = sizeof(double) * (static_cast<size_t>(nmax) * (P->p + 2) + 2);
+        if (lift_lds > static_cast<size_t>(kLdsLimit)) {
+            set_error("Dirichlet data: a side of %d basis functions exceeds the LDS of the projection", nmax);
+            return IGA_ERR_INVALID_ARG;
+        }
     }
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
@@ -1522,8 +1816,24 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
     const int ng = static_cast<int>(P->grids.size());
     HIP_OK(launch_assemble(P->dim, a ? a->kind : IGA_FIELD_NONE, f ? f->kind : IGA_FIELD_NONE,
                            dim3(blocks_for(P->nqp_total)), st, K, to_dev(a), to_dev(f), ng, err));
+    if (lift) {
+        // boundary coefficients of the lift, then its load correction with the
+        // element-local sums
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(P->nlift)), dim3(kBlock), 0, st, K.lift_rw, P->nlift);
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lift_edges<1>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lift_lds)));
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lift_edges<2>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lift_lds)));
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lift_edges<3>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lift_lds)));
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lift_edges<4>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lift_lds)));
+        HIP_OK(launch_lift_edges(P->p, dim3(ng, 4), lift_lds, st, K, to_dev(g)));
+        K.lift = K.lift_rw;
+    }
     // element-local sums (one lane group per element), then one thread per unknown
-    HIP_OK(launch_loadiag(P->dim, P->p, P->ncompG == (P->dim == 2 ? 6 : 10), st, K, blocks_for(P->ndof_total)));
+    HIP_OK(launch_loadiag(P->dim, P->p, P->ncompG == (P->dim == 2 ? 6 : 10), lift, st, K, blocks_for(P->ndof_total)));
+    P->lifted = lift;
     HIP_OK(launch_loga(a ? a->kind : IGA_FIELD_NONE, dim3(blocks_for(P->ndof_total)), st, K, to_dev(a), ng));
     P->assembled = true;
     P->solved = false;
@@ -1546,23 +1856,25 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     }
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
-    const bool lp = o->precision != IGA_PREC_FP64;  // FD blocking of the factor precision
+    // a mixed mode is declined where FP32 factors cannot hold the 1D pencils
+    const int prec = effective_precision(P, o->precision);
+    const bool lp = prec != IGA_PREC_FP64;  // FD blocking of the factor precision
     Params K = make_params(P, lp);
     if (o->plain_fd) K.fdscale = nullptr;  // unscaled pencil
     const std::vector<Grid>& grids = lp ? P->grids_lp : P->grids;
     const size_t nfd = (lp ? P->fdtask_lp : P->fdtask).size();
     const int ng = static_cast<int>(P->grids.size());
     SolveArgs A;
-    A.prec = o->precision;
+    A.prec = prec;
     A.maxit = o->maxit;
-    A.max_refine = o->precision == IGA_PREC_FP64 ? std::max(1, o->max_refine > 0 ? o->max_refine : 3)
+    A.max_refine = prec == IGA_PREC_FP64 ? std::max(1, o->max_refine > 0 ? o->max_refine : 3)
                                                  : std::max(1, o->max_refine);
     A.tol2 = o->tol * o->tol;
     // FP64: the inner test equals the outer one; mixed: loose inner tolerance
-    double ti = o->precision == IGA_PREC_FP64 ? o->tol : (o->tol_inner > 0 ? o->tol_inner : 1e-4);
+    double ti = prec == IGA_PREC_FP64 ? o->tol : (o->tol_inner > 0 ? o->tol_inner : 1e-4);
     A.tol_in2 = ti * ti;
     A.max_sweeps = (A.maxit + 2) * (A.max_refine + 1) + 4;
-    A.continue_cg = o->continue_cg != 0 && o->precision != IGA_PREC_FP64;
+    A.continue_cg = o->continue_cg != 0 && prec != IGA_PREC_FP64;
     A.learned = o->precond == 1 ? 1 : 0;
     A.learned_iters = o->learned_iters > 0 ? o->learned_iters : 0;
     if (A.learned && (P->dim != 3 || !P->nn)) {
@@ -1583,7 +1895,12 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     // launch whose grids are each a few tasks: forced by schedule 3, chosen
     // when every grid has one FD block and at most four operator tiles.
     bool whole = false;
-    if (o->batched) {
+    const int npat = static_cast<int>(P->patches.size());
+    if (o->schedule == 3 && npat > 1) {
+        set_error("the whole-grid schedule solves one patch grid per workgroup: not for several patches");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (o->batched && npat == 1) {
         bool small = true;
         for (const Grid& g : grids) small = small && g.nblk == 1 && g.ntile <= 4;
         whole = o->schedule == 3 || (o->schedule == 0 && small);
@@ -1598,7 +1915,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         A.op_e = ope;
         A.fd_b = fdb;
         A.fd_e = fde;
-        A.ndone_target = g1 - g0;
+        A.ndone_target = (g1 - g0) / npat;  // solver-state groups
         int want = std::max(ope - opb, fde - fdb);
         if (o->workgroups > 0) want = o->workgroups;
         int nwg = std::max(1, std::min(want, P->max_wg));
@@ -1627,8 +1944,8 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             // 256: 77.7 against 107 ms; its FP64 operator spills, so plain
             // FP64 keeps the one-workgroup build)
             const int waves =
-                o->precision != IGA_PREC_FP64 && 2 * (ldsg + 1024) <= static_cast<size_t>(kLdsLimit) ? 2 : 1;
-            const void* fk = solve_kernel(P->p, o->precision, P->dim, nar, waves);
+                prec != IGA_PREC_FP64 && 2 * (ldsg + 1024) <= static_cast<size_t>(kLdsLimit) ? 2 : 1;
+            const void* fk = solve_kernel(P->p, prec, P->dim, nar, waves);
             int occg = 0;
             HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occg, fk, solve_threads(P->dim, nar), ldsg));
             int nw = std::max(1, std::min(fde - fdb, std::max(1, occg) * P->num_cu));
@@ -1637,7 +1954,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             P->last_solve_coop = 0;
             return IGA_OK;
         }
-        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, o->precision, P->dim, narrow), dim3(nwg),
+        HIP_OK(hipLaunchCooperativeKernel(solve_kernel(P->p, prec, P->dim, narrow), dim3(nwg),
                                           dim3(solve_threads(P->dim, narrow)), args, static_cast<unsigned>(lds), st));
         P->last_solve_coop = 1;
         return IGA_OK;
@@ -1646,9 +1963,10 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         iga_status s = launch(0, ng, 0, static_cast<int>(P->optask.size()), 0, static_cast<int>(nfd));
         if (s != IGA_OK) return s;
     } else {
-        for (int gi = 0; gi < ng; ++gi) {
+        // one launch per solver-state group (a grid, or the patch grids of a component)
+        for (int gi = 0; gi < ng; gi += npat) {
             const Grid& g = grids[gi];
-            iga_status s = launch(gi, gi + 1, g.tile_off, g.tile_off + g.ntile, g.blk_off, g.blk_off + g.nblk);
+            iga_status s = launch(gi, gi + npat, g.gtile_off, g.gtile_off + g.gntile, g.gblk_off, g.gblk_off + g.gnblk);
             if (s != IGA_OK) return s;
         }
     }
@@ -1663,8 +1981,9 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
                           hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     for (int gi = 0; gi < ng; ++gi) {
-        const GState& a = both[gi];
-        const GState& b = both[ng + gi];
+        const int sg = P->grids[gi].state;  // the grid's solver-state group
+        const GState& a = both[sg];
+        const GState& b = both[ng + sg];
         // the buffer written last holds the final state: DONE wins, else the later one
         if (a.stage == STAGE_DONE && b.stage != STAGE_DONE) stv[gi] = a;
         else if (b.stage == STAGE_DONE && a.stage != STAGE_DONE) stv[gi] = b;
@@ -1675,7 +1994,7 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     for (int gi = 0; gi < ng; ++gi) {
         const GState& s = stv[gi];
         // the state buffer of the parity last written holds DONE for finished grids
-        total += s.total_it;
+        if (P->grids[gi].state == gi) total += s.total_it;  // once per group
         if (s.stage != STAGE_DONE || s.status == GS_MAXIT || s.status == GS_RUNNING) {
             if (ret == IGA_OK) ret = IGA_ERR_NOT_CONVERGED;
         }
@@ -1684,6 +2003,8 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     if (rep) {
         rep->ncomp = ninstances(P);
         rep->total_iters = total;
+        rep->precision = prec;
+        rep->lam_ratio = P->lam_ratio;
         for (int gi = 0; gi < ng; ++gi) {
             const GState& s = stv[gi];
             const int c = instance_of(P, P->grids[gi]);
@@ -1786,9 +2107,38 @@ iga_status iga_sg_coeffs(iga_sg_plan P, int comp, double* out) {
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
+    int64_t o = 0;  // the patch grids of a component one after another
     for (const Grid& g : P->grids)
-        if (instance_of(P, g) == comp)
-            HIP_OK(hipMemcpyAsync(out, K.x + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+        if (instance_of(P, g) == comp) {
+            HIP_OK(hipMemcpyAsync(out + o, K.x + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+            o += g.ndof;
+        }
+    return IGA_OK;
+}
+
+iga_status iga_sg_coeffs_full(iga_sg_plan P, int comp, double* out) {
+    if (!P || comp < 0 || comp >= ninstances(P) || !out) {
+        set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->solved) {
+        set_error("iga_sg_coeffs_full before iga_sg_solve");
+        return IGA_ERR_STATE;
+    }
+    if (const iga_status ws = check_workspace(P)) return ws;
+    int g0 = -1, g1 = -1;
+    int64_t nt = 0;
+    for (int gi = 0; gi < static_cast<int>(P->grids.size()); ++gi)
+        if (instance_of(P, P->grids[gi]) == comp) {
+            if (g0 < 0) g0 = gi;
+            g1 = gi + 1;
+            const Grid& g = P->grids[gi];
+            nt += static_cast<int64_t>(g.nb[0]) * g.nb[1] * g.nb[2];
+        }
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    Params K = make_params(P);
+    hipLaunchKernelGGL(k_full_coeffs, dim3(blocks_for(nt / std::max(1, g1 - g0))), dim3(kBlock), 0, st, K, g0, g1, out);
+    HIP_OK(hipGetLastError());
     return IGA_OK;
 }
 
@@ -1804,9 +2154,12 @@ iga_status iga_sg_loga(iga_sg_plan P, int comp, double* out) {
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
+    int64_t o = 0;  // the patch grids of a component one after another
     for (const Grid& g : P->grids)
-        if (instance_of(P, g) == comp)
-            HIP_OK(hipMemcpyAsync(out, K.loga + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+        if (instance_of(P, g) == comp) {
+            HIP_OK(hipMemcpyAsync(out + o, K.loga + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+            o += g.ndof;
+        }
     return IGA_OK;
 }
 
@@ -1852,9 +2205,12 @@ iga_status iga_sg_rhs(iga_sg_plan P, int comp, double* out) {
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
+    int64_t o = 0;  // the patch grids of a component one after another
     for (const Grid& g : P->grids)
-        if (instance_of(P, g) == comp)
-            HIP_OK(hipMemcpyAsync(out, K.b + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+        if (instance_of(P, g) == comp) {
+            HIP_OK(hipMemcpyAsync(out + o, K.b + g.dof_off, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+            o += g.ndof;
+        }
     return IGA_OK;
 }
 
@@ -1870,9 +2226,12 @@ iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
     if (const iga_status ws = check_workspace(P)) return ws;
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     Params K = make_params(P);
+    int64_t o = 0;
     for (const Grid& g : P->grids)
-        if (instance_of(P, g) == comp)
-            HIP_OK(hipMemcpyAsync(K.b + g.dof_off, b, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+        if (instance_of(P, g) == comp) {
+            HIP_OK(hipMemcpyAsync(K.b + g.dof_off, b + o, sizeof(double) * g.ndof, hipMemcpyDeviceToDevice, st));
+            o += g.ndof;
+        }
     P->solved = false;
     return IGA_OK;
 }
@@ -1880,6 +2239,10 @@ iga_status iga_sg_set_rhs(iga_sg_plan P, int comp, const double* b) {
 iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, double* y) {
     if (!P || comp < 0 || comp >= ninstances(P) || !x || !y || which < 0 || which > 6) {
         set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (P->patches.size() > 1) {
+        set_error("iga_sg_apply acts on one patch grid: not for several patches");
         return IGA_ERR_INVALID_ARG;
     }
     if (!P->assembled) {
@@ -1973,10 +2336,11 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
     hipError_t ge = hipGraphGetNodes(g, nullptr, &nn);
     std::vector<hipGraphNode_t> nodes(nn);
     if (ge == hipSuccess && nn) ge = hipGraphGetNodes(g, nodes.data(), &nn);
-    const void* fsolve = solve_kernel(P->p, o->precision, P->dim, 0);
-    const void* fsolve_narrow = solve_kernel(P->p, o->precision, P->dim, 1);
+    const void* fsolve = solve_kernel(P->p, effective_precision(P, o->precision), P->dim, 0);
+    const void* fsolve_narrow = solve_kernel(P->p, effective_precision(P, o->precision), P->dim, 1);
     // the whole-grid solve is a plain kernel node: nothing to mark
-    const int want_marked = !P->last_solve_coop ? 0 : (o->batched ? 1 : static_cast<int>(P->grids.size()));
+    const int want_marked = !P->last_solve_coop ? 0
+                            : (o->batched ? 1 : static_cast<int>(P->grids.size() / P->patches.size()));
     int marked = 0;
     for (size_t i = 0; ge == hipSuccess && i < nn; ++i) {
         hipGraphNodeType t;

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <functional>
 #include <map>
 #include <set>
 #include <mutex>
@@ -145,13 +146,16 @@ struct FDEntry {
 };
 
 std::mutex g_fd_mu;
-std::map<std::tuple<int, int, int, int, double, int>, FDEntry> g_fd_cache;
+std::map<std::tuple<int, int, int, int, double, int, int>, FDEntry> g_fd_cache;
 
-// 1D interior stiffness/mass by Gauss quadrature and their eigen-pairs.
+// 1D stiffness/mass by Gauss quadrature on the unknowns of one direction
+// (basis functions lo .. nb-1-hi: lo / hi = 1 drops the function of a
+// Dirichlet end, 0 keeps the function of an interface end) and their
+// eigen-pairs.
 const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, const double* gx,
-                        const double* gw, bool* ok) {
+                        const double* gw, int lo, int hi, bool* ok) {
     std::lock_guard<std::mutex> lk(g_fd_mu);
-    auto key = std::make_tuple(p, r, lev, gk, gamma, nq);
+    auto key = std::make_tuple(p, r, lev, gk, gamma, nq, lo * 2 + hi);
     auto it = g_fd_cache.find(key);
     if (it != g_fd_cache.end()) {
         *ok = true;
@@ -160,7 +164,7 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
     FDEntry e;
     std::vector<double> U = make_knots(p, r, lev, gk, gamma);
     int nk = static_cast<int>(U.size());
-    int nb = nk - p - 1, ni = nb - 2;
+    int nb = nk - p - 1, ni = nb - lo - hi;
     e.n = ni;
     e.K.assign(static_cast<size_t>(ni) * ni, 0.0);
     e.M.assign(static_cast<size_t>(ni) * ni, 0.0);
@@ -172,10 +176,10 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
             double x = U[s] + 0.5 * h * (gx[q] + 1.0), w = 0.5 * h * gw[q];
             basis_funs(p, U.data(), s, x, N, dN);
             for (int a = 0; a <= p; ++a) {
-                int ia = s - p + a - 1;
+                int ia = s - p + a - lo;
                 if (ia < 0 || ia >= ni) continue;
                 for (int b = 0; b <= p; ++b) {
-                    int ib = s - p + b - 1;
+                    int ib = s - p + b - lo;
                     if (ib < 0 || ib >= ni) continue;
                     e.K[static_cast<size_t>(ia) * ni + ib] += w * dN[a] * dN[b];
                     e.M[static_cast<size_t>(ia) * ni + ib] += w * N[a] * N[b];
@@ -216,13 +220,14 @@ int env_int(const char* name, int dflt) {
     return x > 0 ? x : dflt;
 }
 
-// Element index range touching interior unknowns [a, b) of one direction.
-void elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi) {
-    int lo_basis = a + 1, hi_basis = b;  // basis indices of the first/last owned unknown
-    int lo = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
-    int hi = hi_basis / m;
-    *elo = std::max(0, lo);
-    *ehi = std::min(E - 1, hi);
+// Element index range touching unknowns [a, b) of one direction whose first
+// unknown is basis function lo.
+void elem_range(int a, int b, int p, int m, int E, int* elo, int* ehi, int lo = 1) {
+    const int lo_basis = a + lo, hi_basis = b - 1 + lo;  // basis indices of the first/last owned unknown
+    const int e0 = (lo_basis - p <= 0) ? 0 : (lo_basis - p + m - 1) / m;
+    const int e1 = hi_basis / m;
+    *elo = std::max(0, e0);
+    *ehi = std::min(E - 1, e1);
 }
 
 }  // namespace
@@ -248,8 +253,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         set_error("npatch must be in [1, %d]", kMaxPatch);
         return IGA_ERR_INVALID_ARG;
     }
-    if (geom->npatch != 1) {
-        set_error("several patches are not supported by the GPU path");
+    if (geom->npatch > 1 && d != 2) {
+        set_error("several patches are supported in two dimensions");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (geom->ninterface < 0 || (geom->ninterface > 0 && !geom->interfaces)) {
+        set_error("bad interface list");
         return IGA_ERR_INVALID_ARG;
     }
     const int p = disc->p, r = disc->r;
@@ -338,6 +347,81 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
         }
         P->patches.push_back(std::move(H));
     }
+    // ---- conforming interfaces; every other side carries Dirichlet data -----
+    // bc[pt][s] = 1: side s of patch pt is a Dirichlet side (its functions are
+    // not unknowns), 0: an interface side (its functions are shared with the
+    // neighbouring patch).  The same multi-index levels apply on every patch,
+    // so the two sides of an interface run along the same direction, whose
+    // knots (grading) must agree.
+    for (int pt = 0; pt < kMaxPatch; ++pt)
+        for (int sd = 0; sd < 6; ++sd) P->bc[pt][sd] = 1;
+    for (int f = 0; f < geom->ninterface; ++f) {
+        const iga_interface& I = geom->interfaces[f];
+        auto fail = [&](const char* what) {
+            set_error("interface %d: %s", f, what);
+            delete P;
+            return IGA_ERR_GEOMETRY;
+        };
+        if (I.patch_a < 0 || I.patch_a >= geom->npatch || I.patch_b < 0 || I.patch_b >= geom->npatch ||
+            I.patch_a == I.patch_b)
+            return fail("bad patch index");
+        if (I.side_a < 0 || I.side_a >= 2 * d || I.side_b < 0 || I.side_b >= 2 * d) return fail("bad side");
+        if (!P->bc[I.patch_a][I.side_a] || !P->bc[I.patch_b][I.side_b]) return fail("side glued twice");
+        const int ta = 1 - I.side_a / 2, tb = 1 - I.side_b / 2;
+        if (ta != tb) return fail("the two sides run along different parametric directions");
+        const PatchHost &A = P->patches[I.patch_a], &B = P->patches[I.patch_b];
+        if (A.grading[ta] != B.grading[ta] || A.gamma[ta] != B.gamma[ta])
+            return fail("non-conforming: the knots along the interface differ");
+        P->bc[I.patch_a][I.side_a] = 0;
+        P->bc[I.patch_b][I.side_b] = 0;
+        P->ifaces.push_back(I);
+    }
+    for (int pt = 0; pt < geom->npatch; ++pt) {
+        bool dir = false;
+        for (int sd = 0; sd < 2 * d; ++sd) dir = dir || P->bc[pt][sd] != 0;
+        if (!dir) {
+            set_error("patch %d has no Dirichlet side", pt);
+            delete P;
+            return IGA_ERR_GEOMETRY;
+        }
+    }
+    // vertices between two interface sides of a patch are unknowns of its
+    // tensor set; they must carry Dirichlet data (a vertex glued to a
+    // Dirichlet side of some patch), their value is then fixed
+    if (geom->npatch > 1) {
+        const int nn = geom->npatch * 4;  // (patch, corner e0 + 2 e1)
+        std::vector<int> par(nn);
+        for (int i = 0; i < nn; ++i) par[i] = i;
+        std::function<int(int)> find = [&](int i) { return par[i] == i ? i : (par[i] = find(par[i])); };
+        for (const iga_interface& I : P->ifaces) {
+            const int ka = I.side_a / 2, kb = I.side_b / 2;
+            for (int et = 0; et < 2; ++et) {
+                int ea[2], eb[2];
+                ea[ka] = I.side_a % 2;
+                ea[1 - ka] = et;
+                eb[kb] = I.side_b % 2;
+                eb[1 - kb] = et;
+                const int u = find(I.patch_a * 4 + ea[0] + 2 * ea[1]), v = find(I.patch_b * 4 + eb[0] + 2 * eb[1]);
+                if (u != v) par[std::max(u, v)] = std::min(u, v);
+            }
+        }
+        std::vector<char> cls_dir(nn, 0);
+        for (int i = 0; i < nn; ++i) {
+            const int pt = i / 4, e0 = i % 2, e1 = (i / 2) % 2;
+            if (P->bc[pt][e0] || P->bc[pt][2 + e1]) cls_dir[find(i)] = 1;
+        }
+        for (int i = 0; i < nn; ++i) {
+            const int pt = i / 4, e0 = i % 2, e1 = (i / 2) % 2;
+            P->pin_corner[pt][i % 4] = 0;
+            if (P->bc[pt][e0] || P->bc[pt][2 + e1]) continue;
+            if (!cls_dir[find(i)]) {
+                set_error("patch %d: a vertex shared by several patches inside the domain is not supported", pt);
+                delete P;
+                return IGA_ERR_GEOMETRY;
+            }
+            P->pin_corner[pt][i % 4] = 1;
+        }
+    }
     // ---- components (eq. TD-combi-tec), lexicographic, level 1 slowest ----
     const int J = P->w - d * P->lmin;
     int lmax_set = 0;
@@ -410,7 +494,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     P->tabs.resize(ntab);
     P->K1d.resize(ntab);
     P->M1d.resize(ntab);
-    std::map<std::tuple<int, double, int>, std::array<int64_t, 9>> fd_off;
+    std::map<std::tuple<int, double, int, int>, std::array<int64_t, 9>> fd_off;
     for (int pt = 0; pt < geom->npatch; ++pt)
         for (int k = 0; k < d; ++k)
             for (int lev = 0; lev <= P->Lmax; ++lev) {
@@ -420,8 +504,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 std::vector<double> U = make_knots(p, r, lev, H.grading[k], H.gamma[k]);
                 T.nk = static_cast<int>(U.size());
                 T.nb = T.nk - p - 1;
-                T.ni = T.nb - 2;
-                T.lo = 1;
+                T.lo = P->bc[pt][2 * k];
+                const int thi = P->bc[pt][2 * k + 1];
+                T.ni = T.nb - T.lo - thi;
                 T.E = 1 << lev;
                 T.Q = T.E * nq;
                 T.m = p - r;
@@ -454,7 +539,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 // fast-diagonalisation factors (shared by equal knot families)
                 bool ok = true;
                 const FDEntry& F = fd_entry(p, r, lev, H.grading[k], H.gamma[k], nq, P->gauss_x.data(),
-                                            P->gauss_w.data(), &ok);
+                                            P->gauss_w.data(), T.lo, thi, &ok);
                 if (!ok) {
                     set_error("eigen-decomposition failed (level %d)", lev);
                     delete P;
@@ -462,7 +547,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
                 P->K1d[tab_index(P, pt, k, lev)] = F.K;
                 P->M1d[tab_index(P, pt, k, lev)] = F.M;
-                auto fkey = std::make_tuple(H.grading[k], H.gamma[k], lev);
+                auto fkey = std::make_tuple(H.grading[k], H.gamma[k], lev, T.lo * 2 + thi);
                 auto fit = fd_off.find(fkey);
                 if (fit == fd_off.end()) {
                     // U and U^T stored row-major with a padded row stride (a multiple of 8
@@ -646,9 +731,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     int t1 = std::min(g.ni[0], std::max(1, TT / t2));
                     int n1 = (g.ni[0] + t1 - 1) / t1, n2 = (g.ni[1] + t2 - 1) / t2;
                     int lo, hi, e1, e2;
-                    elem_range(0, t1, p, m, g.E[0], &lo, &hi);
+                    elem_range(0, t1, p, m, g.E[0], &lo, &hi, P->tabs[g.tab[0]].lo);
                     e1 = hi - lo + 1 + (t1 < g.ni[0] ? 1 : 0);
-                    elem_range(0, t2, p, m, g.E[1], &lo, &hi);
+                    elem_range(0, t2, p, m, g.E[1], &lo, &hi, P->tabs[g.tab[1]].lo);
                     e2 = hi - lo + 1 + (t2 < g.ni[1] ? 1 : 0);
                     long work = static_cast<long>(n1) * n2 * e1 * e2 + 64L * n1 * n2;
                     if (best < 0 || work < best) {
@@ -673,7 +758,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                         size_t nel = 1, halo = 1, ntl = 1;
                         for (int k = 0; k < 3; ++k) {
                             int lo, hi;
-                            elem_range(0, t[k], p, m, g.E[k], &lo, &hi);
+                            elem_range(0, t[k], p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
                             const int ne = hi - lo + 1 + (t[k] < g.ni[k] ? 1 : 0);
                             nel *= ne;
                             halo *= static_cast<size_t>(ne - 1) * m + p + 1;
@@ -702,7 +787,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     int lo, hi, bestk = 0;
                     for (int t = 0; t < g.ntd[k]; ++t) {
                         int a = t * g.tile[k], b = std::min(g.ni[k], a + g.tile[k]);
-                        elem_range(a, b, p, m, g.E[k], &lo, &hi);
+                        elem_range(a, b, p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
                         bestk = std::max(bestk, hi - lo + 1);
                     }
                     nel *= bestk;
@@ -718,7 +803,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     int lo, hi, best = 0;
                     for (int t = 0; t < g.ntd[k]; ++t) {
                         int a = t * g.tile[k], b = std::min(g.ni[k], a + g.tile[k]);
-                        elem_range(a, b, p, m, g.E[k], &lo, &hi);
+                        elem_range(a, b, p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
                         best = std::max(best, hi - lo + 1);
                     }
                     nel *= best;
@@ -752,6 +837,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     // single-block grids stage the long factor as well when it fits
                     gc.fdstage = wide ? 0 : 1;
                     if (!wide && fd_layout(gc, ls, lb, usize).total + kSolveLdsHead > kLdsLimit) gc.fdstage = 0;
+                    // long grids: the block's slab of the long factor is read from
+                    // memory when it does not fit beside the grid vectors
+                    if (wide && fd_layout(gc, ls, lb, usize).total + kSolveLdsHead > kLdsLimit) gc.fdstage = -1;
                     lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(gc, ls, lb, usize).total));
                 }
             } else {
@@ -778,6 +866,84 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);
         }
+    // interfaces, fixed vertices, solver-state groups and the lift arrays of
+    // the grids of one sample (grid c * npatch + pt is patch pt of component c)
+    const int npat = geom->npatch;
+    int64_t nlift = 0;
+    for (size_t gi = 0; gi < P->grids.size(); ++gi) {
+        Grid& g = P->grids[gi];
+        const int c = g.comp, pt = g.patch;
+        g.state = c * npat;
+        g.nbr_on = 0;
+        for (int sd = 0; sd < 4; ++sd) {
+            g.nbr_base[sd] = 0;
+            g.nbr_stride[sd] = 0;
+            g.pin[sd] = -1;
+        }
+        if (d == 2) {
+            g.lift_off = nlift;
+            nlift += static_cast<int64_t>(g.nb[0]) * g.nb[1];
+            for (int e = 0; e < 4; ++e)
+                if (P->pin_corner[pt][e]) {
+                    const int i0 = (e & 1) ? g.ni[0] - 1 : 0, i1 = (e & 2) ? g.ni[1] - 1 : 0;
+                    g.pin[e] = i0 + g.ni[0] * i1;
+                }
+            for (const iga_interface& I : P->ifaces)
+                for (int side = 0; side < 2; ++side) {
+                    const int sa = side ? I.side_b : I.side_a, pa = side ? I.patch_b : I.patch_a;
+                    const int sb = side ? I.side_a : I.side_b, pb = side ? I.patch_a : I.patch_b;
+                    if (pa != pt) continue;
+                    const Grid& h = P->grids[static_cast<size_t>(c) * npat + pb];
+                    const int t = 1 - sa / 2, kb = sb / 2;
+                    const int fixb = (sb % 2) ? h.ni[kb] - 1 : 0;
+                    const int shift = P->tabs[g.tab[t]].lo - P->tabs[h.tab[t]].lo;
+                    const int64_t rel = h.dof_off - g.dof_off;
+                    g.nbr_on |= 1 << sa;
+                    g.nbr_base[sa] = static_cast<int>(rel + (kb == 0 ? fixb + h.ni[0] * shift : h.ni[0] * fixb + shift));
+                    g.nbr_stride[sa] = kb == 0 ? h.ni[0] : 1;
+                    // every unknown of the side that is not fixed has its partner
+                    const int fix_a = (sa % 2) ? g.ni[sa / 2] - 1 : 0;
+                    for (int it = 0; it < g.ni[t]; ++it) {
+                        int ia[2];
+                        ia[sa / 2] = fix_a;
+                        ia[t] = it;
+                        const int lin = ia[0] + g.ni[0] * ia[1];
+                        bool fixed = false;
+                        for (int e = 0; e < 4; ++e) fixed = fixed || g.pin[e] == lin;
+                        if (fixed) continue;
+                        if (it + shift < 0 || it + shift >= h.ni[t]) {
+                            set_error("interface of patches %d and %d: unknowns do not match", pt, pb);
+                            delete P;
+                            return IGA_ERR_GEOMETRY;
+                        }
+                    }
+                }
+        } else {
+            g.lift_off = 0;
+        }
+        // the low-precision blocking's copy of the grid shares these fields
+        Grid& gl = P->grids_lp[gi];
+        gl.state = g.state;
+        gl.nbr_on = g.nbr_on;
+        for (int sd = 0; sd < 4; ++sd) {
+            gl.nbr_base[sd] = g.nbr_base[sd];
+            gl.nbr_stride[sd] = g.nbr_stride[sd];
+            gl.pin[sd] = g.pin[sd];
+        }
+        gl.lift_off = g.lift_off;
+    }
+    P->nlift = nlift;
+    for (const Grid& g : P->grids)
+        for (int k = 0; k < d; ++k) {
+            const Tab1D& T = P->tabs[g.tab[k]];
+            double lmin = 0.0, lmax = 0.0;
+            for (int i = 0; i < T.ni; ++i) {
+                const double v = P->dpool[T.oLam + i];
+                lmin = i == 0 ? v : std::min(lmin, v);
+                lmax = i == 0 ? v : std::max(lmax, v);
+            }
+            if (lmin > 0.0) P->lam_ratio = std::max(P->lam_ratio, lmax / lmin);
+        }
     // further samples: the same grids (tables, blocking and tiles shared) over
     // their own unknowns and Gauss points, sample-major
     {
@@ -791,11 +957,16 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 gl.dof_off = g.dof_off;
                 g.qp_off += smp * nq1;
                 gl.qp_off = g.qp_off;
+                g.state += smp * static_cast<int>(ng1);
+                gl.state = g.state;
+                g.lift_off += smp * nlift;
+                gl.lift_off = g.lift_off;
                 P->grids.push_back(g);
                 P->grids_lp.push_back(gl);
             }
         P->ndof_total = nd1 * P->nsamples;
         P->nqp_total = nq1 * P->nsamples;
+        P->nlift = nlift * P->nsamples;
     }
     if (lds_max + kSolveLdsHead > kLdsLimit) {
         set_error("a component grid needs %zu bytes of LDS (limit %d)", lds_max + kSolveLdsHead, kLdsLimit);
@@ -806,34 +977,65 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     // without the learned preconditioner's activations (3D): the operator
     // tiles and the FD layouts alone
     P->lds_plain = (d == 3 ? std::max(lds_op, lds_fd_plain) : lds_max) + kSolveLdsHead;
-    // task lists in decreasing grid size (longest-processing-time order)
-    std::vector<int> ord(P->grids.size());
-    for (size_t i = 0; i < ord.size(); ++i) ord[i] = static_cast<int>(i);
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return P->grids[a].ndof > P->grids[b].ndof; });
-    for (int gi : ord) {
-        Grid& g = P->grids[gi];
-        g.tile_off = static_cast<int>(P->optask.size());
-        P->grids_lp[gi].tile_off = g.tile_off;
-        for (int t = 0; t < g.ntile; ++t) P->optask.push_back({gi, t});
+    // task lists in decreasing size of the solver-state groups (longest-
+    // processing-time order; a group is one grid, or the patch grids of one
+    // component), the tasks of a group contiguous so that its partial sums
+    // form one range
+    const int ngrp = static_cast<int>(P->grids.size()) / npat;
+    std::vector<int> ord(ngrp);
+    for (int i = 0; i < ngrp; ++i) ord[i] = i;
+    auto gsum = [&](const std::vector<Grid>& gv, int grp, auto f) {
+        double v = 0.0;
+        for (int pt = 0; pt < npat; ++pt) v += f(gv[static_cast<size_t>(grp) * npat + pt]);
+        return v;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        auto nd = [](const Grid& g) { return static_cast<double>(g.ndof); };
+        return gsum(P->grids, a, nd) > gsum(P->grids, b, nd);
+    });
+    for (int grp : ord) {
+        const int off = static_cast<int>(P->optask.size());
+        int cnt = 0;
+        for (int pt = 0; pt < npat; ++pt) {
+            const int gi = grp * npat + pt;
+            Grid& g = P->grids[gi];
+            g.tile_off = static_cast<int>(P->optask.size());
+            P->grids_lp[gi].tile_off = g.tile_off;
+            for (int t = 0; t < g.ntile; ++t) P->optask.push_back({gi, t});
+            cnt += g.ntile;
+        }
+        for (int pt = 0; pt < npat; ++pt) {
+            for (Grid* g : {&P->grids[grp * npat + pt], &P->grids_lp[grp * npat + pt]}) {
+                g->gtile_off = off;
+                g->gntile = cnt;
+            }
+        }
     }
-    // FD tasks: the blocks of a grid are contiguous (partial sums), grids in
+    // FD tasks: the blocks of a group are contiguous (partial sums), groups in
     // decreasing cost of one block, so that the costliest blocks are taken
     // first by the persistent workgroups.  Cost ~ unknowns x (short length +
     // block width): the short-direction product plus the block's long product.
     for (int cls = 0; cls < 2; ++cls) {
         std::vector<Grid>& gv = cls == 0 ? P->grids : P->grids_lp;
         std::vector<Task>& tv = cls == 0 ? P->fdtask : P->fdtask_lp;
-        auto cost = [&](int gi) {
-            const Grid& g = gv[gi];
+        auto cost = [&](const Grid& g) {
             const int nsm = d == 2 ? g.ni[1 - g.big] : 1;
             return static_cast<double>(g.ndof) * (nsm + std::min(g.blk, g.ni[g.big]));
         };
         std::vector<int> fo(ord);
-        std::stable_sort(fo.begin(), fo.end(), [&](int a, int b) { return cost(a) > cost(b); });
-        for (int gi : fo) {
-            gv[gi].blk_off = static_cast<int>(tv.size());
-            for (int t = 0; t < gv[gi].nblk; ++t) tv.push_back({gi, t});
+        std::stable_sort(fo.begin(), fo.end(),
+                         [&](int a, int b) { return gsum(gv, a, cost) > gsum(gv, b, cost); });
+        for (int grp : fo) {
+            const int off = static_cast<int>(tv.size());
+            for (int pt = 0; pt < npat; ++pt) {
+                Grid& g = gv[grp * npat + pt];
+                g.blk_off = static_cast<int>(tv.size());
+                for (int t = 0; t < g.nblk; ++t) tv.push_back({grp * npat + pt, t});
+            }
+            for (int pt = 0; pt < npat; ++pt) {
+                gv[grp * npat + pt].gblk_off = off;
+                gv[grp * npat + pt].gnblk = static_cast<int>(tv.size()) - off;
+            }
         }
     }
     // ---- workspace layout ----------------------------------------------------
@@ -873,6 +1075,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     // two sums per local basis function of each element; an element has as
     // many local functions as Gauss points, (p+1)^d
     L.loc = take(sizeof(double) * 2 * nqp);
+    L.lift = take(sizeof(double) * static_cast<size_t>(P->nlift));
     L.gmeta = take(sizeof(TaskMeta) * ng);
     L.gmeta_lp = take(sizeof(TaskMeta) * ng);
     L.oplist = take(sizeof(Task) * 2 * P->optask.size());

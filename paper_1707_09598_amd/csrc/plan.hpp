@@ -37,6 +37,8 @@ struct iga_sg_plan_s {
     int dim = 0, p = 0, r = 0, w = 0, lmin = 0, nq = 0;
     std::vector<igasg::PatchHost> patches;
     std::vector<iga_interface> ifaces;
+    int bc[igasg::kMaxPatch][6] = {};          // 1: Dirichlet side, 0: interface side
+    int pin_corner[igasg::kMaxPatch][4] = {};  // vertex between two interfaces with a fixed value
     // components of the combination technique
     int ncomp = 0;
     int nsamples = 1;              // coefficient samples planned together
@@ -61,6 +63,9 @@ struct iga_sg_plan_s {
     int ncompG = 0;
     int rational_any = 0;
     int64_t nqp_total = 0, ndof_total = 0;
+    double lam_ratio = 1.0;       // largest max/min eigenvalue ratio of the 1D tables the grids use
+    int64_t nlift = 0;            // doubles of the Dirichlet lift arrays (2D: all basis functions of every grid)
+    bool lifted = false;          // the last assembly had Dirichlet data
     size_t lds_bytes = 0;
     size_t lds_plain = 0;  // LDS of a solve without the learned preconditioner (3D: no activations)
     igasg::Layout lay{};

@@ -31,7 +31,35 @@ struct OpIO {
     const double* rhs;
     double* part;         // per-tile partial: in.(A in) or ||b - A x||^2 (or nullptr)
     int lowp;             // 1: FP32 coefficients and arithmetic
+    int isum = 0;         // several patches: in_a summed across interfaces (iface_add)
 };
+
+// Several patches (2D): a vector assembled patch by patch (an operator
+// output, a preconditioned residual) holds at an interface unknown the
+// contribution of its own patch only.  iface_add returns x (the value at
+// unknown (i1, i2) of grid g) plus the partner's value from the neighbouring
+// patch's grid, and 0 at a fixed vertex; other unknowns keep x.  Both
+// copies of an interface unknown form the same sum (addition commutes), so
+// the copies stay equal.
+__device__ __forceinline__ bool iface_pinned(const Grid& g, int lin) {
+    return g.pin[0] == lin || g.pin[1] == lin || g.pin[2] == lin || g.pin[3] == lin;
+}
+// side of grid g whose interface holds unknown (i1, i2), or -1
+__device__ __forceinline__ int iface_side(const Grid& g, int i1, int i2) {
+    if ((g.nbr_on & 1) && i1 == 0) return 0;
+    if ((g.nbr_on & 2) && i1 == g.ni[0] - 1) return 1;
+    if ((g.nbr_on & 4) && i2 == 0) return 2;
+    if ((g.nbr_on & 8) && i2 == g.ni[1] - 1) return 3;
+    return -1;
+}
+__device__ __forceinline__ double iface_add(const Grid& g, const double* v, int i1, int i2, double x) {
+    if (!g.nbr_on) return x;
+    if (iface_pinned(g, i1 + g.ni[0] * i2)) return 0.0;
+    const int sd = iface_side(g, i1, i2);
+    if (sd < 0) return x;
+    const int t = sd < 2 ? i2 : i1;
+    return x + v[g.dof_off + g.nbr_base[sd] + static_cast<int64_t>(g.nbr_stride[sd]) * t];
+}
 
 // One row j2 of Gauss points of one element, by sum factorisation: the
 // element's (p+1)^2 output contributions from that row,
@@ -111,11 +139,12 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
     const int a1 = t1 * g.tile[0], b1 = min(g.ni[0], a1 + g.tile[0]);
     const int a2 = t2 * g.tile[1], b2 = min(g.ni[1], a2 + g.tile[1]);
     int el1, eh1, el2, eh2;
-    d_elem_range(a1, b1, p, m1, g.E[0], &el1, &eh1);
-    d_elem_range(a2, b2, p, m2, g.E[1], &el2, &eh2);
+    d_elem_range(a1, b1, p, m1, g.E[0], T1.lo, &el1, &eh1);
+    d_elem_range(a2, b2, p, m2, g.E[1], T2.lo, &el2, &eh2);
     const int ne1 = eh1 - el1 + 1, ne2 = eh2 - el2 + 1;
-    const int hl1 = el1 * m1 - 1, hl2 = el2 * m2 - 1;           // interior index of halo start
-    const int nh1 = eh1 * m1 + p - 1 - hl1 + 1, nh2 = eh2 * m2 + p - 1 - hl2 + 1;
+    const int hl1 = el1 * m1 - T1.lo, hl2 = el2 * m2 - T2.lo;   // unknown index of halo start
+    // halo: unknowns hl .. (last basis function of the last element) - lo
+    const int nh1 = eh1 * m1 + p - T1.lo - hl1 + 1, nh2 = eh2 * m2 + p - T2.lo - hl2 + 1;
     double* X = lds;
     double* Y = lds + nh1 * nh2;
     double* red = Y + ne1 * ne2 * (p + 1) * (p + 1);
@@ -130,6 +159,7 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
         if (i1 >= 0 && i1 < n1 && i2 >= 0 && i2 < n2) {
             int64_t gi = off + static_cast<int64_t>(i2) * n1 + i1;
             v = io.in_a[gi];
+            if (io.isum) v = iface_add(g, io.in_a, i1, i2, v);
             if (io.in_b) v += io.beta * io.in_b[gi];
             if (io.out_in && i1 >= a1 && i1 < b1 && i2 >= a2 && i2 < b2) io.out_in[gi] = v;
         }
@@ -151,7 +181,7 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
         int r1;
         const int q1 = de.div(el, &r1);
         const int e1 = el1 + r1, e2 = el2 + q1;
-        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2;
+        const int x1 = e1 * m1 - T1.lo - hl1, x2 = e2 * m2 - T2.lo - hl2;
         const int jr = j2 < NQ ? j2 : 0;
         const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
         const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
@@ -204,10 +234,10 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
         int r1;
         const int q1 = dw.div(o, &r1);
         const int i1 = a1 + r1, i2 = a2 + q1;
-        const int I1 = i1 + 1, I2 = i2 + 1;
+        const int I1 = i1 + T1.lo, I2 = i2 + T2.lo;
         int lo1, hi1, lo2, hi2;
-        d_elem_range(i1, i1 + 1, p, m1, g.E[0], &lo1, &hi1);
-        d_elem_range(i2, i2 + 1, p, m2, g.E[1], &lo2, &hi2);
+        d_elem_range(i1, i1 + 1, p, m1, g.E[0], T1.lo, &lo1, &hi1);
+        d_elem_range(i2, i2 + 1, p, m2, g.E[1], T2.lo, &lo2, &hi2);
         double s = 0.0;
         for (int e2 = lo2; e2 <= hi2; ++e2)
             for (int e1 = lo1; e1 <= hi1; ++e1) {
@@ -359,12 +389,13 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
     const int a2 = t2 * g.tile[1], b2 = min(g.ni[1], a2 + g.tile[1]);
     const int a3 = t3 * g.tile[2], b3 = min(g.ni[2], a3 + g.tile[2]);
     int el1, eh1, el2, eh2, el3, eh3;
-    d_elem_range(a1, b1, p, m1, g.E[0], &el1, &eh1);
-    d_elem_range(a2, b2, p, m2, g.E[1], &el2, &eh2);
-    d_elem_range(a3, b3, p, m3, g.E[2], &el3, &eh3);
+    d_elem_range(a1, b1, p, m1, g.E[0], T1.lo, &el1, &eh1);
+    d_elem_range(a2, b2, p, m2, g.E[1], T2.lo, &el2, &eh2);
+    d_elem_range(a3, b3, p, m3, g.E[2], T3.lo, &el3, &eh3);
     const int ne1 = eh1 - el1 + 1, ne2 = eh2 - el2 + 1, ne3 = eh3 - el3 + 1;
-    const int hl1 = el1 * m1 - 1, hl2 = el2 * m2 - 1, hl3 = el3 * m3 - 1;
-    const int nh1 = eh1 * m1 + p - hl1, nh2 = eh2 * m2 + p - hl2, nh3 = eh3 * m3 + p - hl3;
+    const int hl1 = el1 * m1 - T1.lo, hl2 = el2 * m2 - T2.lo, hl3 = el3 * m3 - T3.lo;
+    const int nh1 = eh1 * m1 + p - T1.lo - hl1 + 1, nh2 = eh2 * m2 + p - T2.lo - hl2 + 1,
+              nh3 = eh3 * m3 + p - T3.lo - hl3 + 1;
     double* X = lds;
     double* Y = lds + nh1 * nh2 * nh3;
     double* red = Y + ne1 * ne2 * ne3 * NE;
@@ -400,7 +431,7 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         const int q2 = de12.div(el, &r);
         q1 = de1.div(r, &r);
         const int e1 = el1 + r, e2 = el2 + q1, e3 = el3 + q2;
-        const int x1 = e1 * m1 - 1 - hl1, x2 = e2 * m2 - 1 - hl2, x3 = e3 * m3 - 1 - hl3;
+        const int x1 = e1 * m1 - T1.lo - hl1, x2 = e2 * m2 - T2.lo - hl2, x3 = e3 * m3 - T3.lo - hl3;
         const int jr = j3 < NQ ? j3 : 0;
         const double* B1 = P.dpool + T1.oB + static_cast<int64_t>(e1) * nqp1;
         const double* D1 = P.dpool + T1.oD + static_cast<int64_t>(e1) * nqp1;
@@ -449,15 +480,15 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         q1 = dw1.div(r, &r);
         const int i1 = a1 + r, i2 = a2 + q1, i3 = a3 + q2;
         int lo1, hi1, lo2, hi2, lo3, hi3;
-        d_elem_range(i1, i1 + 1, p, m1, g.E[0], &lo1, &hi1);
-        d_elem_range(i2, i2 + 1, p, m2, g.E[1], &lo2, &hi2);
-        d_elem_range(i3, i3 + 1, p, m3, g.E[2], &lo3, &hi3);
+        d_elem_range(i1, i1 + 1, p, m1, g.E[0], T1.lo, &lo1, &hi1);
+        d_elem_range(i2, i2 + 1, p, m2, g.E[1], T2.lo, &lo2, &hi2);
+        d_elem_range(i3, i3 + 1, p, m3, g.E[2], T3.lo, &lo3, &hi3);
         double s = 0.0;
         for (int e3 = lo3; e3 <= hi3; ++e3)
             for (int e2 = lo2; e2 <= hi2; ++e2)
                 for (int e1 = lo1; e1 <= hi1; ++e1) {
                     const int el = ((e3 - el3) * ne2 + (e2 - el2)) * ne1 + (e1 - el1);
-                    s += Y[el * NE + (i1 + 1 - e1 * m1) + NQ * ((i2 + 1 - e2 * m2) + NQ * (i3 + 1 - e3 * m3))];
+                    s += Y[el * NE + (i1 + T1.lo - e1 * m1) + NQ * ((i2 + T2.lo - e2 * m2) + NQ * (i3 + T3.lo - e3 * m3))];
                 }
         const int64_t gi = off + (static_cast<int64_t>(i3) * n2 + i2) * n1 + i1;
         if (io.rhs) {
@@ -604,6 +635,10 @@ struct FdIO {
     const double* rdot;   // backward: dot partner (or nullptr)
     int prec;             // 0 FP64, 1 FP32, 2 BF16 factors
     const double* scale;  // diagonal scaling s (z = s P^-1 (s r)), or nullptr
+    // several patches (2D): interface sums of q (or of the residual in q),
+    // fixed vertices kept at 0, interface unknowns weighted 1/2 in ||r||^2
+    int mp = 0;
+    int resq = 0;         // residual sweep: the patch-local residual b - A x is in q
     // learned preconditioner (3D backward transform only)
     int learned;
     const double* rold;   // previous residual: part2 = z . rold (flexible CG)
@@ -669,11 +704,11 @@ __device__ __forceinline__ void g2l_bytes(const void* src, int bytes, void* dst)
 // fastest (contiguous) for big == 1.
 struct FdBlock {
     int n1, n2, n, big, nbig, nsm, k0, bs, nown;
-    bool wide, sbig;
+    bool wide, sbig;  // wide: the block's slab of the long factor is staged in LDS
     FDiv dbs;
     __device__ explicit FdBlock(const Grid& g, int blk)
         : n1(g.ni[0]), n2(g.ni[1]), n(g.ni[0] * g.ni[1]), big(g.big), nbig(g.ni[g.big]), nsm(g.ni[1 - g.big]),
-          k0(blk * g.blk), bs(min(g.blk, g.ni[g.big] - blk * g.blk)), nown(0), wide(g.nblk > 1),
+          k0(blk * g.blk), bs(min(g.blk, g.ni[g.big] - blk * g.blk)), nown(0), wide(g.nblk > 1 && g.fdstage >= 0),
           sbig(g.nblk <= 1 && g.fdstage != 0), dbs(min(g.blk, g.ni[g.big] - blk * g.blk)) {
         nown = nsm * bs;
     }
@@ -814,7 +849,22 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
     const int n1 = B.n1, n2 = B.n2;
     const TU *Us, *Ub, *Ubig;
     fd_factor_ptrs<TU>(P, M, true, &Us, &Ub, &Ubig);
-    if (io.scale) {
+    if (io.mp) {
+        // interface sums of q (r = r_old - alpha q) or of the residual itself
+        const FDiv d1(n1);
+        for (int i = threadIdx.x; i < B.n; i += kBlock) {
+            int i1;
+            const int i2 = d1.div(i, &i1);
+            const double qv = iface_add(g, io.q, i1, i2, L.S[i]);
+            const double v = io.resq ? qv : L.R[i] - io.alpha * qv;
+            L.S[i] = v;
+            // Neumann-Neumann weights: an interface unknown's residual is
+            // shared half and half by the two patch solves (and so is their
+            // correction, in the backward transform)
+            const double wv = iface_side(g, i1, i2) >= 0 ? 0.5 : 1.0;
+            L.R[i] = (io.scale ? v * io.scale[off + i] : v) * wv;
+        }
+    } else if (io.scale) {
         // the update in S (written out below), the scaled residual s r in R
         for (int i = threadIdx.x; i < B.n; i += kBlock) {
             const double v = io.q ? L.R[i] - io.alpha * L.S[i] : L.R[i];
@@ -825,7 +875,7 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
         for (int i = threadIdx.x; i < B.n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
     }
     __syncthreads();
-    const double* Ru = io.scale ? L.S : L.R;
+    const double* Ru = (io.scale || io.mp) ? L.S : L.R;
     const double* Pw = L.Own;
     const double* Dw = L.Own + B.nown;
     const double* Iw = L.Own + 2 * B.nown;
@@ -835,7 +885,9 @@ __device__ __forceinline__ void fd_fwd_run(const Params& P, const TaskMeta& M, i
         const double v = Ru[gi];
         if (io.r_out) io.r_out[off + gi] = v;
         if (io.dvec) io.dvec[off + gi] = Dw[o] + io.alpha * Pw[o];
-        nrm += v * v;
+        // an interface unknown has a copy in both patches: half weight each
+        const double wgt = io.mp && iface_side(g, gi % n1, gi / n1) >= 0 ? 0.5 : 1.0;
+        nrm += wgt * v * v;
     }
     if (io.part) {
         const double t = wg_sum(nrm, L.red);
@@ -908,7 +960,12 @@ __device__ __forceinline__ void fd_bwd_run(const Params& P, const TaskMeta& M, i
     const double* Rd = L.Own;
     for (int o = threadIdx.x; o < B.nown; o += kBlock) {
         const int64_t gi = off + B.gi(o);
-        const double zv = io.scale ? L.Out[o] * io.scale[gi] : L.Out[o];
+        double zv = io.scale ? L.Out[o] * io.scale[gi] : L.Out[o];
+        if (io.mp) {
+            const int lo = B.gi(o);
+            if (iface_pinned(g, lo)) zv = 0.0;  // a fixed vertex stays at its value
+            else if (iface_side(g, lo % n1, lo / n1) >= 0) zv *= 0.5;  // Neumann-Neumann weight
+        }
         io.z[gi] = zv;
         if (io.rdot) dot += Rd[o] * zv;
     }
@@ -1337,17 +1394,23 @@ __device__ __forceinline__ double sum_strided(const double* p, int count) {
 
 // Issue the loads of a task context (wavefront 0 only): the grid state and
 // the partial sums of the previous phases.
+// The state and partial sums are those of the grid's solver-state group (the
+// grid itself, or the patch grids of one component of a multipatch plan).
 __device__ __forceinline__ void ctx_issue(const Params& P, const Grid& g, const GState* S0, int gi, int cur, int nxt,
                                           int phase, CtxLoads& c) {
-    c.st = S0[gi];
-    c.vrz = sum_strided(part_ptr(P, PK_RZ, nxt) + g.blk_off, g.nblk);
-    c.vzro = phase == 1 ? sum_strided(part_ptr(P, PK_ZRO, nxt) + g.blk_off, g.nblk) : 0.0;
+    (void)gi;
+    c.st = S0[g.state];
+    c.vrz = sum_strided(part_ptr(P, PK_RZ, nxt) + g.gblk_off, g.gnblk);
+    c.vzro = phase == 1 ? sum_strided(part_ptr(P, PK_ZRO, nxt) + g.gblk_off, g.gnblk) : 0.0;
     c.vpq = 0.0;
     c.vres = 0.0;
-    if (phase >= 2) {
-        c.vpq = sum_strided(part_ptr(P, PK_PQ, cur) + g.tile_off, g.ntile);
-        c.vres = sum_strided(part_ptr(P, PK_RES, cur) + g.tile_off, g.ntile);
-    }
+    if (phase >= 2) c.vpq = sum_strided(part_ptr(P, PK_PQ, cur) + g.gtile_off, g.gntile);
+    // ||b - A x||^2 of a residual sweep: from the operator tiles, or with
+    // several patches from the interface-summed residual of the FD forward
+    // tasks (phase 3 only)
+    if (phase == 3)
+        c.vres = P.mp ? sum_strided(part_ptr(P, PK_RR, cur) + g.gblk_off, g.gnblk)
+                      : sum_strided(part_ptr(P, PK_RES, cur) + g.gtile_off, g.gntile);
 }
 
 // Reduce and decide (wavefront 0 only); lane 0 writes the context to LDS.
@@ -1434,7 +1497,7 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
             __syncthreads();
             const int act = ctx->D.act;
             if (act == ACT_SKIP) {
-                if (M.local == 0 && threadIdx.x == 0) S1[M.grid] = ctx->st;  // carry DONE forward
+                if (M.local == 0 && threadIdx.x == 0 && g.state == M.grid) S1[M.grid] = ctx->st;  // carry DONE forward
                 continue;
             }
             OpIO io;
@@ -1443,7 +1506,7 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                 io.in_b = p_old;
                 // beta = 0 at the start of a solve; after a residual replacement
                 // either restart (0) or continue with the previous rho (continue_cg)
-                const bool fresh = ctx->st.it == 0 && (!A.continue_cg || ctx->st.refine <= 1);
+                const bool fresh = ctx->st.it == 0 && (!A.continue_cg || ctx->st.refine <= 1 || ctx->st.op64);
                 // flexible CG (variable preconditioner): beta = z.(r - r_old) / rho_old
                 const double num = A.learned && ctx->st.it > 0 ? ctx->D.rho - ctx->zro : ctx->D.rho;
                 io.beta = fresh ? 0.0 : num / ctx->st.rho;
@@ -1451,14 +1514,17 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                 io.out = P.q;
                 io.rhs = nullptr;
                 io.part = part_ptr(P, PK_PQ, cur) + g.tile_off + M.local;
-                io.lowp = lowp;
+                io.lowp = lowp && !ctx->st.op64;
+                io.isum = P.mp;  // z of a multipatch plan is assembled patch by patch
             } else if (act == ACT_RESID) {
                 // r = b - A (x + d): the pending update d is folded into x in phase 2
                 io.in_a = P.x;
                 io.in_b = P.d;
                 io.beta = 1.0;
                 io.out_in = nullptr;
-                io.out = r_new;
+                // several patches: the patch-local residual goes to q, the FD
+                // forward tasks sum it across interfaces into r
+                io.out = P.mp ? P.q : r_new;
                 io.rhs = P.b;
                 io.part = part_ptr(P, PK_RES, cur) + g.tile_off + M.local;
                 io.lowp = 0;
@@ -1502,6 +1568,8 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
             io.z = nullptr;
             io.rdot = nullptr;
             io.part = part_ptr(P, PK_RR, cur) + g.blk_off + M.local;
+            io.mp = DIM == 2 ? P.mp : 0;
+            io.resq = 0;
             if (act == ACT_ITER) {
                 const double pq = ctx->pq;
                 if (!(pq > 0.0) || !isfinite(ctx->D.rho / pq)) continue;  // breakdown: committed in phase 3
@@ -1514,8 +1582,9 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
             } else if (act == ACT_RESID) {
                 io.alpha = 0.0;
                 io.r_old = r_new;
-                io.q = nullptr;
-                io.r_out = nullptr;
+                io.q = io.mp ? P.q : nullptr;
+                io.resq = io.mp;
+                io.r_out = io.mp ? r_new : nullptr;
                 io.dvec = nullptr;
                 io.pvec = nullptr;
                 // x += d, d = 0 on the owned unknowns (phase 1 has read both); a
@@ -1537,8 +1606,11 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                     }
                 }
                 // the residual sweep transforms r_new, not the prefetched r_old
-                g2l_vec(r_new + g.dof_off, g.ndof, fd_lds<TU>(M, lds).R);
-                g2l_wait_sync();
+                // (several patches: the prefetched q, summed across interfaces)
+                if (!io.mp) {
+                    g2l_vec(r_new + g.dof_off, g.ndof, fd_lds<TU>(M, lds).R);
+                    g2l_wait_sync();
+                }
             } else {
                 continue;
             }
@@ -1571,6 +1643,7 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                 io.rdot = r_new;
                 io.prec = FDP;
                 io.scale = P.fdscale;
+                io.mp = DIM == 2 ? P.mp : 0;
                 io.part = part_ptr(P, PK_RZ, cur) + g.blk_off + M.local;
                 // the learned map preconditions the residuals of the CG iterations
                 // (up to learned_iters of them per inner solve); the FP64 residual
@@ -1594,7 +1667,15 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                 if (act == ACT_ITER) {
                     ns.rhob = D.rhob;
                     ns.rho0 = D.rho0;
-                    if (!run_bwd) {
+                    if (!run_bwd && lowp && !st.op64) {
+                        // the FP32 operator lost positive definiteness: the
+                        // inner solves of this grid continue with the FP64
+                        // operator from a fresh FP64 residual
+                        ns.op64 = 1;
+                        ns.stage = STAGE_RESID;
+                        ns.total_it += st.it;
+                        ns.it = 0;
+                    } else if (!run_bwd) {
                         ns.stage = STAGE_DONE;
                         ns.status = GS_BREAKDOWN;
                         ns.total_it += st.it;
@@ -1623,9 +1704,12 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                     ns.prelres = D.rhob > 0.0 ? sqrt(D.rho / D.rhob) : 0.0;
                     finish = true;
                 }
-                S1[gi] = ns;
+                // the group's first grid keeps its state; every grid of a
+                // group that continues puts its own tasks on the lists
+                const bool lead = g.state == gi;
+                if (lead) S1[gi] = ns;
                 if (finish) {
-                    atomicAdd(&P.bar[kBarDone], 1u);
+                    if (lead) atomicAdd(&P.bar[kBarDone], 1u);
                 } else if (A.active) {
                     // the grid keeps iterating: its tasks go on the next sweep's lists
                     const unsigned o = atomicAdd(&P.bar[kBarOpLen + nxt], static_cast<unsigned>(g.ntile));
@@ -1669,7 +1753,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
     st.stage = STAGE_RESID;
     st.it = st.total_it = st.refine = 0;
     st.status = GS_RUNNING;
-    st.pad = 0;
+    st.op64 = 0;
     double rz = 0.0, zro = 0.0;
     int pr = 0, pp = 0;  // buffer parities of r and p
     double* sl = slots;   // partial sum of one tile / block (written by thread 0)
@@ -1709,7 +1793,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
         fio.part = sl;
         if (D.act == ACT_ITER) {
             // p = z + beta p, q = A p, p.q
-            const bool fresh = st.it == 0 && (!A.continue_cg || st.refine <= 1);
+            const bool fresh = st.it == 0 && (!A.continue_cg || st.refine <= 1 || st.op64);
             const double num = A.learned && st.it > 0 ? D.rho - zro : D.rho;
             OpIO io;
             io.in_a = P.z;
@@ -1719,15 +1803,23 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             io.out = P.q;
             io.rhs = nullptr;
             io.part = sl;
-            io.lowp = FDP != 0;
+            io.lowp = FDP != 0 && !st.op64;
             const double pq = tiles([&](int t) {
                 if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
                 else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
             }, g.ntile);
             if (!(pq > 0.0) || !isfinite(D.rho / pq)) {
+                st.total_it += st.it;
+                if (FDP != 0 && !st.op64) {
+                    // FP32 operator no longer positive definite: continue with
+                    // the FP64 operator from a fresh FP64 residual
+                    st.op64 = 1;
+                    st.stage = STAGE_RESID;
+                    st.it = 0;
+                    continue;
+                }
                 st.stage = STAGE_DONE;
                 st.status = GS_BREAKDOWN;
-                st.total_it += st.it;
                 break;
             }
             // alpha, d += alpha p, r -= alpha q, forward transform
