@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--learned-train", type=int, default=8, help="training coefficient samples")
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
     ap.add_argument("--no-annulus", action="store_true", help="skip the quarter-annulus (cfg2) measurements")
+    ap.add_argument("--no-lshape", action="store_true", help="skip the L-shape (cfg4, three patches) measurements")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the annulus run with assembly + solve replayed as one HIP graph")
     ap.add_argument("--no-small", action="store_true",
@@ -508,6 +509,50 @@ def run_small_configs(S, W, torch, refs):
     return out
 
 
+def run_lshape(S, W, torch, args, ref):
+    """The L-shaped domain (cfg4): three bilinear patches, one-sided radical
+    knots (exponent 3) toward the re-entrant corner, Dirichlet data
+    r^(2/3) sin(2 theta / 3), p=2 C^1, level w=11: 23 components x 3 patch
+    grids coupled across the two interfaces.  Assembly (with the Dirichlet
+    lift) + batched solve, FP64 and the mixed request (declined to FP64 when
+    the graded 1D pencils exceed what FP32 factors hold), median of five
+    runs; accuracy against the oracle at points of all three patches."""
+    wl = W.config("cfg4")
+    t0 = time.perf_counter()
+    P = S.Plan(wl)
+    t_plan = time.perf_counter() - t0
+    P.bind(device="cuda:0")
+    ndof = int(P.ndof.sum())
+    out = {"workload": (f"cfg4: L-shape, 3 patches, radical knots (exponent 3) toward the re-entrant corner, "
+                        f"g = r^(2/3) sin(2 theta/3), p=2 C^1, w=11, {P.ncomp} components, {ndof} unknowns "
+                        f"(interface unknowns stored in both patches)"), "plan_host_s": t_plan}
+    xi, pid, u_ref, err_a = ref if ref is not None else (None, None, None, None)
+    out["oracle_patch_test_max_error"] = err_a
+    for key, kw in (("B_fp64", dict(precision="fp64")),
+                    ("C_mixed_request", dict(precision="fp32", continue_cg=True))):
+        kw = dict(kw, tol=1e-10, tol_inner=args.tol_inner, maxit=3000, max_refine=6)
+        P.assemble()
+        rep = P.solve(check=False, **kw)
+        ms = []
+        for _ in range(5):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(P.stream)
+            P.assemble()
+            P.solve_async(**kw)
+            ev[1].record(P.stream)
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        t = float(np.median(ms))
+        r = {"dof_per_s": ndof / (t / 1e3), "ms_assemble_solve": t, "ran_in": rep["precision"],
+             "lam_ratio": rep["lam_ratio"], "codes": int(rep["code"]), "cg_iterations": int(rep["total_iters"]),
+             "status": np.bincount(rep["status"], minlength=7).tolist()}
+        if xi is not None:
+            u = P.combine(xi, patch=pid).cpu().numpy()
+            r["rel_l2_vs_oracle"] = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+        out[key] = r
+    return out
+
+
 def host_cpu():
     """CPU model (from /proc/cpuinfo) and the cores this process may use
     (capped at 16, the host share of one GPU)."""
@@ -608,6 +653,19 @@ def cpu_leg(args, W, xi, sub):
         xi3, _ = W.eval_points(3, 32768, lattice=0, seed=12345)
         return xi3, Po.sg_eval(Po.solve_all(), xi3)
 
+    def lshape_ref():
+        Po = O.Problem(W.config("cfg4"))
+        xi_l, pid = W.eval_points(2, 4096, lattice=32, seed=5, npatch=3)
+        # the oracle's own accuracy at this level: its error on the affine
+        # patch test (exactly representable), limited by the conditioning of
+        # the graded meshes
+        aff = W._field("affine", 1.0, 1.0, 2.0)
+        Pa = O.Problem(W.config("cfg4", f=W._field("const", 0.0), g=aff, exact=aff))
+        off = np.array([[-1, 0], [0, 0], [-1, -1]], float)
+        x = xi_l + off[pid]
+        err_a = float(np.abs(Pa.sg_eval(Pa.solve_all(), xi_l, pid) - (1 + x[:, 0] + 2 * x[:, 1])).max())
+        return xi_l, pid, Po.sg_eval(Po.solve_all(), xi_l, pid), err_a
+
     def small_ref(name):
         wl = W.config(name)
         Po = O.Problem(wl)
@@ -620,6 +678,8 @@ def cpu_leg(args, W, xi, sub):
         jobs["cfg2"] = (annulus_ref,)
     if not args.no_learned:
         jobs["learned"] = (learned_ref,)
+    if not args.no_lshape:
+        jobs["cfg4"] = (lshape_ref,)
     if not args.no_small:
         jobs["cfg1"] = (small_ref, "cfg1")
         jobs["cfg3"] = (small_ref, "cfg3")
@@ -627,7 +687,7 @@ def cpu_leg(args, W, xi, sub):
         fut = {k: ex.submit(v[0], *v[1:]) for k, v in jobs.items()}
         res = {k: f.result() for k, f in fut.items()}
     refs = {"cube": {k[1]: v for k, v in res.items() if isinstance(k, tuple)}}
-    for k in ("cfg2", "learned", "cfg1", "cfg3"):
+    for k in ("cfg2", "learned", "cfg1", "cfg3", "cfg4"):
         refs[k] = res.get(k)
     return cpu, refs
 
@@ -645,7 +705,7 @@ def main():
     import workloads as W
     S.lib()  # fail loudly if the HIP library is missing
     if args.headline_only:
-        args.no_cpu_baseline = args.no_learned = args.no_annulus = args.no_small = True
+        args.no_cpu_baseline = args.no_learned = args.no_annulus = args.no_small = args.no_lshape = True
     if args.calibrate_copy > 0:
         # plain copy of a known size: reads and writes calibrate the HBM counters
         n = args.calibrate_copy * (1 << 20) // 8
@@ -719,6 +779,9 @@ def main():
     if not args.no_annulus:
         line["annulus_cfg2"] = run_annulus(S, W, torch, args, xi, sub, refs["cfg2"])
         print(f"[bench] annulus done", file=sys.stderr, flush=True)
+    if not args.no_lshape:
+        line["lshape_cfg4"] = run_lshape(S, W, torch, args, refs["cfg4"])
+        print(f"[bench] L-shape done", file=sys.stderr, flush=True)
     if not args.no_learned:
         line["learned_cfg5"] = run_learned(S, W, torch, args, refs["learned"])
         print(f"[bench] learned done", file=sys.stderr, flush=True)

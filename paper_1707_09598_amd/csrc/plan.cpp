@@ -189,7 +189,28 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
     }
     e.U.assign(static_cast<size_t>(ni) * ni, 0.0);
     e.lam.assign(ni, 0.0);
-    *ok = ni > 0 && gen_eig_banded(ni, p, e.K.data(), e.M.data(), e.U.data(), e.lam.data());
+    // Graded knots make the pencil graded: its large entries sit at the fine
+    // end.  The eigen-solver (Householder from the first row, QR steps chasing
+    // downward) resolves the small eigenvalues of a matrix graded with its
+    // large entries first (one-sided radical knots toward 1, level 10:
+    // relative residual of the smallest pair 2.4 in the given order, 2e-4
+    // reversed), so a pencil graded toward its last index is solved in
+    // reversed order.
+    const bool rev = ni > 1 && e.K[static_cast<size_t>(ni) * ni - 1] > e.K[0];
+    if (rev) {
+        std::vector<double> Kr(e.K.size()), Mr(e.M.size()), Ur(e.U.size());
+        for (int i = 0; i < ni; ++i)
+            for (int j = 0; j < ni; ++j) {
+                Kr[static_cast<size_t>(ni - 1 - i) * ni + (ni - 1 - j)] = e.K[static_cast<size_t>(i) * ni + j];
+                Mr[static_cast<size_t>(ni - 1 - i) * ni + (ni - 1 - j)] = e.M[static_cast<size_t>(i) * ni + j];
+            }
+        *ok = gen_eig_banded(ni, p, Kr.data(), Mr.data(), Ur.data(), e.lam.data());
+        for (int i = 0; i < ni; ++i)
+            std::memcpy(&e.U[static_cast<size_t>(i) * ni], &Ur[static_cast<size_t>(ni - 1 - i) * ni],
+                        sizeof(double) * ni);
+    } else {
+        *ok = ni > 0 && gen_eig_banded(ni, p, e.K.data(), e.M.data(), e.U.data(), e.lam.data());
+    }
     auto res = g_fd_cache.emplace(key, std::move(e));
     return res.first->second;
 }
