@@ -34,6 +34,23 @@ extern "C" {
 /* Number of FP32 parameters of the network (negative if the description is invalid). */
 int64_t iga_nn_param_count(const int* channels, int nlayers);
 
+/* Seeded initial parameters (host array of iga_nn_param_count floats): He
+ * normal weights, std sqrt(2 / (27 c_in)), from a splitmix64 stream with the
+ * given seed (Box-Muller normals), zero biases, and a zero last layer, so
+ * that the untrained network leaves the fast-diagonalisation preconditioner
+ * unchanged.  Deterministic on every host. */
+iga_status iga_nn_init(const int* channels, int nlayers, uint64_t seed, float* params_host);
+
+/* Write / read a network file: the magic "IGANNv01", layer count, head,
+ * channels, parameter count, the FP32 parameters (host arrays) and a CRC-32
+ * of all of it.  iga_nn_load checks the magic, the sizes and the checksum
+ * (IGA_ERR_INVALID_ARG on any mismatch); channels may be NULL (sized
+ * nlayers + 1 otherwise), params_host may be NULL to query the description
+ * first, else it holds capacity floats. */
+iga_status iga_nn_save(const char* path, const int* channels, int nlayers, int head, const float* params_host);
+iga_status iga_nn_load(const char* path, int* channels, int* nlayers, int* head, float* params_host,
+                       int64_t capacity);
+
 /* Forward pass over nb tensors of shape n[3]: x_dev [nb][channels[0]][n] ->
  * y_dev [nb][channels[nlayers]][n].  acts_dev may be NULL, or hold
  * sum_{l=1}^{nlayers-1} nb * channels[l] * n floats that receive the hidden

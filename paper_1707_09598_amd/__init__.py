@@ -32,6 +32,7 @@ EXPORTS = (
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
     "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
+    "iga_nn_init", "iga_nn_save", "iga_nn_load",
 )
 
 
@@ -136,6 +137,9 @@ def lib():
         L.iga_sg_set_network.argtypes = [vp, _ip, C.c_int, vp, C.c_int]
         L.iga_nn_param_count.argtypes = [_ip, C.c_int]
         L.iga_nn_param_count.restype = C.c_int64
+        L.iga_nn_init.argtypes = [_ip, C.c_int, C.c_uint64, C.POINTER(C.c_float)]
+        L.iga_nn_save.argtypes = [C.c_char_p, _ip, C.c_int, C.c_int, C.POINTER(C.c_float)]
+        L.iga_nn_load.argtypes = [C.c_char_p, _ip, _ip, _ip, C.POINTER(C.c_float), C.c_int64]
         L.iga_nn_forward.argtypes = [_ip, C.c_int, vp, C.c_int, _ip, vp, vp, vp, vp]
         L.iga_nn_backward.argtypes = [_ip, C.c_int, vp, C.c_int, _ip, vp, vp, vp, vp, C.c_int, C.c_double, vp,
                                       vp, vp, vp]
@@ -498,6 +502,35 @@ class Network:
         self.v = torch.zeros_like(self.params)
         self.grads = torch.zeros_like(self.params)
         self.step = 0
+
+    @staticmethod
+    def init_params(channels, seed: int = 0) -> np.ndarray:
+        """Seeded initial parameters from the library (iga_nn_init)."""
+        ch = (C.c_int * len(channels))(*[int(c) for c in channels])
+        n = int(lib().iga_nn_param_count(ch, len(channels) - 1))
+        if n < 0:
+            raise ValueError("invalid network description")
+        out = np.zeros(n, dtype=np.float32)
+        _check(lib().iga_nn_init(ch, len(channels) - 1, int(seed), out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def save(self, path: str) -> None:
+        """Write the parameters (and the description) to a checked file."""
+        p = np.ascontiguousarray(self.params.detach().cpu().numpy(), dtype=np.float32)
+        _check(lib().iga_nn_save(path.encode(), self._ch, self.nl, self.head,
+                                 p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    @classmethod
+    def load(cls, path: str, device="cuda:0", stream=None) -> "Network":
+        nl, head = C.c_int(), C.c_int()
+        _check(lib().iga_nn_load(path.encode(), None, C.byref(nl), C.byref(head), None, 0))
+        ch = (C.c_int * (nl.value + 1))()
+        _check(lib().iga_nn_load(path.encode(), ch, C.byref(nl), C.byref(head), None, 0))
+        n = int(lib().iga_nn_param_count(ch, nl.value))
+        p = np.zeros(n, dtype=np.float32)
+        _check(lib().iga_nn_load(path.encode(), ch, C.byref(nl), C.byref(head),
+                                 p.ctypes.data_as(C.POINTER(C.c_float)), n))
+        return cls(tuple(ch), p, device=device, stream=stream, head=head.value)
 
     def _s(self):
         import torch

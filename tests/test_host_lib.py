@@ -168,3 +168,38 @@ def test_index_set_plan(S):
     with pytest.raises(S.IgaError) as e:
         S.Plan(W.config("cfg2", w=10), index_set=[(0, 0), (2, 0)])
     assert e.value.code == 1
+
+
+def test_network_init_save_load_roundtrip(tmp_path):
+    """Seeded initialisation is deterministic (same seed, same parameters;
+    another seed, others), He-scaled with a zero last layer; a saved network
+    loads back bit for bit; a corrupted byte or a truncated file is refused
+    (checksum and size checks)."""
+    import ctypes as C
+    import numpy as np
+    import paper_1707_09598_amd as S
+    L = S.lib()
+    ch = (3, 32, 48, 1)
+    a = S.Network.init_params(ch, seed=0)
+    assert a.size == 3 * 32 * 27 + 32 + 32 * 48 * 27 + 48 + 48 * 27 + 1 == 45441
+    assert np.array_equal(a, S.Network.init_params(ch, seed=0))
+    assert not np.array_equal(a, S.Network.init_params(ch, seed=1))
+    w1 = a[:3 * 32 * 27]
+    assert abs(w1.std() - np.sqrt(2.0 / 81)) < 0.02 and abs(w1.mean()) < 0.02
+    assert np.all(a[-(48 * 27 + 1):] == 0)
+    cha = (C.c_int * 4)(*ch)
+    path = str(tmp_path / "net.bin")
+    p = np.random.default_rng(3).standard_normal(a.size).astype(np.float32)
+    assert L.iga_nn_save(path.encode(), cha, 3, 1, p.ctypes.data_as(C.POINTER(C.c_float))) == 0
+    nl, hd = C.c_int(), C.c_int()
+    out = np.zeros_like(p)
+    chb = (C.c_int * 4)()
+    assert L.iga_nn_load(path.encode(), chb, C.byref(nl), C.byref(hd), out.ctypes.data_as(C.POINTER(C.c_float)),
+                         out.size) == 0
+    assert nl.value == 3 and hd.value == 1 and tuple(chb) == ch and np.array_equal(out, p)
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 0x10
+    open(path, "wb").write(bytes(raw))
+    assert L.iga_nn_load(path.encode(), chb, C.byref(nl), C.byref(hd), None, 0) == 1
+    open(path, "wb").write(bytes(raw[:-9]))
+    assert L.iga_nn_load(path.encode(), chb, C.byref(nl), C.byref(hd), None, 0) == 1
