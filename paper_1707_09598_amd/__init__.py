@@ -89,6 +89,28 @@ class _Report(C.Structure):
 _lib = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
+_plans = None  # live plans (weak references), released before interpreter teardown
+
+
+def _release_plans():
+    """atexit: destroy every live plan (graphs, events) while the HIP runtime
+    is still up; a destructor run from interpreter or library teardown would
+    call into an already finalised runtime (or profiler)."""
+    if _plans is None:
+        return
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for p in list(_plans):
+        try:
+            if getattr(p, "h", None):
+                _lib.iga_sg_destroy(p.h)
+                p.h = None
+        except Exception:
+            pass
 
 
 def lib():
@@ -147,6 +169,12 @@ def lib():
                                   C.c_int, vp]
         L.iga_nn_pair.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_int, vp, vp, vp]
         _lib = L
+        global _plans
+        import atexit
+        import weakref
+        _plans = weakref.WeakSet()
+        # registered after torch's import, so it runs before torch's own exit handlers
+        atexit.register(_release_plans)
     return _lib
 
 
@@ -227,6 +255,7 @@ class Plan:
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h
+        _plans.add(self)
         self.ws = None
         self.stream = None
         n = C.c_int()
