@@ -1122,7 +1122,9 @@ __device__ __forceinline__ void cnn_layer(const float* __restrict__ w, const flo
 // network y = N(r / ||r||, z_FD / s, log a - mean), s = ||z_FD||, corrects
 // z_FD: z = z_FD + s y (additive head) or z = z_FD exp(y) (log-scale head),
 // unless r . z <= 0 (then z = z_FD); part2 (if set) = z . rold.
-template <typename TU, typename TC>
+// LEARN = false compiles the transform without the network (builds that
+// never run the learned correction keep its registers free).
+template <typename TU, typename TC, bool LEARN = true>
 __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, const FdIO& io, double* lds) {
     const Grid& g = M.g;
     const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
@@ -1141,7 +1143,7 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     }
     double scale = 0.0;  // s (additive head), -1 (log-scale head), 0: no learned correction
     float* Y = nullptr;
-    if (io.learned) {
+    if (LEARN && io.learned) {
         // features in LDS after the factor region: X0 [3][n], H1, H2, Y [n]
         const int ld[3] = {M.t[0].ldu, M.t[1].ldu, M.t[2].ldu};
         float* X0 = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + fd_layout_3d(g, ld, sizeof(TU)).total);
@@ -1740,7 +1742,7 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
 // operator tiles and the FD transforms are those of k_solve (decide,
 // op_tile_*, fd*_run), so a grid follows the same iteration as there.
 // ===========================================================================
-template <int PP, int FDP, int DIM>
+template <int PP, int FDP, int DIM, bool LEARN>
 __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs& A, const TaskMeta& M,
                                                double* slots, double* lds) {
     using TU = typename FdTypes<FDP>::TU;
@@ -1853,7 +1855,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
                 if constexpr (DIM == 3) {
                     fd3_issue_bwd<TU>(P, M, P.rt, r_oth, lds);
                     g2l_wait_sync();
-                    fd3_bwd_run<TU, TC>(P, M, fio, lds);
+                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);
                 } else {
                     __syncthreads();
                     fd_issue_bwd<TU>(P, M, b, P.rt, r_oth, lds);
@@ -1919,7 +1921,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
                 if constexpr (DIM == 3) {
                     fd3_issue_bwd<TU>(P, M, P.rt, r_cur, lds);
                     g2l_wait_sync();
-                    fd3_bwd_run<TU, TC>(P, M, fio, lds);
+                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);
                 } else {
                     __syncthreads();
                     fd_issue_bwd<TU>(P, M, b, P.rt, r_cur, lds);
@@ -1967,7 +1969,8 @@ __global__ void __launch_bounds__(NT, WAVES) k_solve_grid(Params P, SolveArgs A)
         const Task tk = P.fdtask[A.fd_b + t];
         if (tk.local != 0) continue;  // the first block of a grid stands for the grid
         meta_fill(P, tk, meta);
-        solve_one_grid<PP, FDP, DIM>(P, A, *meta, slots, lds);
+        // the two-workgroup build serves solves without the network only
+        solve_one_grid<PP, FDP, DIM, WAVES == 1>(P, A, *meta, slots, lds);
     }
 }
 
