@@ -182,7 +182,17 @@ typedef struct {
                           grid has one fast-diagonalisation block and at most four operator
                           tiles, else 1 when each workgroup has at most one task per phase,
                           else 2.  Schedule 3 follows the same iteration per grid; its
-                          reductions may group differently (rounding) */
+                          reductions may group differently (rounding).  4 whole-device
+                          kernels: the single grid of a full tensor plan (disc.full, one
+                          patch, one sample) with its vectors in device memory, each CG step
+                          a launch over the device (operator tiles, the preconditioner's mode
+                          products as FP64 matrix-core GEMMs, elementwise updates with
+                          fixed-order sums); FP64 only (a mixed request runs FP64, reported),
+                          precond 0, plain_fd 0.  A full grid whose preconditioner vectors do
+                          not fit the LDS of one workgroup is always solved this way (the
+                          standard-IGA comparison of Sec. 4.2 at the paper's sizes); CG on
+                          the recursive residual, the FP64 residual b - A x replacing it when
+                          the test passes (at most max_refine restarts). */
 } iga_sg_solve_opts;
 
 /* Per-instance results (component c of sample s at s * ncomp + c); arrays
@@ -352,6 +362,41 @@ iga_status iga_sg_matrices_1d(iga_sg_plan plan, int dir, int lev, int* n, double
 iga_status iga_sg_graph_capture(iga_sg_plan plan, const iga_field* f, const iga_field* a,
                                 const iga_sg_solve_opts* opts);
 iga_status iga_sg_graph_launch(iga_sg_plan plan);
+
+/* The sparse-grid combination as a preconditioner of the full tensor
+ * problem (the outlook of Sec. 5; eq. TD-combi-tec).  full: a full tensor
+ * plan (disc.full, one patch, one sample, level w); sg: a plan of the same
+ * geometry, degree, regularity and grading whose component levels are at
+ * most w (a sparse grid, or a caller's index set), so that every component
+ * space is nested in the full space.  Both bound to the same stream and
+ * assembled with the same data (homogeneous Dirichlet).  Flexible CG on the
+ * full problem with the two-level preconditioner
+ *     z = y + S P^-1 S (r - A y),   y = sum_i c_i P_i A_i^-1 P_i^T r,
+ * P_i the tensor product of the 1D prolongations from the component's levels
+ * to w (interior unknowns), A_i the component's own Galerkin matrix (its
+ * assembly), A_i^-1 applied by iga_sg_solve(sg, inner) (batched, to
+ * inner->tol), S P^-1 S the full grid's scaled fast diagonalisation.  The
+ * combination term alone does not act on the error outside the sparse-grid
+ * space, hence the second level.  coarse_every = k > 0: the two-level
+ * preconditioner on the first direction of each (re)start and on
+ * iterations k, 2k, ...; the fast diagonalisation alone on the others;
+ * coarse_every = 0: on the first direction only.  The stopping test and
+ * restarts are those of schedule 4 (outer->tol, maxit, max_refine; the
+ * solve runs in FP64).  report (nullable; one instance): iters = outer
+ * iterations, sweeps = CG iterations of all inner solves.  The solution is
+ * the full plan's (iga_sg_coeffs / iga_sg_combine of full); the sparse-grid
+ * plan's load vector and solution are overwritten (assemble it again to
+ * restore them).  Synchronises the stream once per outer iteration.
+ * Errors: IGA_ERR_INVALID_ARG (plans that do not nest, other streams, bad
+ * options), IGA_ERR_STATE (not assembled), the errors of iga_sg_solve. */
+iga_status iga_sg_solve_twolevel(iga_sg_plan full, iga_sg_plan sg, const iga_sg_solve_opts* outer,
+                                 const iga_sg_solve_opts* inner, int coarse_every, iga_sg_report* report);
+
+/* Test hook: the 1D prolongation of a full tensor plan from level lev to the
+ * plan's level w in direction dir (0-based), interior unknowns: T_host
+ * [nf][nc] row-major (coarse function j = sum_i T[i][j] fine function i),
+ * nf, nc set (T_host may be NULL to query the sizes). */
+iga_status iga_sg_prolongation(iga_sg_plan plan, int dir, int lev, int* nf, int* nc, double* T_host);
 
 void iga_sg_destroy(iga_sg_plan plan);
 const char* iga_sg_last_error(void);

@@ -20,7 +20,7 @@ FIELD = {None: -1, "none": -1, "const": 0, "sinprod": 1, "sincos": 2, "annulus_r
          "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7}
 GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
-SCHED = {"auto": 0, "static": 1, "lists": 2, "grid": 3}
+SCHED = {"auto": 0, "static": 1, "lists": 2, "grid": 3, "stream": 4}
 STATUS = {0: "IGA_OK", 1: "IGA_ERR_INVALID_ARG", 2: "IGA_ERR_GEOMETRY", 3: "IGA_ERR_OUT_OF_MEMORY",
           4: "IGA_ERR_DEVICE", 5: "IGA_ERR_NOT_CONVERGED", 6: "IGA_ERR_BREAKDOWN", 7: "IGA_ERR_STATE"}
 APPLY = {"op64": 0, "op32": 1, "fd64": 2, "fd32": 3, "fd16": 4, "res64": 5, "fds64": 6}
@@ -30,7 +30,8 @@ EXPORTS = (
     "iga_sg_assemble", "iga_sg_solve", "iga_sg_combine", "iga_sg_eval", "iga_sg_coeffs",
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
-    "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full",
+    "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full", "iga_sg_solve_twolevel",
+    "iga_sg_prolongation",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
     "iga_nn_init", "iga_nn_save", "iga_nn_load",
 )
@@ -140,6 +141,9 @@ def lib():
         L.iga_sg_components.argtypes = [vp, _ip, _ip, C.POINTER(C.c_int64), _dp]
         L.iga_sg_assemble.argtypes = [vp, C.POINTER(_Field), C.POINTER(_Field), C.POINTER(_Field)]
         L.iga_sg_solve.argtypes = [vp, C.POINTER(_Opts), C.POINTER(_Report)]
+        L.iga_sg_solve_twolevel.argtypes = [vp, vp, C.POINTER(_Opts), C.POINTER(_Opts), C.c_int,
+                                            C.POINTER(_Report)]
+        L.iga_sg_prolongation.argtypes = [vp, C.c_int, C.c_int, _ip, _ip, _dp]
         L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
@@ -389,6 +393,40 @@ class Plan:
         if check:
             _check(code)
         return rep
+
+    def solve_twolevel(self, sg: "Plan", tol: float = 1e-11, maxit: int = 500, max_refine: int = 3,
+                       inner_tol: float = 1e-6, inner_precision: str = "fp64", inner_maxit: int = 500,
+                       coarse_every: int = 1, timing: bool = False, check: bool = True) -> Dict[str, Any]:
+        """Flexible CG on this full tensor plan with the sparse-grid plan
+        ``sg`` as the coarse level of a two-level preconditioner
+        (iga_sg_solve_twolevel)."""
+        o = _Opts(PREC["fp64"], 1, tol, 0.0, maxit, max_refine, 0, int(timing), 0, 0, 0, 0, 0)
+        oi = _Opts(PREC[inner_precision], 1, inner_tol, 1e-4, inner_maxit, 0, 0, 0,
+                   int(inner_precision != "fp64"), 0, 0, 0, 0)
+        it = np.zeros(1, dtype=np.int32)
+        rf = np.zeros(1, dtype=np.int32)
+        rr = np.zeros(1)
+        pr = np.zeros(1)
+        stt = np.zeros(1, dtype=np.int32)
+        R = _Report(1, it.ctypes.data_as(_ip), rf.ctypes.data_as(_ip), _ptr(rr), _ptr(pr),
+                    stt.ctypes.data_as(_ip), 0, 0)
+        code = lib().iga_sg_solve_twolevel(self.h, sg.h, C.byref(o), C.byref(oi), int(coarse_every), C.byref(R))
+        rep = {"code": code, "iters": int(it[0]), "restarts": int(rf[0]), "relres": float(rr[0]),
+               "prelres": float(pr[0]), "status": int(stt[0]), "inner_iters": R.sweeps,
+               "kernel_ms": list(R.kernel_ms)}
+        if check:
+            _check(code)
+        return rep
+
+    def prolongation(self, direction: int, level: int) -> np.ndarray:
+        """1D prolongation of a full tensor plan from ``level`` to its own
+        level (interior unknowns, [n_fine, n_coarse]; host tables only)."""
+        nf = C.c_int(0)
+        nc = C.c_int(0)
+        _check(lib().iga_sg_prolongation(self.h, direction, level, C.byref(nf), C.byref(nc), _dp()))
+        T = np.zeros((nf.value, nc.value))
+        _check(lib().iga_sg_prolongation(self.h, direction, level, C.byref(nf), C.byref(nc), _ptr(T)))
+        return T
 
     def solve_async(self, precision: str = "fp64", tol: float = 1e-11, tol_inner: float = 1e-4,
                     maxit: int = 500, max_refine: int = 0, batched: bool = True,

@@ -31,6 +31,7 @@ constexpr int kMaxPatch = 4;
 constexpr int kBlock = IGASG_THREADS;
 constexpr int kBlockSolve3 = 256;  // threads of the 3D solve kernels
 constexpr int kWaves = kBlock / 64;
+constexpr int kFdStream = -2;   // Grid::fdstage of a grid solved by whole-device kernels
 constexpr int kBigRed = 2048;     // doubles of LDS for cross-wavefront partial sums of FD tasks
 
 // Grid stages of the persistent refinement/CG state machine.
@@ -92,7 +93,9 @@ struct Grid {
     int blk;          // block length
     int blk_off;      // first FD task
     int fdstage;      // 2D single-block grids: the long direction's factor is staged in LDS; blocked
-                      // grids: 0 the block's slab is staged, -1 it is read from memory (long grids)
+                      // grids: 0 the block's slab is staged, -1 it is read from memory (long grids);
+                      // kFdStream: a full tensor grid too large for the LDS of one workgroup, solved
+                      // by whole-device kernels with the grid vectors in memory
     // operator tiles
     int tile[3];      // tile size in unknowns per direction
     int ntd[3];       // tiles per direction
@@ -247,6 +250,10 @@ constexpr int kBarGroups = 8;
 constexpr int kBarOpLen = kBarGroup + kBarStride * kBarGroups;  // + parity
 constexpr int kBarFdLen = kBarOpLen + 2;                        // + parity
 constexpr int kBarBytes = 4 * (kBarOpLen + kBarStride);
+// whole-device solves of a full tensor grid: reduction blocks and partial-sum kinds
+constexpr int kFgBlocks = 256;
+constexpr int kFgKinds = 4;
+constexpr int kFgScalars = 32;
 
 struct Layout {
     size_t tabs, grids, grids_lp, dpool, ipool, fpool, hpool, ctrl;
@@ -263,6 +270,7 @@ struct Layout {
     size_t oplist, fdlist;        // active task lists [2 parities][tasks]
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
+    size_t fg;                    // whole-device solves: partial sums [kFgKinds][kFgBlocks], scalars
     size_t total;
 };
 

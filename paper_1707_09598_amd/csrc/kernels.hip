@@ -1623,6 +1623,8 @@ iga_status bind_impl(iga_sg_plan P, void* ws, size_t bytes, void* stream);
 
 }  // namespace
 
+iga_status igasg::workspace_ok(const iga_sg_plan_s* P) { return check_workspace(P); }
+
 extern "C" {
 
 iga_status iga_sg_bind(iga_sg_plan P, void* ws, size_t bytes, void* stream) {
@@ -1850,11 +1852,20 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         return IGA_ERR_STATE;
     }
     if (o->precision < IGA_PREC_FP64 || o->precision > IGA_PREC_BF16FD || !(o->tol > 0) || o->maxit < 1 ||
-        o->schedule < 0 || o->schedule > 3) {
+        o->schedule < 0 || o->schedule > 4) {
         set_error("invalid solve options");
         return IGA_ERR_INVALID_ARG;
     }
     if (const iga_status ws = check_workspace(P)) return ws;
+    // a full tensor grid too large for one workgroup (or schedule 4): whole-device kernels
+    if (P->streamed || o->schedule == 4) {
+        if (P->xfer_off.empty() || P->grids.size() != 1 || o->precond != 0 || o->plain_fd) {
+            set_error("schedule 4 (whole-device kernels) solves the single grid of a full tensor plan of one "
+                      "patch and one sample with the scaled fast diagonalisation");
+            return IGA_ERR_INVALID_ARG;
+        }
+        return fg_solve_plain(P, o, rep);
+    }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     // a mixed mode is declined where FP32 factors cannot hold the 1D pencils
     const int prec = effective_precision(P, o->precision);
@@ -2253,6 +2264,11 @@ iga_status iga_sg_apply(iga_sg_plan P, int comp, int which, const double* x, dou
     int gi = -1;
     for (int i = 0; i < static_cast<int>(P->grids.size()); ++i)
         if (instance_of(P, P->grids[i]) == comp) gi = i;
+    if (P->streamed && which >= 2 && which != 5) {
+        set_error("iga_sg_apply: the fast diagonalisation of a grid solved by whole-device kernels has no "
+                  "block tasks");
+        return IGA_ERR_INVALID_ARG;
+    }
     const bool lp = which == 3 || which == 4;  // FD with FP32/BF16 factors uses their blocking
     const Grid& g = (lp ? P->grids_lp : P->grids)[gi];
     hipStream_t st = static_cast<hipStream_t>(P->stream);
@@ -2307,6 +2323,10 @@ iga_status iga_sg_graph_capture(iga_sg_plan P, const iga_field* f, const iga_fie
         return IGA_ERR_INVALID_ARG;
     }
     if (const iga_status ws = check_workspace(P)) return ws;
+    if (P->streamed || o->schedule == 4) {
+        set_error("graph capture records the persistent solve: not for whole-device full-grid solves");
+        return IGA_ERR_INVALID_ARG;
+    }
     hipStream_t st = static_cast<hipStream_t>(P->stream);
     if (!st) {
         set_error("graph capture needs a plan bound to a created stream, not the default stream");

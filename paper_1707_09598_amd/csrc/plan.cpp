@@ -215,6 +215,65 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
     return res.first->second;
 }
 
+// Prolongation between nested spline spaces of degree p (coarse knots Uc,
+// fine knots Uf, every coarse breakpoint a fine one with at least its
+// multiplicity): coarse function j equals sum_i T[i][j] (fine function i).
+// T is the L2 projection of the coarse basis onto the fine space, M_f T =
+// M_fc, exact up to rounding because the coarse space lies in the fine one;
+// both Gram matrices by nq-point Gauss rules on the fine elements (nq >= p+1
+// integrates the products of degree 2p exactly), M_f by a banded Cholesky
+// factorisation (half bandwidth p).  T is row-major [nb_f][nb_c].
+bool prolongation_1d(int p, const std::vector<double>& Uc, const std::vector<double>& Uf, int nq, const double* gx,
+                     const double* gw, std::vector<double>* Tout) {
+    const int nkc = static_cast<int>(Uc.size()), nkf = static_cast<int>(Uf.size());
+    const int nc = nkc - p - 1, nf = nkf - p - 1, bw = p;
+    std::vector<double> Mf(static_cast<size_t>(nf) * (bw + 1), 0.0);  // Mf[i][i - j], j <= i
+    std::vector<double>& T = *Tout;
+    T.assign(static_cast<size_t>(nf) * nc, 0.0);
+    double Nf[kMaxP + 1], Nc[kMaxP + 1];
+    for (int e = p; e < nf; ++e) {
+        const double a = Uf[e], b = Uf[e + 1];
+        if (!(b > a)) continue;
+        for (int q = 0; q < nq; ++q) {
+            const double x = 0.5 * (a + b) + 0.5 * (b - a) * gx[q], wq = 0.5 * (b - a) * gw[q];
+            const int sc = igasg::find_interval(p, nkc, Uc.data(), x);
+            igasg::basis_funs(p, Uf.data(), e, x, Nf, nullptr);
+            igasg::basis_funs(p, Uc.data(), sc, x, Nc, nullptr);
+            for (int i = 0; i <= p; ++i) {
+                const int fi = e - p + i;
+                for (int j = 0; j <= i; ++j) Mf[static_cast<size_t>(fi) * (bw + 1) + (i - j)] += wq * Nf[i] * Nf[j];
+                for (int j = 0; j <= p; ++j) T[static_cast<size_t>(fi) * nc + sc - p + j] += wq * Nf[i] * Nc[j];
+            }
+        }
+    }
+    auto m = [&](int i, int j) -> double& { return Mf[static_cast<size_t>(i) * (bw + 1) + (i - j)]; };
+    for (int i = 0; i < nf; ++i) {  // M_f = L L^T, L in place of the lower band
+        for (int j = std::max(0, i - bw); j <= i; ++j) {
+            double v = m(i, j);
+            for (int k = std::max(0, i - bw); k < j; ++k) v -= m(i, k) * m(j, k);
+            if (i == j) {
+                if (!(v > 0.0)) return false;
+                m(i, i) = std::sqrt(v);
+            } else {
+                m(i, j) = v / m(j, j);
+            }
+        }
+    }
+    for (int c = 0; c < nc; ++c) {  // forward and back substitution per coarse function
+        for (int i = 0; i < nf; ++i) {
+            double v = T[static_cast<size_t>(i) * nc + c];
+            for (int k = std::max(0, i - bw); k < i; ++k) v -= m(i, k) * T[static_cast<size_t>(k) * nc + c];
+            T[static_cast<size_t>(i) * nc + c] = v / m(i, i);
+        }
+        for (int i = nf - 1; i >= 0; --i) {
+            double v = T[static_cast<size_t>(i) * nc + c];
+            for (int k = i + 1; k <= std::min(nf - 1, i + bw); ++k) v -= m(k, i) * T[static_cast<size_t>(k) * nc + c];
+            T[static_cast<size_t>(i) * nc + c] = v / m(i, i);
+        }
+    }
+    return true;
+}
+
 uint16_t to_bf16(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -509,7 +568,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
     }
     P->ncomp = static_cast<int>(P->comp_coef.size());
-    P->Lmax = disc->nindex > 0 ? lmax_set : P->lmin + J;
+    P->Lmax = disc->nindex > 0 ? lmax_set : disc->full ? P->w : P->lmin + J;
     // ---- 1D tables per (patch, dir, level) ---------------------------------
     const int ntab = geom->npatch * d * (P->Lmax + 1);
     P->tabs.resize(ntab);
@@ -618,6 +677,31 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 T.oKd = fit->second[7];
                 T.oMd = fit->second[8];
             }
+    // prolongations of a full tensor plan: level l -> level w per direction
+    if (disc->full && geom->npatch == 1) {
+        P->xfer_off.assign(static_cast<size_t>(d) * (P->w + 1), -1);
+        for (int k = 0; k < d; ++k) {
+            const PatchHost& H = P->patches[0];
+            const Tab1D& Tf = P->tabs[tab_index(P, 0, k, P->w)];
+            const std::vector<double> Uf = make_knots(p, r, P->w, H.grading[k], H.gamma[k]);
+            for (int lev = 0; lev < P->w; ++lev) {
+                const Tab1D& Tc = P->tabs[tab_index(P, 0, k, lev)];
+                const std::vector<double> Uc = make_knots(p, r, lev, H.grading[k], H.gamma[k]);
+                std::vector<double> T;
+                if (!prolongation_1d(p, Uc, Uf, nq, P->gauss_x.data(), P->gauss_w.data(), &T)) {
+                    set_error("prolongation from level %d failed", lev);
+                    delete P;
+                    return IGA_ERR_GEOMETRY;
+                }
+                const int nbc = Tc.nb;
+                auto& dp = P->dpool;
+                P->xfer_off[static_cast<size_t>(k) * (P->w + 1) + lev] = static_cast<int64_t>(dp.size());
+                for (int i = 0; i < Tf.ni; ++i)
+                    for (int j = 0; j < Tc.ni; ++j)
+                        dp.push_back(T[static_cast<size_t>(Tf.lo + i) * nbc + Tc.lo + j]);
+            }
+        }
+    }
     // homogeneous control points (w P, w) per patch
     for (int pt = 0; pt < geom->npatch; ++pt) {
         const PatchHost& H = P->patches[pt];
@@ -694,6 +778,9 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     }
     // ---- grids, tiles, preconditioner blocks --------------------------------
     size_t lds_max = 0, lds_op = 0, lds_fd_plain = 0;
+    // the full tensor grid of one patch and one sample may exceed the LDS of a
+    // workgroup: it is then solved by whole-device kernels
+    const bool stream_ok = disc->full && geom->npatch == 1 && P->nsamples == 1;
     for (int c = 0; c < P->ncomp; ++c)
         for (int pt = 0; pt < geom->npatch; ++pt) {
             Grid g;
@@ -772,20 +859,47 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.tile[0] = g.ni[0];
                 g.tile[1] = g.ni[1];
                 g.tile[2] = g.ni[2];
+                // the largest element range of a tile of t unknowns along direction k
+                std::vector<int> maxel(3 * 65, -1);
+                auto max_elems = [&](int k, int t) {
+                    int& v = maxel[k * 65 + std::min(t, 64)];
+                    if (t > 64 || v < 0) {
+                        int lo, hi, best_k = 0;
+                        for (int a = 0; a < g.ni[k]; a += t) {
+                            elem_range(a, std::min(g.ni[k], a + t), p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
+                            best_k = std::max(best_k, hi - lo + 1);
+                        }
+                        if (t > 64) return best_k;
+                        v = best_k;
+                    }
+                    return v;
+                };
+                // tiles of about TT unknowns first; where none fits (a full grid long in
+                // every direction), any smaller tile
+                for (int pass = 0; pass < 2 && best < 0; ++pass)
                 for (int t3 = 1; t3 <= std::min(g.ni[2], 64); ++t3)
-                    for (int t2 = 1; t2 <= std::min(g.ni[1], 64); ++t2) {
-                        const int t1 = std::min(g.ni[0], std::max(1, TT / (t2 * t3)));
+                    for (int t2 = 1; t2 <= std::min(g.ni[1], 64); ++t2)
+                    for (int t1s = 1; t1s <= (pass == 0 ? 1 : std::min(g.ni[0], 64)); ++t1s) {
+                        const int t1 = pass == 0 ? std::min(g.ni[0], std::max(1, TT / (t2 * t3))) : t1s;
                         const int t[3] = {t1, t2, t3};
-                        size_t nel = 1, halo = 1, ntl = 1;
+                        // work estimate from the first tile (pass 0) or the largest one;
+                        // the fit test always with the largest element range over the tiles
+                        size_t nel = 1, halo = 1, ntl = 1, nelx = 1, halox = 1;
                         for (int k = 0; k < 3; ++k) {
                             int lo, hi;
-                            elem_range(0, t[k], p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
-                            const int ne = hi - lo + 1 + (t[k] < g.ni[k] ? 1 : 0);
+                            const int nex = max_elems(k, t[k]);
+                            int ne = nex;
+                            if (pass == 0) {
+                                elem_range(0, t[k], p, m, g.E[k], &lo, &hi, P->tabs[g.tab[k]].lo);
+                                ne = hi - lo + 1 + (t[k] < g.ni[k] ? 1 : 0);
+                            }
                             nel *= ne;
                             halo *= static_cast<size_t>(ne - 1) * m + p + 1;
+                            nelx *= nex;
+                            halox *= static_cast<size_t>(nex - 1) * m + p + 1;
                             ntl *= (g.ni[k] + t[k] - 1) / t[k];
                         }
-                        const size_t lds = (halo + nel * pl + kWaves) * sizeof(double);
+                        const size_t lds = (std::max(halo, halox) + std::max(nel, nelx) * pl + kWaves) * sizeof(double);
                         if (lds + kSolveLdsHead > kLdsLimit) continue;
                         const double work = static_cast<double>(ntl) * (nel + 64.0);
                         if (best < 0 || work < best) {
@@ -861,6 +975,13 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     // long grids: the block's slab of the long factor is read from
                     // memory when it does not fit beside the grid vectors
                     if (wide && fd_layout(gc, ls, lb, usize).total + kSolveLdsHead > kLdsLimit) gc.fdstage = -1;
+                    // a full tensor grid whose vectors do not fit: whole-device kernels
+                    if (stream_ok && (fd_layout(gc, ls, lb, usize).total + kSolveLdsHead > kLdsLimit ||
+                                      (cls == 1 && g.fdstage == kFdStream))) {
+                        gc.fdstage = kFdStream;
+                        P->streamed = true;
+                        continue;
+                    }
                     lds_max = std::max(lds_max, static_cast<size_t>(fd_layout(gc, ls, lb, usize).total));
                 }
             } else {
@@ -878,11 +999,17 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     g.fdstage |= 1 << k;
                     if (fd_layout_3d(g, ld, 8).total + nn_bytes + kSolveLdsHead > kLdsLimit) g.fdstage &= ~(1 << k);
                 }
+                if (stream_ok && fd_layout_3d(g, ld, 8).total + kSolveLdsHead > kLdsLimit) {
+                    g.fdstage = kFdStream;  // a full tensor grid whose vectors do not fit
+                    P->streamed = true;
+                }
                 glp = g;
                 // + the activations of the learned preconditioner
-                lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total) +
-                                                static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float));
-                lds_fd_plain = std::max(lds_fd_plain, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
+                if (g.fdstage != kFdStream) {
+                    lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total) +
+                                                    static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float));
+                    lds_fd_plain = std::max(lds_fd_plain, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
+                }
             }
             P->grids_lp.push_back(glp);
             P->grids.push_back(g);
@@ -1106,6 +1233,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.fdtask_lp = take(sizeof(Task) * P->fdtask_lp.size());
     L.bar = take(kBarBytes);
     L.trace = take(sizeof(unsigned long long) * (1 + 6 * 4096));
+    L.fg = take(sizeof(double) * (kFgKinds * kFgBlocks + kFgScalars));
     L.total = off;
     *out = P;
     return IGA_OK;
@@ -1167,6 +1295,22 @@ iga_status iga_sg_fd_factor(iga_sg_plan plan, int dir, int lev, int* n, double* 
             std::memcpy(U_host + static_cast<size_t>(i) * T.ni, &plan->dpool[T.oU + static_cast<int64_t>(i) * T.ldu],
                         T.ni * sizeof(double));
     if (lam_host) std::memcpy(lam_host, &plan->dpool[T.oLam], T.ni * sizeof(double));
+    return IGA_OK;
+}
+
+iga_status iga_sg_prolongation(iga_sg_plan plan, int dir, int lev, int* nf, int* nc, double* T_host) {
+    if (!plan || !nf || !nc || dir < 0 || dir >= plan->dim || lev < 0 || lev >= plan->w || plan->xfer_off.empty()) {
+        set_error("iga_sg_prolongation: a full tensor plan of one patch, 0 <= dir < dim, 0 <= lev < w");
+        return IGA_ERR_INVALID_ARG;
+    }
+    const Tab1D& Tf = plan->tabs[tab_index(plan, 0, dir, plan->w)];
+    const Tab1D& Tc = plan->tabs[tab_index(plan, 0, dir, lev)];
+    *nf = Tf.ni;
+    *nc = Tc.ni;
+    if (T_host) {
+        const int64_t o = plan->xfer_off[static_cast<size_t>(dir) * (plan->w + 1) + lev];
+        std::memcpy(T_host, plan->dpool.data() + o, sizeof(double) * static_cast<size_t>(Tf.ni) * Tc.ni);
+    }
     return IGA_OK;
 }
 

@@ -68,6 +68,11 @@ struct iga_sg_plan_s {
     bool lifted = false;          // the last assembly had Dirichlet data
     size_t lds_bytes = 0;
     size_t lds_plain = 0;  // LDS of a solve without the learned preconditioner (3D: no activations)
+    bool streamed = false;  // a full tensor grid solved by whole-device kernels (kFdStream)
+    // full tensor plans (one patch): the prolongation from level l to level w in
+    // direction k, interior unknowns, row-major [ni(w)][ni(l)] in the double
+    // pool at xfer_off[k * (w + 1) + l] (-1 where absent)
+    std::vector<int64_t> xfer_off;
     igasg::Layout lay{};
     // binding
     void* ws = nullptr;
@@ -89,4 +94,8 @@ struct iga_sg_plan_s {
 namespace igasg {
 int tab_index(const iga_sg_plan_s* P, int patch, int dir, int lev);
 Params make_params(iga_sg_plan_s* P, bool lowp_fd = false);
+// IGA_ERR_STATE when the plan's static workspace was taken over by another plan
+iga_status workspace_ok(const iga_sg_plan_s* P);
+// whole-device FD-preconditioned CG of a full tensor plan's single grid
+iga_status fg_solve_plain(iga_sg_plan_s* P, const iga_sg_solve_opts* o, iga_sg_report* rep);
 }  // namespace igasg
