@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--learned-test", type=int, default=4, help="held-out coefficient samples")
     ap.add_argument("--no-annulus", action="store_true", help="skip the quarter-annulus (cfg2) measurements")
     ap.add_argument("--no-lshape", action="store_true", help="skip the L-shape (cfg4, three patches) measurements")
+    ap.add_argument("--no-full", action="store_true",
+                    help="skip the full-grid IGA comparison and the sparse-grid preconditioner")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the annulus run with assembly + solve replayed as one HIP graph")
     ap.add_argument("--no-small", action="store_true",
@@ -633,6 +635,113 @@ def cpu_baseline(O, W, args):
     }
 
 
+def annulus_exact_quadrature(nc: int, nq: int = 4):
+    """Gauss points of nc x nc parametric cells (nq x nq each), weights
+    w |det DF| and the exact solution of the paper's regular annulus problem,
+    u = -(x^2+y^2-1)(x^2+y^2-4) x y^2, in closed form: the quarter annulus is
+    F(xi) = (1 + xi_1) A(xi_2) with A the rational quadratic quarter arc of the
+    unit circle (control points (1,0), (1,1), (0,1), weights 1, 1/sqrt 2, 1)."""
+    g, w = np.polynomial.legendre.leggauss(nq)
+    g, w = (g + 1.0) / 2.0, w / 2.0
+    t = ((np.arange(nc)[:, None] + g[None, :]) / nc).ravel()
+    wt = np.tile(w, nc) / nc
+    T2, T1 = np.meshgrid(t, t, indexing="ij")   # direction 1 fastest
+    W2, W1 = np.meshgrid(wt, wt, indexing="ij")
+    xi = np.stack([T1.ravel(), T2.ravel()], axis=1)
+    v = xi[:, 1]
+    s = 1.0 / np.sqrt(2.0)
+    B = [(1 - v) ** 2, 2 * v * (1 - v), v ** 2]
+    dB = [-2 * (1 - v), 2 - 4 * v, 2 * v]
+    wts, P = [1.0, s, 1.0], [(1.0, 0.0), (1.0, 1.0), (0.0, 1.0)]
+    Wt = sum(wk * b for wk, b in zip(wts, B))
+    dW = sum(wk * b for wk, b in zip(wts, dB))
+    N = [sum(wk * b * p[c] for wk, b, p in zip(wts, B, P)) for c in range(2)]
+    dN = [sum(wk * b * p[c] for wk, b, p in zip(wts, dB, P)) for c in range(2)]
+    A = [n / Wt for n in N]
+    dA = [(dn * Wt - n * dW) / Wt ** 2 for n, dn in zip(N, dN)]
+    rad = 1.0 + xi[:, 0]
+    x, y = rad * A[0], rad * A[1]
+    wq = (W1 * W2).ravel() * rad * np.abs(A[0] * dA[1] - A[1] * dA[0])
+    r2 = x * x + y * y
+    return xi, wq, -(r2 - 1.0) * (r2 - 4.0) * x * y * y
+
+
+def run_full_vs_sg(S, W, torch, args):
+    """Standard IGA on the full tensor grid against SG-IGA on the paper's
+    regular annulus problem (Sec. 4.2: a = 1, f = -Laplace u, p=3 C^2; the
+    error-against-unknowns and error-against-time comparisons and the IGA
+    rows of Table 2) at levels 5-8, FP64 to 1e-12: relative L2 error against
+    the exact solution by Gauss quadrature (256 x 256 parametric cells, 4 x 4
+    points, weights w |det DF|), unknowns, and assembly + solve time (median
+    of three, host clock around synchronised calls; full grids of level >= 6
+    run on the whole-device path).  Then the sparse grid as a preconditioner
+    of the level-8 full problem (Sec. 5 outlook): outer iterations, inner CG
+    iterations and time of the two-level flexible CG against FD-PCG alone."""
+    xq, wq, uex = annulus_exact_quadrature(256)
+    xt = torch.as_tensor(xq, device="cuda:0")
+    nrm = float(np.sqrt(np.sum(wq * uex ** 2)))
+
+    def wl_of(J):
+        return W.config("cfg2", w=J, f=W._field("annulus_rhs", 0.0), a=W._field("const", 1.0),
+                        exact=W._field("annulus_u"))
+
+    def timed_solve(P, **kw):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.assemble()
+            rep = P.solve(check=False, **kw)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return rep, float(np.median(ts))
+
+    rows = []
+    for J in range(5, 9):
+        for full in (False, True):
+            P = S.Plan(wl_of(J), full=full)
+            P.bind(device="cuda:0")
+            rep, ms = timed_solve(P, precision="fp64", tol=1e-12, maxit=2000, max_refine=3)
+            u = P.combine(xt).cpu().numpy()
+            rows.append({"method": "IGA" if full else "SG-IGA", "J": J, "unknowns": int(P.ndof.sum()),
+                         "grids": int(P.ncomp), "rel_l2_error": float(np.sqrt(np.sum(wq * (u - uex) ** 2)) / nrm),
+                         "ms_assemble_solve": ms, "cg_iterations": int(rep["total_iters"]), "code": int(rep["code"])})
+    out = {"workload": "paper's regular quarter annulus (a = 1, f = -Laplace u), p=3 C^2, levels 5-8, FP64 tol 1e-12",
+           "rows": rows}
+    for key in ("IGA", "SG-IGA"):
+        r = np.array([(row["J"], row["rel_l2_error"]) for row in rows if row["method"] == key])
+        out[f"l2_rate_{key}"] = float(-np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0])
+    J = 8
+    F = S.Plan(wl_of(J), full=True)
+    F.bind(device="cuda:0")
+    G = S.Plan(wl_of(J))
+    G.bind(device="cuda:0", stream=F.stream)
+    G.assemble()
+    rep, ms = timed_solve(F, precision="fp64", tol=1e-12, maxit=2000, max_refine=3)
+    u0 = F.coeffs(0).cpu().numpy()
+    tl = {"level": J, "unknowns": int(F.ndof.sum()),
+          "fd_pcg": {"iterations": int(rep["iters"][0]), "ms_assemble_solve": ms, "code": int(rep["code"])}}
+    for key, every, prec in (("two_level_every_iteration_fp64_inner", 1, "fp64"),
+                             ("two_level_every_iteration_mixed_inner", 1, "fp32"),
+                             ("two_level_first_direction_only", 0, "fp64")):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F.assemble()
+            G.assemble()
+            r2 = F.solve_twolevel(G, tol=1e-12, maxit=500, inner_tol=1e-8, inner_precision=prec,
+                                  coarse_every=every, check=False)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        u = F.coeffs(0).cpu().numpy()
+        tl[key] = {"outer_iterations": r2["iters"], "inner_cg_iterations": int(r2["inner_iters"]),
+                   "ms_assemble_solve": float(np.median(ts)), "code": int(r2["code"]),
+                   "rel_diff_vs_fd_pcg": float(np.linalg.norm(u - u0) / np.linalg.norm(u0))}
+    out["sparse_grid_preconditioner"] = tl
+    return out
+
+
 def cpu_leg(args, W, xi, sub):
     """The CPU side of the benchmark, the only part that runs the oracle: its
     timing (unless --no-cpu-baseline) and the reference values every accuracy
@@ -713,6 +822,7 @@ def main():
     S.lib()  # fail loudly if the HIP library is missing
     if args.headline_only:
         args.no_cpu_baseline = args.no_learned = args.no_annulus = args.no_small = args.no_lshape = True
+        args.no_full = True
     if args.calibrate_copy > 0:
         # plain copy of a known size: reads and writes calibrate the HBM counters
         n = args.calibrate_copy * (1 << 20) // 8
@@ -794,6 +904,9 @@ def main():
         print(f"[bench] learned done", file=sys.stderr, flush=True)
     if not args.no_small:
         line.update(run_small_configs(S, W, torch, {"cfg1": refs["cfg1"], "cfg3": refs["cfg3"]}))
+    if not args.no_full:
+        line["iga_vs_sg_annulus"] = run_full_vs_sg(S, W, torch, args)
+        print(f"[bench] full grid and two-level done", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -3,8 +3,9 @@ solved by the same GPU kernels as the sparse-grid components, against the
 oracle and against the sparse-grid solution (the paper's comparison, Sec. 4,
 Table 2, regular quarter annulus, d = 2, p = 3, C^2).
 
-The GPU keeps a 2D grid's fast-diagonalisation work vectors in LDS, so full
-grids are limited to about 4k unknowns (J <= 5 here)."""
+Full grids up to level 5 (1,089 unknowns) run in the persistent solve like
+the components; larger ones (levels 6-8, up to 66,049 unknowns) on the
+whole-device path (schedule 4), chosen by the plan."""
 import sys
 
 import numpy as np
@@ -82,8 +83,6 @@ def test_full_grid_against_sparse_grid(S):
         wl = _annulus_paper(J)
         Po = O.Problem(wl)
         for full in (False, True):
-            if full and J > 5:
-                continue
             P = S.Plan(wl, full=full)
             P.bind()
             P.assemble()
@@ -98,6 +97,8 @@ def test_full_grid_against_sparse_grid(S):
                 ev[1].record(P.stream)
                 torch.cuda.synchronize()
                 ms.append(ev[0].elapsed_time(ev[1]))
+            rep = _solve(P, "fp64")  # the whole-device path synchronises inside: its report is exact
+            assert np.all(rep["status"] == 0)
             if full:
                 e = Po.full_errors([J, J], _full_array(P, Po, 0), 128)
             else:
@@ -106,11 +107,20 @@ def test_full_grid_against_sparse_grid(S):
             rows.append((J, full, int(P.ndof.sum()), e[0] / e[2], e[1] / e[3]))
             log(f"  {'IGA   ' if full else 'SG-IGA'} J={J} unknowns={rows[-1][2]:6d} "
                 f"relative L2 {rows[-1][3]:.3e} H1 {rows[-1][4]:.3e} GPU {np.median(ms):.3f} ms")
-    for J in range(3, 6):
+    for J in range(3, 9):
         sg = [r for r in rows if r[0] == J and not r[1]][0]
         fu = [r for r in rows if r[0] == J and r[1]][0]
         assert fu[3] <= sg[3] and fu[4] <= sg[4]
-    # at matched accuracy the sparse grid needs fewer unknowns: the largest
-    # full grid is beaten by a sparse grid of no more unknowns
-    fu5 = [r for r in rows if r[0] == 5 and r[1]][0]
-    assert any(r[2] <= fu5[2] and r[3] <= fu5[3] for r in rows if not r[1])
+    # at matched accuracy the sparse grid needs fewer unknowns: each full grid
+    # of level 5-7 is matched in L2 by a sparse grid with fewer unknowns
+    for J in (5, 6, 7):
+        fu = [r for r in rows if r[0] == J and r[1]][0]
+        assert any(r[2] < fu[2] and r[3] <= fu[3] for r in rows if not r[1]), J
+    # full-grid rates on levels 5-8 against the provable p + 1 = 4 (L2) and
+    # p = 3 (H1) and the IGA row of Table 2 (d = 2, C^2, p = 3: 4.08 / 2.93)
+    r = np.array([(row[0], row[3], row[4]) for row in rows if row[1] and row[0] >= 5])
+    l2 = -np.polyfit(r[:, 0], np.log2(r[:, 1]), 1)[0]
+    h1 = -np.polyfit(r[:, 0], np.log2(r[:, 2]), 1)[0]
+    log(f"  full-grid rates over J=5..8: L2 {l2:.2f} (Table 2: 4.08), H1 {h1:.2f} (Table 2: 2.93)")
+    assert abs(l2 - 4.0) < 0.3 and abs(l2 - 4.08) < 0.4
+    assert abs(h1 - 3.0) < 0.3 and abs(h1 - 2.93) < 0.4
