@@ -68,3 +68,21 @@ def low_regular_annulus(W, J, r=2):
     """The paper's low-regular problem: quarter annulus, a = 1, f = 1, no exact
     solution (Sec. 4.3, Table 3)."""
     return W.config("cfg2", w=J, r=r, f=W._field("const", 1.0), a=W._field("const", 1.0), exact=None)
+
+
+def graded_gauss(level: int, kind: str, gamma: float, nq: int):
+    """Tensor Gauss points of the level-`level` parametric mesh graded by the
+    radical map of Sec. 4.4 in both directions (breakpoints f(k / 2^level))
+    and their parametric weights: exact for piecewise polynomials on that
+    mesh and on every coarser mesh of the same grading."""
+    import oracle as O
+    t = np.array([O.grade(kind, gamma, k / 2 ** level) for k in range(2 ** level + 1)])
+    g, w = np.polynomial.legendre.leggauss(nq)
+    g, w = (g + 1.0) / 2.0, w / 2.0
+    h = np.diff(t)
+    x1 = (t[:-1, None] + h[:, None] * g[None, :]).ravel()
+    w1 = (h[:, None] * w[None, :]).ravel()
+    X2, X1 = np.meshgrid(x1, x1, indexing="ij")  # direction 1 fastest
+    W2, W1 = np.meshgrid(w1, w1, indexing="ij")
+    xi = np.stack([X1.ravel(), X2.ravel()], axis=1)
+    return xi, (W1 * W2).ravel()
