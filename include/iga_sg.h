@@ -116,6 +116,10 @@ typedef struct {
      * given together with full, returns IGA_ERR_INVALID_ARG. */
     const int* index_host;
     int nindex;
+    /* nonzero with nindex > 0: every multi-index of the set gets a grid, also
+     * those with c_b = 0 (their coefficient stays 0 in the combination), so
+     * that the details of iga_sg_detail_norms can be formed */
+    int keep_all;
 } iga_sg_disc;
 
 /* Fields (right-hand side f, coefficient a, Dirichlet data g). */
@@ -391,6 +395,23 @@ iga_status iga_sg_graph_launch(iga_sg_plan plan);
  * options), IGA_ERR_STATE (not assembled), the errors of iga_sg_solve. */
 iga_status iga_sg_solve_twolevel(iga_sg_plan full, iga_sg_plan sg, const iga_sg_solve_opts* outer,
                                  const iga_sg_solve_opts* inner, int coarse_every, iga_sg_report* report);
+
+/* Details of the combination technique (Sec. 3; the profits of the
+ * knapsack choice, Sec. 4.2): for every grid b of a plan built from a
+ * downward-closed index set with keep_all,
+ *     norms_dev[b] = ( sum_q wq_dev[q] Delta_b(x_q)^2 )^(1/2),
+ *     Delta_b = sum over z in {0,1}^d of (-1)^|z| u_(b-z)   (u of a negative
+ *               level is 0),
+ * with u_b the grid's solution (lift included) at the parametric points
+ * xi_dev [n][dim] (device, FP64) and the caller's quadrature weights wq_dev
+ * [n] (device, including |det DF|).  vals_dev: caller-owned device scratch of
+ * ngrid * n doubles (the grid values, [grid][point], left there).  norms_dev:
+ * [ngrid] device, grid order of iga_sg_components.  One patch, one sample.
+ * Sums in a fixed order (reproducible).  Errors: IGA_ERR_INVALID_ARG (a plan
+ * without keep_all, several patches or samples, null pointers),
+ * IGA_ERR_STATE before iga_sg_solve. */
+iga_status iga_sg_detail_norms(iga_sg_plan plan, const double* xi_dev, const double* wq_dev, int64_t n,
+                               double* vals_dev, double* norms_dev);
 
 /* Test hook: the 1D prolongation of a full tensor plan from level lev to the
  * plan's level w in direction dir (0-based), interior unknowns: T_host

@@ -31,7 +31,7 @@ EXPORTS = (
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
     "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full", "iga_sg_solve_twolevel",
-    "iga_sg_prolongation",
+    "iga_sg_prolongation", "iga_sg_detail_norms",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
     "iga_nn_init", "iga_nn_save", "iga_nn_load",
 )
@@ -63,7 +63,8 @@ class _Geometry(C.Structure):
 class _Disc(C.Structure):
     _fields_ = [("p", C.c_int), ("r", C.c_int), ("w", C.c_int), ("lmin", C.c_int), ("nq", C.c_int),
                 ("nsamples", C.c_int), ("op_tile", C.c_int), ("op_tile3", C.c_int), ("fd_tasks", C.c_int),
-                ("full", C.c_int), ("index_host", C.POINTER(C.c_int)), ("nindex", C.c_int)]
+                ("full", C.c_int), ("index_host", C.POINTER(C.c_int)), ("nindex", C.c_int),
+                ("keep_all", C.c_int)]
 
 
 class _Field(C.Structure):
@@ -144,6 +145,7 @@ def lib():
         L.iga_sg_solve_twolevel.argtypes = [vp, vp, C.POINTER(_Opts), C.POINTER(_Opts), C.c_int,
                                             C.POINTER(_Report)]
         L.iga_sg_prolongation.argtypes = [vp, C.c_int, C.c_int, _ip, _ip, _dp]
+        L.iga_sg_detail_norms.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
@@ -208,11 +210,13 @@ class Plan:
     ``full`` plans the single full tensor-product grid at level w in every
     direction (standard IGA) instead of the combination technique;
     ``index_set`` ([n, d] absolute levels, downward closed) the combination
-    over that set instead of the sparse-grid set of level w.
+    over that set instead of the sparse-grid set of level w; ``keep_all``
+    gives every index of the set a grid (also those with coefficient 0), for
+    ``detail_norms``.
     """
 
     def __init__(self, wl: Dict[str, Any], nsamples: int = 1, shape: Optional[Dict[str, int]] = None,
-                 full: bool = False, index_set=None):
+                 full: bool = False, index_set=None, keep_all: bool = False):
         self.wl = wl
         self.dim = d = int(wl["dim"])
         self._keep = []
@@ -256,6 +260,7 @@ class Plan:
             self._keep.append(iset)
             D.index_host = iset.ctypes.data_as(_ip)
             D.nindex = len(iset)
+            D.keep_all = int(keep_all)
         h = C.c_void_p()
         _check(lib().iga_sg_plan_create(C.byref(G), C.byref(D), C.byref(h)))
         self.h = h
@@ -475,6 +480,20 @@ class Plan:
             u = u.view(self.nsamples, n)
             g = g.view(self.nsamples, n, self.dim) if grad else None
         return (u, g) if grad else u
+
+    def detail_norms(self, xi, wq):
+        """||Delta_b||_L2 of every grid b under the quadrature (xi [n, d]
+        parametric points, wq [n] weights including |det DF|); a plan built
+        with keep_all (iga_sg_detail_norms)."""
+        import torch
+        xi = torch.as_tensor(xi, dtype=torch.float64, device=self.device).contiguous()
+        wq = torch.as_tensor(wq, dtype=torch.float64, device=self.device).contiguous()
+        n = xi.shape[0]
+        vals = torch.empty(self.ncomp * max(n, 1), dtype=torch.float64, device=self.device)
+        out = torch.empty(self.ncomp, dtype=torch.float64, device=self.device)
+        _check(lib().iga_sg_detail_norms(self.h, C.c_void_p(xi.data_ptr()), C.c_void_p(wq.data_ptr()), n,
+                                         C.c_void_p(vals.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out.cpu().numpy()
 
     def eval(self, comp: int, xi, patch=None, grad: bool = False):
         import torch

@@ -1170,6 +1170,31 @@ __global__ void __launch_bounds__(kBlock) k_full_coeffs(Params P, int g0, int g1
     }
 }
 
+// Detail norms: workgroup b forms Delta_b(x_i) = sum_z (-1)^|z| u_(b-z)(x_i)
+// from the grid values vals[grid][i] (the table nb[b][z] names grid b - z,
+// -1 for a negative level) and sums w_i Delta_b(x_i)^2 over the points in a
+// fixed order (thread-strided partial sums, then the workgroup tree).
+__global__ void __launch_bounds__(kBlock) k_detail_norms(const double* vals, const double* wq, int64_t n,
+                                                         const int* nb, int nz, double* out) {
+    __shared__ double red[kWaves];
+    const int b = blockIdx.x;
+    int g[8];
+    double sg[8];
+    for (int z = 0; z < 8; ++z) {
+        g[z] = z < nz ? nb[b * 8 + z] : -1;
+        sg[z] = (__popc(z) & 1) ? -1.0 : 1.0;
+    }
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+        double dv = 0.0;
+        for (int z = 0; z < nz; ++z)
+            if (g[z] >= 0) dv += sg[z] * vals[static_cast<int64_t>(g[z]) * n + i];
+        acc += wq[i] * dv * dv;
+    }
+    const double t = wg_sum(acc, red);
+    if (threadIdx.x == 0) out[b] = sqrt(t);
+}
+
 // Clears the lift arrays (a kernel, so that the assembly can be captured).
 __global__ void __launch_bounds__(kBlock) k_zero(double* v, int64_t n) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
@@ -2102,6 +2127,34 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
     Params K = make_params(P);
     HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, g0, g1), blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
     if (grad) HIP_OK(launch_combine_grad(P->dim, P->p, blocks_for(n), st, K, xi, patch, n, grad, g0, g1, 0));
+    HIP_OK(hipGetLastError());
+    return IGA_OK;
+}
+
+iga_status iga_sg_detail_norms(iga_sg_plan P, const double* xi, const double* wq, int64_t n, double* vals,
+                               double* norms) {
+    if (!P || n < 0 || (n > 0 && (!xi || !wq || !vals)) || !norms) {
+        set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (P->detail_off < 0 || P->patches.size() != 1 || P->nsamples != 1) {
+        set_error("iga_sg_detail_norms needs a plan of one patch and one sample built from an index set "
+                  "with keep_all");
+        return IGA_ERR_INVALID_ARG;
+    }
+    if (!P->solved) {
+        set_error("iga_sg_detail_norms before iga_sg_solve");
+        return IGA_ERR_STATE;
+    }
+    if (const iga_status ws = check_workspace(P)) return ws;
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    Params K = make_params(P);
+    const int ng = static_cast<int>(P->grids.size());
+    for (int g = 0; g < ng && n > 0; ++g)
+        HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, g, g + 1), blocks_for(n), st, K, xi, nullptr, n,
+                              vals + static_cast<int64_t>(g) * n, g, g + 1, 0));
+    hipLaunchKernelGGL(k_detail_norms, dim3(ng), dim3(kBlock), 0, st, vals, wq, n, K.ipool + P->detail_off,
+                       1 << P->dim, norms);
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }

@@ -545,7 +545,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     }
                 if (I.count(bz)) c += (nz & 1) ? -1 : 1;
             }
-            if (c == 0) continue;
+            if (c == 0 && !disc->keep_all) continue;
             for (int k = 0; k < d; ++k) P->comp_levels.push_back(b[k]);
             P->comp_coef.push_back(static_cast<double>(c));
         }
@@ -568,6 +568,30 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 }
     }
     P->ncomp = static_cast<int>(P->comp_coef.size());
+    if (disc->keep_all && disc->nindex > 0) {
+        // the details' table: component of levels b - z for z in {0,1}^d
+        std::map<std::array<int, 3>, int> at;
+        for (int c = 0; c < P->ncomp; ++c) {
+            std::array<int, 3> b{0, 0, 0};
+            for (int k = 0; k < d; ++k) b[k] = P->comp_levels[c * d + k];
+            at[b] = c;
+        }
+        P->detail_off = static_cast<int64_t>(P->ipool.size());
+        for (int c = 0; c < P->ncomp; ++c)
+            for (int z = 0; z < 8; ++z) {
+                int idx = -1;
+                if (z < (1 << d)) {
+                    std::array<int, 3> b{0, 0, 0};
+                    bool neg = false;
+                    for (int k = 0; k < d; ++k) {
+                        b[k] = P->comp_levels[c * d + k] - ((z >> k) & 1);
+                        neg = neg || b[k] < 0;
+                    }
+                    if (!neg) idx = at.at(b);  // the set is downward closed
+                }
+                P->ipool.push_back(idx);
+            }
+    }
     P->Lmax = disc->nindex > 0 ? lmax_set : disc->full ? P->w : P->lmin + J;
     // ---- 1D tables per (patch, dir, level) ---------------------------------
     const int ntab = geom->npatch * d * (P->Lmax + 1);

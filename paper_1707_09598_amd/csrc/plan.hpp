@@ -73,6 +73,9 @@ struct iga_sg_plan_s {
     // direction k, interior unknowns, row-major [ni(w)][ni(l)] in the double
     // pool at xfer_off[k * (w + 1) + l] (-1 where absent)
     std::vector<int64_t> xfer_off;
+    // index-set plans with keep_all: per grid the grids of levels b - z,
+    // z in {0,1}^d (-1 for a negative level), [ngrid][8] in the int pool
+    int64_t detail_off = -1;
     igasg::Layout lay{};
     // binding
     void* ws = nullptr;
