@@ -134,7 +134,11 @@ enum {
     IGA_FIELD_GRID3D = 5,       /* trilinear interpolation on the vertex grid m/(n-1) of
                                    [0,1]^3; data_dev [n3][n2][n1], x fastest */
     IGA_FIELD_CORNER = 6,       /* r^(2/3) sin(2 theta/3), theta in [0, 2 pi) */
-    IGA_FIELD_AFFINE = 7        /* prm[0] + prm[1] x + prm[2] y + prm[3] z */
+    IGA_FIELD_AFFINE = 7,       /* prm[0] + prm[1] x + prm[2] y + prm[3] z */
+    IGA_FIELD_QP_SAMPLES = 8    /* values given at the Gauss points: data_dev [nqp_total] in the
+                                   order of iga_sg_quad_points (every Gauss point of every grid of
+                                   every sample); for f and a only; with a coefficient of this kind
+                                   the learned preconditioner's log a input is 0 */
 };
 
 typedef struct {
@@ -277,9 +281,16 @@ iga_status iga_sg_components(iga_sg_plan plan, int* n, int* levels_host, int64_t
  * Jacobian, a, f and the operator coefficients a w |det DF| DF^-1 DF^-T
  * (Sec. 2.2, Galerkin form of Problem 1), then the load vectors and the
  * diagonal of each operator (for the preconditioner's scaling), both summed
- * element by element.  f and a are required; g must be NULL or of kind
- * IGA_FIELD_NONE (homogeneous Dirichlet: the GPU path has no lifting; other
- * data returns IGA_ERR_INVALID_ARG).  Enqueued on the plan's stream. */
+ * element by element.  f and a are required (analytic, GRID3D in 3D, or
+ * QP_SAMPLES).  g: NULL or IGA_FIELD_NONE for homogeneous Dirichlet data;
+ * otherwise an analytic field on a two-dimensional plan with polynomial maps
+ * (Problem 1 with u = g on the boundary): the lift u_D interpolates g at the
+ * patch corners and is the L2 projection (arc length) of g on each Dirichlet
+ * side's trace space with the corners fixed; the load is corrected by
+ * -a(u_D, phi) and u_D enters iga_sg_combine / iga_sg_eval /
+ * iga_sg_coeffs_full.  Other data returns IGA_ERR_INVALID_ARG.  Enqueued
+ * on the plan's stream; a non-positive det DF at a Gauss point sets a flag
+ * that the next iga_sg_solve with a report returns as IGA_ERR_GEOMETRY. */
 iga_status iga_sg_assemble(iga_sg_plan plan, const iga_field* f, const iga_field* a,
                            const iga_field* g);
 
@@ -412,6 +423,17 @@ iga_status iga_sg_solve_twolevel(iga_sg_plan full, iga_sg_plan sg, const iga_sg_
  * IGA_ERR_STATE before iga_sg_solve. */
 iga_status iga_sg_detail_norms(iga_sg_plan plan, const double* xi_dev, const double* wq_dev, int64_t n,
                                double* vals_dev, double* norms_dev);
+
+/* The Gauss points of the plan, for fields sampled there (IGA_FIELD_QP_SAMPLES:
+ * a random coefficient drawn at the quadrature points, data of another
+ * code): xq_dev [nqp_total][dim] (device, FP64) receives the physical point
+ * F(xi_q) of every Gauss point (the p+1-point rules per element of Sec. 4.1,
+ * grid after grid in iga_sg_components order, sample after sample, within a
+ * grid direction 1 fastest), wq_dev [nqp_total] (device, nullable) the
+ * weight w_q |det DF(xi_q)|.  *nq_host receives nqp_total; with cap <
+ * nqp_total (or xq_dev NULL) only the count is returned.  Asynchronous on the
+ * plan's stream.  Errors: IGA_ERR_STATE before iga_sg_bind. */
+iga_status iga_sg_quad_points(iga_sg_plan plan, double* xq_dev, double* wq_dev, int64_t cap, int64_t* nq_host);
 
 /* Test hook: the 1D prolongation of a full tensor plan from level lev to the
  * plan's level w in direction dir (0-based), interior unknowns: T_host

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigasg.so")
 
 FIELD = {None: -1, "none": -1, "const": 0, "sinprod": 1, "sincos": 2, "annulus_rhs": 3,
-         "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7}
+         "poly_rhs": 4, "grid3d": 5, "corner": 6, "affine": 7, "qp_samples": 8}
 GRADE = {"uniform": 0, "radical": 1, "toward0": 2, "toward1": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16fd": 2}
 SCHED = {"auto": 0, "static": 1, "lists": 2, "grid": 3, "stream": 4}
@@ -31,7 +31,7 @@ EXPORTS = (
     "iga_sg_apply", "iga_sg_rhs", "iga_sg_set_rhs", "iga_sg_fd_factor", "iga_sg_matrices_1d", "iga_sg_destroy",
     "iga_sg_last_error", "iga_sg_version", "iga_sg_loga", "iga_sg_set_network", "iga_sg_graph_capture",
     "iga_sg_graph_launch", "iga_sg_bind_static", "iga_sg_coeffs_full", "iga_sg_solve_twolevel",
-    "iga_sg_prolongation", "iga_sg_detail_norms",
+    "iga_sg_prolongation", "iga_sg_detail_norms", "iga_sg_quad_points",
     "iga_nn_param_count", "iga_nn_forward", "iga_nn_backward", "iga_nn_adam", "iga_nn_pair",
     "iga_nn_init", "iga_nn_save", "iga_nn_load",
 )
@@ -146,6 +146,7 @@ def lib():
                                             C.POINTER(_Report)]
         L.iga_sg_prolongation.argtypes = [vp, C.c_int, C.c_int, _ip, _ip, _dp]
         L.iga_sg_detail_norms.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+        L.iga_sg_quad_points.argtypes = [vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.iga_sg_combine.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_eval.argtypes = [vp, C.c_int, vp, vp, C.c_int64, vp, vp]
         L.iga_sg_coeffs.argtypes = [vp, C.c_int, vp]
@@ -357,11 +358,12 @@ class Plan:
             t = t.to(device=self.device, dtype=torch.float64).contiguous()
             keep.append(t)
             F.data_dev = t.data_ptr()
-            shp = tuple(t.shape)[::-1]
-            for k in range(3):
-                F.n[k] = int(shp[k])
-            if t.dim() == 4:  # one field per sample
-                F.sample_stride = int(shp[0] * shp[1] * shp[2])
+            if spec["kind"] != "qp_samples":  # a gridded field: [samples,] n3, n2, n1
+                shp = tuple(t.shape)[::-1]
+                for k in range(3):
+                    F.n[k] = int(shp[k])
+                if t.dim() == 4:  # one field per sample
+                    F.sample_stride = int(shp[0] * shp[1] * shp[2])
         return F
 
     def assemble(self, f=None, a=None, g=None) -> None:
@@ -480,6 +482,20 @@ class Plan:
             u = u.view(self.nsamples, n)
             g = g.view(self.nsamples, n, self.dim) if grad else None
         return (u, g) if grad else u
+
+    def quad_points(self, weights: bool = False):
+        """Physical Gauss points of every grid ([nqp_total, d], device), and
+        with ``weights`` the weights w |det DF| (iga_sg_quad_points): where a
+        QP_SAMPLES field (``{"kind": "qp_samples", "data": values}``) is
+        sampled."""
+        import torch
+        n = C.c_int64(0)
+        _check(lib().iga_sg_quad_points(self.h, None, None, 0, C.byref(n)))
+        xq = torch.empty((n.value, self.dim), dtype=torch.float64, device=self.device)
+        wq = torch.empty(n.value, dtype=torch.float64, device=self.device) if weights else None
+        _check(lib().iga_sg_quad_points(self.h, C.c_void_p(xq.data_ptr()),
+                                        C.c_void_p(wq.data_ptr() if weights else 0), n.value, C.byref(n)))
+        return (xq, wq) if weights else xq
 
     def detail_norms(self, xi, wq):
         """||Delta_b||_L2 of every grid b under the quadrature (xi [n, d]

@@ -319,8 +319,11 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
             inv[2][2] = (DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]) / det;
         }
         if (!(det > 0.0)) atomicOr(err, 1);
-        const double av = field_eval_k<KA>(field_of_sample(fa, g.sample), d, x);
-        const double fv = field_eval_k<KF>(field_of_sample(ff, g.sample), d, x);
+        // a field sampled at the Gauss points holds its value at index gq
+        const double av = fa.kind == IGA_FIELD_QP_SAMPLES ? fa.data[gq]
+                                                          : field_eval_k<KA>(field_of_sample(fa, g.sample), d, x);
+        const double fv = ff.kind == IGA_FIELD_QP_SAMPLES ? ff.data[gq]
+                                                          : field_eval_k<KF>(field_of_sample(ff, g.sample), d, x);
         const double s = av * wq * fabs(det);
         // parametric coefficients Gp = a w |det| DF^-1 DF^-T (symmetric)
         double Gp[3][3];
@@ -636,7 +639,35 @@ __global__ void __launch_bounds__(kBlock) k_loga(Params P, FieldDev fa, int g0, 
         }
         double x[3] = {0, 0, 0};
         for (int k = 0; k < d; ++k) x[k] = Xh[k] / Xh[3];
-        P.loga[gi] = log(field_eval_k<KA>(field_of_sample(fa, g.sample), d, x));
+        P.loga[gi] = fa.kind == IGA_FIELD_QP_SAMPLES ? 0.0 : log(field_eval_k<KA>(field_of_sample(fa, g.sample), d, x));
+    }
+}
+
+// Physical Gauss points F(xi_q) and weights w_q |det DF(xi_q)| of every grid.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_quad_points(Params P, double* xq, double* wq) {
+    constexpr int d = DIM;
+    for (int64_t gq = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gq < P.nqp_total;
+         gq += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int gi = grid_of_qp(P, 0, P.ngrid, gq);
+        const Grid& g = P.grids[gi];
+        const int64_t l = gq - g.qp_off;
+        int qk[3];
+        qk[0] = static_cast<int>(l % g.Q[0]);
+        qk[1] = static_cast<int>((l / g.Q[0]) % g.Q[1]);
+        qk[2] = static_cast<int>(l / (static_cast<int64_t>(g.Q[0]) * g.Q[1]));
+        double x[3] = {0, 0, 0}, DF[3][3], W, dW[3] = {0, 0, 0};
+        geom_at<DIM>(P, g, qk, x, DF, &W, dW);
+        for (int k = 0; k < d; ++k) xq[gq * d + k] = x[k];
+        if (wq) {
+            double w = 1.0;
+            for (int k = 0; k < d; ++k) w *= P.dpool[P.tabs[g.tab[k]].oWq + qk[k]];
+            const double det = d == 2 ? DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]
+                                      : DF[0][0] * (DF[1][1] * DF[2][2] - DF[1][2] * DF[2][1]) -
+                                            DF[0][1] * (DF[1][0] * DF[2][2] - DF[1][2] * DF[2][0]) +
+                                            DF[0][2] * (DF[1][0] * DF[2][1] - DF[1][1] * DF[2][0]);
+            wq[gq] = w * fabs(det);
+        }
     }
 }
 
@@ -1580,7 +1611,8 @@ FieldDev to_dev(const iga_field* f) {
 
 bool field_ok(const iga_field* f, int dim) {
     if (!f) return false;
-    if (f->kind < IGA_FIELD_CONST || f->kind > IGA_FIELD_AFFINE) return false;
+    if (f->kind < IGA_FIELD_CONST || f->kind > IGA_FIELD_QP_SAMPLES) return false;
+    if (f->kind == IGA_FIELD_QP_SAMPLES && !f->data_dev) return false;
     if (f->kind == IGA_FIELD_GRID3D && (dim != 3 || !f->data_dev || f->n[0] < 2 || f->n[1] < 2 || f->n[2] < 2))
         return false;
     return true;
@@ -1821,7 +1853,8 @@ iga_status iga_sg_assemble(iga_sg_plan P, const iga_field* f, const iga_field* a
         return IGA_ERR_INVALID_ARG;
     }
     const bool lift = g && g->kind != IGA_FIELD_NONE;
-    if (lift && (P->dim != 2 || P->rational_any || !field_ok(g, P->dim) || g->kind == IGA_FIELD_GRID3D)) {
+    if (lift && (P->dim != 2 || P->rational_any || !field_ok(g, P->dim) || g->kind == IGA_FIELD_GRID3D ||
+                 g->kind == IGA_FIELD_QP_SAMPLES)) {
         set_error("Dirichlet data: two-dimensional plans with polynomial maps and an analytic field");
         return IGA_ERR_INVALID_ARG;
     }
@@ -2015,7 +2048,14 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
     std::vector<GState> both(2 * static_cast<size_t>(ng)), stv(ng);
     HIP_OK(hipMemcpyAsync(both.data(), reinterpret_cast<char*>(P->ws) + P->lay.st2, sizeof(GState) * 2 * ng,
                           hipMemcpyDeviceToHost, st));
+    int geom_err = 0;  // the assembly's flag: a non-positive det DF at some Gauss point
+    HIP_OK(hipMemcpyAsync(&geom_err, reinterpret_cast<char*>(P->ws) + P->lay.bar + 64, sizeof(int),
+                          hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    if (geom_err) {
+        set_error("the geometry map has a non-positive Jacobian determinant at a Gauss point");
+        return IGA_ERR_GEOMETRY;
+    }
     for (int gi = 0; gi < ng; ++gi) {
         const int sg = P->grids[gi].state;  // the grid's solver-state group
         const GState& a = both[sg];
@@ -2127,6 +2167,26 @@ iga_status iga_sg_eval(iga_sg_plan P, int comp, const double* xi, const int* pat
     Params K = make_params(P);
     HIP_OK(launch_combine(P->dim, P->p, uniform_tables(P, g0, g1), blocks_for(n), st, K, xi, patch, n, u, g0, g1, 0));
     if (grad) HIP_OK(launch_combine_grad(P->dim, P->p, blocks_for(n), st, K, xi, patch, n, grad, g0, g1, 0));
+    HIP_OK(hipGetLastError());
+    return IGA_OK;
+}
+
+iga_status iga_sg_quad_points(iga_sg_plan P, double* xq, double* wq, int64_t cap, int64_t* nq) {
+    if (!P || !nq) {
+        set_error("invalid arguments");
+        return IGA_ERR_INVALID_ARG;
+    }
+    *nq = P->nqp_total;
+    if (!xq || cap < P->nqp_total) return IGA_OK;
+    if (!P->bound) {
+        set_error("iga_sg_quad_points before iga_sg_bind");
+        return IGA_ERR_STATE;
+    }
+    if (const iga_status ws = check_workspace(P)) return ws;
+    hipStream_t st = static_cast<hipStream_t>(P->stream);
+    Params K = make_params(P);
+    if (P->dim == 2) hipLaunchKernelGGL(k_quad_points<2>, dim3(blocks_for(P->nqp_total)), dim3(kBlock), 0, st, K, xq, wq);
+    else hipLaunchKernelGGL(k_quad_points<3>, dim3(blocks_for(P->nqp_total)), dim3(kBlock), 0, st, K, xq, wq);
     HIP_OK(hipGetLastError());
     return IGA_OK;
 }

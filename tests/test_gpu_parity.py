@@ -324,3 +324,78 @@ def test_index_set_combination_parity(S, precision, bar):
         coef, _ = Po.solve([int(v) for v in lv])
         ref += c * Po.eval([int(v) for v in lv], coef, xi)
     assert rel(u, ref) < bar
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg5"])
+def test_fields_sampled_at_gauss_points(S, name):
+    """iga_sg_quad_points and IGA_FIELD_QP_SAMPLES: the points and weights
+    equal the oracle's map and |det DF| at the same parametric Gauss points,
+    the weights integrate 1 to the domain's area on every grid, and the
+    coordinates lie in
+    the domain; coefficient and load sampled at those points by the caller
+    give the solve of the same fields given analytically (to rounding of
+    the two evaluations of the same formulas), and that solve matches the
+    oracle's."""
+    import torch
+    if name == "cfg2":
+        wl = W.config("cfg2", w=7)
+        area = 3 * np.pi / 4
+    else:
+        wl = W.config("cfg5", w=5, a=W._field("const", 1.0), f=W._field("sinprod", 3 * np.pi ** 2))
+        area = 1.0
+    P = S.Plan(wl)
+    P.bind()
+    xq, wq = P.quad_points(weights=True)
+    x, w = xq.cpu().numpy(), wq.cpu().numpy()
+    assert x.shape == (len(w), wl["dim"])
+    # every grid's points are the tensor Gauss rule of its uniform elements
+    # (direction 1 fastest): coordinates and weights against the oracle's
+    # geometry map at the same parametric points, and the weights' sum
+    # against the area (exact for the cube; the annulus's rational |det DF|
+    # is not integrated exactly by p+1 points on its coarsest grids: 8.7e-6
+    # on the grid with one element around the arc)
+    Po = O.Problem(wl)
+    g1, w1 = np.polynomial.legendre.leggauss(wl["p"] + 1)
+    g1, w1 = (g1 + 1) / 2, w1 / 2
+    off = 0
+    for c in range(P.ncomp):
+        axes = []
+        for l in P.levels[c]:
+            E = 2 ** int(l)
+            axes.append((((np.arange(E)[:, None] + g1[None, :]) / E).ravel(), np.tile(w1, E) / E))
+        nq = int(np.prod([len(t) for t, _ in axes]))
+        mesh = np.meshgrid(*[t for t, _ in axes][::-1], indexing="ij")
+        wmesh = np.meshgrid(*[ww for _, ww in axes][::-1], indexing="ij")
+        xi = np.stack([m.ravel() for m in mesh[::-1]], axis=1)
+        wpar = np.prod(np.stack([m.ravel() for m in wmesh], axis=1), axis=1)
+        pick = np.random.default_rng(c).choice(nq, size=min(nq, 200), replace=False)
+        for i in pick:
+            xp, jac, _, _ = Po.geometry(xi[i])
+            assert np.abs(x[off + i] - xp).max() < 1e-13
+            assert abs(w[off + i] - wpar[i] * abs(np.linalg.det(jac))) < 1e-13 * max(w[off + i], 1e-300) + 1e-300
+        assert abs(w[off:off + nq].sum() - area) < (1e-4 if name == "cfg2" else 1e-12) * area
+        off += nq
+    assert off == len(w)
+    if name == "cfg2":
+        r = np.hypot(x[:, 0], x[:, 1])
+        assert r.min() > 1 - 1e-12 and r.max() < 2 + 1e-12 and x.min() > -1e-12
+        a_q = 1 + 0.5 * np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+        fa = {"kind": "qp_samples", "data": torch.as_tensor(a_q, device="cuda")}
+        ff = None
+    else:
+        assert x.min() > -1e-15 and x.max() < 1 + 1e-15
+        f_q = 3 * np.pi ** 2 * np.prod(np.sin(np.pi * x), axis=1)
+        fa = None
+        ff = {"kind": "qp_samples", "data": torch.as_tensor(f_q, device="cuda")}
+    P.assemble()
+    P.solve(precision="fp64", tol=1e-12, maxit=800, max_refine=3)
+    ref = [P.coeffs(c).cpu().numpy() for c in range(P.ncomp)]
+    P.assemble(a=fa, f=ff)
+    P.solve(precision="fp64", tol=1e-12, maxit=800, max_refine=3)
+    for c in range(P.ncomp):
+        got = P.coeffs(c).cpu().numpy()
+        assert np.linalg.norm(got - ref[c]) <= 1e-12 * np.linalg.norm(ref[c]), c
+    pts, _ = W.eval_points(wl["dim"], 4096, lattice=0, seed=21)
+    u = P.combine(pts).cpu().numpy()
+    uo = Po.sg_eval(Po.solve_all(), pts)
+    assert np.linalg.norm(u - uo) <= 1e-10 * np.linalg.norm(uo)
