@@ -304,7 +304,7 @@ struct Params {
     double* q;
     double* rt;
     GState* st2;       // two buffers of ngrid
-    double* part;      // partial sums: [5 kinds][2 parity][max(nop, nfd)]
+    double* part;      // partial sums: [6 kinds][2 parity][max(nop, nfd)]
     int64_t part_stride;
     const Task* optask;
     const Task* fdtask;

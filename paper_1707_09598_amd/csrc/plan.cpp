@@ -1241,7 +1241,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.rt = take(sizeof(double) * nd);
     L.st2 = take(sizeof(GState) * ng * 2);
     size_t pst = std::max(P->optask.size(), std::max(P->fdtask.size(), P->fdtask_lp.size()));
-    L.part = take(sizeof(double) * pst * 10);
+    L.part = take(sizeof(double) * pst * 12);  // [6 kinds][2 parities][tasks]
     L.loga = take(sizeof(double) * nd);
     L.fdscale = take(sizeof(double) * nd);
     // two sums per local basis function of each element; an element has as

@@ -643,6 +643,7 @@ struct FdIO {
     int learned;
     const double* rold;   // previous residual: part2 = z . rold (flexible CG)
     double* part2;
+    double* part3 = nullptr;  // r . z_FD of the plain preconditioner (learned solves: the stopping test)
 };
 
 
@@ -1186,13 +1187,14 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
         rz = wg_sum(rz, L.red);
         if (rz > 0.0 && isfinite(rz)) scale = mult ? -1.0 : s;
     }
-    double dot = 0.0, dot2 = 0.0;
+    double dot = 0.0, dot2 = 0.0, dot3 = 0.0;
     for (int o = threadIdx.x; o < n; o += kBlock) {
         const double zo = scale > 0.0 ? L.R[o] + scale * Y[o]
                                       : (scale < 0.0 ? L.R[o] * exp(static_cast<double>(Y[o])) : L.R[o]);
         io.z[off + o] = zo;
         if (io.rdot) dot += L.Own[o] * zo;
         if (io.part2) dot2 += io.rold[off + o] * zo;
+        if (io.part3) dot3 += L.Own[o] * L.R[o];
     }
     if (io.part) {
         const double t = wg_sum(dot, L.red);
@@ -1201,6 +1203,10 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     if (io.part2) {
         const double t = wg_sum(dot2, L.red);
         if (threadIdx.x == 0) *io.part2 = t;
+    }
+    if (io.part3) {
+        const double t = wg_sum(dot3, L.red);
+        if (threadIdx.x == 0) *io.part3 = t;
     }
     __syncthreads();
 }
@@ -1312,7 +1318,7 @@ __device__ __forceinline__ void trace_mark(const SolveArgs& A, int sweep, int ph
 __device__ __forceinline__ double* part_ptr(const Params& P, int kind, int parity) {
     return P.part + static_cast<int64_t>(kind * 2 + parity) * P.part_stride;
 }
-enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3, PK_ZRO = 4 };
+enum { PK_PQ = 0, PK_RES = 1, PK_RR = 2, PK_RZ = 3, PK_ZRO = 4, PK_RZF = 5 };
 enum { ACT_SKIP = 0, ACT_RESID, ACT_ITER, ACT_DONE };
 
 struct Decision {
@@ -1329,7 +1335,12 @@ __device__ __forceinline__ double wave_sum_partials(const double* part, int coun
     return v;
 }
 
-__device__ inline Decision decide(const SolveArgs& A, const GState& st, double rho) {
+// rho: r . z of the last preconditioning (the search preconditioner: CG beta
+// and alpha); rhof: r . z_FD of the plain preconditioner for the same r.  The
+// stopping tests of a learned solve use rhof: the learned r . z does not
+// measure the error (it can fall below the target long before r . P^-1 r
+// does, which ended inner solves early and spent the refinement budget).
+__device__ inline Decision decide(const SolveArgs& A, const GState& st, double rho, double rhof) {
     Decision D;
     D.status = GS_OK;
     D.rho = rho;
@@ -1355,7 +1366,8 @@ __device__ inline Decision decide(const SolveArgs& A, const GState& st, double r
             D.act = ACT_ITER;
             D.rho0 = rho;
         }
-    } else if (rho <= A.tol_in2 * st.rho0 || rho <= A.tol2 * st.rhob || st.it >= A.maxit) {
+    } else if ((A.learned ? rhof : rho) <= A.tol_in2 * st.rho0 || (A.learned ? rhof : rho) <= A.tol2 * st.rhob ||
+               st.it >= A.maxit) {
         // inner solve done (its own tolerance, or the outer target reached by the
         // recursive residual): x += d and replace r by the FP64 residual
         D.act = ACT_RESID;
@@ -1379,7 +1391,7 @@ static_assert(sizeof(TaskCtx) <= kCtxBytes, "TaskCtx too large");
 // Wavefront-0 registers of a task context between issue and finish.
 struct CtxLoads {
     GState st;
-    double vrz, vpq, vres, vzro;
+    double vrz, vpq, vres, vzro, vrzf;
 };
 
 __device__ __forceinline__ double sum_strided(const double* p, int count) {
@@ -1404,6 +1416,7 @@ __device__ __forceinline__ void ctx_issue(const Params& P, const Grid& g, const 
     c.st = S0[g.state];
     c.vrz = sum_strided(part_ptr(P, PK_RZ, nxt) + g.gblk_off, g.gnblk);
     c.vzro = phase == 1 ? sum_strided(part_ptr(P, PK_ZRO, nxt) + g.gblk_off, g.gnblk) : 0.0;
+    c.vrzf = sum_strided(part_ptr(P, PK_RZF, nxt) + g.gblk_off, g.gnblk);
     c.vpq = 0.0;
     c.vres = 0.0;
     if (phase >= 2) c.vpq = sum_strided(part_ptr(P, PK_PQ, cur) + g.gtile_off, g.gntile);
@@ -1422,8 +1435,9 @@ __device__ __forceinline__ void ctx_finish(const SolveArgs& A, CtxLoads& c, int 
         c.vpq += __shfl_xor(c.vpq, o, 64);
         c.vres += __shfl_xor(c.vres, o, 64);
         c.vzro += __shfl_xor(c.vzro, o, 64);
+        c.vrzf += __shfl_xor(c.vrzf, o, 64);
     }
-    const Decision D = decide(A, c.st, c.st.stage == STAGE_ITER ? c.vrz : 0.0);
+    const Decision D = decide(A, c.st, c.st.stage == STAGE_ITER ? c.vrz : 0.0, c.st.stage == STAGE_ITER ? c.vrzf : 0.0);
     if (threadIdx.x == 0) {
         ctx->st = c.st;
         ctx->D = D;
@@ -1658,6 +1672,7 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
                 io.rold = r_old;
                 io.part2 = DIM == 3 && A.learned && act == ACT_ITER ? part_ptr(P, PK_ZRO, cur) + g.blk_off + M.local
                                                                     : nullptr;
+                io.part3 = DIM == 3 && A.learned ? part_ptr(P, PK_RZF, cur) + g.blk_off + M.local : nullptr;
                 if constexpr (DIM == 3) fd3_bwd_run<TU, TC>(P, M, io, lds);
                 else fd_bwd_run<TU, TC>(P, M, M.local, io, lds);
             }
@@ -1756,10 +1771,11 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
     st.it = st.total_it = st.refine = 0;
     st.status = GS_RUNNING;
     st.op64 = 0;
-    double rz = 0.0, zro = 0.0;
+    double rz = 0.0, zro = 0.0, rzf = 0.0;
     int pr = 0, pp = 0;  // buffer parities of r and p
     double* sl = slots;   // partial sum of one tile / block (written by thread 0)
     double* sl2 = slots + 1;
+    double* sl3 = slots + 2;
     // sum of the per-tile or per-block partials, in tile order (every thread)
     auto tiles = [&](auto&& body, int n) {
         double acc = 0.0;
@@ -1771,7 +1787,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
         return acc;
     };
     for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
-        const Decision D = decide(A, st, st.stage == STAGE_ITER ? rz : 0.0);
+        const Decision D = decide(A, st, st.stage == STAGE_ITER ? rz : 0.0, st.stage == STAGE_ITER ? rzf : 0.0);
         if (D.act == ACT_DONE) {
             st.stage = STAGE_DONE;
             st.status = D.status;
@@ -1790,6 +1806,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
         fio.learned = 0;
         fio.rold = nullptr;
         fio.part2 = nullptr;
+        fio.part3 = nullptr;
         fio.z = nullptr;
         fio.rdot = nullptr;
         fio.part = sl;
@@ -1850,7 +1867,8 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
                           (A.learned_iters == 0 || st.it + 1 < A.learned_iters);
             fio.rold = r_cur;
             fio.part2 = DIM == 3 && A.learned ? sl2 : nullptr;
-            double z2 = 0.0;
+            fio.part3 = DIM == 3 && A.learned ? sl3 : nullptr;
+            double z2 = 0.0, z3 = 0.0;
             const double rzn = tiles([&](int b) {
                 if constexpr (DIM == 3) {
                     fd3_issue_bwd<TU>(P, M, P.rt, r_oth, lds);
@@ -1865,6 +1883,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
                 if (fio.part2) {
                     __syncthreads();
                     z2 += *sl2;
+                    z3 += *sl3;
                 }
             }, g.nblk);
             st.rhob = D.rhob;
@@ -1874,6 +1893,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             st.rho = D.rho;
             rz = rzn;
             zro = z2;
+            rzf = fio.part3 ? z3 : rzn;
             pr ^= 1;
             pp ^= 1;
         } else {
@@ -1939,6 +1959,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             st.it = 0;
             st.refine += 1;
             rz = rzn;
+            rzf = rzn;
         }
     }
     if (threadIdx.x == 0) {

@@ -282,22 +282,21 @@ def test_learned_solve_parity_and_fallback(S):
 
 def test_training_lowers_loss_and_report_gain(S):
     """Train on the library's kernels (pairs from the plain PCG on training
-    samples), then report iterations and time of the learned and plain
-    solves on held-out samples.  The loss must fall and the plain and the
-    windowed learned solves (correction on the first ten iterations) must
-    converge.  The gain is reported, not asserted: on these problems the
-    trained correction takes more iterations than the diagonally scaled
-    fast-diagonalisation preconditioner alone, each of them costs several
-    times more, and with the correction on every iteration flexible CG can
-    stall (status 5), which this test prints."""
+    samples), then solve held-out samples with the trained correction on
+    every iteration of flexible CG: every grid converges (status 0), the
+    solutions equal the oracle's direct solves (1e-9), at w=5 and, with the
+    same network, at w=7 on a 64^3 field.  Iterations and time of the
+    learned and plain solves are reported; the gain is not asserted (on
+    these problems the trained correction costs iterations against the
+    diagonally scaled fast diagonalisation alone)."""
     import torch
     from paper_1707_09598_amd import learn
     w, ntr, nte = 5, 6, 2
     log(f"case learned training cfg5 w={w} train {ntr} held-out {nte}")
     fields = W.grf_samples(ntr + nte, n=24)
 
-    def plan_for(a):
-        P = S.Plan(W.config("cfg5", w=w, a=W._field("grid3d", data=a)))
+    def plan_for(a, level=w):
+        P = S.Plan(W.config("cfg5", w=level, a=W._field("grid3d", data=a)))
         P.bind()
         P.assemble()
         return P
@@ -315,22 +314,32 @@ def test_training_lowers_loss_and_report_gain(S):
     after = learn.evaluate(net, pairs, shapes)
     log(f"  training loss over all pairs: before {before:.4e} after {after:.4e}")
     assert after < before
-    for s in range(ntr, ntr + nte):
-        P = plan_for(fields[s])
+
+    def held_out(P, wl, tag):
         P.set_network(net)
         res = {}
         for key, mode, k in (("plain", False, 0), ("learned", True, 0), ("learned-10", True, 10)):
             P.assemble()
-            rep = P.solve(precision="fp64", tol=1e-10, maxit=600, max_refine=4, learned=mode,
+            rep = P.solve(precision="fp64", tol=1e-11, maxit=600, max_refine=4, learned=mode,
                           learned_iters=k, check=False)
-            # the correction on every iteration may stall flexible CG (reported);
-            # the plain and the windowed solves must converge
-            assert rep["code"] == 0 or key == "learned", (key, rep["code"])
+            assert rep["code"] == 0 and np.all(rep["status"] == 0), (tag, key, rep["status"])
+            if key == "learned":
+                Po = O.Problem(wl)
+                xi, _ = W.eval_points(3, 2048, lattice=8, seed=12345)
+                u = P.combine(xi).cpu().numpy()
+                u_ref = Po.sg_eval(Po.solve_all(), xi)
+                e = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+                log(f"  {tag} learned on every iteration: u_sg rel {e:.2e} against the oracle")
+                assert e <= 1e-9
             P.assemble()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            P.solve_async(precision="fp64", tol=1e-10, maxit=600, max_refine=4, learned=mode, learned_iters=k)
+            P.solve_async(precision="fp64", tol=1e-11, maxit=600, max_refine=4, learned=mode, learned_iters=k)
             torch.cuda.synchronize()
-            res[key] = (rep["total_iters"], 1e3 * (time.perf_counter() - t0), rep["code"])
-        log(f"  sample {s}: " + " | ".join(f"{k} {v[0]} iterations {v[1]:.2f} ms (status {v[2]})"
-                                          for k, v in res.items()))
+            res[key] = (rep["total_iters"], 1e3 * (time.perf_counter() - t0))
+        log(f"  {tag}: " + " | ".join(f"{k} {v[0]} iterations {v[1]:.2f} ms" for k, v in res.items()))
+
+    for s in range(ntr, ntr + nte):
+        held_out(plan_for(fields[s]), W.config("cfg5", w=w, a=W._field("grid3d", data=fields[s])), f"sample {s} w={w}")
+    a7 = W.grf_samples(1, n=64, first_seed=ntr)[0]
+    held_out(plan_for(a7, 7), W.config("cfg5", w=7, a=W._field("grid3d", data=a7)), "sample 6 w=7 64^3 field")
