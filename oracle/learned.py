@@ -27,6 +27,16 @@ from typing import Callable, List, Sequence, Tuple
 import numpy as np
 
 
+def to_bf16(x) -> np.ndarray:
+    """x rounded to bfloat16 (8 significand bits; nearest, ties to even)
+    through float32, as FP32 values are converted on the GPU; returned as
+    float64 (finite inputs)."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def shift(x: np.ndarray, d3: int, d2: int, d1: int) -> np.ndarray:
     """y[..., i3, i2, i1] = x[..., i3 + d3, i2 + d2, i1 + d1], zero outside."""
     y = np.zeros_like(x)
@@ -114,6 +124,18 @@ class Net:
             acts.append(h)
         return h, acts
 
+    def infer_bf16(self, x: np.ndarray) -> np.ndarray:
+        """Output in the solve's inference precision: the input features, the
+        weights and every hidden activation rounded to BF16 (the activations
+        after bias and ReLU, through FP32), the sums formed exactly (FP64),
+        the output rounded to FP32."""
+        h = to_bf16(x)
+        for li, (w, b) in enumerate(self.layers):
+            h = conv3d(h, to_bf16(w), b).astype(np.float32).astype(np.float64)
+            if li + 1 < len(self.layers):
+                h = to_bf16(np.maximum(h, 0.0))
+        return h
+
     def loss_and_grad(self, x: np.ndarray, t: np.ndarray, count: int, head: int = 0):
         """L = sum (pred - t)^2 / (2 count) and its gradients (list of (dw, db));
         pred = y (head 0) or x[1] exp(y) (head 1)."""
@@ -145,12 +167,14 @@ def features(r: np.ndarray, zfd: np.ndarray, loga: np.ndarray) -> Tuple[np.ndarr
     return np.stack([r / sr, zfd / s, la]), s
 
 
-def precondition(net: Net, r: np.ndarray, zfd: np.ndarray, loga: np.ndarray, head: int = 0) -> np.ndarray:
+def precondition(net: Net, r: np.ndarray, zfd: np.ndarray, loga: np.ndarray, head: int = 0,
+                 bf16: bool = False) -> np.ndarray:
     """z = z_FD + s y (head 0) or z_FD exp(y) (head 1) with
     y = N(r / ||r||, z_FD / s, log a - mean), s = ||z_FD||; z_FD itself when
-    the corrected z is not a descent direction."""
+    the corrected z is not a descent direction.  bf16: the network in the
+    solve's inference precision (Net.infer_bf16)."""
     x, s = features(r, zfd, loga)
-    y, _ = net.forward(x)
+    y = net.infer_bf16(x) if bf16 else net.forward(x)[0]
     z = zfd + s * y[0] if head == 0 else zfd * np.exp(y[0])
     rz = float(np.sum(r * z))
     return z if (rz > 0.0 and np.isfinite(rz)) else zfd

@@ -152,8 +152,14 @@ constexpr int kMetaFd = 5;     // cached fast-diagonalisation tasks per workgrou
 constexpr int kMetaSlots = kMetaOp + kMetaFd + 1;  // + one slot for tasks beyond the cache
 constexpr int kCtxBytes = 256;  // LDS for the per-task context
 constexpr int kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
-constexpr int kNnHidden = 16;           // hidden channels of the learned preconditioner (max)
-constexpr int kNnFloatsPerDof = 3 + 2 * kNnHidden + 1;  // its LDS activations per unknown
+// learned preconditioner 3 -> h1 -> h2 -> 1: the largest hidden layers, and
+// the LDS bytes per unknown of its BF16 activations (3 features padded to 8
+// channels, h1, h2) and FP32 output
+constexpr int kNnMaxH1 = 32;
+constexpr int kNnMaxH2 = 48;
+constexpr int kNnLdsBytesPerDof = 2 * (8 + kNnMaxH1 + kNnMaxH2) + 4;
+// packed BF16 weights of the largest network: [16 ceil(cout/16)][27][cin rounded to 8] per layer
+constexpr int kNnPackedMax = 32 * 27 * 8 + 48 * 27 * kNnMaxH1 + 16 * 27 * kNnMaxH2;
 
 // LDS layout (byte offsets) of a 2D fast-diagonalisation task:
 //   R, S      two grid-sized FP64 work vectors
@@ -271,6 +277,7 @@ struct Layout {
     size_t bar;                   // barrier + counters
     size_t trace;                 // phase timestamps
     size_t fg;                    // whole-device solves: partial sums [kFgKinds][kFgBlocks], scalars
+    size_t nnw;                   // packed BF16 network weights (kNnPackedMax)
     size_t total;
 };
 
@@ -323,6 +330,8 @@ struct Params {
     double* lift_rw;     // the lift arrays (written by the assembly)
     int mp;            // several patches: interface sums and grouped solver states
     const float* nn;   // learned preconditioner parameters (or nullptr)
+    const uint16_t* nnw;  // its weights packed in BF16 (workspace; filled at each learned solve)
+    uint16_t* nnw_rw;
     int nn_ch[4];      // channels of its three layers (3, h1, h2, 1)
     int nn_head;       // 0: z = z_FD + s y; 1: z = z_FD exp(y)
 };

@@ -671,6 +671,28 @@ __global__ void __launch_bounds__(kBlock) k_quad_points(Params P, double* xq, do
     }
 }
 
+// Packs the network's FP32 weights w[co][ci][t] into the BF16 layout of the
+// solve's convolutions, Wp[co][t][ci] per layer with co rounded up to 16 and
+// ci to 8 (zero-filled); one thread per packed element.
+__global__ void __launch_bounds__(kBlock) k_nn_pack(Params P) {
+    const int ch[4] = {3, P.nn_ch[1], P.nn_ch[2], 1};
+    int64_t base_w = 0, base_p = 0;
+    for (int l = 0; l < 3; ++l) {
+        const int cin = ch[l], cout = ch[l + 1], cip = nn_pad8(cin);
+        const int64_t np = nn_packed_layer(cin, cout);
+        for (int64_t e = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; e < np;
+             e += static_cast<int64_t>(gridDim.x) * kBlock) {
+            const int ci = static_cast<int>(e % cip);
+            const int t = static_cast<int>((e / cip) % 27);
+            const int co = static_cast<int>(e / (static_cast<int64_t>(cip) * 27));
+            const float v = (co < cout && ci < cin) ? P.nn[base_w + (static_cast<int64_t>(co) * cin + ci) * 27 + t] : 0.0f;
+            reinterpret_cast<__bf16*>(P.nnw_rw)[base_p + e] = static_cast<__bf16>(v);
+        }
+        base_w += static_cast<int64_t>(cout) * cin * 27 + cout;
+        base_p += np;
+    }
+}
+
 // Clears the assembly error flag.
 __global__ void k_clear_flag(int* flag) {
     if (threadIdx.x == 0) *flag = 0;
@@ -1555,6 +1577,8 @@ Params make_params(iga_sg_plan_s* P, bool lowp_fd) {
     }
     K.nn = P->nn;
     for (int i = 0; i < 4; ++i) K.nn_ch[i] = P->nn_ch[i];
+    K.nnw_rw = reinterpret_cast<uint16_t*>(base + L.nnw);
+    K.nnw = K.nnw_rw;
     K.nn_head = P->nn_head;
     for (int i = 0; i < P->nq && i < 8; ++i) {
         K.gx[i] = P->gauss_x[i];
@@ -1950,6 +1974,11 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
         set_error("learned preconditioning needs a three-dimensional plan and an attached network");
         return IGA_ERR_INVALID_ARG;
     }
+    if (A.learned) {
+        // the network's weights in the BF16 layout of the solve's convolutions
+        hipLaunchKernelGGL(k_nn_pack, dim3(64), dim3(kBlock), 0, st, K);
+        HIP_OK(hipGetLastError());
+    }
     char* trbase = reinterpret_cast<char*>(P->ws) + P->lay.trace;
     A.trace = o->timing >= 2 ? reinterpret_cast<unsigned long long*>(trbase) : nullptr;
     A.trace_sweeps = kTraceSweeps;
@@ -2302,9 +2331,9 @@ iga_status iga_sg_set_network(iga_sg_plan P, const int* channels, int nlayers, c
         return IGA_OK;
     }
     if (P->dim != 3 || !channels || nlayers != 3 || channels[0] != 3 || channels[3] != 1 || channels[1] < 1 ||
-        channels[1] > kNnHidden || channels[2] < 1 || channels[2] > kNnHidden) {
-        set_error("the learned preconditioner takes 3 layers, channels 3 -> h1 -> h2 -> 1 (h <= %d), 3D plans",
-                  kNnHidden);
+        channels[1] > kNnMaxH1 || channels[2] < 1 || channels[2] > kNnMaxH2) {
+        set_error("the learned preconditioner takes 3 layers, channels 3 -> h1 -> h2 -> 1 (h1 <= %d, h2 <= %d), "
+                  "3D plans", kNnMaxH1, kNnMaxH2);
         return IGA_ERR_INVALID_ARG;
     }
     if (head < 0 || head > 1) {

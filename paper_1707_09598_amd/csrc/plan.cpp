@@ -1018,7 +1018,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 int ord3[3] = {0, 1, 2};
                 std::sort(ord3, ord3 + 3, [&](int a, int b) { return g.ni[a] < g.ni[b]; });
                 g.fdstage = 0;
-                const size_t nn_bytes = static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float);
+                const size_t nn_bytes = static_cast<size_t>(kNnLdsBytesPerDof) * g.ndof;
                 for (int k : ord3) {
                     g.fdstage |= 1 << k;
                     if (fd_layout_3d(g, ld, 8).total + nn_bytes + kSolveLdsHead > kLdsLimit) g.fdstage &= ~(1 << k);
@@ -1031,7 +1031,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 // + the activations of the learned preconditioner
                 if (g.fdstage != kFdStream) {
                     lds_max = std::max(lds_max, static_cast<size_t>(fd_layout_3d(g, ld, 8).total) +
-                                                    static_cast<size_t>(kNnFloatsPerDof) * g.ndof * sizeof(float));
+                                                    static_cast<size_t>(kNnLdsBytesPerDof) * g.ndof);
                     lds_fd_plain = std::max(lds_fd_plain, static_cast<size_t>(fd_layout_3d(g, ld, 8).total));
                 }
             }
@@ -1258,6 +1258,7 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
     L.bar = take(kBarBytes);
     L.trace = take(sizeof(unsigned long long) * (1 + 6 * 4096));
     L.fg = take(sizeof(double) * (kFgKinds * kFgBlocks + kFgScalars));
+    L.nnw = take(sizeof(uint16_t) * kNnPackedMax);
     L.total = off;
     *out = P;
     return IGA_OK;

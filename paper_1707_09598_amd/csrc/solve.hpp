@@ -1080,43 +1080,81 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
     __syncthreads();
 }
-// One 3x3x3 convolution layer on LDS tensors (zero padding): out[co][i] =
-// b[co] + sum_ci sum_t w[co][ci][t] in[ci](i + t - 1), optional ReLU; weights
-// from global memory (the same for every workgroup).
-__device__ __forceinline__ void cnn_layer(const float* __restrict__ w, const float* __restrict__ b, const float* in,
-                                          int cin, float* out, int cout, int n1, int n2, int n3, bool relu) {
+// One 3x3x3 convolution layer (zero padding) as an implicit GEMM on the
+// matrix cores in BF16 with FP32 accumulation:
+//   out[i][co] = b[co] + sum over taps t and input channels ci of
+//                w[co][ci][t] in[i + off(t)][ci],
+// M = points (direction 1 fastest), N = output channels, K = 27 x cip with
+// the taps slowest (k = t cip + ci), so that the 8 K values a lane holds are
+// 8 consecutive channels of one neighbour: one 16-byte load of the
+// point-major BF16 activations in LDS, and one of the packed BF16 weights
+// Wp[co][t][ci] in memory (co padded to 16, ci to cip, zero-filled).
+// 16x16x32 BF16 MFMA: lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16]
+// and D[4(l/16)+r][l%16] (checked on the device).  Each wavefront takes
+// 16-point x 16-channel tiles.  The epilogue adds the bias (FP32), applies
+// the ReLU and rounds to BF16 (out[i][c] for c < coutp, pad channels 0), or
+// writes FP32 values to yout (the output layer, one channel).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void cnn_layer_mfma(const uint16_t* __restrict__ Wp, const float* __restrict__ bias,
+                                               const uint16_t* in, int cip, uint16_t* out, int coutp, int cout,
+                                               float* yout, int n1, int n2, int n3, bool relu) {
     const int n = n1 * n2 * n3;
-    const FDiv dn(n), d1(n1), d12(n1 * n2);
-    for (int o = threadIdx.x; o < cout * n; o += kBlock) {
-        int i;
-        const int co = dn.div(o, &i);
-        int r, i1;
-        const int i3 = d12.div(i, &r);
-        const int i2 = d1.div(r, &i1);
-        float s = b[co];
-        for (int ci = 0; ci < cin; ++ci) {
-            const float* wc = w + (co * cin + ci) * 27;
-            const float* xc = in + ci * n;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mt = (n + 15) >> 4, nt = (cout + 15) >> 4;
+    const int K = 27 * cip, nkb = (K + 31) >> 5;
+    const FDiv d1(n1), d12(n1 * n2), dcip(cip);
+    for (int u = wave; u < mt * nt; u += kWaves) {  // uniform per wavefront
+        const int ti = u / nt, tj = u - ti * nt;
+        const int i = 16 * ti + (lane & 15), co = 16 * tj + (lane & 15);
+        const bool iv = i < n;
+        int i1 = 0, i2 = 0, i3 = 0;
+        if (iv) {
+            int rr;
+            i3 = d12.div(i, &rr);
+            i2 = d1.div(rr, &i1);
+        }
+        v4f_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kb = 0; kb < nkb; ++kb) {
+            const int k0 = 32 * kb + 8 * (lane >> 4);
+            bf16x8_t av, bv;
+            for (int j = 0; j < 8; ++j) {
+                av[j] = static_cast<__bf16>(0.0f);
+                bv[j] = static_cast<__bf16>(0.0f);
+            }
+            if (k0 < K) {
+                int ci;
+                const int t = dcip.div(k0, &ci);
+                const int t3 = t / 9, t2 = (t / 3) % 3, t1 = t % 3;
+                const int j1 = i1 + t1 - 1, j2 = i2 + t2 - 1, j3 = i3 + t3 - 1;
+                if (iv && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2 && j3 >= 0 && j3 < n3)
+                    av = *reinterpret_cast<const bf16x8_t*>(in + static_cast<int64_t>((j3 * n2 + j2) * n1 + j1) * cip + ci);
+                bv = *reinterpret_cast<const bf16x8_t*>(Wp + static_cast<int64_t>(co * 27 + t) * cip + ci);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+        const int c = 16 * tj + (lane & 15);
 #pragma unroll
-            for (int t3 = 0; t3 < 3; ++t3) {
-                const int j3 = i3 + t3 - 1;
-                if (j3 < 0 || j3 >= n3) continue;
-#pragma unroll
-                for (int t2 = 0; t2 < 3; ++t2) {
-                    const int j2 = i2 + t2 - 1;
-                    if (j2 < 0 || j2 >= n2) continue;
-#pragma unroll
-                    for (int t1 = 0; t1 < 3; ++t1) {
-                        const int j1 = i1 + t1 - 1;
-                        if (j1 < 0 || j1 >= n1) continue;
-                        s += wc[(t3 * 3 + t2) * 3 + t1] * xc[(j3 * n2 + j2) * n1 + j1];
-                    }
-                }
+        for (int r = 0; r < 4; ++r) {
+            const int pi = 16 * ti + 4 * (lane >> 4) + r;
+            if (pi >= n) continue;
+            float v = c < cout ? acc[r] + bias[c] : 0.0f;
+            if (relu && v < 0.0f) v = 0.0f;
+            if (yout) {
+                if (c == 0) yout[pi] = v;
+            } else if (c < coutp) {
+                reinterpret_cast<__bf16*>(out)[static_cast<int64_t>(pi) * coutp + c] = static_cast<__bf16>(v);
             }
         }
-        out[o] = relu && s < 0.0f ? 0.0f : s;
     }
     __syncthreads();
+}
+
+// Packed BF16 weights of the network (cnn_layer_mfma): per layer
+// [16 ceil(cout / 16)][27][cip] with cip the input channels rounded up to 8
+// (3 -> 8), zero-filled; element counts per layer.
+__host__ __device__ inline int nn_pad8(int c) { return (c + 7) & ~7; }
+__host__ __device__ inline int64_t nn_packed_layer(int cin, int cout) {
+    return static_cast<int64_t>(16 * ((cout + 15) / 16)) * 27 * nn_pad8(cin);
 }
 
 // backward: z = (U1 (x) U2 (x) U3) Rt; part = rdot . z.  With io.learned the
@@ -1145,13 +1183,16 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     double scale = 0.0;  // s (additive head), -1 (log-scale head), 0: no learned correction
     float* Y = nullptr;
     if (LEARN && io.learned) {
-        // features in LDS after the factor region: X0 [3][n], H1, H2, Y [n]
+        // BF16 activations in LDS after the factor region, point-major:
+        // X0 [n][8] (3 feature channels, 5 zero), H1 [n][h1p], H2 [n][h2p];
+        // then the FP32 output Y [n]
         const int ld[3] = {M.t[0].ldu, M.t[1].ldu, M.t[2].ldu};
-        float* X0 = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + fd_layout_3d(g, ld, sizeof(TU)).total);
+        uint16_t* X0 = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + fd_layout_3d(g, ld, sizeof(TU)).total);
         const int h1 = P.nn_ch[1], h2 = P.nn_ch[2];
-        float* H1 = X0 + 3 * n;
-        float* H2 = H1 + kNnHidden * n;
-        Y = H2 + kNnHidden * n;
+        const int h1p = nn_pad8(h1), h2p = nn_pad8(h2);
+        uint16_t* H1 = X0 + 8 * n;
+        uint16_t* H2 = H1 + static_cast<int64_t>(h1p) * n;
+        Y = reinterpret_cast<float*>(H2 + static_cast<int64_t>(h2p) * n);
         double r2 = 0.0, z2 = 0.0, sa = 0.0;
         for (int i = threadIdx.x; i < n; i += kBlock) {
             r2 += L.Own[i] * L.Own[i];
@@ -1164,21 +1205,24 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
         const double sr = r2 > 0.0 ? sqrt(r2) : 1.0;
         const double s = z2 > 0.0 ? sqrt(z2) : 1.0;
         const double mean = sa / n;
+        __bf16* xb = reinterpret_cast<__bf16*>(X0);
         for (int i = threadIdx.x; i < n; i += kBlock) {
-            X0[i] = static_cast<float>(L.Own[i] / sr);
-            X0[n + i] = static_cast<float>(L.R[i] / s);
-            X0[2 * n + i] = static_cast<float>(P.loga[off + i] - mean);
+            xb[8 * i] = static_cast<__bf16>(static_cast<float>(L.Own[i] / sr));
+            xb[8 * i + 1] = static_cast<__bf16>(static_cast<float>(L.R[i] / s));
+            xb[8 * i + 2] = static_cast<__bf16>(static_cast<float>(P.loga[off + i] - mean));
+            for (int c = 3; c < 8; ++c) xb[8 * i + c] = static_cast<__bf16>(0.0f);
         }
         __syncthreads();
-        const float* w1 = P.nn;
-        const float* b1 = w1 + h1 * 3 * 27;
-        const float* w2 = b1 + h1;
-        const float* b2 = w2 + h2 * h1 * 27;
-        const float* w3 = b2 + h2;
-        const float* b3 = w3 + h2 * 27;
-        cnn_layer(w1, b1, X0, 3, H1, h1, n1, n2, n3, true);
-        cnn_layer(w2, b2, H1, h1, H2, h2, n1, n2, n3, true);
-        cnn_layer(w3, b3, H2, h2, Y, 1, n1, n2, n3, false);
+        // biases from the FP32 parameters, weights packed in BF16
+        const float* b1 = P.nn + h1 * 3 * 27;
+        const float* b2 = b1 + h1 + h2 * h1 * 27;
+        const float* b3 = b2 + h2 + h2 * 27;
+        const uint16_t* W1 = P.nnw;
+        const uint16_t* W2 = W1 + nn_packed_layer(3, h1);
+        const uint16_t* W3 = W2 + nn_packed_layer(h1, h2);
+        cnn_layer_mfma(W1, b1, X0, 8, H1, h1p, h1, nullptr, n1, n2, n3, true);
+        cnn_layer_mfma(W2, b2, H1, h1p, H2, h2p, h2, nullptr, n1, n2, n3, true);
+        cnn_layer_mfma(W3, b3, H2, h2p, nullptr, 0, 1, Y, n1, n2, n3, false);
         // acceptance: the corrected z must be a descent direction (r . z > 0)
         const bool mult = P.nn_head == 1;
         double rz = 0.0;

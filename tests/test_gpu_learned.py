@@ -181,14 +181,17 @@ def _oracle_loga(Po, lv):
 
 def test_learned_fcg_iterates_match_oracle(S):
     """x_k of the in-kernel flexible CG equals the oracle's flexible CG with
-    the oracle network (plain preconditioner on the initial residual), to the
-    FP32 inference error."""
+    the oracle network (plain preconditioner on the initial residual).  The
+    solve infers in BF16 (features, weights and activations rounded to BF16,
+    FP32 accumulation on the matrix cores); the oracle rounds the same
+    quantities to BF16 and sums exactly, so the two differ by the FP32
+    accumulation and the rare BF16 rounding it flips (bar 1e-3)."""
     wl = _cube(3)
     log("case learned fcg iterates cfg5 w=3")
     P = S.Plan(wl)
     P.bind()
     P.assemble()
-    ch = (3, 16, 16, 1)
+    ch = (3, 32, 48, 1)
     flat = _params(ch, seed=21, last_scale=0.02)
     net = S.Network(ch, flat)
     P.set_network(net)
@@ -213,7 +216,7 @@ def test_learned_fcg_iterates_match_oracle(S):
 
         def prec(res):
             zfd = np.linalg.solve(Pk, res)
-            return OL.precondition(onet, res.reshape(shp), zfd.reshape(shp), la.reshape(shp)).reshape(-1)
+            return OL.precondition(onet, res.reshape(shp), zfd.reshape(shp), la.reshape(shp), bf16=True).reshape(-1)
 
         for k in (1, 2, 4):
             xo, _, _ = OL.fcg(Ag, bg, prec, 1e-30, k, prec0=lambda res: np.linalg.solve(Pk, res))
@@ -222,7 +225,7 @@ def test_learned_fcg_iterates_match_oracle(S):
             xg = P.coeffs(c).cpu().numpy()
             e = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
             log(f"  comp {c} {lv.tolist()} k={k} rel {e:.2e}")
-            assert e < 1e-4, (c, k, e)
+            assert e < 1e-3, (c, k, e)
         checked += 1
         if checked == 4:
             break
@@ -255,7 +258,7 @@ def test_learned_solve_parity_and_fallback(S):
     P = S.Plan(wl)
     P.bind()
     P.assemble()
-    ch = (3, 16, 16, 1)
+    ch = (3, 32, 48, 1)
     net = S.Network(ch, _params(ch, seed=4, last_scale=0.02))
     P.set_network(net)
     rep_plain = _solve_vs_oracle(P, wl, False, 1e-10)
@@ -307,8 +310,9 @@ def test_training_lowers_loss_and_report_gain(S):
         learn.collect_pairs(P, pairs=pairs)
         P0 = P0 or P
     shapes = {c: learn.grid_shape(P0, c) for c in range(P0.ncomp)}
-    ch = (3, 16, 16, 1)
+    ch = (3, 32, 48, 1)
     net = S.Network(ch, learn.init_params(ch, seed=0))
+    assert net.count == 45441
     before = learn.evaluate(net, pairs, shapes)
     learn.train(net, pairs, shapes, steps=600, lr=2e-3, batch=16, seed=1)
     after = learn.evaluate(net, pairs, shapes)

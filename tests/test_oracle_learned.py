@@ -189,3 +189,40 @@ def test_rejected_correction_falls_back_to_fd():
     zfd = np.abs(rng.standard_normal((2, 3, 4))) + 0.1
     r = zfd.copy()
     assert np.array_equal(L.precondition(net, r, zfd, np.zeros_like(r), 0), zfd)
+
+
+def test_to_bf16_rounding():
+    """Rounding to bfloat16: torch's own conversion (round to nearest even)
+    on random values, exact values kept, halfway cases to the even
+    neighbour, and the relative error within half a unit of the last of
+    its 8 significand bits (2^-8)."""
+    import torch
+    rng = _rng(21)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-8, 8, 10000), [1.0, -2.5, 0.0]])
+    want = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = L.to_bf16(x)
+    assert np.array_equal(got, want)
+    assert L.to_bf16(1.0) == 1.0 and L.to_bf16(-2.5) == -2.5
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: to the even significand (1)
+    assert L.to_bf16(1.0 + 2.0 ** -8) == 1.0
+    assert L.to_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    nz = x != 0
+    assert np.max(np.abs(got[nz] - x[nz]) / np.abs(x[nz])) <= 2.0 ** -8 * (1 + 1e-6)
+
+
+def test_bf16_inference_close_to_exact():
+    """The network in BF16 inference precision stays within the BF16 error
+    of the exact forward pass (relative 2e-2 on the output of a random
+    network), and equals it for weights and inputs that BF16 holds exactly
+    and activations that stay exact (integer data, small sums)."""
+    rng = _rng(22)
+    net = L.Net((3, 8, 8, 1), seed=5)
+    x = rng.standard_normal((3, 4, 5, 6))
+    y = net.forward(x)[0]
+    yb = net.infer_bf16(x)
+    assert np.linalg.norm(yb - y) <= 2e-2 * np.linalg.norm(y)
+    net2 = L.Net((3, 2, 2, 1), seed=0)
+    net2.layers = [(rng.integers(-2, 3, w.shape).astype(float), rng.integers(-2, 3, b.shape).astype(float))
+                   for w, b in net2.layers]
+    xi = rng.integers(-2, 3, (3, 3, 3, 3)).astype(float)
+    assert np.array_equal(net2.infer_bf16(xi), net2.forward(xi)[0])
