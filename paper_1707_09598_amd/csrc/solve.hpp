@@ -513,14 +513,18 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
 // C[m][n] = sum_k A(m, k) B(k, n) on the matrix cores, operands addressed by
 // strides (A(m, k) = A[m sAm + k sAk], ...), nb independent products at batch
 // strides.  Each wavefront takes 16 x 16 output tiles in turn and walks K in
-// steps of 4 with the 16x16x4 MFMA (FP64 for TC = double, FP32 for TC = float;
-// BF16 operands are widened to FP32), two accumulator chains (even and odd
-// steps) in flight.  Lane l supplies A(16 t_m + l % 16, k + l / 16) and
+// steps of 4 with the 16x16x4 MFMA (FP64 for TC = double, FP32 for TC =
+// float), two accumulator chains (even and odd steps) in flight; with BF16
+// factors (an operand of type uint16_t) in steps of 32 with the 16x16x32 BF16
+// MFMA, the other operand rounded to BF16 and the products accumulated in
+// FP32 (lane l supplies A(16 t_m + l % 16, k + 8 (l / 16) + j) and
+// B(k + 8 (l / 16) + j, 16 t_n + l % 16), j < 8).  Lane l supplies A(16 t_m + l % 16, k + l / 16) and
 // B(k + l / 16, 16 t_n + l % 16); out-of-range operands are zero.  The
 // accumulation order is fixed, so results are reproducible.  Ends with a
 // workgroup barrier.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 template <typename TC> struct Mfma;
 template <> struct Mfma<double> {
     using V = v4d_t;
@@ -553,10 +557,11 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, tmn = tm * tn, units = tmn * nb;
     // fewer tiles than wavefronts: K is cut into ks slices whose partial tiles
     // are summed in slice order through red (ks * M * N <= kBigRed doubles)
+    constexpr bool kBf = std::is_same<TA, uint16_t>::value || std::is_same<TB, uint16_t>::value;
     int ks = 1;
     if (red && nb == 1)
         while (2 * ks * units <= kWaves && 2 * ks * M * N <= kBigRed && K >= 16 * ks) ks *= 2;
-    const int kc = ((K + ks - 1) / ks + 7) & ~7;
+    const int kc = kBf ? (((K + ks - 1) / ks + 31) & ~31) : (((K + ks - 1) / ks + 7) & ~7);
     for (int w = wave; w < units * ks; w += kWaves) {  // uniform per wavefront
         const int u = w / ks, sl = w - u * ks;
         const int bt = u / tmn, t = u - bt * tmn;
@@ -569,6 +574,20 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
         const int kb0 = sl * kc, kb1 = min(K, kb0 + kc);
         V acc0 = {TC(0), TC(0), TC(0), TC(0)};
         V acc1 = acc0;
+        if constexpr (kBf) {
+            static_assert(std::is_same<TC, float>::value, "BF16 products accumulate in FP32");
+            for (int k0 = kb0; k0 < kb1; k0 += 32) {
+                bf16x8_t av, bv;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int k = k0 + 8 * lk + jj;
+                    const bool kin = k < kb1;
+                    av[jj] = static_cast<__bf16>(iv && kin ? mm_ld<float>(Ab, i * sAm + k * sAk) : 0.0f);
+                    bv[jj] = static_cast<__bf16>(jv && kin ? mm_ld<float>(Bb, k * sBk + j * sBn) : 0.0f);
+                }
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc0, 0, 0, 0);
+            }
+        } else
         for (int k0 = kb0; k0 < kb1; k0 += 8) {
             const int ka = k0 + lk, kb = k0 + 4 + lk;
             const TC a0 = iv && ka < kb1 ? mm_ld<TC>(Ab, i * sAm + ka * sAk) : TC(0);
@@ -1094,7 +1113,6 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
 // 16-point x 16-channel tiles.  The epilogue adds the bias (FP32), applies
 // the ReLU and rounds to BF16 (out[i][c] for c < coutp, pad channels 0), or
 // writes FP32 values to yout (the output layer, one channel).
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void cnn_layer_mfma(const uint16_t* __restrict__ Wp, const float* __restrict__ bias,
                                                const uint16_t* in, int cip, uint16_t* out, int coutp, int cout,
                                                float* yout, int n1, int n2, int n3, bool relu) {
