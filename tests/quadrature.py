@@ -86,3 +86,20 @@ def graded_gauss(level: int, kind: str, gamma: float, nq: int):
     W2, W1 = np.meshgrid(w1, w1, indexing="ij")
     xi = np.stack([X1.ravel(), X2.ravel()], axis=1)
     return xi, (W1 * W2).ravel()
+
+
+def golden_rates(name: str):
+    """Rows of a printed rate table (tests/golden/<name>.txt): {(continuity,
+    degree, method): {"d2_H1": .., "d2_L2": .., "d3_H1": .., "d3_L2": ..,
+    "prov_H1": .., "prov_L2": ..}}."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".txt")
+    cols = ["d2_H1", "d2_L2", "d3_H1", "d3_L2", "prov_H1", "prov_L2"]
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            t = line.split()
+            out[(t[0], int(t[1]), t[2])] = dict(zip(cols, map(float, t[3:])))
+    return out

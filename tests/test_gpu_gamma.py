@@ -27,7 +27,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from quadrature import annulus_detjac, graded_gauss, low_regular_annulus
+from quadrature import annulus_detjac, golden_rates, graded_gauss, low_regular_annulus
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,19 @@ def test_rate_against_gamma(S, p, cont):
         log(f"  p={p} {cont} gamma={gamma}: SG-IGA L2 {table[(gamma, False)][0]:.2f} "
             f"H1 {table[(gamma, False)][1]:.2f} | IGA L2 {table[(gamma, True)][0]:.2f} "
             f"H1 {table[(gamma, True)][1]:.2f}")
+    # uniform knots (gamma = 1): the rows of Table 3 (tests/golden/table3_rates.txt)
+    # for the discretisations it lists, within 0.2 of the provable rates and
+    # 0.4 of the printed ones
+    cname = {(2, "C0"): "C0", (2, "Cmax"): "C1", (3, "C0"): "C0", (3, "Cmax"): "C2"}.get((p, cont))
+    if cname is not None:
+        gold = golden_rates("table3_rates")
+        for full, method in ((False, "SG-IGA"), (True, "IGA")):
+            g = gold[(cname, p, method)]
+            l2, h1 = table[(1.0, full)]
+            log(f"  Table 3 {cname} p={p} {method}: L2 {l2:.2f} (printed {g['d2_L2']}, provable "
+                f"{g['prov_L2']:g}), H1 {h1:.2f} (printed {g['d2_H1']}, provable {g['prov_H1']:g})")
+            assert abs(l2 - g["prov_L2"]) < 0.2 and abs(h1 - g["prov_H1"]) < 0.2
+            assert abs(l2 - g["d2_L2"]) < 0.4 and abs(h1 - g["d2_H1"]) < 0.4
     for full in (False, True):
         for k, name in ((0, "L2"), (1, "H1")):
             rates = [table[(g, full)][k] for g in GAMMAS]
