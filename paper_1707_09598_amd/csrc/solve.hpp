@@ -373,7 +373,126 @@ __device__ __forceinline__ void elem_layer_3d(const double* X, int nh1, int nh2,
     }
 }
 
-template <int PP>
+// The FP64 element layer of the residual sweeps with fewer live registers:
+// instead of accumulating the (p+1)^2 x 2 partial sums Zb, Zd over the rows
+// j2 and expanding them by the direction-3 factors at the end, each row's
+// contributions are expanded, summed over the element's NG layer lanes by the
+// same butterfly and added to the element's outputs Ye in LDS at once (lane
+// j3 == 0 writes; the rows in order, so the sums are reproducible).  Same
+// arithmetic as elem_layer_3d followed by the expansion, grouped by rows.
+template <int PP, bool RAT>
+__device__ __forceinline__ void elem_layer_3d_rows(const double* X, int nh1, int nh2, int x1, int x2, int x3,
+                                                   const double* B1, const double* D1, const double* B2,
+                                                   const double* D2, const double* B3r, const double* D3r,
+                                                   const double* Gl, int64_t nqp, int Q1, int j3, double* Ye) {
+    constexpr int NQ = PP + 1;
+    constexpr int NG = NQ <= 2 ? 2 : (NQ <= 4 ? 4 : 8);
+    double tb[PP + 1][PP + 1], td[PP + 1][PP + 1], b3[PP + 1], d3[PP + 1];
+#pragma unroll
+    for (int a = 0; a <= PP; ++a) {
+        b3[a] = B3r[a];
+        d3[a] = D3r[a];
+    }
+#pragma unroll
+    for (int a2 = 0; a2 <= PP; ++a2)
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) {
+            double u = 0.0, v = 0.0;
+#pragma unroll
+            for (int a3 = 0; a3 <= PP; ++a3) {
+                const double c = X[((x3 + a3) * nh2 + x2 + a2) * nh1 + x1 + a1];
+                u += b3[a3] * c;
+                v += d3[a3] * c;
+            }
+            tb[a1][a2] = u;
+            td[a1][a2] = v;
+        }
+#pragma unroll 1
+    for (int j2 = 0; j2 < NQ; ++j2) {
+        double b2[PP + 1], d2[PP + 1];
+#pragma unroll
+        for (int a = 0; a <= PP; ++a) {
+            b2[a] = B2[j2 * NQ + a];
+            d2[a] = D2[j2 * NQ + a];
+        }
+        double ub[PP + 1], u2[PP + 1], u3[PP + 1];
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) {
+            double s0 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 <= PP; ++a2) {
+                s0 += b2[a2] * tb[a1][a2];
+                s2 += d2[a2] * tb[a1][a2];
+                s3 += b2[a2] * td[a1][a2];
+            }
+            ub[a1] = s0;
+            u2[a1] = s2;
+            u3[a1] = s3;
+        }
+        double w0[PP + 1], w2[PP + 1], w3[PP + 1];
+#pragma unroll
+        for (int a1 = 0; a1 <= PP; ++a1) w0[a1] = w2[a1] = w3[a1] = 0.0;
+        const double* Gr = Gl + static_cast<int64_t>(j2) * Q1;
+#pragma unroll 1
+        for (int j1 = 0; j1 < NQ; ++j1) {
+            double b1[PP + 1], d1[PP + 1];
+#pragma unroll
+            for (int a = 0; a <= PP; ++a) {
+                b1[a] = B1[j1 * NQ + a];
+                d1[a] = D1[j1 * NQ + a];
+            }
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 <= PP; ++a1) {
+                if (RAT) v0 += b1[a1] * ub[a1];
+                v1 += d1[a1] * ub[a1];
+                v2 += b1[a1] * u2[a1];
+                v3 += b1[a1] * u3[a1];
+            }
+            double F0 = 0.0, F1, F2, F3;
+            if (RAT) {
+                const double g00 = Gr[j1], g01 = Gr[nqp + j1], g02 = Gr[2 * nqp + j1], g03 = Gr[3 * nqp + j1];
+                const double g11 = Gr[4 * nqp + j1], g12 = Gr[5 * nqp + j1], g13 = Gr[6 * nqp + j1];
+                const double g22 = Gr[7 * nqp + j1], g23 = Gr[8 * nqp + j1], g33 = Gr[9 * nqp + j1];
+                F0 = g00 * v0 + g01 * v1 + g02 * v2 + g03 * v3;
+                F1 = g01 * v0 + g11 * v1 + g12 * v2 + g13 * v3;
+                F2 = g02 * v0 + g12 * v1 + g22 * v2 + g23 * v3;
+                F3 = g03 * v0 + g13 * v1 + g23 * v2 + g33 * v3;
+            } else {
+                const double g11 = Gr[j1], g12 = Gr[nqp + j1], g13 = Gr[2 * nqp + j1];
+                const double g22 = Gr[3 * nqp + j1], g23 = Gr[4 * nqp + j1], g33 = Gr[5 * nqp + j1];
+                F1 = g11 * v1 + g12 * v2 + g13 * v3;
+                F2 = g12 * v1 + g22 * v2 + g23 * v3;
+                F3 = g13 * v1 + g23 * v2 + g33 * v3;
+            }
+#pragma unroll
+            for (int a1 = 0; a1 <= PP; ++a1) {
+                w0[a1] += (RAT ? b1[a1] * F0 : 0.0) + d1[a1] * F1;
+                w2[a1] += b1[a1] * F2;
+                w3[a1] += b1[a1] * F3;
+            }
+        }
+        // this row's share of the outputs, summed over the layer lanes
+#pragma unroll
+        for (int a3 = 0; a3 < NQ; ++a3)
+#pragma unroll
+            for (int a2 = 0; a2 < NQ; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < NQ; ++a1) {
+                    double v = b3[a3] * (b2[a2] * w0[a1] + d2[a2] * w2[a1]) + d3[a3] * (b2[a2] * w3[a1]);
+                    if (j3 >= NQ) v = 0.0;
+#pragma unroll
+                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
+                    double* y = Ye + a1 + NQ * (a2 + NQ * a3);
+                    if (j3 == 0) *y = j2 == 0 ? v : *y + v;
+                }
+    }
+}
+
+// ROWS64: the FP64 element layers by rows (elem_layer_3d_rows), for builds
+// whose register budget the accumulating form exceeds (two workgroups per
+// CU); the FP64-only solve keeps the accumulating form (fewer shuffles).
+template <int PP, bool ROWS64 = false>
 __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const Tab1D& T1, const Tab1D& T2,
                                            const Tab1D& T3, int tile, const OpIO& io, double* lds) {
     constexpr int NQ = PP + 1;
@@ -462,6 +581,10 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
             if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
             else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
             finish(Zb, Zd, b3v, d3v);
+        } else if constexpr (ROWS64) {
+            const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
+            if (rat) elem_layer_3d_rows<PP, true>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
+            else elem_layer_3d_rows<PP, false>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
         } else {
             double Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
             const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
@@ -1818,8 +1941,11 @@ __global__ void __launch_bounds__(NT) k_solve(Params P, SolveArgs A) {
 // large batch keep every CU busy.  The refinement / CG state machine, the
 // operator tiles and the FD transforms are those of k_solve (decide,
 // op_tile_*, fd*_run), so a grid follows the same iteration as there.
+// LEARN: the build runs the learned correction (the 512-thread,
+// one-workgroup-per-CU build); ROWS64: the FP64 element layers of the
+// residual sweeps by rows (op_tile_3d), in the two-workgroup build.
 // ===========================================================================
-template <int PP, int FDP, int DIM, bool LEARN>
+template <int PP, int FDP, int DIM, bool LEARN, bool ROWS64>
 __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs& A, const TaskMeta& M,
                                                double* slots, double* lds) {
     using TU = typename FdTypes<FDP>::TU;
@@ -1886,7 +2012,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             io.part = sl;
             io.lowp = FDP != 0 && !st.op64;
             const double pq = tiles([&](int t) {
-                if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
+                if constexpr (DIM == 3) op_tile_3d<PP, ROWS64>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
                 else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
             }, g.ntile);
             if (!(pq > 0.0) || !isfinite(D.rho / pq)) {
@@ -1970,7 +2096,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             io.part = sl;
             io.lowp = 0;
             const double rn2 = tiles([&](int t) {
-                if constexpr (DIM == 3) op_tile_3d<PP>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
+                if constexpr (DIM == 3) op_tile_3d<PP, ROWS64>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
                 else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
             }, g.ntile);
             for (int o = threadIdx.x; o < g.ndof; o += kBlock) {
@@ -2052,8 +2178,10 @@ __global__ void __launch_bounds__(NT, WAVES) k_solve_grid(Params P, SolveArgs A)
         const Task tk = P.fdtask[A.fd_b + t];
         if (tk.local != 0) continue;  // the first block of a grid stands for the grid
         meta_fill(P, tk, meta);
-        // the two-workgroup build serves solves without the network only
-        solve_one_grid<PP, FDP, DIM, WAVES == 1>(P, A, *meta, slots, lds);
+        // learned solves run the 512-thread one-workgroup build only (the host
+        // picks it for them); the other builds compile the transform without
+        // the network
+        solve_one_grid<PP, FDP, DIM, WAVES == 1 && NT == 512, WAVES == 2>(P, A, *meta, slots, lds);
     }
 }
 
