@@ -88,9 +88,87 @@ __device__ __forceinline__ float load_f<float>(const float* p, int64_t i) { retu
 template <>
 __device__ __forceinline__ float load_f<uint16_t>(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
 
-// Deterministic workgroup sum (fixed shuffle tree, then fixed LDS order).
+// Value of lane (lane ^ M), M = 1, 2, 4 or 8, by DPP moves: a VALU operation
+// inside a row of 16 lanes, without the LDS round trip of ds_bpermute.
+//   M = 1, 2: quad permutations (1,0,3,2) and (2,3,0,1);
+//   M = 4: lane i reads i + 4 (row shift left) when bit 2 of i is clear and
+//          i - 4 (row shift right) when it is set;
+//   M = 8: row rotation by 8, i -> (i + 8) mod 16 = i ^ 8.
+// Every lane of the row must be active.
+template <int M>
+__device__ __forceinline__ int lane_xor_i(int v) {
+    static_assert(M == 1 || M == 2 || M == 4 || M == 8, "DPP lane exchange inside a row");
+    if constexpr (M == 1) {
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (M == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (M == 4) {
+        const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false);
+        const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+        return (threadIdx.x & 4) ? dn : up;
+    } else {
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    }
+}
+template <int M>
+__device__ __forceinline__ float lane_xor(float v) {
+    return __int_as_float(lane_xor_i<M>(__float_as_int(v)));
+}
+template <int M>
+__device__ __forceinline__ double lane_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor_i<M>(static_cast<int>(b));
+    const int hi = lane_xor_i<M>(static_cast<int>(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Reduce-scatter over an aligned group of NG = 2, 4 or 8 lanes: c[k] is this
+// lane's share of output k; the result is the group's sum of output
+// j = lane % NG.  Pairs are summed first (xor 1), then pairs of pairs (xor 2,
+// xor 4): ((c_0 + c_1) + (c_2 + c_3)) + ... for every output, in every lane,
+// the order of a butterfly of xor steps 1, 2, 4.
+template <int NG, typename T>
+__device__ __forceinline__ T group_reduce_scatter(const T (&c)[NG], int j) {
+    static_assert(NG == 2 || NG == 4 || NG == 8, "group of 2, 4 or 8 lanes");
+    const bool b0 = j & 1;
+    T h[NG / 2];
+#pragma unroll
+    for (int k = 0; k < NG / 2; ++k) {
+        const T mine = b0 ? c[2 * k + 1] : c[2 * k];
+        const T send = b0 ? c[2 * k] : c[2 * k + 1];
+        h[k] = mine + lane_xor<1>(send);  // output 2k + (j & 1)
+    }
+    if constexpr (NG == 2) {
+        return h[0];
+    } else {
+        const bool b1 = j & 2;
+        T q[NG / 4];
+#pragma unroll
+        for (int k = 0; k < NG / 4; ++k) {
+            const T mine = b1 ? h[2 * k + 1] : h[2 * k];
+            const T send = b1 ? h[2 * k] : h[2 * k + 1];
+            q[k] = mine + lane_xor<2>(send);  // output 4k + (j & 3)
+        }
+        if constexpr (NG == 4) {
+            return q[0];
+        } else {
+            const bool b2 = j & 4;
+            const T mine = b2 ? q[1] : q[0];
+            const T send = b2 ? q[0] : q[1];
+            return mine + lane_xor<4>(send);
+        }
+    }
+}
+
+// Deterministic workgroup sum (fixed butterfly, then fixed LDS order): xor 32
+// and 16 by ds_bpermute, xor 8, 4, 2, 1 by DPP.
 __device__ __forceinline__ double wg_sum(double v, double* red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += __shfl_xor(v, 32, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += lane_xor<8>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<1>(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wave] = v;

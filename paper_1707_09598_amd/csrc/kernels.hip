@@ -2041,8 +2041,13 @@ iga_status iga_sg_solve(iga_sg_plan P, const iga_sg_solve_opts* o, iga_sg_report
             // modes (random-field batch of 256 samples, FP32 inner solve, tile
             // 256: 77.7 against 107 ms; its FP64 operator spills, so plain
             // FP64 keeps the one-workgroup build)
-            const int waves =
-                prec != IGA_PREC_FP64 && 2 * (ldsg + 1024) <= static_cast<size_t>(kLdsLimit) ? 2 : 1;
+            int waves = 1;
+            if (prec != IGA_PREC_FP64) {
+                int occ2 = 0;
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ2, solve_kernel(P->p, prec, P->dim, nar, 2), solve_threads(P->dim, nar), ldsg));
+                if (occ2 >= 2) waves = 2;
+            }
             const void* fk = solve_kernel(P->p, prec, P->dim, nar, waves);
             int occg = 0;
             HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occg, fk, solve_threads(P->dim, nar), ldsg));

@@ -167,8 +167,9 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
     }
     __syncthreads();
     // items: (element, row j2 of Gauss points), NG lanes per element (NG the
-    // power of two >= p+1); the rows of an element are summed by a fixed
-    // butterfly over its lanes
+    // power of two >= p+1); the rows of an element are summed over its lanes
+    // in a fixed order (group_reduce_scatter), lane j2 keeping the outputs of
+    // a2 = j2
     constexpr int NQ = PP + 1;
     constexpr int NG = NQ <= 2 ? 2 : (NQ <= 4 ? 4 : 8);
     const int nqp1 = NQ * NQ;
@@ -188,42 +189,37 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
         const double* B2r = P.dpool + T2.oB + static_cast<int64_t>(e2) * nqp1 + jr * NQ;
         const double* D2r = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1 + jr * NQ;
         const int64_t qrow = static_cast<int64_t>(e2 * NQ + jr) * g.Q[0] + static_cast<int64_t>(e1) * NQ;
-        double yv[NQ][NQ];
+        double yv[NQ];
         if (io.lowp) {
             float y[NQ][NQ];
             const float* Gr = P.G32 + g.qp_off * P.ncompG + qrow;
             if (rat) elem_row_2d<PP, true, float>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
             else elem_row_2d<PP, false, float>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
 #pragma unroll
-            for (int a1 = 0; a1 < NQ; ++a1)
+            for (int a1 = 0; a1 < NQ; ++a1) {
+                float c[NG];
 #pragma unroll
-                for (int a2 = 0; a2 < NQ; ++a2) {
-                    float v = j2 < NQ ? y[a1][a2] : 0.0f;
-#pragma unroll
-                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                    yv[a1][a2] = static_cast<double>(v);
-                }
+                for (int a2 = 0; a2 < NG; ++a2) c[a2] = a2 < NQ && j2 < NQ ? y[a1][a2] : 0.0f;
+                yv[a1] = static_cast<double>(group_reduce_scatter<NG>(c, j2));
+            }
         } else {
             double y[NQ][NQ];
             const double* Gr = P.G64 + g.qp_off * P.ncompG + qrow;
             if (rat) elem_row_2d<PP, true, double>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
             else elem_row_2d<PP, false, double>(X, nh1, x1, x2, B1, D1, B2r, D2r, Gr, nqp, y);
 #pragma unroll
-            for (int a1 = 0; a1 < NQ; ++a1)
+            for (int a1 = 0; a1 < NQ; ++a1) {
+                double c[NG];
 #pragma unroll
-                for (int a2 = 0; a2 < NQ; ++a2) {
-                    double v = j2 < NQ ? y[a1][a2] : 0.0;
-#pragma unroll
-                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                    yv[a1][a2] = v;
-                }
+                for (int a2 = 0; a2 < NG; ++a2) c[a2] = a2 < NQ && j2 < NQ ? y[a1][a2] : 0.0;
+                yv[a1] = group_reduce_scatter<NG>(c, j2);
+            }
         }
-        if (j2 == 0) {
-            double* Ye = Y + el * nqp1;
+        // lane j2 holds the outputs of a2 = j2 summed over the element's rows
+        if (j2 < NQ) {
+            double* Ye = Y + el * nqp1 + NQ * j2;
 #pragma unroll
-            for (int a2 = 0; a2 < NQ; ++a2)
-#pragma unroll
-                for (int a1 = 0; a1 < NQ; ++a1) Ye[a1 + NQ * a2] = yv[a1][a2];
+            for (int a1 = 0; a1 < NQ; ++a1) Ye[a1] = yv[a1];
         }
     }
     __syncthreads();
@@ -264,7 +260,8 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
 // operator application (3D).  Items are (element, layer j3 of Gauss points);
 // one item computes the element's (p+1)^3 output contributions of its layer by
 // sum factorisation through the directions 3, 2, 1 and back; the NG lanes of
-// an element add their layers by a fixed butterfly.
+// an element add their layers in a fixed order (group_reduce_scatter, DPP
+// lane exchanges), lane j3 keeping the outputs of a3 = j3.
 // ---------------------------------------------------------------------------
 template <int PP, bool RAT, typename T>
 __device__ __forceinline__ void elem_layer_3d(const double* X, int nh1, int nh2, int x1, int x2, int x3,
@@ -376,9 +373,10 @@ __device__ __forceinline__ void elem_layer_3d(const double* X, int nh1, int nh2,
 // The FP64 element layer of the residual sweeps with fewer live registers:
 // instead of accumulating the (p+1)^2 x 2 partial sums Zb, Zd over the rows
 // j2 and expanding them by the direction-3 factors at the end, each row's
-// contributions are expanded, summed over the element's NG layer lanes by the
-// same butterfly and added to the element's outputs Ye in LDS at once (lane
-// j3 == 0 writes; the rows in order, so the sums are reproducible).  Same
+// contributions are expanded, summed over the element's NG layer lanes in the
+// same order and added to the element's outputs Ye in LDS at once (lane j3
+// accumulates the outputs of a3 = j3; the rows in order, so the sums are
+// reproducible).  Same
 // arithmetic as elem_layer_3d followed by the expansion, grouped by rows.
 template <int PP, bool RAT>
 __device__ __forceinline__ void elem_layer_3d_rows(const double* X, int nh1, int nh2, int x1, int x2, int x3,
@@ -472,20 +470,24 @@ __device__ __forceinline__ void elem_layer_3d_rows(const double* X, int nh1, int
                 w3[a1] += b1[a1] * F3;
             }
         }
-        // this row's share of the outputs, summed over the layer lanes
+        // this row's share of the outputs, summed over the layer lanes; lane
+        // j3 keeps and accumulates the outputs of a3 = j3
 #pragma unroll
-        for (int a3 = 0; a3 < NQ; ++a3)
+        for (int a2 = 0; a2 < NQ; ++a2)
 #pragma unroll
-            for (int a2 = 0; a2 < NQ; ++a2)
+            for (int a1 = 0; a1 < NQ; ++a1) {
+                double c[NG];
 #pragma unroll
-                for (int a1 = 0; a1 < NQ; ++a1) {
-                    double v = b3[a3] * (b2[a2] * w0[a1] + d2[a2] * w2[a1]) + d3[a3] * (b2[a2] * w3[a1]);
-                    if (j3 >= NQ) v = 0.0;
-#pragma unroll
-                    for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                    double* y = Ye + a1 + NQ * (a2 + NQ * a3);
-                    if (j3 == 0) *y = j2 == 0 ? v : *y + v;
+                for (int a3 = 0; a3 < NG; ++a3)
+                    c[a3] = a3 < NQ && j3 < NQ
+                                ? b3[a3] * (b2[a2] * w0[a1] + d2[a2] * w2[a1]) + d3[a3] * (b2[a2] * w3[a1])
+                                : 0.0;
+                const double v = group_reduce_scatter<NG>(c, j3);
+                if (j3 < NQ) {
+                    double* y = Ye + a1 + NQ * (a2 + NQ * j3);
+                    *y = j2 == 0 ? v : *y + v;
                 }
+            }
     }
 }
 
@@ -561,19 +563,21 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         // Gauss point (e1 NQ + j1, e2 NQ + j2, e3 NQ + j3), direction 1 fastest
         const int64_t ql = (static_cast<int64_t>(e3 * NQ + jr) * g.Q[1] + e2 * NQ) * g.Q[0] + e1 * NQ;
         double* Ye = Y + el * NE;
+        // the layers' shares of output (a1, a2, a3) summed over the NG lanes
+        // of the element; lane j3 keeps and writes the outputs of a3 = j3
         auto finish = [&](auto& Zb, auto& Zd, auto& b3v, auto& d3v) {
+            using TV = typename std::remove_reference<decltype(b3v[0])>::type;
 #pragma unroll
-            for (int a3 = 0; a3 < NQ; ++a3)
+            for (int a2 = 0; a2 < NQ; ++a2)
 #pragma unroll
-                for (int a2 = 0; a2 < NQ; ++a2)
+                for (int a1 = 0; a1 < NQ; ++a1) {
+                    TV c[NG];
 #pragma unroll
-                    for (int a1 = 0; a1 < NQ; ++a1) {
-                        auto v = b3v[a3] * Zb[a1][a2] + d3v[a3] * Zd[a1][a2];
-                        if (j3 >= NQ) v = 0;
-#pragma unroll
-                        for (int sft = 1; sft < NG; sft <<= 1) v += __shfl_xor(v, sft, 64);
-                        if (j3 == 0) Ye[a1 + NQ * (a2 + NQ * a3)] = static_cast<double>(v);
-                    }
+                    for (int a3 = 0; a3 < NG; ++a3)
+                        c[a3] = a3 < NQ && j3 < NQ ? b3v[a3] * Zb[a1][a2] + d3v[a3] * Zd[a1][a2] : TV(0);
+                    const TV v = group_reduce_scatter<NG>(c, j3);
+                    if (j3 < NQ) Ye[a1 + NQ * (a2 + NQ * j3)] = static_cast<double>(v);
+                }
         };
         if (io.lowp) {
             float Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
@@ -581,16 +585,17 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
             if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
             else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
             finish(Zb, Zd, b3v, d3v);
-        } else if constexpr (ROWS64) {
-            const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
-            if (rat) elem_layer_3d_rows<PP, true>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
-            else elem_layer_3d_rows<PP, false>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
         } else {
-            double Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
             const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
-            if (rat) elem_layer_3d<PP, true, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
-            else elem_layer_3d<PP, false, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
-            finish(Zb, Zd, b3v, d3v);
+            if constexpr (ROWS64) {
+                if (rat) elem_layer_3d_rows<PP, true>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
+                else elem_layer_3d_rows<PP, false>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
+            } else {
+                double Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
+                if (rat) elem_layer_3d<PP, true, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+                else elem_layer_3d<PP, false, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+                finish(Zb, Zd, b3v, d3v);
+            }
         }
     }
     __syncthreads();
@@ -675,12 +680,35 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
                                           int sBb = 0, int sCb = 0, double* red = nullptr) {
     using MF = Mfma<TC>;
     using V = typename MF::V;
+    constexpr bool kBf = std::is_same<TA, uint16_t>::value || std::is_same<TB, uint16_t>::value;
+    // Small FP64/FP32 products (K <= 64 and at most 64 multiply-adds per
+    // thread of the workgroup): one output per thread on the vector units, in
+    // the same precision TC, with K in order.  The short directions of the
+    // component grids (2 to about 33 unknowns) would leave the 16 x 16
+    // matrix-core tiles mostly padding and spend the product on operand
+    // staging and the split-K reduction; long contractions (a long direction
+    // of a 2D grid, full grids) stay on the matrix cores.
+    if (!kBf && K <= 64 && static_cast<int64_t>(M) * N * nb * K <= 64 * kBlock) {
+        const int mn = M * N, tot = mn * nb;
+        const FDiv dmn(mn), dn(N);
+        for (int o = threadIdx.x; o < tot; o += kBlock) {
+            int r, n;
+            const int bt = dmn.div(o, &r);
+            const int m = dn.div(r, &n);
+            const TA* Ar = A + bt * sAb + m * sAm;
+            const TB* Bc = B + bt * sBb + n * sBn;
+            TC acc = TC(0);
+            for (int k = 0; k < K; ++k) acc = fma(mm_ld<TC>(Ar, k * sAk), mm_ld<TC>(Bc, k * sBk), acc);
+            C[bt * sCb + m * sCm + n * sCn] = static_cast<double>(acc);
+        }
+        __syncthreads();
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, tmn = tm * tn, units = tmn * nb;
     // fewer tiles than wavefronts: K is cut into ks slices whose partial tiles
     // are summed in slice order through red (ks * M * N <= kBigRed doubles)
-    constexpr bool kBf = std::is_same<TA, uint16_t>::value || std::is_same<TB, uint16_t>::value;
     int ks = 1;
     if (red && nb == 1)
         while (2 * ks * units <= kWaves && 2 * ks * M * N <= kBigRed && K >= 16 * ks) ks *= 2;
