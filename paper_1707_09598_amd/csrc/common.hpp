@@ -264,6 +264,8 @@ constexpr int kFgScalars = 32;
 struct Layout {
     size_t tabs, grids, grids_lp, dpool, ipool, fpool, hpool, ctrl;
     size_t G64, G32, Fq;          // operator coefficients and load density at Gauss points
+                                  // (per grid [coefficient][point]; the points in tensor
+                                  // order in 2D, element-major in 3D)
     size_t b, x, d, r2, z, p2, q, rt;
     size_t st2;                   // GState[2][ngrid]
     size_t part;                  // partial sums

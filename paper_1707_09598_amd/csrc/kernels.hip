@@ -288,11 +288,29 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
          gq += static_cast<int64_t>(gridDim.x) * kBlock) {
         const int gi = grid_of_qp(P, g0, g1, gq);
         const Grid& g = P.grids[gi];
+        // storage index l of the point; lt its index in the tensor order of
+        // the grid's Gauss points (fields sampled at the points).  2D: the
+        // same.  3D: element-major, l = ((element * NQ + j3) * NQ + j2) * NQ + j1
+        // with the elements direction 1 fastest, so that the coefficients of
+        // an element (and of one of its layers) are contiguous for the
+        // operator and the element sums
         const int64_t l = gq - g.qp_off;
+        int64_t lt = l;
         int qk[3];
-        qk[0] = static_cast<int>(l % g.Q[0]);
-        qk[1] = static_cast<int>((l / g.Q[0]) % g.Q[1]);
-        qk[2] = static_cast<int>(l / (static_cast<int64_t>(g.Q[0]) * g.Q[1]));
+        if constexpr (DIM == 3) {
+            const int nq = P.p + 1, nq2 = nq * nq;
+            const int64_t e = l / (nq2 * nq);
+            const int r = static_cast<int>(l - e * nq2 * nq);
+            const int64_t e23 = e / g.E[0];
+            qk[0] = static_cast<int>(e - e23 * g.E[0]) * nq + r % nq;
+            qk[1] = static_cast<int>(e23 % g.E[1]) * nq + (r / nq) % nq;
+            qk[2] = static_cast<int>(e23 / g.E[1]) * nq + r / nq2;
+            lt = (static_cast<int64_t>(qk[2]) * g.Q[1] + qk[1]) * g.Q[0] + qk[0];
+        } else {
+            qk[0] = static_cast<int>(l % g.Q[0]);
+            qk[1] = static_cast<int>((l / g.Q[0]) % g.Q[1]);
+            qk[2] = 0;
+        }
         double x[3] = {0, 0, 0}, DF[3][3], W, dW[3] = {0, 0, 0};
         geom_at<DIM>(P, g, qk, x, DF, &W, dW);
         double wq = 1.0;
@@ -319,10 +337,11 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
             inv[2][2] = (DF[0][0] * DF[1][1] - DF[0][1] * DF[1][0]) / det;
         }
         if (!(det > 0.0)) atomicOr(err, 1);
-        // a field sampled at the Gauss points holds its value at index gq
-        const double av = fa.kind == IGA_FIELD_QP_SAMPLES ? fa.data[gq]
+        // a field sampled at the Gauss points holds its value at the point's
+        // index in the tensor order
+        const double av = fa.kind == IGA_FIELD_QP_SAMPLES ? fa.data[g.qp_off + lt]
                                                           : field_eval_k<KA>(field_of_sample(fa, g.sample), d, x);
-        const double fv = ff.kind == IGA_FIELD_QP_SAMPLES ? ff.data[gq]
+        const double fv = ff.kind == IGA_FIELD_QP_SAMPLES ? ff.data[g.qp_off + lt]
                                                           : field_eval_k<KF>(field_of_sample(ff, g.sample), d, x);
         const double s = av * wq * fabs(det);
         // parametric coefficients Gp = a w |det| DF^-1 DF^-T (symmetric)
@@ -435,7 +454,8 @@ __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
         if (live) {
             gi = grid_of_qp(P, 0, P.ngrid, el * NLOC);
             const Grid& g = P.grids[gi];
-            int64_t r = el - g.qp_off / NLOC;
+            const int64_t rel = el - g.qp_off / NLOC;  // element index in the grid
+            int64_t r = rel;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
                 ek[k] = static_cast<int>(r % g.E[k]);
@@ -450,7 +470,9 @@ __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
                 if (pos < NLOC) {
                     const int dg[3] = {pos % NQ, (pos / NQ) % NQ, DIM > 2 ? pos / (NQ * NQ) : 0};
                     // stage Gauss point pos of the element (off-diagonal coefficients doubled)
-                    const int64_t lq = qbase + dg[0] + static_cast<int64_t>(g.Q[0]) * (dg[1] + static_cast<int64_t>(g.Q[1]) * dg[2]);
+                    // storage index: tensor order (2D), element-major (3D)
+                    const int64_t lq = DIM == 3 ? g.qp_off + rel * NLOC + pos
+                                                : qbase + dg[0] + static_cast<int64_t>(g.Q[0]) * (dg[1] + static_cast<int64_t>(g.Q[1]) * dg[2]);
                     const double* G = P.G64 + g.qp_off * NC + (lq - g.qp_off);
                     int c = 0;
 #pragma unroll

@@ -560,8 +560,9 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         const double* D2 = P.dpool + T2.oD + static_cast<int64_t>(e2) * nqp1;
         const double* B3r = P.dpool + T3.oB + static_cast<int64_t>(e3) * nqp1 + jr * NQ;
         const double* D3r = P.dpool + T3.oD + static_cast<int64_t>(e3) * nqp1 + jr * NQ;
-        // Gauss point (e1 NQ + j1, e2 NQ + j2, e3 NQ + j3), direction 1 fastest
-        const int64_t ql = (static_cast<int64_t>(e3 * NQ + jr) * g.Q[1] + e2 * NQ) * g.Q[0] + e1 * NQ;
+        // coefficients of layer jr of the element (element-major storage: the
+        // layer's NQ x NQ points contiguous, direction 1 fastest)
+        const int64_t ql = ((static_cast<int64_t>(e3) * g.E[1] + e2) * g.E[0] + e1) * NE + jr * NQ * NQ;
         double* Ye = Y + el * NE;
         // the layers' shares of output (a1, a2, a3) summed over the NG lanes
         // of the element; lane j3 keeps and writes the outputs of a3 = j3
@@ -582,18 +583,18 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         if (io.lowp) {
             float Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
             const float* Gl = P.G32 + g.qp_off * P.ncompG + ql;
-            if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
-            else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+            if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
+            else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
             finish(Zb, Zd, b3v, d3v);
         } else {
             const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
             if constexpr (ROWS64) {
-                if (rat) elem_layer_3d_rows<PP, true>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
-                else elem_layer_3d_rows<PP, false>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], j3, Ye);
+                if (rat) elem_layer_3d_rows<PP, true>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, j3, Ye);
+                else elem_layer_3d_rows<PP, false>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, j3, Ye);
             } else {
                 double Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
-                if (rat) elem_layer_3d<PP, true, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
-                else elem_layer_3d<PP, false, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, g.Q[0], Zb, Zd, b3v, d3v);
+                if (rat) elem_layer_3d<PP, true, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
+                else elem_layer_3d<PP, false, double>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
                 finish(Zb, Zd, b3v, d3v);
             }
         }
