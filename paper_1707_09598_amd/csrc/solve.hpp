@@ -815,6 +815,11 @@ struct FdIO {
     const double* rold;   // previous residual: part2 = z . rold (flexible CG)
     double* part2;
     double* part3 = nullptr;  // r . z_FD of the plain preconditioner (learned solves: the stopping test)
+    // 3D, one workgroup per grid: the forward transform leaves its output
+    // (times 1 / lambda) in LDS and the residual in the backward transform's
+    // dot-partner slot, so that the backward transform of the same workgroup
+    // follows without reloading them (rt is then not written)
+    int keep = 0;
 };
 
 
@@ -1218,23 +1223,15 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     const Fd3Lds<TU> L = fd3_lds<TU>(P, M, lds);
     const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2], n = n1 * n2 * n3, n12 = n1 * n2;
     const int64_t off = g.dof_off;
-    if (io.scale) {
-        // the update in S (written out below), the scaled residual s r in R
-        for (int i = threadIdx.x; i < n; i += kBlock) {
-            const double v = io.q ? L.R[i] - io.alpha * L.S[i] : L.R[i];
-            L.S[i] = v;
-            L.R[i] = v * io.scale[off + i];
-        }
-    } else if (io.q) {
-        for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] -= io.alpha * L.S[i];
-    }
-    __syncthreads();
-    const double* Ru = io.scale ? L.S : L.R;
+    // the residual update r = r_old - alpha q, written out with d += alpha p;
+    // the scaled residual s r in R (the transform's input); ||r||^2
     double nrm = 0.0;
-    for (int o = threadIdx.x; o < n; o += kBlock) {
-        const double v = Ru[o];
-        if (io.r_out) io.r_out[off + o] = v;
-        if (io.dvec) io.dvec[off + o] = L.Own[n + o] + io.alpha * L.Own[o];
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        const double v = io.q ? L.R[i] - io.alpha * L.S[i] : L.R[i];
+        L.R[i] = io.scale ? v * io.scale[off + i] : v;
+        if (io.r_out) io.r_out[off + i] = v;
+        if (io.dvec) io.dvec[off + i] = L.Own[n + i] + io.alpha * L.Own[i];
+        if (io.keep) L.Own[i] = v;
         nrm += v * v;
     }
     if (io.part) {
@@ -1248,7 +1245,11 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, n3, 0, n12, n12);
     // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1]
     mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, 1, 0, 0, 0, L.red);
-    for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
+    if (io.keep) {
+        for (int o = threadIdx.x; o < n; o += kBlock) L.R[o] *= L.Own[2 * n + o];
+    } else {
+        for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
+    }
     __syncthreads();
 }
 // One 3x3x3 convolution layer (zero padding) as an implicit GEMM on the
@@ -2027,6 +2028,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
         fio.z = nullptr;
         fio.rdot = nullptr;
         fio.part = sl;
+        fio.keep = DIM == 3;
         if (D.act == ACT_ITER) {
             // p = z + beta p, q = A p, p.q
             const bool fresh = st.it == 0 && (!A.continue_cg || st.refine <= 1 || st.op64);
@@ -2088,9 +2090,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             double z2 = 0.0, z3 = 0.0;
             const double rzn = tiles([&](int b) {
                 if constexpr (DIM == 3) {
-                    fd3_issue_bwd<TU>(P, M, P.rt, r_oth, lds);
-                    g2l_wait_sync();
-                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);
+                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);  // its inputs kept in LDS
                 } else {
                     __syncthreads();
                     fd_issue_bwd<TU>(P, M, b, P.rt, r_oth, lds);
@@ -2156,9 +2156,7 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             fio.rdot = r_cur;
             const double rzn = tiles([&](int b) {
                 if constexpr (DIM == 3) {
-                    fd3_issue_bwd<TU>(P, M, P.rt, r_cur, lds);
-                    g2l_wait_sync();
-                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);
+                    fd3_bwd_run<TU, TC, LEARN>(P, M, fio, lds);  // its inputs kept in LDS
                 } else {
                     __syncthreads();
                     fd_issue_bwd<TU>(P, M, b, P.rt, r_cur, lds);
