@@ -649,8 +649,9 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
 // FP32 (lane l supplies A(16 t_m + l % 16, k + 8 (l / 16) + j) and
 // B(k + 8 (l / 16) + j, 16 t_n + l % 16), j < 8).  Lane l supplies A(16 t_m + l % 16, k + l / 16) and
 // B(k + l / 16, 16 t_n + l % 16); out-of-range operands are zero.  The
-// accumulation order is fixed, so results are reproducible.  Ends with a
-// workgroup barrier.
+// accumulation order is fixed, so results are reproducible.  E (optional):
+// each output multiplied by E at the output's index in C (a diagonal scaling
+// in the epilogue).  Ends with a workgroup barrier.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -678,7 +679,8 @@ __device__ __forceinline__ TC mm_ld(const T* p, int i) {
 template <typename TA, typename TB, typename TC>
 __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int sAm, int sAk, const TB* B, int sBk,
                                           int sBn, double* C, int sCm, int sCn, int nb = 1, int sAb = 0,
-                                          int sBb = 0, int sCb = 0, double* red = nullptr) {
+                                          int sBb = 0, int sCb = 0, double* red = nullptr,
+                                          const double* E = nullptr) {
     using MF = Mfma<TC>;
     using V = typename MF::V;
     constexpr bool kBf = std::is_same<TA, uint16_t>::value || std::is_same<TB, uint16_t>::value;
@@ -700,7 +702,8 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
             const TB* Bc = B + bt * sBb + n * sBn;
             TC acc = TC(0);
             for (int k = 0; k < K; ++k) acc = fma(mm_ld<TC>(Ar, k * sAk), mm_ld<TC>(Bc, k * sBk), acc);
-            C[bt * sCb + m * sCm + n * sCn] = static_cast<double>(acc);
+            const int ci = bt * sCb + m * sCm + n * sCn;
+            C[ci] = E ? static_cast<double>(acc) * E[ci] : static_cast<double>(acc);
         }
         __syncthreads();
         return;
@@ -754,7 +757,7 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
             const int ii = 16 * ti + MF::row(lane, r);
             if (ii < M && jv) {
                 const double v = static_cast<double>(acc0[r] + acc1[r]);
-                if (ks == 1) Cb[ii * sCm + j * sCn] = v;
+                if (ks == 1) Cb[ii * sCm + j * sCn] = E ? v * E[bt * sCb + ii * sCm + j * sCn] : v;
                 else red[(sl * M + ii) * N + j] = v;
             }
         }
@@ -767,7 +770,7 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, const TA* A, int 
             const int m = dN.div(o, &n);
             double v = 0.0;
             for (int sl = 0; sl < ks; ++sl) v += red[sl * M * N + o];
-            C[m * sCm + n * sCn] = v;
+            C[m * sCm + n * sCn] = E ? v * E[m * sCm + n * sCn] : v;
         }
         __syncthreads();
     }
@@ -1243,14 +1246,13 @@ __device__ __forceinline__ void fd3_fwd_run(const Params& P, const TaskMeta& M, 
     mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.R, n1, 1, L.U1, L.ld1, 1, L.S, n1, 1, 1, 0, 0, 0, L.red);
     // T[i3][k2][k1] = sum_i2 U2[i2][k2] S[i3][i2][k1]
     mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, 1, L.ld2, L.S, n1, 1, L.T, n1, 1, n3, 0, n12, n12);
-    // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1]
-    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, 1, 0, 0, 0, L.red);
-    if (io.keep) {
-        for (int o = threadIdx.x; o < n; o += kBlock) L.R[o] *= L.Own[2 * n + o];
-    } else {
+    // R[k3][k2 k1] = sum_i3 U3[i3][k3] T[i3][k2 k1] (kept: times 1 / lambda)
+    mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, 1, L.ld3, L.T, n12, 1, L.R, n12, 1, 1, 0, 0, 0, L.red,
+                              io.keep ? L.Own + 2 * n : nullptr);
+    if (!io.keep) {
         for (int o = threadIdx.x; o < n; o += kBlock) io.rt[off + o] = L.R[o] * L.Own[2 * n + o];
+        __syncthreads();
     }
-    __syncthreads();
 }
 // One 3x3x3 convolution layer (zero padding) as an implicit GEMM on the
 // matrix cores in BF16 with FP32 accumulation:
@@ -1344,13 +1346,9 @@ __device__ __forceinline__ void fd3_bwd_run(const Params& P, const TaskMeta& M, 
     mfma_gemm<TU, double, TC>(n3, n12, n3, L.U3, L.ld3, 1, L.R, n12, 1, L.T, n12, 1, 1, 0, 0, 0, L.red);
     // S[i3][i2][k1] = sum_k2 U2[i2][k2] T[i3][k2][k1]
     mfma_gemm<TU, double, TC>(n2, n1, n2, L.U2, L.ld2, 1, L.T, n1, 1, L.S, n1, 1, n3, 0, n12, n12);
-    // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1]
-    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, 1, 0, 0, 0, L.red);
-    if (io.scale) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kBlock) L.R[i] *= io.scale[off + i];
-        __syncthreads();
-    }
+    // Z[i3 i2][i1] = sum_k1 S[i3 i2][k1] U1[i1][k1], times the diagonal scaling
+    mfma_gemm<double, TU, TC>(n2 * n3, n1, n1, L.S, n1, 1, L.U1, 1, L.ld1, L.R, n1, 1, 1, 0, 0, 0, L.red,
+                              io.scale ? io.scale + off : nullptr);
     double scale = 0.0;  // s (additive head), -1 (log-scale head), 0: no learned correction
     float* Y = nullptr;
     if (LEARN && io.learned) {
