@@ -220,6 +220,18 @@ __device__ __forceinline__ int grid_of_qp(const Params& P, int g0, int g1, int64
     }
     return lo;
 }
+// The same for all lanes of a wavefront at once: the grid of the first active
+// lane's point is searched with wavefront-uniform indices (one search per
+// wavefront), lanes whose point lies outside that grid search their own.
+__device__ __forceinline__ int grid_of_qp_w(const Params& P, int g0, int g1, int64_t gq) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(gq));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(static_cast<uint64_t>(gq) >> 32));
+    const int64_t q0 = static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+    const int gw = grid_of_qp(P, g0, g1, q0);
+    const Grid& G = P.grids[gw];
+    if (gq >= G.qp_off && gq < G.qp_off + G.nqp) return gw;
+    return grid_of_qp(P, g0, g1, gq);
+}
 __device__ __forceinline__ int grid_of_dof(const Params& P, int g0, int g1, int64_t gi) {
     if (g0 == 0 && g1 == P.ngrid && P.ngrid1 < P.ngrid) {
         const int smp = static_cast<int>(gi / P.ndof1);
@@ -286,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Params P, FieldDev fa, Fiel
     constexpr int d = DIM;
     for (int64_t gq = q0 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; gq < q1;
          gq += static_cast<int64_t>(gridDim.x) * kBlock) {
-        const int gi = grid_of_qp(P, g0, g1, gq);
+        const int gi = grid_of_qp_w(P, g0, g1, gq);
         const Grid& g = P.grids[gi];
         // storage index l of the point; lt its index in the tensor order of
         // the grid's Gauss points (fields sampled at the points).  2D: the
@@ -452,7 +464,7 @@ __global__ void __launch_bounds__(kBlock) k_elemloc(Params P) {
         double Bv[LPL][DIM][NQ], Dv[LPL][DIM][NQ];
         double (*T)[NT] = sh[wave][slot];
         if (live) {
-            gi = grid_of_qp(P, 0, P.ngrid, el * NLOC);
+            gi = grid_of_qp_w(P, 0, P.ngrid, el * NLOC);
             const Grid& g = P.grids[gi];
             const int64_t rel = el - g.qp_off / NLOC;  // element index in the grid
             int64_t r = rel;
