@@ -487,6 +487,9 @@ __device__ __forceinline__ void elem_layer_3d_rows(const double* X, int nh1, int
                     double* y = Ye + a1 + NQ * (a2 + NQ * j3);
                     *y = j2 == 0 ? v : *y + v;
                 }
+                // one output at a time: keeps the scheduler from interleaving
+                // all of them, which would exceed the register budget
+                __builtin_amdgcn_sched_barrier(0);
             }
     }
 }
