@@ -89,8 +89,8 @@ iga_status iga_nn_pair(const double* r_dev, const double* zfd_dev, const double*
 iga_status iga_sg_loga(iga_sg_plan plan, int comp, double* out_dev);
 
 /* Attach the network used by learned solves (iga_sg_solve_opts.precond = 1;
- * three-dimensional plans, three input and one output channel, hidden
- * channels <= 16; head as in iga_nn_backward).  params_dev stays owned by the
+ * three-dimensional plans, three input and one output channel, at most 32
+ * and 48 channels in the two hidden layers; head as in iga_nn_backward).  params_dev stays owned by the
  * caller and must stay valid while such solves run; NULL detaches. */
 iga_status iga_sg_set_network(iga_sg_plan plan, const int* channels, int nlayers, const float* params_dev,
                               int head);
