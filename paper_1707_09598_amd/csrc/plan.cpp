@@ -923,7 +923,10 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                             halox *= static_cast<size_t>(nex - 1) * m + p + 1;
                             ntl *= (g.ni[k] + t[k] - 1) / t[k];
                         }
-                        const size_t lds = (std::max(halo, halox) + std::max(nel, nelx) * pl + kWaves) * sizeof(double);
+                        // + the FP32 copy of the halo block
+                        const size_t lds =
+                            (std::max(halo, halox) + std::max(nel, nelx) * pl + kWaves) * sizeof(double) +
+                            std::max(halo, halox) * sizeof(float);
                         if (lds + kSolveLdsHead > kLdsLimit) continue;
                         const double work = static_cast<double>(ntl) * (nel + 64.0);
                         if (best < 0 || work < best) {
@@ -939,7 +942,8 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.ntd[k] = (g.ni[k] + g.tile[k] - 1) / g.tile[k];
                 g.ntile *= g.ntd[k];
             }
-            // LDS of one operator tile: halo unknowns + element outputs
+            // LDS of one operator tile: halo unknowns (FP64 and an FP32 copy) +
+            // element outputs
             if (d == 3) {
                 size_t halo = 1, nel = 1;
                 for (int k = 0; k < 3; ++k) {
@@ -953,8 +957,8 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                     halo *= static_cast<size_t>(bestk - 1) * m + p + 1;
                 }
                 const size_t pl = static_cast<size_t>(p + 1) * (p + 1) * (p + 1);
-                lds_max = std::max(lds_max, (halo + nel * pl + kWaves) * sizeof(double));
-                lds_op = std::max(lds_op, (halo + nel * pl + kWaves) * sizeof(double));
+                lds_max = std::max(lds_max, (halo + nel * pl + kWaves) * sizeof(double) + halo * sizeof(float));
+                lds_op = std::max(lds_op, (halo + nel * pl + kWaves) * sizeof(double) + halo * sizeof(float));
             }
             if (d == 2) {
                 size_t halo = 1, nel = 1;

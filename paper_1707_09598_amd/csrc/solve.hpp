@@ -263,8 +263,8 @@ __device__ __forceinline__ void op_tile_2d(const Params& P, const Grid& g, const
 // an element add their layers in a fixed order (group_reduce_scatter, DPP
 // lane exchanges), lane j3 keeping the outputs of a3 = j3.
 // ---------------------------------------------------------------------------
-template <int PP, bool RAT, typename T>
-__device__ __forceinline__ void elem_layer_3d(const double* X, int nh1, int nh2, int x1, int x2, int x3,
+template <int PP, bool RAT, typename T, typename TX>
+__device__ __forceinline__ void elem_layer_3d(const TX* X, int nh1, int nh2, int x1, int x2, int x3,
                                               const double* B1, const double* D1, const double* B2,
                                               const double* D2, const double* B3r, const double* D3r,
                                               const T* Gl, int64_t nqp, int Q1, T (&Zb)[PP + 1][PP + 1],
@@ -523,6 +523,8 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
     double* X = lds;
     double* Y = lds + nh1 * nh2 * nh3;
     double* red = Y + ne1 * ne2 * ne3 * NE;
+    // FP32 element arithmetic: an FP32 copy of the halo block after red
+    float* Xf = reinterpret_cast<float*>(red + kWaves);
     const int64_t off = g.dof_off;
     const int n1 = g.ni[0], n2 = g.ni[1], n3 = g.ni[2];
     {
@@ -541,6 +543,7 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
                     io.out_in[gi] = v;
             }
             X[idx] = v;
+            if (io.lowp) Xf[idx] = static_cast<float>(v);
         }
     }
     __syncthreads();
@@ -586,8 +589,8 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         if (io.lowp) {
             float Zb[NQ][NQ], Zd[NQ][NQ], b3v[NQ], d3v[NQ];
             const float* Gl = P.G32 + g.qp_off * P.ncompG + ql;
-            if (rat) elem_layer_3d<PP, true, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
-            else elem_layer_3d<PP, false, float>(X, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
+            if (rat) elem_layer_3d<PP, true, float>(Xf, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
+            else elem_layer_3d<PP, false, float>(Xf, nh1, nh2, x1, x2, x3, B1, D1, B2, D2, B3r, D3r, Gl, nqp, NQ, Zb, Zd, b3v, d3v);
             finish(Zb, Zd, b3v, d3v);
         } else {
             const double* Gl = P.G64 + g.qp_off * P.ncompG + ql;
