@@ -618,13 +618,23 @@ __device__ __forceinline__ void op_tile_3d(const Params& P, const Grid& g, const
         d_elem_range(i1, i1 + 1, p, m1, g.E[0], T1.lo, &lo1, &hi1);
         d_elem_range(i2, i2 + 1, p, m2, g.E[1], T2.lo, &lo2, &hi2);
         d_elem_range(i3, i3 + 1, p, m3, g.E[2], T3.lo, &lo3, &hi3);
+        // the contributions of the support's elements, e3 and e2 outer, e1 inner
+        // (at most NQ elements a direction); the e1 run unrolled to NQ with the
+        // elements past hi1 adding 0, so that its loads are issued together
         double s = 0.0;
+        const int d1 = hi1 - lo1;
         for (int e3 = lo3; e3 <= hi3; ++e3)
-            for (int e2 = lo2; e2 <= hi2; ++e2)
-                for (int e1 = lo1; e1 <= hi1; ++e1) {
-                    const int el = ((e3 - el3) * ne2 + (e2 - el2)) * ne1 + (e1 - el1);
-                    s += Y[el * NE + (i1 + T1.lo - e1 * m1) + NQ * ((i2 + T2.lo - e2 * m2) + NQ * (i3 + T3.lo - e3 * m3))];
+            for (int e2 = lo2; e2 <= hi2; ++e2) {
+                const int el = ((e3 - el3) * ne2 + (e2 - el2)) * ne1 + (lo1 - el1);
+                const int base = el * NE + (i1 + T1.lo - lo1 * m1) +
+                                 NQ * ((i2 + T2.lo - e2 * m2) + NQ * (i3 + T3.lo - e3 * m3));
+#pragma unroll
+                for (int t1 = 0; t1 < NQ; ++t1) {
+                    // element lo1 + t1: element index + 1, local index - m1
+                    const double v = Y[t1 <= d1 ? base + t1 * (NE - m1) : base];
+                    s += t1 <= d1 ? v : 0.0;
                 }
+            }
         const int64_t gi = off + (static_cast<int64_t>(i3) * n2 + i2) * n1 + i1;
         if (io.rhs) {
             s = io.rhs[gi] - s;
