@@ -48,9 +48,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve3_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "1b5f3e726cda6face87a1233d5987dd6edfd80a2d1bd020cde138ef94f7769bc",
-    "fetch_kib": 71141171.27, "write_kib": 31205074.19,
-    "fetch_factor": 262144.0 / 131088.38, "write_factor": 262144.0 / 262144.0,
+    "sha256": "91868f2787723c899339eb97f47c32b8c3cb5643ccbb3c9250d23b5cd03077c2",
+    "fetch_kib": 68866508.58, "write_kib": 26758829.18,
+    "fetch_factor": 262144.0 / 131089.00, "write_factor": 262144.0 / 262144.0,
     "tol": 1e-10, "tol_inner": 1e-05,
 }
 
