@@ -2138,10 +2138,25 @@ __device__ __forceinline__ void solve_one_grid(const Params& P, const SolveArgs&
             io.rhs = P.b;
             io.part = sl;
             io.lowp = 0;
-            const double rn2 = tiles([&](int t) {
-                if constexpr (DIM == 3) op_tile_3d<PP, ROWS64>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
-                else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
-            }, g.ntile);
+            double rn2;
+            if (DIM == 3 && st.refine == 0 && g.ntile == 1) {
+                // the first residual of the solve: x = d = 0 (cleared at its
+                // start), so r = b; ||r||^2 in the order of the operator tile's
+                // sum (one tile: unknown o on thread o mod kBlock)
+                double acc = 0.0;
+                for (int o = threadIdx.x; o < g.ndof; o += kBlock) {
+                    const double v = P.b[g.dof_off + o];
+                    r_cur[g.dof_off + o] = v;
+                    acc += v * v;
+                }
+                rn2 = 0.0 + wg_sum(acc, lds);
+                __syncthreads();
+            } else {
+                rn2 = tiles([&](int t) {
+                    if constexpr (DIM == 3) op_tile_3d<PP, ROWS64>(P, g, M.t[0], M.t[1], M.t[2], t, io, lds);
+                    else op_tile_2d<PP>(P, g, M.t[0], M.t[1], t, io, lds);
+                }, g.ntile);
+            }
             for (int o = threadIdx.x; o < g.ndof; o += kBlock) {
                 const int64_t k = g.dof_off + o;
                 P.x[k] += P.d[k];
