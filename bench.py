@@ -48,9 +48,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve3_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "91868f2787723c899339eb97f47c32b8c3cb5643ccbb3c9250d23b5cd03077c2",
-    "fetch_kib": 68866508.58, "write_kib": 26758829.18,
-    "fetch_factor": 262144.0 / 131089.00, "write_factor": 262144.0 / 262144.0,
+    "sha256": "4fba9a49528fe904e35ef2000835cb1a1a4d0d10cf92aff9162d0d7b2f2680a4",
+    "fetch_kib": 66314398.14, "write_kib": 26500552.30,
+    "fetch_factor": 262144.0 / 131088.25, "write_factor": 262144.0 / 262144.0,
     "tol": 1e-10, "tol_inner": 1e-05,
 }
 
@@ -124,8 +124,10 @@ def solve_bytes(P, rep, precision):
     operator coefficients at its Gauss points (ncompG values, 4 B in the
     FP32 inner operator, 8 B in FP64) and 64 B per unknown of FP64 vectors
     (eight passes); per refinement sweep the FP64 coefficients and the same
-    vector bytes.  The 1D factors U_l are shared by every grid of a level and
-    charged once per distinct table and sweep (forward and backward reads).
+    vector bytes, except that the first residual of a solve, from the zero
+    initial guess, is b itself and needs no coefficients.  The 1D factors U_l
+    are shared by every grid of a level and charged once per distinct table
+    and sweep (forward and backward reads).
     """
     wl = P.wl
     ncompG, p, d = _ncompG(wl), int(wl["p"]), int(wl["dim"])
@@ -138,7 +140,7 @@ def solve_bytes(P, rep, precision):
         nqp = float(np.prod([2 ** int(l) * (p + 1) for l in lv]))
         ndof = float(np.prod(ni))
         it, rf = int(rep["iters"][c]), int(rep["refinements"][c])
-        total += it * (ncompG * nqp * b_in + 64 * ndof) + rf * (ncompG * nqp * 8 + 64 * ndof)
+        total += it * (ncompG * nqp * b_in + 64 * ndof) + rf * 64 * ndof + max(rf - 1, 0) * ncompG * nqp * 8
     sweeps = int(np.max(rep["iters"] + 2 * rep["refinements"]))
     levels = sorted({int(l) for lv in P.levels for l in lv})
     total += sweeps * sum(2 * (2 ** l + p - 2) ** 2 * b_u for l in levels) * d
