@@ -48,9 +48,9 @@ SOLVE_TRAFFIC = {
     "sources": ["paper_1707_09598_amd/csrc/solve.hpp", "paper_1707_09598_amd/csrc/solve3_p3.hip",
                 "paper_1707_09598_amd/csrc/common.hpp", "paper_1707_09598_amd/csrc/device.hpp",
                 "paper_1707_09598_amd/csrc/plan.cpp", "paper_1707_09598_amd/csrc/kernels.hip"],
-    "sha256": "4fba9a49528fe904e35ef2000835cb1a1a4d0d10cf92aff9162d0d7b2f2680a4",
-    "fetch_kib": 66314398.14, "write_kib": 26500552.30,
-    "fetch_factor": 262144.0 / 131088.25, "write_factor": 262144.0 / 262144.0,
+    "sha256": "38cf66f6919cd5b756760707854eb422d700ba04ea6edfb3ce9e0121231023ae",
+    "fetch_kib": 66341922.67, "write_kib": 26499089.28,
+    "fetch_factor": 262144.0 / 131088.56, "write_factor": 262144.0 / 262144.0,
     "tol": 1e-10, "tol_inner": 1e-05,
 }
 

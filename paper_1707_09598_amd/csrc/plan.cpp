@@ -143,6 +143,7 @@ std::vector<double> make_knots(int p, int r, int lev, int gk, double gamma) {
 struct FDEntry {
     std::vector<double> K, M, U, lam;
     int n = 0;
+    bool ok = false;  // the decomposition succeeded (or there is nothing to decompose)
 };
 
 std::mutex g_fd_mu;
@@ -158,7 +159,7 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
     auto key = std::make_tuple(p, r, lev, gk, gamma, nq, lo * 2 + hi);
     auto it = g_fd_cache.find(key);
     if (it != g_fd_cache.end()) {
-        *ok = true;
+        *ok = it->second.ok;
         return it->second;
     }
     FDEntry e;
@@ -209,8 +210,11 @@ const FDEntry& fd_entry(int p, int r, int lev, int gk, double gamma, int nq, con
             std::memcpy(&e.U[static_cast<size_t>(i) * ni], &Ur[static_cast<size_t>(ni - 1 - i) * ni],
                         sizeof(double) * ni);
     } else {
-        *ok = ni > 0 && gen_eig_banded(ni, p, e.K.data(), e.M.data(), e.U.data(), e.lam.data());
+        // no interior unknowns (degree 1 at level 0): an empty factor
+        *ok = ni == 0 || gen_eig_banded(ni, p, e.K.data(), e.M.data(), e.U.data(), e.lam.data());
     }
+    // failures are cached as failures, so a later plan reports them too
+    e.ok = *ok;
     auto res = g_fd_cache.emplace(key, std::move(e));
     return res.first->second;
 }
@@ -831,6 +835,12 @@ iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc,
                 g.ndof *= g.ni[k];
                 g.nqp *= g.Q[k];
                 g.fdc[k] = 1.0;
+            }
+            if (g.ndof <= 0) {
+                // degree 1 at level 0 with Dirichlet ends: only boundary functions
+                set_error("component grid %d has no interior unknowns (degree %d at level 0): raise lmin", c, p);
+                delete P;
+                return IGA_ERR_INVALID_ARG;
             }
             g.dof_off = P->ndof_total;
             P->ndof_total += g.ndof;

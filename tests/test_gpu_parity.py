@@ -73,7 +73,7 @@ def _config(name, w):
     (a = exp(g) on a 24^3 vertex grid, seed 0).  Variants: '_c0' / '_c1'
     lower the continuity (interior knots of multiplicity p or p - 1),
     '_graded' uses radical knots (two-sided in direction 1, toward 0 in
-    direction 2; eq. of Sec. 4.4)."""
+    direction 2; eq. of Sec. 4.4), '_p<k>' degree k with maximal continuity."""
     if name == "cfg5":
         a = W.grf_samples(1, n=24)[0]
         return W.config(name, w=w, a=W._field("grid3d", data=a))
@@ -85,6 +85,9 @@ def _config(name, w):
     if var == "graded":
         return W.config(base, w=w, grading=[("radical", 3.0), ("toward0", 2.0)] +
                         ([("uniform", 1.0)] if base in ("cfg3", "cfg5") else []))
+    if var.startswith("p"):
+        deg = int(var[1:])
+        return W.config(base, w=w, p=deg, r=deg - 1)
     return W.config(name, w=w)
 
 
@@ -93,7 +96,10 @@ def _config(name, w):
                                           ("cfg3", 5, None), ("cfg3", 7, [0, 1, 2, 5, 9, 14]),
                                           ("cfg5", 4, [0, 3, 6, 10]),
                                           ("cfg1_c0", 4, None), ("cfg2_c1", 5, [0, 2, 5, 8, 10]),
-                                          ("cfg2_graded", 5, [0, 3, 7, 10]), ("cfg3_c1", 4, None)])
+                                          ("cfg2_graded", 5, [0, 3, 7, 10]), ("cfg3_c1", 4, None),
+                                          # 3D degrees 1, 2, 4: element layers summed over groups of 2,
+                                          # 4 (one padding lane) and 8 lanes
+                                          ("cfg3_p1", 5, None), ("cfg3_p2", 4, None), ("cfg3_p4", 4, [0, 1])])
 def test_rhs_and_operator_parity(S, name, w, comps):
     wl = _config(name, w)
     log(f"case rhs/operator {name} w={w}")

@@ -96,6 +96,20 @@ def test_invalid_arguments_are_rejected(S):
     assert e.value.code == 2
 
 
+def test_degree_one_plans_are_deterministic(S):
+    """Degree 1 at level 0 leaves no interior unknowns: a plan whose combination
+    uses such a grid is rejected with the same error every time (the 1D factor
+    cache keeps failures as failures), and one whose levels start at 1 builds
+    every time, its unused level-0 tables empty."""
+    for _ in range(2):
+        with pytest.raises(S.IgaError) as e:
+            S.Plan(W.config("cfg1", w=4, p=1, r=0))
+        assert e.value.code == 1 and "no interior unknowns" in str(e.value)
+    for _ in range(2):
+        P = S.Plan(W.config("cfg3", w=5, p=1, r=0))
+        assert P.ncomp == 10 and int(P.ndof.min()) >= 1
+
+
 def test_call_order_state_errors(S):
     P = S.Plan(W.config("cfg1"))
     L = S.lib()
