@@ -233,7 +233,11 @@ typedef struct {
 /* Build a plan: index set and combination coefficients (eq. TD-combi-tec),
  * knot vectors per level (Sec. 3; grading Sec. 4.4), Gauss rules, 1D
  * stiffness/mass matrices and their generalised eigen-decompositions for the
- * fast-diagonalisation preconditioner, task lists.  Host only; no GPU call. */
+ * fast-diagonalisation preconditioner, task lists.  Host only; no GPU call.
+ * Errors: IGA_ERR_INVALID_ARG for unsupported sizes or combinations, among
+ * them a component grid without interior unknowns (degree 1 at level 0:
+ * raise lmin); IGA_ERR_GEOMETRY for bad patch data or a failed 1D
+ * eigen-decomposition. */
 iga_status iga_sg_plan_create(const iga_geometry* geom, const iga_sg_disc* disc, iga_sg_plan* out);
 
 /* Bytes of device workspace the plan needs (256-byte aligned sub-buffers). */
